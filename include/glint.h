@@ -1,0 +1,243 @@
+/*
+ * glint.h -- C ABI of libglint: constant-cost spatio-angular range queries of
+ * a glint P-NDF compressed by CP (tensor-rank) decomposition, on AMD gfx950.
+ *
+ * Method: Deng et al., "Constant-Cost Spatio-Angular Prefiltering of Glinty
+ * Appearance Using Tensor Decomposition".  Sec. 3.1 (Eq. geom) defines the
+ * P-NDF, Sec. 4.1 the footprint pyramid over every texel and level, Sec. 4.2
+ * (Eq. compress) the CP fit by alternating least squares, Sec. 4.3
+ * (Eq. decompress) the point query and Sec. 4.4 (Eq. rangeDecom, summed-area
+ * tables, and the Appendix proposition) the constant-cost range query.
+ *
+ * Conventions for every call:
+ *   - Pointers are DEVICE pointers unless a parameter says "host".  The caller
+ *     owns every buffer (inputs, outputs, workspace); the library allocates
+ *     nothing and keeps no state between calls.
+ *   - Each call validates its arguments on the host and returns a status
+ *     synchronously; on success the work is enqueued on `stream` and the call
+ *     returns without waiting.  A failed kernel launch returns GLINT_E_HIP.
+ *     Faults inside kernels surface at the caller's next synchronisation.
+ *   - glint_last_error() gives a human-readable detail of the last non-OK
+ *     status returned on the calling thread.
+ *   - Tensors are row-major; "[a][b]" means b is the fastest index.
+ *   - No call throws across the ABI.
+ *
+ * Query records are int32 [7] = (u, v, l, s_lo, s_hi, t_lo, t_hi): footprint
+ * centre (u, v), level l (a 2^l x 2^l texel box), and half-open bin ranges
+ * [s_lo, s_hi) x [t_lo, t_hi).  Index rules (kernels never fault on them):
+ * u, v wrap modulo the map size (maps are tileable); l clamps to
+ * [0, nlevels-1] (footprints beyond the pyramid clamp to its coarsest level,
+ * Sec. 5.1); bin bounds clamp to [0, nbins]; a box with lo >= hi on either
+ * axis gives exactly 0.  The value returned is the box SUM of bin masses;
+ * the paper's box average is sum / ((s_hi - s_lo) * (t_hi - t_lo)).
+ */
+#ifndef GLINT_H
+#define GLINT_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t glint_status;
+#define GLINT_OK             0
+#define GLINT_E_INVALID     (-1)   /* bad argument: null pointer, size, alignment */
+#define GLINT_E_UNSUPPORTED (-2)   /* valid but not implemented (dtype, rank, size) */
+#define GLINT_E_HIP         (-3)   /* a HIP runtime call or kernel launch failed */
+#define GLINT_E_WORKSPACE   (-4)   /* workspace smaller than the *_workspace size */
+
+typedef enum glint_dtype {
+  GLINT_F64 = 0,
+  GLINT_F32 = 1,
+  GLINT_BF16 = 2,       /* bfloat16, stored as uint16 bit patterns */
+  GLINT_FP8E4M3 = 3     /* OCP E4M3FN, stored as uint8, with per-column FP32 scales */
+} glint_dtype;
+
+/* The NDF tensor T[u][v][l][s][t] of a normal map (Sec. 3.1, Sec. 4.1).
+ * A texel with projected normal (n_x, n_y) contributes m_x[s] * m_y[t] to bin
+ * (s, t), where m_x[i] is the mass of a Gaussian of standard deviation sigma
+ * centred on n_x inside bin i, edges e_i = -1 + 2i/N, renormalised to the mass
+ * inside [-1, 1].  Level l averages the texels of the box of side k = 2^l
+ * anchored at (u - k/2, v - k/2) (integer division), wrapping. */
+typedef struct glint_ndf_desc {
+  int32_t nu, nv;       /* normal-map size in texels (u slow, v fast), >= 1 */
+  int32_t nlevels;      /* footprint levels, 1..16; 2^(nlevels-1) <= min(nu, nv) */
+  int32_t nbins;        /* N: bins per axis over [-1, 1]; power of two, 4..256 */
+  double sigma;         /* intrinsic roughness, > 0 */
+} glint_ndf_desc;
+
+/* Compressed factors for the range query (Sec. 4.4, Eq. rangeDecom):
+ *   q = sum_r c[r] * U[u][r] V[v][r] L[l][r] (CS[s_hi][r] - CS[s_lo][r])
+ *                                         (CT[t_hi][r] - CT[t_lo][r]),
+ * values decoded exactly from their storage type, and c[r] the product (FP32,
+ * in the order U, V, L, CS, CT) of the per-column scales given (a NULL scale
+ * is 1).  CS, CT are the 1D summed-area tables of the S and T factors:
+ * CS[j][r] = sum_{s<j} S[s][r], j = 0..nbins. */
+typedef struct glint_factors {
+  int32_t R;            /* rank: 16, 32, 64, 128 or 256 */
+  int32_t nu, nv, nl;   /* rows of U, V, L */
+  int32_t nbins;        /* N; CS and CT have N+1 rows */
+  glint_dtype dtype;    /* storage of U, V, L: F32, BF16 or FP8E4M3 */
+  glint_dtype cum_dtype;/* storage of CS, CT: F32, BF16 or FP8E4M3 */
+  const void* U;        /* [nu][R], 16-byte aligned */
+  const void* V;        /* [nv][R] */
+  const void* L;        /* [nl][R] */
+  const void* CS;       /* [N+1][R] */
+  const void* CT;       /* [N+1][R] */
+  const float* scale_U; /* [R] per-column scale of U (FP8 storage), or NULL */
+  const float* scale_V;
+  const float* scale_L;
+  const float* scale_CS;
+  const float* scale_CT;
+} glint_factors;
+
+/* ---- identification ------------------------------------------------------ */
+const char* glint_status_string(glint_status s);
+const char* glint_last_error(void);
+int32_t glint_version(void);
+
+/* ---- step 1: per-texel angular binning (Sec. 3.1, Eq. geom) --------------- */
+
+/* Half-width K of the per-texel bin window: K = ceil(8 sigma / w) + 1 with
+ * w = 2/N.  Bins further than K from a texel's centre bin hold less than
+ * Phi(-8) of its mass and are treated as 0.  Returns -1 for an invalid desc. */
+int32_t glint_window_radius(const glint_ndf_desc* desc);
+
+/* For every texel (u, v) and axis a (0: s from n_x, 1: t from n_y):
+ *   bins[(u*nv + v)*2 + a] = i0 = clamp(floor((n + 1) * N/2), 0, N-1), in FP64;
+ *   mass[((u*nv + v)*2 + a)*(2K+1) + j] = normalised mass of bin i0 - K + j
+ *     (0 where that bin is outside [0, N)).
+ * nxy: [nu][nv][2] float32 projected normals.  bins: int32, mass: double. */
+glint_status glint_texel_bins(const glint_ndf_desc* desc, const float* nxy,
+                              int32_t* bins, double* mass, hipStream_t stream);
+
+/* ---- step 2: NDF tensor over every texel and level (Sec. 4.1) ------------ */
+
+/* Workspace bytes for glint_build_tensor (the bin windows). */
+size_t glint_build_tensor_workspace(const glint_ndf_desc* desc);
+
+/* T[u][v][l][s][t] (dtype F64 or F32), every entry written.  Levels
+ * l < direct_levels are built directly from their footprint texels (the
+ * texels' bin windows staged in LDS); each higher level is the exact mean of
+ * four shifted blocks of the level below (a 2k box is two k boxes per axis).
+ * direct_levels <= 0 selects the default (4); values above nlevels mean
+ * "every level directly".  T must be 16-byte aligned. */
+glint_status glint_build_tensor(const glint_ndf_desc* desc, const float* nxy,
+                                void* T, glint_dtype T_dtype, int32_t direct_levels,
+                                void* workspace, size_t workspace_bytes,
+                                hipStream_t stream);
+
+/* Brute-force range integral for the refinement targets and the error
+ * against the exact NDF: out[i] = (1/k^2) sum over footprint texels of
+ * (mass of the texel's s-window inside [s_lo, s_hi)) * (same for t), FP64.
+ * bins, mass: output of glint_texel_bins for the same desc.  q: [nq][7]. */
+glint_status glint_range_bruteforce(const glint_ndf_desc* desc, const int32_t* bins,
+                                    const double* mass, int64_t nq, const int32_t* q,
+                                    double* out, hipStream_t stream);
+
+/* ---- step 3: CP decomposition by ALS (Sec. 4.2, Eq. compress) ------------ */
+
+/* Workspace bytes for glint_cp_als on a materialised T of this desc. */
+size_t glint_cp_als_workspace(const glint_ndf_desc* desc, int32_t R, glint_dtype T_dtype);
+
+/* Rank-R CP-ALS of T (dtype F64: FP64 matrix-core MTTKRP; F32: FP32
+ * matrix-core MTTKRP).  Factors are FP64 [rows][R] in/out: on entry the
+ * initial factors, on exit the fit with unit-norm columns in U, V, S, Tf and
+ * the column weights lambda absorbed into L.  Each sweep updates the modes in
+ * the order u, v, l, s, t; a mode update is A_n = M_n G^-1 with the Gram
+ * Hadamard product G factored by FP64 Cholesky.  fit_hist[iters] receives
+ * 1 - ||T - T^|| / ||T|| after each sweep (sweeps skipped after convergence
+ * repeat the last value).  If tol > 0 the sweeps stop once the fit changes by
+ * less than tol.  info (int32[4], may be NULL): sweeps run, mode updates whose
+ * Gram was not positive definite (that factor then keeps its previous value),
+ * and two reserved zeros.  R in {16, 32, 64, 128}; nbins >= 16. */
+glint_status glint_cp_als(const glint_ndf_desc* desc, const void* T, glint_dtype T_dtype,
+                          int32_t R, int32_t iters, double tol,
+                          double* U, double* V, double* L, double* S, double* Tf,
+                          double* fit_hist, int32_t* info,
+                          void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* The MTTKRP of one mode, the contraction a mode update of glint_cp_als
+ * starts from: M[i][r] = sum over the other four indices of T times the
+ * product of the other four factors' entries in column r.  mode: 0 u, 1 v,
+ * 2 l, 3 s, 4 t.  Uses the same matrix-core passes as glint_cp_als (the
+ * (s,t) contraction pass for modes u, v, l; the cell contraction pass for
+ * modes s, t).  Factors FP64 [rows][R], M FP64 [rows of the mode][R];
+ * workspace of glint_cp_als_workspace bytes; same limits as glint_cp_als. */
+glint_status glint_mttkrp(const glint_ndf_desc* desc, const void* T, glint_dtype T_dtype,
+                          int32_t R, int32_t mode, const double* U, const double* V,
+                          const double* L, const double* S, const double* Tf, double* M,
+                          void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ---- step 4: summed-area tables and storage types (Sec. 4.4) ------------ */
+
+/* C[j][r] = sum_{s<j} S[s][r] for j = 0..n, accumulated in FP64 and then
+ * stored as out_dtype: F64, F32 (round to nearest even from FP64), BF16
+ * (FP64 -> FP32 -> BF16, each round to nearest even) or FP8E4M3 (per-column
+ * scale = amax/448 of the FP32 values, code = RNE(x/scale), saturating; the
+ * scales go to col_scale[R], which must then be non-NULL).
+ * S: [n][R] of dtype in_dtype (F64 or F32).  C: [n+1][R]. */
+glint_status glint_make_cumulative(int32_t n, int32_t R, const void* S, glint_dtype in_dtype,
+                                   void* C, glint_dtype out_dtype, float* col_scale,
+                                   hipStream_t stream);
+
+/* Storage conversion of a factor table [rows][R]: in F64 or F32; out F32,
+ * BF16 or FP8E4M3 (per-column scales as in glint_make_cumulative, written to
+ * col_scale). */
+glint_status glint_convert(int64_t rows, int32_t R, const void* in, glint_dtype in_dtype,
+                           void* out, glint_dtype out_dtype, float* col_scale,
+                           hipStream_t stream);
+
+/* ---- step 5: the range query (Sec. 4.4, Eq. rangeDecom; Appendix) ------- */
+
+/* out[i] for each record q[i] (int32 [nq][7], see the header comment), FP32
+ * arithmetic on values decoded exactly from their storage types.
+ * nq = 0 is a no-op.  Requires f->nbins in 4..256 and the tables to fit the
+ * kernel's on-chip staging (L, CS, CT together at most 96 KiB as FP32). */
+glint_status glint_query(const glint_factors* f, int64_t nq, const int32_t* q,
+                         float* out, hipStream_t stream);
+
+/* Grouped form for shading points that share a footprint: uvl int32
+ * [npts][3] = (u, v, l), boxes int32 [npts][K][4] = (s_lo, s_hi, t_lo, t_hi),
+ * out float [npts][K].  Same value as glint_query on the expanded records. */
+glint_status glint_query_grouped(const glint_factors* f, int64_t npts, int32_t K,
+                                 const int32_t* uvl, const int32_t* boxes,
+                                 float* out, hipStream_t stream);
+
+/* ---- step 6: gradient of the query (not in the paper) -------------------- */
+
+/* Gradients of sum_i gout[i] * q[i] with respect to the stored values of U,
+ * V, L, CS and CT (FP32, overwritten: the call clears them first).  f->dtype
+ * and f->cum_dtype must be F32 or BF16.  dU [nu][R], dV [nv][R], dL [nl][R],
+ * dCS, dCT [N+1][R].  Accumulation uses atomics, so the summation order (and
+ * the last bits) vary between runs. */
+glint_status glint_query_backward(const glint_factors* f, int64_t nq, const int32_t* q,
+                                  const float* gout, float* dU, float* dV, float* dL,
+                                  float* dCS, float* dCT, hipStream_t stream);
+
+/* Chain rule through the summed-area table: dS[s][r] = sum_{j>s} dC[j][r].
+ * dC: [n+1][R], dS: [n][R], FP32. */
+glint_status glint_cumulative_backward(int32_t n, int32_t R, const float* dC, float* dS,
+                                       hipStream_t stream);
+
+/* ---- step 7: refinement helpers (not in the paper) ----------------------- */
+
+/* Mean squared error against FP64 targets: loss[0] = (1/nq) sum (q - t)^2
+ * (FP64), gout[i] = 2 (q[i] - t[i]) / nq (FP32).  loss may be NULL. */
+glint_status glint_mse_grad(int64_t nq, const float* q, const double* target,
+                            float* gout, double* loss, hipStream_t stream);
+
+/* One Adam step (Kingma and Ba) on n FP32 parameters, step >= 1:
+ * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * p -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps). */
+glint_status glint_adam_step(int64_t n, float* p, const float* g, float* m, float* v,
+                             float lr, float b1, float b2, float eps, int32_t step,
+                             hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GLINT_H */

@@ -16,7 +16,8 @@ tensors stopped at an error of 1e-4 or 500 sweeps):
   * After each update the columns are scaled to unit 2-norm and the norms
     kept as lambda; a zero column is left as it is.  After the last sweep
     lambda is absorbed into the level factor L.
-  * G is factored by Cholesky; if that fails the eigen-decomposition
+  * G is factored by Cholesky; it counts as failed when a pivot is not above
+    1e-13 times the matching diagonal entry of G; then the eigen-decomposition
     pseudo-inverse with eigenvalues below 1e-12 * max eigenvalue dropped is
     used instead.
   * A fixed number of sweeps; optionally stop once |fit_k - fit_{k-1}| < tol.
@@ -47,10 +48,19 @@ def gram_hadamard(A, n: int) -> np.ndarray:
     return G
 
 
+PIVOT_RTOL = 1e-13
+
+
 def solve_gram(M: np.ndarray, G: np.ndarray):
-    """X = M G^-1 (G symmetric PSD).  Returns (X, used_fallback)."""
+    """X = M G^-1 (G symmetric PSD).  Returns (X, used_fallback).
+
+    Cholesky counts as failed when a pivot is not above PIVOT_RTOL times the
+    matching diagonal entry of G (a singular PSD matrix can leave a tiny
+    positive pivot after rounding)."""
     try:
         c = np.linalg.cholesky(G)
+        if np.any(np.diag(c) ** 2 <= PIVOT_RTOL * np.diag(G)):
+            raise np.linalg.LinAlgError("relative pivot breakdown")
         X = scipy.linalg.cho_solve((c, True), M.T).T
         return X, False
     except np.linalg.LinAlgError:

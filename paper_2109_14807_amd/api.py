@@ -1,0 +1,184 @@
+"""Allocation and call sequencing over libglint (no arithmetic of its own).
+
+Each helper allocates device tensors with torch and calls the C entry points
+in ``_lib`` on the current stream; every value is computed by the library's
+kernels.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from ._lib import NdfDesc
+
+_DEV = "cuda"
+
+
+def desc_of(nu, nv, nlevels, nbins, sigma) -> NdfDesc:
+    return NdfDesc.make(nu, nv, nlevels, nbins, sigma)
+
+
+def _dev(x, dtype):
+    if isinstance(x, torch.Tensor):
+        return x.to(device=_DEV, dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device=_DEV)
+
+
+def texel_bins(nxy, desc: NdfDesc):
+    """Centre bins int32 [nu*nv*2] and window masses float64 [nu*nv*2*(2K+1)]."""
+    nxy = _dev(nxy, torch.float32)
+    K = L.glint_window_radius(desc)
+    n2 = desc.nu * desc.nv * 2
+    bins = torch.empty(n2, dtype=torch.int32, device=_DEV)
+    mass = torch.empty(n2 * (2 * K + 1), dtype=torch.float64, device=_DEV)
+    L.glint_texel_bins(desc, nxy, bins, mass)
+    return bins, mass
+
+
+def build_tensor(nxy, desc: NdfDesc, dtype=torch.float32, direct_levels: int = 0, out=None):
+    """T[u][v][l][s][t] on the GPU."""
+    nxy = _dev(nxy, torch.float32)
+    shape = (desc.nu, desc.nv, desc.nlevels, desc.nbins, desc.nbins)
+    T = torch.empty(shape, dtype=dtype, device=_DEV) if out is None else out
+    ws = torch.empty(L.glint_build_tensor_workspace(desc), dtype=torch.uint8, device=_DEV)
+    L.glint_build_tensor(desc, nxy, T, direct_levels, ws)
+    return T
+
+
+def range_bruteforce(nxy, desc: NdfDesc, q, bins_mass=None):
+    """Exact box sums of the brute-force NDF for each query (FP64)."""
+    bins, mass = texel_bins(nxy, desc) if bins_mass is None else bins_mass
+    q = _dev(q, torch.int32)
+    out = torch.empty(q.shape[0], dtype=torch.float64, device=_DEV)
+    L.glint_range_bruteforce(desc, bins, mass, q, out)
+    return out
+
+
+@dataclasses.dataclass
+class AlsResult:
+    factors: tuple          # (U, V, L*lambda, S, T) FP64 device tensors
+    fits: torch.Tensor      # [iters] FP64
+    info: torch.Tensor      # int32 [4]: sweeps run, non-PD Gram updates, 0, 0
+
+
+def als_workspace(desc: NdfDesc, R: int, T_dtype) -> torch.Tensor:
+    n = L.glint_cp_als_workspace(desc, R, L.DTYPE_OF[T_dtype])
+    if n == 0:
+        raise ValueError("unsupported ALS configuration")
+    return torch.empty(n, dtype=torch.uint8, device=_DEV)
+
+
+def cp_als(T: torch.Tensor, desc: NdfDesc, init, iters: int, tol: float = 0.0,
+           workspace=None) -> AlsResult:
+    R = int(init[0].shape[1])
+    F = tuple(_dev(a, torch.float64).clone() for a in init)
+    fits = torch.zeros(iters, dtype=torch.float64, device=_DEV)
+    info = torch.zeros(4, dtype=torch.int32, device=_DEV)
+    ws = als_workspace(desc, R, T.dtype) if workspace is None else workspace
+    L.glint_cp_als(desc, T, R, iters, tol, *F, fits, info, ws)
+    return AlsResult(F, fits, info)
+
+
+def mttkrp(T: torch.Tensor, desc: NdfDesc, factors, mode: int, workspace=None):
+    """MTTKRP of one mode (FP64 [rows][R]) with the ALS matrix-core passes."""
+    R = int(factors[0].shape[1])
+    F = tuple(_dev(a, torch.float64) for a in factors)
+    rows = (desc.nu, desc.nv, desc.nlevels, desc.nbins, desc.nbins)[mode]
+    M = torch.empty((rows, R), dtype=torch.float64, device=_DEV)
+    ws = als_workspace(desc, R, T.dtype) if workspace is None else workspace
+    L.glint_mttkrp(desc, T, R, mode, *F, M, ws)
+    return M
+
+
+# ----------------------------------------------------------------------------
+# query tables
+# ----------------------------------------------------------------------------
+
+_STORE = {"f32": torch.float32, "bf16": torch.bfloat16, "fp8": torch.float8_e4m3fn,
+          "f64": torch.float64}
+
+
+@dataclasses.dataclass
+class QueryTables:
+    U: torch.Tensor
+    V: torch.Tensor
+    L: torch.Tensor
+    CS: torch.Tensor
+    CT: torch.Tensor
+    scales: tuple           # five per-column FP32 scales or None
+
+    def factors(self) -> L.Factors:
+        return L.make_factors(self.U, self.V, self.L, self.CS, self.CT, self.scales)
+
+    @property
+    def R(self):
+        return self.U.shape[1]
+
+
+def convert(x, dtype: str):
+    """Store a factor table as f32, bf16 or fp8 (+ per-column scales)."""
+    x = x if isinstance(x, torch.Tensor) and x.is_cuda else _dev(x, torch.float64)
+    if x.dtype not in (torch.float64, torch.float32):
+        x = x.to(torch.float64)
+    out = torch.empty(x.shape, dtype=_STORE[dtype], device=_DEV)
+    sc = torch.empty(x.shape[1], dtype=torch.float32, device=_DEV) if dtype == "fp8" else None
+    L.glint_convert(x.contiguous(), out, sc)
+    return out, sc
+
+
+def cumulative(S, dtype: str = "f32"):
+    """Summed-area table [N+1][R] of S (FP64 accumulation) in a storage type."""
+    S = S if isinstance(S, torch.Tensor) and S.is_cuda else _dev(S, torch.float64)
+    if S.dtype not in (torch.float64, torch.float32):
+        S = S.to(torch.float64)
+    C = torch.empty((S.shape[0] + 1, S.shape[1]), dtype=_STORE[dtype], device=_DEV)
+    sc = torch.empty(S.shape[1], dtype=torch.float32, device=_DEV) if dtype == "fp8" else None
+    L.glint_make_cumulative(S.contiguous(), C, sc)
+    return C, sc
+
+
+def make_tables(U, V, Lf, S, Tf, dtype: str = "f32", cum_dtype: str = "f32") -> QueryTables:
+    u, su = convert(U, dtype)
+    v, sv = convert(V, dtype)
+    l, sl = convert(Lf, dtype)
+    cs, scs = cumulative(S, cum_dtype)
+    ct, sct = cumulative(Tf, cum_dtype)
+    return QueryTables(u, v, l, cs, ct, (su, sv, sl, scs, sct))
+
+
+def query(tables: QueryTables, q, out=None):
+    q = _dev(q, torch.int32)
+    out = torch.empty(q.shape[0], dtype=torch.float32, device=_DEV) if out is None else out
+    f = tables.factors()
+    L.glint_query(f, q, out)
+    return out
+
+
+def query_grouped(tables: QueryTables, uvl, boxes, out=None):
+    uvl = _dev(uvl, torch.int32)
+    boxes = _dev(boxes, torch.int32)
+    out = (torch.empty(boxes.shape[0], boxes.shape[1], dtype=torch.float32, device=_DEV)
+           if out is None else out)
+    f = tables.factors()
+    L.glint_query_grouped(f, uvl, boxes, out)
+    return out
+
+
+def query_backward(tables: QueryTables, q, gout):
+    """Gradients (dU, dV, dL, dCS, dCT) of sum gout * q w.r.t. the stored tables."""
+    R = tables.R
+    z = lambda rows: torch.empty((rows, R), dtype=torch.float32, device=_DEV)
+    dU, dV, dLt = z(tables.U.shape[0]), z(tables.V.shape[0]), z(tables.L.shape[0])
+    dCS, dCT = z(tables.CS.shape[0]), z(tables.CT.shape[0])
+    L.glint_query_backward(tables.factors(), _dev(q, torch.int32), gout.contiguous(),
+                           dU, dV, dLt, dCS, dCT)
+    return dU, dV, dLt, dCS, dCT
+
+
+def cumulative_backward(dC):
+    dS = torch.empty((dC.shape[0] - 1, dC.shape[1]), dtype=torch.float32, device=_DEV)
+    L.glint_cumulative_backward(dC.contiguous(), dS)
+    return dS

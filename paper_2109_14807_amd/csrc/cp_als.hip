@@ -1,0 +1,859 @@
+// CP decomposition of the NDF tensor by alternating least squares
+// (Sec. 4.2, Eq. compress), entirely on the GPU with no host synchronisation.
+//
+// A sweep updates the factors in the order u, v, l, s, t; the update of mode n
+// is A_n = M_n G^-1 with M_n the MTTKRP and G the Hadamard product of the other
+// factors' Grams.  The five MTTKRPs of a sweep need only two passes over T:
+//
+//   Z pass  Z[cell][r] = sum_{s,t} T[cell][s,t] S[s][r] Tf[t][r]
+//           (a GEMM ncells x N^2 times the N^2 x R Khatri-Rao block of S and
+//           Tf, formed in registers), then
+//           M_U[u] = sum_{v,l} V[v] L[l] Z[u,v,l],  M_V and M_L likewise with
+//           the freshly updated factors (Z does not depend on U, V, L);
+//   Y pass  Y[s,t][r] = sum_cell T[cell][s,t] U[u][r] V[v][r] L[l][r]
+//           (a split-K GEMM N^2 x ncells times ncells x R), then
+//           M_S[s] = sum_t Tf[t] Y[s,t],  M_T[t] = sum_s S_new[s] Y[s,t].
+//
+// Both passes run on the matrix cores (v_mfma_f64_16x16x4f64 for an FP64 T,
+// v_mfma_f32_16x16x4f32 for an FP32 T) reading each T element once.  Grams,
+// the Cholesky factorisation, the triangular solves, the column norms and the
+// fit are FP64.  Every kernel reads a "done" flag first so that a sweep loop
+// stopped by the tolerance costs only empty launches.
+#include <math.h>
+
+#include <algorithm>
+#include <type_traits>
+
+#include "common.h"
+
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename AT>
+struct Mfma;
+
+// Both 16x16x4 shapes take A[i][k] from lane i + 16k and B[k][j] from lane
+// j + 16k; the result D[i][j] sits in lane j + 16*(i/4) item i%4 for FP32 but
+// in lane j + 16*(i%4) item i/4 for FP64 (measured on gfx950).  row(g, q) is
+// the D row held in item q by the lanes of group g = lane/16.
+template <>
+struct Mfma<float> {
+  typedef f32x4 acc_t;
+  static __device__ __forceinline__ acc_t run(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int g, int q) { return 4 * g + q; }
+};
+
+template <>
+struct Mfma<double> {
+  typedef f64x4 acc_t;
+  static __device__ __forceinline__ acc_t run(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int g, int q) { return g + 4 * q; }
+};
+
+// control block in the workspace
+enum { CTRL_DONE = 0, CTRL_SWEEPS = 1, CTRL_FAILS = 2, CTRL_FAILNOW = 3, CTRL_N = 8 };
+
+constexpr double kPivotRtol = 1e-13;
+constexpr int kPad64 = 2;   // LDS row padding (elements) so 16 rows hit distinct banks
+constexpr int kPad32 = 4;
+
+// ---------------------------------------------------------------------------
+// ||T||^2
+// ---------------------------------------------------------------------------
+
+template <typename TT>
+__global__ __launch_bounds__(256) void k_sumsq(const TT* __restrict__ T, int64_t n,
+                                               double* __restrict__ part) {
+  double acc = 0.0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double x = static_cast<double>(T[i]);
+    acc += x * x;
+  }
+  __shared__ double sh[4];
+  acc = glint_wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+__global__ void k_sum_parts(const double* __restrict__ part, int n, double* __restrict__ out,
+                            int* __restrict__ ctrl, double* __restrict__ fitprev) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) acc += part[i];
+  acc = glint_wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[0] = sh[0] + sh[1] + sh[2] + sh[3];
+    for (int i = 0; i < CTRL_N; ++i) ctrl[i] = 0;
+    fitprev[0] = 0.0;
+  }
+}
+
+__global__ void k_ctrl_init(int* __restrict__ ctrl) {
+  if (threadIdx.x < CTRL_N) ctrl[threadIdx.x] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Z pass: Z[cell][r] = sum_k T[cell][k] W2[k][r],  W2[s*N+t][r] = S[s][r] Tf[t][r]
+// A wave owns 16*ROWT cells and all R columns.  Lane (i = l%16, kk = l/16)
+// loads VEC consecutive k of cell i; MFMA sub-step j takes k = k0 + kk*VEC + j.
+// ---------------------------------------------------------------------------
+
+template <typename TT, int R, int ROWT>
+__global__ __launch_bounds__(256) void k_mttkrp_z(const TT* __restrict__ T, int64_t ncells, int N,
+                                                  const double* __restrict__ S,
+                                                  const double* __restrict__ Tf,
+                                                  TT* __restrict__ Z, const int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE]) return;
+  typedef Mfma<TT> M;
+  typedef typename M::acc_t acc_t;
+  typedef typename std::conditional<sizeof(TT) == 4, float4, double2>::type vec_t;
+  constexpr int VEC = 16 / sizeof(TT);
+  constexpr int CT = R / 16;
+  constexpr int PAD = sizeof(TT) == 4 ? kPad32 : kPad64;
+  extern __shared__ __align__(16) unsigned char smem[];
+  TT* TfT = reinterpret_cast<TT*>(smem);   // [R][N + PAD]
+  const int ld = N + PAD;
+  for (int i = threadIdx.x; i < N * R; i += blockDim.x) {
+    const int t = i / R, r = i - (i / R) * R;
+    TfT[r * ld + t] = static_cast<TT>(Tf[i]);
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63;
+  const int i16 = lane & 15;
+  const int kk = lane >> 4;
+  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int64_t cell0 = wave * 16 * ROWT;
+  if (cell0 >= ncells) return;
+  const int64_t NN = static_cast<int64_t>(N) * N;
+
+  acc_t acc[ROWT][CT];
+#pragma unroll
+  for (int rt = 0; rt < ROWT; ++rt)
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc[rt][c] = acc_t{};
+
+  const TT* rowp[ROWT];
+  bool rowok[ROWT];
+#pragma unroll
+  for (int rt = 0; rt < ROWT; ++rt) {
+    const int64_t cell = cell0 + 16 * rt + i16;
+    rowok[rt] = cell < ncells;
+    rowp[rt] = T + (rowok[rt] ? cell : 0) * NN + kk * VEC;
+  }
+
+  const int chunks = N / (4 * VEC);
+  for (int s = 0; s < N; ++s) {
+    TT sv[CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) sv[c] = static_cast<TT>(S[s * R + 16 * c + i16]);
+    for (int tb = 0; tb < chunks; ++tb) {
+      const int t0 = tb * 4 * VEC;
+      const int64_t k0 = static_cast<int64_t>(s) * N + t0;
+      vec_t av[ROWT];
+#pragma unroll
+      for (int rt = 0; rt < ROWT; ++rt) {
+        av[rt] = rowok[rt] ? *reinterpret_cast<const vec_t*>(rowp[rt] + k0) : vec_t{};
+      }
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const vec_t tv = *reinterpret_cast<const vec_t*>(&TfT[(16 * c + i16) * ld + t0 + kk * VEC]);
+        const TT* tvp = reinterpret_cast<const TT*>(&tv);
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+          const TT b = sv[c] * tvp[j];
+#pragma unroll
+          for (int rt = 0; rt < ROWT; ++rt) {
+            const TT a = reinterpret_cast<const TT*>(&av[rt])[j];
+            acc[rt][c] = M::run(a, b, acc[rt][c]);
+          }
+        }
+      }
+    }
+  }
+  // D[m][n]: item q of this lane holds row M::row(lane/16, q), column lane%16
+#pragma unroll
+  for (int rt = 0; rt < ROWT; ++rt)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t cell = cell0 + 16 * rt + M::row(kk, q);
+      if (cell < ncells) {
+#pragma unroll
+        for (int c = 0; c < CT; ++c) Z[cell * R + 16 * c + i16] = acc[rt][c][q];
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Y pass (split K over cells): Ypart[split][k][r] = sum_{cell in split} T[cell][k] C[cell][r],
+// C[cell][r] = U[u][r] V[v][r] L[l][r].  A wave owns 16*VEC rows k (VEC row
+// tiles: tile j holds k = kb + m*VEC + j) and all R columns; 4 cells per step.
+// ---------------------------------------------------------------------------
+
+template <typename TT, int R>
+__global__ __launch_bounds__(256) void k_mttkrp_y(const TT* __restrict__ T, int64_t ncells, int N,
+                                                  int nv, int nl, const double* __restrict__ U,
+                                                  const double* __restrict__ V,
+                                                  const double* __restrict__ L,
+                                                  int64_t cells_per_split, TT* __restrict__ Ypart,
+                                                  const int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE]) return;
+  typedef Mfma<TT> M;
+  typedef typename M::acc_t acc_t;
+  typedef typename std::conditional<sizeof(TT) == 4, float4, double2>::type vec_t;
+  constexpr int VEC = 16 / sizeof(TT);
+  constexpr int CT = R / 16;
+  const int lane = threadIdx.x & 63;
+  const int i16 = lane & 15;
+  const int kk = lane >> 4;
+  const int w = threadIdx.x >> 6;
+  const int64_t NN = static_cast<int64_t>(N) * N;
+  const int64_t kb = (static_cast<int64_t>(blockIdx.x) * 4 + w) * 16 * VEC;
+  const int64_t c_begin = static_cast<int64_t>(blockIdx.y) * cells_per_split;
+  int64_t c_end = c_begin + cells_per_split;
+  if (c_end > ncells) c_end = ncells;
+
+  acc_t acc[VEC][CT];
+#pragma unroll
+  for (int j = 0; j < VEC; ++j)
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc[j][c] = acc_t{};
+
+  if (kb < NN) {
+    for (int64_t c0 = c_begin; c0 < c_end; c0 += 4) {
+      const int64_t cell = c0 + kk;
+      const bool ok = cell < c_end;
+      const int64_t cc = ok ? cell : c_begin;
+      vec_t av = ok ? *reinterpret_cast<const vec_t*>(T + cc * NN + kb + i16 * VEC) : vec_t{};
+      const int l = static_cast<int>(cc % nl);
+      const int64_t uv = cc / nl;
+      const int v = static_cast<int>(uv % nv);
+      const int64_t u = uv / nv;
+      TT bv[CT];
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const int r = 16 * c + i16;
+        bv[c] = static_cast<TT>(U[u * R + r] * V[static_cast<int64_t>(v) * R + r] * L[l * R + r]);
+      }
+#pragma unroll
+      for (int j = 0; j < VEC; ++j) {
+        const TT a = reinterpret_cast<const TT*>(&av)[j];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[j][c] = M::run(a, bv[c], acc[j][c]);
+      }
+    }
+    TT* out = Ypart + static_cast<int64_t>(blockIdx.y) * NN * R;
+#pragma unroll
+    for (int j = 0; j < VEC; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t k = kb + M::row(kk, q) * VEC + j;
+#pragma unroll
+        for (int c = 0; c < CT; ++c) out[k * R + 16 * c + i16] = acc[j][c][q];
+      }
+  }
+}
+
+template <typename TT>
+__global__ void k_reduce_splits(const TT* __restrict__ Ypart, int nsplit, int64_t n,
+                                double* __restrict__ Y, const int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE]) return;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    double acc = 0.0;
+    for (int p = 0; p < nsplit; ++p) acc += static_cast<double>(Ypart[p * n + i]);
+    Y[i] = acc;
+  }
+}
+
+// mode s (which=3): M[s][r] = sum_t F[t][r] Y[s*N+t][r];  mode t (which=4): M[t][r] = sum_s F[s][r] Y[s*N+t][r]
+__global__ void k_mttkrp_st(const double* __restrict__ Y, const double* __restrict__ F, int N, int R,
+                            int which, double* __restrict__ M, const int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE]) return;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N * R) return;
+  const int a = idx / R, r = idx - (idx / R) * R;
+  double acc = 0.0;
+  for (int b = 0; b < N; ++b) {
+    const int64_t k = which == 3 ? static_cast<int64_t>(a) * N + b : static_cast<int64_t>(b) * N + a;
+    acc += F[b * R + r] * Y[k * R + r];
+  }
+  M[idx] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Z reductions for modes u, v, l (FP64)
+// ---------------------------------------------------------------------------
+
+template <typename TT>
+__global__ __launch_bounds__(256) void k_reduce_zu(const TT* __restrict__ Z, int nv, int nl, int R,
+                                                   const double* __restrict__ V,
+                                                   const double* __restrict__ L,
+                                                   double* __restrict__ M, const int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE]) return;
+  __shared__ double sh[256];
+  const int u = blockIdx.x;
+  const int r = threadIdx.x % R;
+  const int parts = blockDim.x / R;
+  const int p = threadIdx.x / R;
+  double acc = 0.0;
+  if (p < parts) {
+    const int64_t base = static_cast<int64_t>(u) * nv * nl;
+    for (int vl = p; vl < nv * nl; vl += parts) {
+      const int v = vl / nl, l = vl - (vl / nl) * nl;
+      acc += V[v * R + r] * L[l * R + r] * static_cast<double>(Z[(base + vl) * R + r]);
+    }
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x < R) {
+    double s = 0.0;
+    for (int q = 0; q < parts; ++q) s += sh[q * R + threadIdx.x];
+    M[u * R + threadIdx.x] = s;
+  }
+}
+
+template <typename TT>
+__global__ __launch_bounds__(256) void k_reduce_zv(const TT* __restrict__ Z, int nu, int nv, int nl,
+                                                   int R, const double* __restrict__ U,
+                                                   const double* __restrict__ L,
+                                                   double* __restrict__ M, const int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE]) return;
+  __shared__ double sh[256];
+  const int v = blockIdx.x;
+  const int r = threadIdx.x % R;
+  const int parts = blockDim.x / R;
+  const int p = threadIdx.x / R;
+  double acc = 0.0;
+  if (p < parts) {
+    for (int ul = p; ul < nu * nl; ul += parts) {
+      const int u = ul / nl, l = ul - (ul / nl) * nl;
+      const int64_t cell = (static_cast<int64_t>(u) * nv + v) * nl + l;
+      acc += U[u * R + r] * L[l * R + r] * static_cast<double>(Z[cell * R + r]);
+    }
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x < R) {
+    double s = 0.0;
+    for (int q = 0; q < parts; ++q) s += sh[q * R + threadIdx.x];
+    M[v * R + threadIdx.x] = s;
+  }
+}
+
+// part[l][u][r] = sum_v U[u][r] V[v][r] Z[u,v,l][r]
+template <typename TT>
+__global__ __launch_bounds__(256) void k_reduce_zl(const TT* __restrict__ Z, int nu, int nv, int nl,
+                                                   int R, const double* __restrict__ U,
+                                                   const double* __restrict__ V,
+                                                   double* __restrict__ part, const int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE]) return;
+  __shared__ double sh[256];
+  const int u = blockIdx.x, l = blockIdx.y;
+  const int r = threadIdx.x % R;
+  const int parts = blockDim.x / R;
+  const int p = threadIdx.x / R;
+  double acc = 0.0;
+  if (p < parts) {
+    for (int v = p; v < nv; v += parts) {
+      const int64_t cell = (static_cast<int64_t>(u) * nv + v) * nl + l;
+      acc += V[v * R + r] * static_cast<double>(Z[cell * R + r]);
+    }
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x < R) {
+    double s = 0.0;
+    for (int q = 0; q < parts; ++q) s += sh[q * R + threadIdx.x];
+    part[(static_cast<int64_t>(l) * nu + u) * R + threadIdx.x] = U[u * R + threadIdx.x] * s;
+  }
+}
+
+__global__ void k_sum_rows(const double* __restrict__ part, int rows, int groups, int R,
+                           double* __restrict__ M, const int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE]) return;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= groups * R) return;
+  const int gidx = idx / R, r = idx - (idx / R) * R;
+  double acc = 0.0;
+  for (int i = 0; i < rows; ++i) acc += part[(static_cast<int64_t>(gidx) * rows + i) * R + r];
+  M[idx] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Grams, Cholesky, solve, normalisation, fit (FP64)
+// ---------------------------------------------------------------------------
+
+__global__ void k_gram(const double* __restrict__ A, int rows, int R, double* __restrict__ G,
+                       const int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE] || ctrl[CTRL_FAILNOW]) return;
+  const int i = blockIdx.y * 16 + threadIdx.y;
+  const int j = blockIdx.x * 16 + threadIdx.x;
+  if (i >= R || j >= R) return;
+  double acc = 0.0;
+  for (int k = 0; k < rows; ++k) acc += A[k * R + i] * A[k * R + j];
+  G[i * R + j] = acc;
+}
+
+// One workgroup: G = Hadamard product of the Grams of the modes other than n,
+// lower Cholesky factor in place (LDS), written as Lc and its transpose LcT.
+__global__ __launch_bounds__(1024) void k_cholesky(const double* __restrict__ grams, int n, int R,
+                                                   double* __restrict__ Lc, double* __restrict__ LcT,
+                                                   int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE]) return;
+  extern __shared__ __align__(16) double G[];   // [R*R] matrix, then [R] original diagonal
+  double* diag0 = G + R * R;
+  const int RR = R * R;
+  for (int i = threadIdx.x; i < RR; i += blockDim.x) {
+    double g = 1.0;
+    for (int m = 0; m < 5; ++m)
+      if (m != n) g *= grams[static_cast<int64_t>(m) * RR + i];
+    G[i] = g;
+    if (i % (R + 1) == 0) diag0[i / (R + 1)] = g;
+  }
+  __syncthreads();
+  bool fail = false;
+  for (int j = 0; j < R; ++j) {
+    const double d = G[j * R + j];
+    // breakdown: a pivot not above kPivotRtol times the original diagonal entry
+    if (!(d > kPivotRtol * diag0[j])) {
+      fail = true;
+      break;
+    }
+    const double ljj = sqrt(d);
+    __syncthreads();
+    for (int i = j + 1 + threadIdx.x; i < R; i += blockDim.x) G[i * R + j] /= ljj;
+    if (threadIdx.x == 0) G[j * R + j] = ljj;
+    __syncthreads();
+    const int w = R - j - 1;
+    for (int idx = threadIdx.x; idx < w * w; idx += blockDim.x) {
+      const int i = j + 1 + idx / w, k = j + 1 + idx % w;
+      if (k <= i) G[i * R + k] -= G[i * R + j] * G[k * R + j];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    ctrl[CTRL_FAILNOW] = fail ? 1 : 0;
+    if (fail) ctrl[CTRL_FAILS] += 1;
+  }
+  if (fail) return;
+  for (int idx = threadIdx.x; idx < RR; idx += blockDim.x) {
+    const int i = idx / R, k = idx % R;
+    const double x = k <= i ? G[idx] : 0.0;
+    Lc[idx] = x;
+    LcT[k * R + i] = x;
+  }
+}
+
+// One wave per row: x = m G^-1 with G = Lc Lc^T (forward then back substitution).
+template <int R>
+__global__ __launch_bounds__(256) void k_solve(const double* __restrict__ M, int rows,
+                                               const double* __restrict__ Lc,
+                                               const double* __restrict__ LcT,
+                                               double* __restrict__ A, const int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE] || ctrl[CTRL_FAILNOW]) return;
+  constexpr int E = (R + 63) / 64;
+  const int lane = threadIdx.x & 63;
+  const int row = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (row >= rows) return;
+  double w[E];
+#pragma unroll
+  for (int t = 0; t < E; ++t) {
+    const int e = lane + 64 * t;
+    w[t] = e < R ? M[static_cast<int64_t>(row) * R + e] : 0.0;
+  }
+  // forward: L y = m
+  for (int j = 0; j < R; ++j) {
+    const int slot = j >> 6, owner = j & 63;
+    double wj = 0.0;
+#pragma unroll
+    for (int t = 0; t < E; ++t)
+      if (t == slot) wj = w[t];
+    const double yj = __shfl(wj, owner) / Lc[j * R + j];
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+      const int e = lane + 64 * t;
+      if (e == j) w[t] = yj;
+      else if (e > j && e < R) w[t] -= LcT[j * R + e] * yj;
+    }
+  }
+  // back: L^T x = y
+  for (int j = R - 1; j >= 0; --j) {
+    const int slot = j >> 6, owner = j & 63;
+    double wj = 0.0;
+#pragma unroll
+    for (int t = 0; t < E; ++t)
+      if (t == slot) wj = w[t];
+    const double xj = __shfl(wj, owner) / Lc[j * R + j];
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+      const int e = lane + 64 * t;
+      if (e == j) w[t] = xj;
+      else if (e < j) w[t] -= Lc[j * R + e] * xj;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < E; ++t) {
+    const int e = lane + 64 * t;
+    if (e < R) A[static_cast<int64_t>(row) * R + e] = w[t];
+  }
+}
+
+__global__ void k_normalize(double* __restrict__ A, int rows, int R, double* __restrict__ lam,
+                            const int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE] || ctrl[CTRL_FAILNOW]) return;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  double s = 0.0;
+  for (int i = 0; i < rows; ++i) {
+    const double x = A[static_cast<int64_t>(i) * R + r];
+    s += x * x;
+  }
+  const double nrm = sqrt(s);
+  lam[r] = nrm;
+  if (nrm > 0.0)
+    for (int i = 0; i < rows; ++i) A[static_cast<int64_t>(i) * R + r] /= nrm;
+}
+
+// fit = 1 - ||T - T^|| / ||T|| after the t update of sweep `it`.
+__global__ __launch_bounds__(256) void k_fit(const double* __restrict__ grams, const double* __restrict__ lam,
+                                             const double* __restrict__ Mt, const double* __restrict__ At,
+                                             int N, int R, const double* __restrict__ normT2, int it,
+                                             double tol, double* __restrict__ fit_hist,
+                                             double* __restrict__ fitprev, int* __restrict__ ctrl) {
+  __shared__ double sh[8];
+  if (ctrl[CTRL_DONE]) {
+    if (threadIdx.x == 0) fit_hist[it] = fitprev[0];
+    return;
+  }
+  double inner = 0.0, hat = 0.0;
+  for (int idx = threadIdx.x; idx < N * R; idx += blockDim.x) {
+    const int r = idx % R;
+    inner += lam[r] * Mt[idx] * At[idx];
+  }
+  const int RR = R * R;
+  for (int idx = threadIdx.x; idx < RR; idx += blockDim.x) {
+    double g = lam[idx / R] * lam[idx % R];
+    for (int m = 0; m < 5; ++m) g *= grams[static_cast<int64_t>(m) * RR + idx];
+    hat += g;
+  }
+  inner = glint_wave_sum(inner);
+  hat = glint_wave_sum(hat);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh[w] = inner;
+    sh[4 + w] = hat;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double in = sh[0] + sh[1] + sh[2] + sh[3];
+    const double nh = sh[4] + sh[5] + sh[6] + sh[7];
+    const double t2 = normT2[0];
+    double res2 = t2 - 2.0 * in + nh;
+    if (res2 < 0.0) res2 = 0.0;
+    const double fit = 1.0 - sqrt(res2) / sqrt(t2);
+    fit_hist[it] = fit;
+    ctrl[CTRL_SWEEPS] = it + 1;
+    if (tol > 0.0 && it > 0 && fabs(fit - fitprev[0]) < tol) ctrl[CTRL_DONE] = 1;
+    fitprev[0] = fit;
+  }
+}
+
+__global__ void k_absorb(double* __restrict__ L, int nl, int R, const double* __restrict__ lam,
+                         const int* __restrict__ ctrl, int* __restrict__ info) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < nl * R) L[idx] *= lam[idx % R];
+  if (idx == 0 && info) {
+    info[0] = ctrl[CTRL_SWEEPS];
+    info[1] = ctrl[CTRL_FAILS];
+    info[2] = 0;
+    info[3] = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------
+
+struct AlsLayout {
+  size_t z, ypart, y, m, lpart, grams, lc, lct, lam, sumsq, scal, ctrl, total;
+  int nsplit;
+  int64_t cells_per_split;
+  int sumsq_blocks;
+};
+
+bool als_layout(const glint_ndf_desc* d, int R, size_t elt, AlsLayout* L) {
+  const int64_t ncells = static_cast<int64_t>(d->nu) * d->nv * d->nlevels;
+  const int64_t NN = static_cast<int64_t>(d->nbins) * d->nbins;
+  const int VEC = static_cast<int>(16 / elt);
+  const int64_t kblocks = (NN + 64 * VEC - 1) / (64 * VEC);
+  int64_t nsplit = 2048 / (kblocks > 0 ? kblocks : 1);
+  if (nsplit < 1) nsplit = 1;
+  if (nsplit > (ncells + 63) / 64) nsplit = (ncells + 63) / 64;
+  if (nsplit < 1) nsplit = 1;
+  int64_t cps = (ncells + nsplit - 1) / nsplit;
+  cps = (cps + 3) / 4 * 4;
+  nsplit = (ncells + cps - 1) / cps;
+  L->nsplit = static_cast<int>(nsplit);
+  L->cells_per_split = cps;
+  L->sumsq_blocks = 1024;
+  const int maxrows = std::max(std::max(d->nu, d->nv), std::max(d->nlevels, d->nbins));
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += glint_round_up(bytes, 256);
+    return at;
+  };
+  L->z = take(elt * ncells * R);
+  L->ypart = take(elt * nsplit * NN * R);
+  L->y = take(sizeof(double) * NN * R);
+  L->m = take(sizeof(double) * maxrows * R);
+  L->lpart = take(sizeof(double) * static_cast<size_t>(d->nlevels) * d->nu * R);
+  L->grams = take(sizeof(double) * 5 * R * R);
+  L->lc = take(sizeof(double) * R * R);
+  L->lct = take(sizeof(double) * R * R);
+  L->lam = take(sizeof(double) * R);
+  L->sumsq = take(sizeof(double) * L->sumsq_blocks);
+  L->scal = take(sizeof(double) * 4);
+  L->ctrl = take(sizeof(int) * CTRL_N);
+  L->total = off;
+  return true;
+}
+
+template <typename TT, int R>
+glint_status run_als(const glint_ndf_desc* d, const TT* T, int iters, double tol, double* F[5],
+                     double* fit_hist, int32_t* info, unsigned char* ws, const AlsLayout& Lo,
+                     hipStream_t stream) {
+  const int nu = d->nu, nv = d->nv, nl = d->nlevels, N = d->nbins;
+  const int rows[5] = {nu, nv, nl, N, N};
+  const int64_t ncells = static_cast<int64_t>(nu) * nv * nl;
+  const int64_t NN = static_cast<int64_t>(N) * N;
+  TT* Z = reinterpret_cast<TT*>(ws + Lo.z);
+  TT* Yp = reinterpret_cast<TT*>(ws + Lo.ypart);
+  double* Y = reinterpret_cast<double*>(ws + Lo.y);
+  double* Mb = reinterpret_cast<double*>(ws + Lo.m);
+  double* lpart = reinterpret_cast<double*>(ws + Lo.lpart);
+  double* grams = reinterpret_cast<double*>(ws + Lo.grams);
+  double* Lc = reinterpret_cast<double*>(ws + Lo.lc);
+  double* LcT = reinterpret_cast<double*>(ws + Lo.lct);
+  double* lam = reinterpret_cast<double*>(ws + Lo.lam);
+  double* sumsq = reinterpret_cast<double*>(ws + Lo.sumsq);
+  double* scal = reinterpret_cast<double*>(ws + Lo.scal);   // [0] ||T||^2, [1] previous fit
+  int* ctrl = reinterpret_cast<int*>(ws + Lo.ctrl);
+
+  constexpr int ROWT = R <= 64 ? 2 : 1;
+  constexpr int PAD = sizeof(TT) == 4 ? kPad32 : kPad64;
+  const size_t z_lds = sizeof(TT) * R * (N + PAD);
+  const size_t chol_lds = sizeof(double) * (R * R + R);
+
+  glint_clear_launch_error();
+  hipLaunchKernelGGL(k_sumsq<TT>, dim3(Lo.sumsq_blocks), dim3(256), 0, stream, T, ncells * NN, sumsq);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, stream, sumsq, Lo.sumsq_blocks, scal, ctrl,
+                     scal + 1);
+  GLINT_LAUNCHED("k_sumsq");
+  const dim3 gblk(16, 16), ggrid((R + 15) / 16, (R + 15) / 16);
+  for (int m = 0; m < 5; ++m)
+    hipLaunchKernelGGL(k_gram, ggrid, gblk, 0, stream, F[m], rows[m], R, grams + m * R * R, ctrl);
+  GLINT_LAUNCHED("k_gram");
+
+  auto update = [&](int n) -> glint_status {
+    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), chol_lds, stream, grams, n, R, Lc, LcT, ctrl);
+    GLINT_LAUNCHED("k_cholesky");
+    const int rws = rows[n];
+    hipLaunchKernelGGL((k_solve<R>), dim3((rws + 3) / 4), dim3(256), 0, stream, Mb, rws, Lc, LcT, F[n], ctrl);
+    GLINT_LAUNCHED("k_solve");
+    hipLaunchKernelGGL(k_normalize, dim3((R + 63) / 64), dim3(64), 0, stream, F[n], rws, R, lam, ctrl);
+    GLINT_LAUNCHED("k_normalize");
+    hipLaunchKernelGGL(k_gram, ggrid, gblk, 0, stream, F[n], rws, R, grams + n * R * R, ctrl);
+    GLINT_LAUNCHED("k_gram");
+    return GLINT_OK;
+  };
+
+  const int64_t zwaves = (ncells + 16 * ROWT - 1) / (16 * ROWT);
+  const unsigned zblocks = static_cast<unsigned>((zwaves + 3) / 4);
+  const int VEC = 16 / sizeof(TT);
+  const unsigned yblocks = static_cast<unsigned>((NN + 64 * VEC - 1) / (64 * VEC));
+  for (int it = 0; it < iters; ++it) {
+    hipLaunchKernelGGL((k_mttkrp_z<TT, R, ROWT>), dim3(zblocks), dim3(256), z_lds, stream, T, ncells,
+                       N, F[3], F[4], Z, ctrl);
+    GLINT_LAUNCHED("k_mttkrp_z");
+    hipLaunchKernelGGL(k_reduce_zu<TT>, dim3(nu), dim3(256), 0, stream, Z, nv, nl, R, F[1], F[2], Mb, ctrl);
+    GLINT_LAUNCHED("k_reduce_zu");
+    glint_status st = update(0);
+    if (st != GLINT_OK) return st;
+    hipLaunchKernelGGL(k_reduce_zv<TT>, dim3(nv), dim3(256), 0, stream, Z, nu, nv, nl, R, F[0], F[2], Mb, ctrl);
+    GLINT_LAUNCHED("k_reduce_zv");
+    if ((st = update(1)) != GLINT_OK) return st;
+    hipLaunchKernelGGL(k_reduce_zl<TT>, dim3(nu, nl), dim3(256), 0, stream, Z, nu, nv, nl, R, F[0], F[1],
+                       lpart, ctrl);
+    hipLaunchKernelGGL(k_sum_rows, dim3((nl * R + 255) / 256), dim3(256), 0, stream, lpart, nu, nl, R, Mb, ctrl);
+    GLINT_LAUNCHED("k_reduce_zl");
+    if ((st = update(2)) != GLINT_OK) return st;
+    hipLaunchKernelGGL((k_mttkrp_y<TT, R>), dim3(yblocks, Lo.nsplit), dim3(256), 0, stream, T, ncells, N,
+                       nv, nl, F[0], F[1], F[2], Lo.cells_per_split, Yp, ctrl);
+    GLINT_LAUNCHED("k_mttkrp_y");
+    hipLaunchKernelGGL(k_reduce_splits<TT>, dim3(static_cast<unsigned>(std::min<int64_t>((NN * R + 255) / 256, 4096))),
+                       dim3(256), 0, stream, Yp, Lo.nsplit, NN * R, Y, ctrl);
+    GLINT_LAUNCHED("k_reduce_splits");
+    hipLaunchKernelGGL(k_mttkrp_st, dim3((N * R + 255) / 256), dim3(256), 0, stream, Y, F[4], N, R, 3, Mb, ctrl);
+    GLINT_LAUNCHED("k_mttkrp_st");
+    if ((st = update(3)) != GLINT_OK) return st;
+    hipLaunchKernelGGL(k_mttkrp_st, dim3((N * R + 255) / 256), dim3(256), 0, stream, Y, F[3], N, R, 4, Mb, ctrl);
+    GLINT_LAUNCHED("k_mttkrp_st");
+    if ((st = update(4)) != GLINT_OK) return st;
+    hipLaunchKernelGGL(k_fit, dim3(1), dim3(256), 0, stream, grams, lam, Mb, F[4], N, R, scal, it, tol,
+                       fit_hist, scal + 1, ctrl);
+    GLINT_LAUNCHED("k_fit");
+  }
+  hipLaunchKernelGGL(k_absorb, dim3((nl * R + 255) / 256), dim3(256), 0, stream, F[2], nl, R, lam, ctrl, info);
+  GLINT_LAUNCHED("k_absorb");
+  return GLINT_OK;
+}
+
+template <typename TT, int R>
+glint_status run_mttkrp(const glint_ndf_desc* d, const TT* T, int mode, const double* const F[5],
+                        double* M, unsigned char* ws, const AlsLayout& Lo, hipStream_t stream) {
+  const int nu = d->nu, nv = d->nv, nl = d->nlevels, N = d->nbins;
+  const int64_t ncells = static_cast<int64_t>(nu) * nv * nl;
+  const int64_t NN = static_cast<int64_t>(N) * N;
+  TT* Z = reinterpret_cast<TT*>(ws + Lo.z);
+  TT* Yp = reinterpret_cast<TT*>(ws + Lo.ypart);
+  double* Y = reinterpret_cast<double*>(ws + Lo.y);
+  double* lpart = reinterpret_cast<double*>(ws + Lo.lpart);
+  int* ctrl = reinterpret_cast<int*>(ws + Lo.ctrl);
+  constexpr int ROWT = R <= 64 ? 2 : 1;
+  constexpr int PAD = sizeof(TT) == 4 ? kPad32 : kPad64;
+  const int VEC = 16 / sizeof(TT);
+  glint_clear_launch_error();
+  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, stream, ctrl);
+  GLINT_LAUNCHED("k_ctrl_init");
+  if (mode <= 2) {
+    const int64_t zwaves = (ncells + 16 * ROWT - 1) / (16 * ROWT);
+    hipLaunchKernelGGL((k_mttkrp_z<TT, R, ROWT>), dim3(static_cast<unsigned>((zwaves + 3) / 4)), dim3(256),
+                       sizeof(TT) * R * (N + PAD), stream, T, ncells, N, F[3], F[4], Z, ctrl);
+    GLINT_LAUNCHED("k_mttkrp_z");
+    if (mode == 0) {
+      hipLaunchKernelGGL(k_reduce_zu<TT>, dim3(nu), dim3(256), 0, stream, Z, nv, nl, R, F[1], F[2], M, ctrl);
+    } else if (mode == 1) {
+      hipLaunchKernelGGL(k_reduce_zv<TT>, dim3(nv), dim3(256), 0, stream, Z, nu, nv, nl, R, F[0], F[2], M, ctrl);
+    } else {
+      hipLaunchKernelGGL(k_reduce_zl<TT>, dim3(nu, nl), dim3(256), 0, stream, Z, nu, nv, nl, R, F[0], F[1],
+                         lpart, ctrl);
+      hipLaunchKernelGGL(k_sum_rows, dim3((nl * R + 255) / 256), dim3(256), 0, stream, lpart, nu, nl, R, M, ctrl);
+    }
+    GLINT_LAUNCHED("k_reduce_z");
+  } else {
+    const unsigned yblocks = static_cast<unsigned>((NN + 64 * VEC - 1) / (64 * VEC));
+    hipLaunchKernelGGL((k_mttkrp_y<TT, R>), dim3(yblocks, Lo.nsplit), dim3(256), 0, stream, T, ncells, N,
+                       nv, nl, F[0], F[1], F[2], Lo.cells_per_split, Yp, ctrl);
+    GLINT_LAUNCHED("k_mttkrp_y");
+    hipLaunchKernelGGL(k_reduce_splits<TT>, dim3(static_cast<unsigned>(std::min<int64_t>((NN * R + 255) / 256, 4096))),
+                       dim3(256), 0, stream, Yp, Lo.nsplit, NN * R, Y, ctrl);
+    hipLaunchKernelGGL(k_mttkrp_st, dim3((N * R + 255) / 256), dim3(256), 0, stream, Y,
+                       mode == 3 ? F[4] : F[3], N, R, mode, M, ctrl);
+    GLINT_LAUNCHED("k_mttkrp_st");
+  }
+  return GLINT_OK;
+}
+
+glint_status check_als_args(const glint_ndf_desc* desc, const void* T, glint_dtype T_dtype, int32_t R,
+                            void* workspace, size_t workspace_bytes, AlsLayout* Lo) {
+  glint_status st = glint_check_desc(desc);
+  if (st != GLINT_OK) return st;
+  GLINT_REQUIRE(T && workspace, "null pointer argument");
+  GLINT_SUPPORT(R == 16 || R == 32 || R == 64 || R == 128, "rank %d not in {16,32,64,128}", R);
+  GLINT_SUPPORT(T_dtype == GLINT_F64 || T_dtype == GLINT_F32, "T dtype must be F64 or F32");
+  GLINT_SUPPORT(desc->nbins >= 16, "ALS needs nbins >= 16");
+  GLINT_REQUIRE(glint_aligned(T, 16) && glint_aligned(workspace, 256),
+                "T must be 16-byte and workspace 256-byte aligned");
+  als_layout(desc, R, glint_dtype_size(T_dtype), Lo);
+  if (workspace_bytes < Lo->total)
+    return glint_fail(GLINT_E_WORKSPACE, "workspace %zu < %zu bytes", workspace_bytes, Lo->total);
+  int dev = 0, max_lds = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return glint_fail(GLINT_E_HIP, "hipDeviceGetAttribute failed");
+  if (static_cast<size_t>(max_lds) < sizeof(double) * (R * R + R))
+    return glint_fail(GLINT_E_UNSUPPORTED, "rank %d Gram does not fit in LDS (%d bytes)", R, max_lds);
+  const size_t pad = T_dtype == GLINT_F32 ? kPad32 : kPad64;
+  if (static_cast<size_t>(max_lds) < glint_dtype_size(T_dtype) * R * (desc->nbins + pad))
+    return glint_fail(GLINT_E_UNSUPPORTED, "rank %d x %d bins factor block does not fit in LDS", R,
+                      desc->nbins);
+  return GLINT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+glint_status glint_mttkrp(const glint_ndf_desc* desc, const void* T, glint_dtype T_dtype, int32_t R,
+                          int32_t mode, const double* U, const double* V, const double* L,
+                          const double* S, const double* Tf, double* M, void* workspace,
+                          size_t workspace_bytes, hipStream_t stream) {
+  AlsLayout Lo;
+  glint_status st = check_als_args(desc, T, T_dtype, R, workspace, workspace_bytes, &Lo);
+  if (st != GLINT_OK) return st;
+  GLINT_REQUIRE(mode >= 0 && mode <= 4, "mode %d outside 0..4", mode);
+  GLINT_REQUIRE(U && V && L && S && Tf && M, "null pointer argument");
+  const double* F[5] = {U, V, L, S, Tf};
+  unsigned char* ws = static_cast<unsigned char*>(workspace);
+  auto go = [&](auto ttag) -> glint_status {
+    using TT = decltype(ttag);
+    const TT* Tp = static_cast<const TT*>(T);
+    switch (R) {
+      case 16: return run_mttkrp<TT, 16>(desc, Tp, mode, F, M, ws, Lo, stream);
+      case 32: return run_mttkrp<TT, 32>(desc, Tp, mode, F, M, ws, Lo, stream);
+      case 64: return run_mttkrp<TT, 64>(desc, Tp, mode, F, M, ws, Lo, stream);
+      default: return run_mttkrp<TT, 128>(desc, Tp, mode, F, M, ws, Lo, stream);
+    }
+  };
+  if (T_dtype == GLINT_F64) return go(double{});
+  return go(float{});
+}
+
+size_t glint_cp_als_workspace(const glint_ndf_desc* desc, int32_t R, glint_dtype T_dtype) {
+  if (glint_check_desc(desc) != GLINT_OK) return 0;
+  if (R < 16 || R > 128 || !glint_pow2(R)) return 0;
+  if (T_dtype != GLINT_F64 && T_dtype != GLINT_F32) return 0;
+  AlsLayout L;
+  als_layout(desc, R, glint_dtype_size(T_dtype), &L);
+  return L.total;
+}
+
+glint_status glint_cp_als(const glint_ndf_desc* desc, const void* T, glint_dtype T_dtype, int32_t R,
+                          int32_t iters, double tol, double* U, double* V, double* L, double* S,
+                          double* Tf, double* fit_hist, int32_t* info, void* workspace,
+                          size_t workspace_bytes, hipStream_t stream) {
+  AlsLayout Lo;
+  glint_status st = check_als_args(desc, T, T_dtype, R, workspace, workspace_bytes, &Lo);
+  if (st != GLINT_OK) return st;
+  GLINT_REQUIRE(U && V && L && S && Tf && fit_hist, "null pointer argument");
+  GLINT_REQUIRE(iters >= 1, "iters must be >= 1");
+  GLINT_REQUIRE(tol >= 0.0, "tol must be >= 0");
+  double* F[5] = {U, V, L, S, Tf};
+  unsigned char* ws = static_cast<unsigned char*>(workspace);
+  auto go = [&](auto ttag) -> glint_status {
+    using TT = decltype(ttag);
+    const TT* Tp = static_cast<const TT*>(T);
+    switch (R) {
+      case 16: return run_als<TT, 16>(desc, Tp, iters, tol, F, fit_hist, info, ws, Lo, stream);
+      case 32: return run_als<TT, 32>(desc, Tp, iters, tol, F, fit_hist, info, ws, Lo, stream);
+      case 64: return run_als<TT, 64>(desc, Tp, iters, tol, F, fit_hist, info, ws, Lo, stream);
+      default: return run_als<TT, 128>(desc, Tp, iters, tol, F, fit_hist, info, ws, Lo, stream);
+    }
+  };
+  if (T_dtype == GLINT_F64) return go(double{});
+  return go(float{});
+}
+
+}  // extern "C"

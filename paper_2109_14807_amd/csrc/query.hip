@@ -1,0 +1,684 @@
+// Summed-area tables, storage conversion and the constant-cost range query
+// (Sec. 4.4, Eq. rangeDecom; Appendix proposition), with its gradient.
+//
+// Query kernel layout: a query is served by LPQ = R / RPL adjacent lanes of a
+// wavefront; lane j owns ranks [j*RPL, (j+1)*RPL) and gathers its slice of
+// the U and V rows with one 16-byte load each (the LPQ lanes of a query read
+// one contiguous row).  The small tables (L with the per-rank scale folded
+// in, CS, CT) are decoded to FP32 once per workgroup into LDS.  The rank sum
+// is finished with DPP row operations inside the lane group.
+#include <type_traits>
+
+#include "common.h"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// storage codecs for the table element types
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__device__ __forceinline__ float dec(T x);
+template <>
+__device__ __forceinline__ float dec<float>(float x) { return x; }
+template <>
+__device__ __forceinline__ float dec<uint16_t>(uint16_t x) { return glint_bf16_to_f32(x); }
+template <>
+__device__ __forceinline__ float dec<uint8_t>(uint8_t x) { return glint_fp8_to_f32(x); }
+
+// Load RPL consecutive stored elements starting at p (16-byte aligned) and
+// decode them to FP32.
+template <typename FT, int RPL>
+__device__ __forceinline__ void load_row(const FT* __restrict__ p, float* out) {
+  constexpr int BYTES = RPL * static_cast<int>(sizeof(FT));
+  static_assert(BYTES % 16 == 0, "row slice must be whole 16-byte words");
+  uint4 w[BYTES / 16];
+#pragma unroll
+  for (int i = 0; i < BYTES / 16; ++i) w[i] = reinterpret_cast<const uint4*>(p)[i];
+  const FT* e = reinterpret_cast<const FT*>(w);
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) out[i] = dec<FT>(e[i]);
+}
+
+struct Scales {
+  const float* s[5];   // U, V, L, CS, CT; NULL = 1
+};
+
+// Folded per-rank scale: the product of the given per-column scales.
+__device__ __forceinline__ float folded_scale(const Scales& sc, int r) {
+  float c = 1.0f;
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+    if (sc.s[i]) c *= sc.s[i][r];
+  return c;
+}
+
+// Decode a stored table [rows][R] into FP32 LDS, optionally times the folded scale.
+template <typename T>
+__device__ void stage_table(float* __restrict__ dst, const T* __restrict__ src, int rows, int R,
+                            const Scales* sc) {
+  const int n = rows * R;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    float x = dec<T>(src[i]);
+    if (sc) x *= folded_scale(*sc, i % R);
+    dst[i] = x;
+  }
+}
+
+struct QueryArgs {
+  const void* U;
+  const void* V;
+  const void* L;
+  const void* CS;
+  const void* CT;
+  Scales scale;
+  int nu, nv, nl, N;
+  int64_t nq;
+  const int32_t* q;
+  float* out;
+};
+
+template <typename FT, typename CT, int R, int RPL>
+__global__ __launch_bounds__(256) void k_query(QueryArgs a) {
+  constexpr int LPQ = R / RPL;
+  constexpr int QPW = 64 / LPQ;
+  static_assert(LPQ >= 1 && LPQ <= 64, "lanes per query");
+  extern __shared__ __align__(16) float lds[];
+  float* Ls = lds;
+  float* CSs = Ls + a.nl * R;
+  float* CTs = CSs + (a.N + 1) * R;
+  stage_table<FT>(Ls, static_cast<const FT*>(a.L), a.nl, R, &a.scale);
+  stage_table<CT>(CSs, static_cast<const CT*>(a.CS), a.N + 1, R, nullptr);
+  stage_table<CT>(CTs, static_cast<const CT*>(a.CT), a.N + 1, R, nullptr);
+  __syncthreads();
+
+  const FT* __restrict__ U = static_cast<const FT*>(a.U);
+  const FT* __restrict__ V = static_cast<const FT*>(a.V);
+  const int lane = threadIdx.x & 63;
+  const int g = lane / LPQ;
+  const int j = lane % LPQ;
+  const int r0 = j * RPL;
+  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
+  for (int64_t base = wave * QPW; base < a.nq; base += nwaves * QPW) {
+    const int64_t qi = base + g;
+    const bool valid = qi < a.nq;
+    const int32_t* rec = a.q + (valid ? qi : a.nq - 1) * 7;
+    const int u = glint_wrap(rec[0], a.nu);
+    const int v = glint_wrap(rec[1], a.nv);
+    const int l = glint_clampi(rec[2], 0, a.nl - 1);
+    const int slo = glint_clampi(rec[3], 0, a.N), shi = glint_clampi(rec[4], 0, a.N);
+    const int tlo = glint_clampi(rec[5], 0, a.N), thi = glint_clampi(rec[6], 0, a.N);
+    float uu[RPL], vv[RPL];
+    load_row<FT, RPL>(U + static_cast<int64_t>(u) * R + r0, uu);
+    load_row<FT, RPL>(V + static_cast<int64_t>(v) * R + r0, vv);
+    const float* lr = Ls + l * R + r0;
+    const float* sh = CSs + shi * R + r0;
+    const float* sl = CSs + slo * R + r0;
+    const float* th = CTs + thi * R + r0;
+    const float* tl = CTs + tlo * R + r0;
+    float acc = 0.0f;
+#pragma unroll
+    for (int e = 0; e < RPL; ++e) {
+      const float dS = sh[e] - sl[e];
+      const float dT = th[e] - tl[e];
+      acc += uu[e] * vv[e] * lr[e] * dS * dT;
+    }
+    acc = glint_group_sum<LPQ>(acc);
+    if (valid && j == 0) a.out[qi] = (slo < shi && tlo < thi) ? acc : 0.0f;
+  }
+}
+
+struct GroupedArgs {
+  const void* U;
+  const void* V;
+  const void* L;
+  const void* CS;
+  const void* CT;
+  Scales scale;
+  int nu, nv, nl, N, K;
+  int64_t npts;
+  const int32_t* uvl;
+  const int32_t* boxes;
+  float* out;
+};
+
+template <typename FT, typename CT, int R, int RPL>
+__global__ __launch_bounds__(256) void k_query_grouped(GroupedArgs a) {
+  constexpr int LPQ = R / RPL;
+  constexpr int QPW = 64 / LPQ;
+  extern __shared__ __align__(16) float lds[];
+  float* Ls = lds;
+  float* CSs = Ls + a.nl * R;
+  float* CTs = CSs + (a.N + 1) * R;
+  stage_table<FT>(Ls, static_cast<const FT*>(a.L), a.nl, R, &a.scale);
+  stage_table<CT>(CSs, static_cast<const CT*>(a.CS), a.N + 1, R, nullptr);
+  stage_table<CT>(CTs, static_cast<const CT*>(a.CT), a.N + 1, R, nullptr);
+  __syncthreads();
+
+  const FT* __restrict__ U = static_cast<const FT*>(a.U);
+  const FT* __restrict__ V = static_cast<const FT*>(a.V);
+  const int lane = threadIdx.x & 63;
+  const int g = lane / LPQ;
+  const int j = lane % LPQ;
+  const int r0 = j * RPL;
+  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
+  for (int64_t base = wave * QPW; base < a.npts; base += nwaves * QPW) {
+    const int64_t pi = base + g;
+    const bool valid = pi < a.npts;
+    const int64_t pc = valid ? pi : a.npts - 1;
+    const int32_t* rec = a.uvl + pc * 3;
+    const int u = glint_wrap(rec[0], a.nu);
+    const int v = glint_wrap(rec[1], a.nv);
+    const int l = glint_clampi(rec[2], 0, a.nl - 1);
+    float w[RPL], vv[RPL];
+    load_row<FT, RPL>(U + static_cast<int64_t>(u) * R + r0, w);
+    load_row<FT, RPL>(V + static_cast<int64_t>(v) * R + r0, vv);
+    const float* lr = Ls + l * R + r0;
+#pragma unroll
+    for (int e = 0; e < RPL; ++e) w[e] = w[e] * vv[e] * lr[e];
+    const int4* bx = reinterpret_cast<const int4*>(a.boxes) + pc * a.K;
+    for (int b = 0; b < a.K; ++b) {
+      const int4 box = bx[b];
+      const int slo = glint_clampi(box.x, 0, a.N), shi = glint_clampi(box.y, 0, a.N);
+      const int tlo = glint_clampi(box.z, 0, a.N), thi = glint_clampi(box.w, 0, a.N);
+      const float* sh = CSs + shi * R + r0;
+      const float* sl = CSs + slo * R + r0;
+      const float* th = CTs + thi * R + r0;
+      const float* tl = CTs + tlo * R + r0;
+      float acc = 0.0f;
+#pragma unroll
+      for (int e = 0; e < RPL; ++e) acc += w[e] * (sh[e] - sl[e]) * (th[e] - tl[e]);
+      acc = glint_group_sum<LPQ>(acc);
+      if (valid && j == 0) a.out[pi * a.K + b] = (slo < shi && tlo < thi) ? acc : 0.0f;
+    }
+  }
+}
+
+// Backward: per query, lane j adds its ranks' partial derivatives.  dL, dCS
+// and dCT (few rows, heavily shared) accumulate in LDS and are flushed once
+// per workgroup; dU and dV go straight to global atomics.
+template <typename FT, typename CT, int R, int RPL>
+__global__ __launch_bounds__(256) void k_query_backward(QueryArgs a, const float* __restrict__ gout,
+                                                        float* __restrict__ dU,
+                                                        float* __restrict__ dV,
+                                                        float* __restrict__ dL,
+                                                        float* __restrict__ dCS,
+                                                        float* __restrict__ dCT) {
+  constexpr int LPQ = R / RPL;
+  constexpr int QPW = 64 / LPQ;
+  extern __shared__ __align__(16) float lds[];
+  const int nl = a.nl, N1 = a.N + 1;
+  float* Ls = lds;                  // decoded L (no scale)
+  float* CSs = Ls + nl * R;
+  float* CTs = CSs + N1 * R;
+  float* sc = CTs + N1 * R;         // [R]
+  float* gL = sc + R;               // [nl][R]
+  float* gCS = gL + nl * R;         // [N1][R]
+  float* gCT = gCS + N1 * R;        // [N1][R]
+  stage_table<FT>(Ls, static_cast<const FT*>(a.L), nl, R, nullptr);
+  stage_table<CT>(CSs, static_cast<const CT*>(a.CS), N1, R, nullptr);
+  stage_table<CT>(CTs, static_cast<const CT*>(a.CT), N1, R, nullptr);
+  for (int i = threadIdx.x; i < R; i += blockDim.x) sc[i] = folded_scale(a.scale, i);
+  for (int i = threadIdx.x; i < (nl + 2 * N1) * R; i += blockDim.x) gL[i] = 0.0f;
+  __syncthreads();
+
+  const FT* __restrict__ U = static_cast<const FT*>(a.U);
+  const FT* __restrict__ V = static_cast<const FT*>(a.V);
+  const int lane = threadIdx.x & 63;
+  const int g = lane / LPQ;
+  const int j = lane % LPQ;
+  const int r0 = j * RPL;
+  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
+  for (int64_t base = wave * QPW; base < a.nq; base += nwaves * QPW) {
+    const int64_t qi = base + g;
+    if (qi >= a.nq) break;          // no cross-lane operations below
+    const int32_t* rec = a.q + qi * 7;
+    const int u = glint_wrap(rec[0], a.nu);
+    const int v = glint_wrap(rec[1], a.nv);
+    const int l = glint_clampi(rec[2], 0, nl - 1);
+    const int slo = glint_clampi(rec[3], 0, a.N), shi = glint_clampi(rec[4], 0, a.N);
+    const int tlo = glint_clampi(rec[5], 0, a.N), thi = glint_clampi(rec[6], 0, a.N);
+    if (!(slo < shi && tlo < thi)) continue;
+    const float gq = gout[qi];
+    float uu[RPL], vv[RPL];
+    load_row<FT, RPL>(U + static_cast<int64_t>(u) * R + r0, uu);
+    load_row<FT, RPL>(V + static_cast<int64_t>(v) * R + r0, vv);
+#pragma unroll
+    for (int e = 0; e < RPL; ++e) {
+      const int r = r0 + e;
+      const float s = sc[r] * gq;
+      const float ll = Ls[l * R + r];
+      const float dS = CSs[shi * R + r] - CSs[slo * R + r];
+      const float dT = CTs[thi * R + r] - CTs[tlo * R + r];
+      const float st = dS * dT;
+      const float uv = uu[e] * vv[e];
+      atomicAdd(&dU[static_cast<int64_t>(u) * R + r], s * vv[e] * ll * st);
+      atomicAdd(&dV[static_cast<int64_t>(v) * R + r], s * uu[e] * ll * st);
+      atomicAdd(&gL[l * R + r], s * uv * st);
+      const float wS = s * uv * ll * dT;
+      atomicAdd(&gCS[shi * R + r], wS);
+      atomicAdd(&gCS[slo * R + r], -wS);
+      const float wT = s * uv * ll * dS;
+      atomicAdd(&gCT[thi * R + r], wT);
+      atomicAdd(&gCT[tlo * R + r], -wT);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nl * R; i += blockDim.x)
+    if (gL[i] != 0.0f) atomicAdd(&dL[i], gL[i]);
+  for (int i = threadIdx.x; i < N1 * R; i += blockDim.x) {
+    if (gCS[i] != 0.0f) atomicAdd(&dCS[i], gCS[i]);
+    if (gCT[i] != 0.0f) atomicAdd(&dCT[i], gCT[i]);
+  }
+}
+
+__global__ void k_fill(float* __restrict__ p, int64_t n, float v) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// summed-area tables and conversion
+// ---------------------------------------------------------------------------
+
+template <typename IN>
+__device__ __forceinline__ double load_in(const IN* p, int64_t i) {
+  return static_cast<double>(p[i]);
+}
+
+// Store an FP64 value into the output type (FP8 uses the column scale).
+template <typename OUT>
+__device__ __forceinline__ OUT enc(double x, float scale);
+template <>
+__device__ __forceinline__ double enc<double>(double x, float) { return x; }
+template <>
+__device__ __forceinline__ float enc<float>(double x, float) { return static_cast<float>(x); }
+template <>
+__device__ __forceinline__ uint16_t enc<uint16_t>(double x, float) {
+  return glint_f32_to_bf16(static_cast<float>(x));
+}
+template <>
+__device__ __forceinline__ uint8_t enc<uint8_t>(double x, float scale) {
+  return static_cast<uint8_t>(glint_f32_to_fp8(static_cast<float>(x) / scale));
+}
+
+// One thread per column: C[j][r] = sum_{s<j} S[s][r] in FP64.
+template <typename IN, typename OUT>
+__global__ void k_cumulative(int n, int R, const IN* __restrict__ S, OUT* __restrict__ C,
+                             float* __restrict__ col_scale) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  float scale = 1.0f;
+  if constexpr (std::is_same<OUT, uint8_t>::value) {
+    double acc = 0.0;
+    float amax = 0.0f;
+    for (int s = 0; s < n; ++s) {
+      acc += load_in(S, static_cast<int64_t>(s) * R + r);
+      amax = fmaxf(amax, fabsf(static_cast<float>(acc)));
+    }
+    scale = amax > 0.0f ? amax / 448.0f : 1.0f;
+    col_scale[r] = scale;
+  }
+  double acc = 0.0;
+  C[r] = enc<OUT>(0.0, scale);
+  for (int s = 0; s < n; ++s) {
+    acc += load_in(S, static_cast<int64_t>(s) * R + r);
+    C[static_cast<int64_t>(s + 1) * R + r] = enc<OUT>(acc, scale);
+  }
+}
+
+// Per-column amax of the FP32-rounded values, then the FP8 scale.
+template <typename IN>
+__global__ __launch_bounds__(256) void k_col_scale(int64_t rows, int R, const IN* __restrict__ in,
+                                                   float* __restrict__ col_scale) {
+  __shared__ float part[256];
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int grp = threadIdx.x >> 6;
+  float amax = 0.0f;
+  if (c < R)
+    for (int64_t i = grp; i < rows; i += 4)
+      amax = fmaxf(amax, fabsf(static_cast<float>(in[i * R + c])));
+  part[threadIdx.x] = amax;
+  __syncthreads();
+  if (grp == 0 && c < R) {
+    amax = fmaxf(fmaxf(part[threadIdx.x], part[threadIdx.x + 64]),
+                 fmaxf(part[threadIdx.x + 128], part[threadIdx.x + 192]));
+    col_scale[c] = amax > 0.0f ? amax / 448.0f : 1.0f;
+  }
+}
+
+template <typename IN, typename OUT>
+__global__ void k_convert(int64_t n, int R, const IN* __restrict__ in, OUT* __restrict__ out,
+                          const float* __restrict__ col_scale) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    float scale = 1.0f;
+    if constexpr (std::is_same<OUT, uint8_t>::value) scale = col_scale[i % R];
+    // every narrow type is reached through FP32 (FP64 -> FP32 -> narrow, each RNE)
+    out[i] = enc<OUT>(static_cast<double>(static_cast<float>(in[i])), scale);
+  }
+}
+
+__global__ void k_cumulative_backward(int n, int R, const float* __restrict__ dC,
+                                      float* __restrict__ dS) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  double acc = 0.0;
+  for (int s = n - 1; s >= 0; --s) {
+    acc += static_cast<double>(dC[static_cast<int64_t>(s + 1) * R + r]);
+    dS[static_cast<int64_t>(s) * R + r] = static_cast<float>(acc);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// dispatch
+// ---------------------------------------------------------------------------
+
+int g_cu_count = 0;
+int g_max_lds = 0;
+
+glint_status device_limits() {
+  if (g_cu_count > 0) return GLINT_OK;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return glint_fail(GLINT_E_HIP, "hipGetDevice failed");
+  int cus = 0, lds = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return glint_fail(GLINT_E_HIP, "hipDeviceGetAttribute failed");
+  g_cu_count = cus;
+  g_max_lds = lds;
+  return GLINT_OK;
+}
+
+template <typename FT>
+constexpr int rpl_for() {
+  return 16 / static_cast<int>(sizeof(FT));
+}
+
+template <typename FT, typename CT, int R>
+glint_status launch_query(const QueryArgs& a, hipStream_t stream) {
+  constexpr int RPL = rpl_for<FT>() <= R ? rpl_for<FT>() : R;
+  const size_t lds = sizeof(float) * static_cast<size_t>(a.nl + 2 * (a.N + 1)) * R;
+  if (static_cast<int>(lds) > g_max_lds)
+    return glint_fail(GLINT_E_UNSUPPORTED, "tables need %zu bytes of LDS (device max %d)", lds, g_max_lds);
+  constexpr int QPW = 64 / (R / RPL);
+  const int64_t waves_needed = (a.nq + QPW - 1) / QPW;
+  int64_t blocks = (waves_needed + 3) / 4;
+  const int64_t cap = static_cast<int64_t>(g_cu_count) * 8;
+  if (blocks > cap) blocks = cap;
+  if (blocks < 1) blocks = 1;
+  glint_clear_launch_error();
+  hipLaunchKernelGGL((k_query<FT, CT, R, RPL>), dim3(static_cast<unsigned>(blocks)), dim3(256), lds,
+                     stream, a);
+  GLINT_LAUNCHED("k_query");
+  return GLINT_OK;
+}
+
+template <typename FT, typename CT, int R>
+glint_status launch_grouped(const GroupedArgs& a, hipStream_t stream) {
+  constexpr int RPL = rpl_for<FT>() <= R ? rpl_for<FT>() : R;
+  const size_t lds = sizeof(float) * static_cast<size_t>(a.nl + 2 * (a.N + 1)) * R;
+  if (static_cast<int>(lds) > g_max_lds)
+    return glint_fail(GLINT_E_UNSUPPORTED, "tables need %zu bytes of LDS (device max %d)", lds, g_max_lds);
+  constexpr int QPW = 64 / (R / RPL);
+  const int64_t waves_needed = (a.npts + QPW - 1) / QPW;
+  int64_t blocks = (waves_needed + 3) / 4;
+  const int64_t cap = static_cast<int64_t>(g_cu_count) * 8;
+  if (blocks > cap) blocks = cap;
+  if (blocks < 1) blocks = 1;
+  glint_clear_launch_error();
+  hipLaunchKernelGGL((k_query_grouped<FT, CT, R, RPL>), dim3(static_cast<unsigned>(blocks)),
+                     dim3(256), lds, stream, a);
+  GLINT_LAUNCHED("k_query_grouped");
+  return GLINT_OK;
+}
+
+template <typename FT, typename CT, int R>
+glint_status launch_backward(const QueryArgs& a, const float* gout, float* dU, float* dV,
+                             float* dL, float* dCS, float* dCT, hipStream_t stream) {
+  constexpr int RPL = rpl_for<FT>() <= R ? rpl_for<FT>() : R;
+  const size_t lds = sizeof(float) * (2 * static_cast<size_t>(a.nl + 2 * (a.N + 1)) * R + R);
+  if (static_cast<int>(lds) > g_max_lds)
+    return glint_fail(GLINT_E_UNSUPPORTED, "backward needs %zu bytes of LDS (device max %d)", lds, g_max_lds);
+  constexpr int QPW = 64 / (R / RPL);
+  const int64_t waves_needed = (a.nq + QPW - 1) / QPW;
+  int64_t blocks = (waves_needed + 3) / 4;
+  const int64_t cap = static_cast<int64_t>(g_cu_count) * 4;
+  if (blocks > cap) blocks = cap;
+  if (blocks < 1) blocks = 1;
+  glint_clear_launch_error();
+  hipLaunchKernelGGL((k_query_backward<FT, CT, R, RPL>), dim3(static_cast<unsigned>(blocks)),
+                     dim3(256), lds, stream, a, gout, dU, dV, dL, dCS, dCT);
+  GLINT_LAUNCHED("k_query_backward");
+  return GLINT_OK;
+}
+
+// R -> template argument
+template <typename FT, typename CT, typename Fn>
+glint_status by_rank(int R, Fn&& fn) {
+  switch (R) {
+    case 16: return fn(std::integral_constant<int, 16>{});
+    case 32: return fn(std::integral_constant<int, 32>{});
+    case 64: return fn(std::integral_constant<int, 64>{});
+    case 128: return fn(std::integral_constant<int, 128>{});
+    case 256: return fn(std::integral_constant<int, 256>{});
+  }
+  return glint_fail(GLINT_E_UNSUPPORTED, "rank %d not in {16,32,64,128,256}", R);
+}
+
+template <typename Fn>
+glint_status by_types(glint_dtype ft, glint_dtype ct, Fn&& fn) {
+  auto with_ct = [&](auto ftag) -> glint_status {
+    using FT = decltype(ftag);
+    switch (ct) {
+      case GLINT_F32: return fn(FT{}, float{});
+      case GLINT_BF16: return fn(FT{}, uint16_t{});
+      case GLINT_FP8E4M3: return fn(FT{}, uint8_t{});
+      default: break;
+    }
+    return glint_fail(GLINT_E_UNSUPPORTED, "cumulative-table dtype %d", static_cast<int>(ct));
+  };
+  switch (ft) {
+    case GLINT_F32: return with_ct(float{});
+    case GLINT_BF16: return with_ct(uint16_t{});
+    case GLINT_FP8E4M3: return with_ct(uint8_t{});
+    default: break;
+  }
+  return glint_fail(GLINT_E_UNSUPPORTED, "factor dtype %d", static_cast<int>(ft));
+}
+
+glint_status check_factors(const glint_factors* f) {
+  GLINT_REQUIRE(f != nullptr, "factors is NULL");
+  GLINT_REQUIRE(f->U && f->V && f->L && f->CS && f->CT, "null factor table");
+  GLINT_REQUIRE(f->nu >= 1 && f->nv >= 1 && f->nl >= 1, "table sizes must be positive");
+  GLINT_REQUIRE(glint_pow2(f->nbins) && f->nbins >= 4 && f->nbins <= 256,
+                "nbins %d must be a power of two in 4..256", f->nbins);
+  GLINT_REQUIRE(glint_aligned(f->U, 16) && glint_aligned(f->V, 16) && glint_aligned(f->L, 16) &&
+                    glint_aligned(f->CS, 16) && glint_aligned(f->CT, 16),
+                "factor tables must be 16-byte aligned");
+  return device_limits();
+}
+
+Scales scales_of(const glint_factors* f) {
+  Scales s;
+  s.s[0] = f->scale_U; s.s[1] = f->scale_V; s.s[2] = f->scale_L;
+  s.s[3] = f->scale_CS; s.s[4] = f->scale_CT;
+  return s;
+}
+
+QueryArgs make_args(const glint_factors* f, int64_t nq, const int32_t* q, float* out) {
+  QueryArgs a;
+  a.U = f->U; a.V = f->V; a.L = f->L; a.CS = f->CS; a.CT = f->CT; a.scale = scales_of(f);
+  a.nu = f->nu; a.nv = f->nv; a.nl = f->nl; a.N = f->nbins;
+  a.nq = nq; a.q = q; a.out = out;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+glint_status glint_query(const glint_factors* f, int64_t nq, const int32_t* q, float* out,
+                         hipStream_t stream) {
+  glint_status st = check_factors(f);
+  if (st != GLINT_OK) return st;
+  GLINT_REQUIRE(nq >= 0, "nq must be >= 0");
+  if (nq == 0) return GLINT_OK;
+  GLINT_REQUIRE(q && out, "null query or output pointer");
+  const QueryArgs a = make_args(f, nq, q, out);
+  return by_types(f->dtype, f->cum_dtype, [&](auto ft, auto ct) -> glint_status {
+    using FT = decltype(ft);
+    using CT = decltype(ct);
+    return by_rank<FT, CT>(f->R, [&](auto rr) -> glint_status {
+      return launch_query<FT, CT, decltype(rr)::value>(a, stream);
+    });
+  });
+}
+
+glint_status glint_query_grouped(const glint_factors* f, int64_t npts, int32_t K,
+                                 const int32_t* uvl, const int32_t* boxes, float* out,
+                                 hipStream_t stream) {
+  glint_status st = check_factors(f);
+  if (st != GLINT_OK) return st;
+  GLINT_REQUIRE(npts >= 0 && K >= 1, "npts must be >= 0 and K >= 1");
+  if (npts == 0) return GLINT_OK;
+  GLINT_REQUIRE(uvl && boxes && out, "null pointer argument");
+  GLINT_REQUIRE(glint_aligned(boxes, 16), "boxes must be 16-byte aligned");
+  GroupedArgs a;
+  a.U = f->U; a.V = f->V; a.L = f->L; a.CS = f->CS; a.CT = f->CT; a.scale = scales_of(f);
+  a.nu = f->nu; a.nv = f->nv; a.nl = f->nl; a.N = f->nbins; a.K = K;
+  a.npts = npts; a.uvl = uvl; a.boxes = boxes; a.out = out;
+  return by_types(f->dtype, f->cum_dtype, [&](auto ft, auto ct) -> glint_status {
+    using FT = decltype(ft);
+    using CT = decltype(ct);
+    return by_rank<FT, CT>(f->R, [&](auto rr) -> glint_status {
+      return launch_grouped<FT, CT, decltype(rr)::value>(a, stream);
+    });
+  });
+}
+
+glint_status glint_query_backward(const glint_factors* f, int64_t nq, const int32_t* q,
+                                  const float* gout, float* dU, float* dV, float* dL,
+                                  float* dCS, float* dCT, hipStream_t stream) {
+  glint_status st = check_factors(f);
+  if (st != GLINT_OK) return st;
+  GLINT_REQUIRE(nq >= 0, "nq must be >= 0");
+  GLINT_REQUIRE(dU && dV && dL && dCS && dCT, "null gradient pointer");
+  GLINT_SUPPORT((f->dtype == GLINT_F32 || f->dtype == GLINT_BF16) &&
+                    (f->cum_dtype == GLINT_F32 || f->cum_dtype == GLINT_BF16),
+                "backward supports F32 and BF16 tables");
+  const int R = f->R;
+  struct { float* p; int64_t n; } bufs[5] = {
+      {dU, static_cast<int64_t>(f->nu) * R}, {dV, static_cast<int64_t>(f->nv) * R},
+      {dL, static_cast<int64_t>(f->nl) * R}, {dCS, static_cast<int64_t>(f->nbins + 1) * R},
+      {dCT, static_cast<int64_t>(f->nbins + 1) * R}};
+  for (auto& b : bufs) {
+    glint_clear_launch_error();
+    const int64_t blocks = (b.n + 255) / 256 < 1024 ? (b.n + 255) / 256 : 1024;
+    hipLaunchKernelGGL(k_fill, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, b.p, b.n, 0.0f);
+    GLINT_LAUNCHED("k_fill");
+  }
+  if (nq == 0) return GLINT_OK;
+  GLINT_REQUIRE(q && gout, "null query or gout pointer");
+  const QueryArgs a = make_args(f, nq, q, nullptr);
+  return by_types(f->dtype, f->cum_dtype, [&](auto ft, auto ct) -> glint_status {
+    using FT = decltype(ft);
+    using CT = decltype(ct);
+    if constexpr (std::is_same<FT, uint8_t>::value || std::is_same<CT, uint8_t>::value) {
+      return glint_fail(GLINT_E_UNSUPPORTED, "backward supports F32 and BF16 tables");
+    } else {
+      return by_rank<FT, CT>(f->R, [&](auto rr) -> glint_status {
+        return launch_backward<FT, CT, decltype(rr)::value>(a, gout, dU, dV, dL, dCS, dCT, stream);
+      });
+    }
+  });
+}
+
+glint_status glint_cumulative_backward(int32_t n, int32_t R, const float* dC, float* dS,
+                                       hipStream_t stream) {
+  GLINT_REQUIRE(n >= 1 && R >= 1, "sizes must be positive");
+  GLINT_REQUIRE(dC && dS, "null pointer argument");
+  glint_clear_launch_error();
+  hipLaunchKernelGGL(k_cumulative_backward, dim3((R + 255) / 256), dim3(256), 0, stream, n, R, dC, dS);
+  GLINT_LAUNCHED("k_cumulative_backward");
+  return GLINT_OK;
+}
+
+glint_status glint_make_cumulative(int32_t n, int32_t R, const void* S, glint_dtype in_dtype,
+                                   void* C, glint_dtype out_dtype, float* col_scale,
+                                   hipStream_t stream) {
+  GLINT_REQUIRE(n >= 1 && R >= 1, "sizes must be positive");
+  GLINT_REQUIRE(S && C, "null pointer argument");
+  GLINT_REQUIRE(out_dtype != GLINT_FP8E4M3 || col_scale, "FP8 output needs col_scale");
+  GLINT_SUPPORT(in_dtype == GLINT_F64 || in_dtype == GLINT_F32, "input dtype must be F64 or F32");
+  const dim3 grid((R + 63) / 64), block(64);
+  auto go = [&](auto in_tag) -> glint_status {
+    using IN = decltype(in_tag);
+    const IN* s = static_cast<const IN*>(S);
+    glint_clear_launch_error();
+    switch (out_dtype) {
+      case GLINT_F64:
+        hipLaunchKernelGGL((k_cumulative<IN, double>), grid, block, 0, stream, n, R, s,
+                           static_cast<double*>(C), col_scale);
+        break;
+      case GLINT_F32:
+        hipLaunchKernelGGL((k_cumulative<IN, float>), grid, block, 0, stream, n, R, s,
+                           static_cast<float*>(C), col_scale);
+        break;
+      case GLINT_BF16:
+        hipLaunchKernelGGL((k_cumulative<IN, uint16_t>), grid, block, 0, stream, n, R, s,
+                           static_cast<uint16_t*>(C), col_scale);
+        break;
+      case GLINT_FP8E4M3:
+        hipLaunchKernelGGL((k_cumulative<IN, uint8_t>), grid, block, 0, stream, n, R, s,
+                           static_cast<uint8_t*>(C), col_scale);
+        break;
+      default:
+        return glint_fail(GLINT_E_UNSUPPORTED, "output dtype %d", static_cast<int>(out_dtype));
+    }
+    GLINT_LAUNCHED("k_cumulative");
+    return GLINT_OK;
+  };
+  if (in_dtype == GLINT_F64) return go(double{});
+  return go(float{});
+}
+
+glint_status glint_convert(int64_t rows, int32_t R, const void* in, glint_dtype in_dtype,
+                           void* out, glint_dtype out_dtype, float* col_scale,
+                           hipStream_t stream) {
+  GLINT_REQUIRE(rows >= 1 && R >= 1, "sizes must be positive");
+  GLINT_REQUIRE(in && out, "null pointer argument");
+  GLINT_REQUIRE(out_dtype != GLINT_FP8E4M3 || col_scale, "FP8 output needs col_scale");
+  GLINT_SUPPORT(in_dtype == GLINT_F64 || in_dtype == GLINT_F32, "input dtype must be F64 or F32");
+  GLINT_SUPPORT(out_dtype == GLINT_F32 || out_dtype == GLINT_BF16 || out_dtype == GLINT_FP8E4M3,
+                "output dtype must be F32, BF16 or FP8E4M3");
+  const int64_t n = rows * R;
+  const unsigned blocks = static_cast<unsigned>((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+  auto go = [&](auto in_tag) -> glint_status {
+    using IN = decltype(in_tag);
+    const IN* src = static_cast<const IN*>(in);
+    glint_clear_launch_error();
+    if (out_dtype == GLINT_FP8E4M3) {
+      hipLaunchKernelGGL((k_col_scale<IN>), dim3((R + 63) / 64), dim3(256), 0, stream, rows, R, src, col_scale);
+      GLINT_LAUNCHED("k_col_scale");
+      hipLaunchKernelGGL((k_convert<IN, uint8_t>), dim3(blocks), dim3(256), 0, stream, n, R, src,
+                         static_cast<uint8_t*>(out), col_scale);
+    } else if (out_dtype == GLINT_BF16) {
+      hipLaunchKernelGGL((k_convert<IN, uint16_t>), dim3(blocks), dim3(256), 0, stream, n, R, src,
+                         static_cast<uint16_t*>(out), col_scale);
+    } else {
+      hipLaunchKernelGGL((k_convert<IN, float>), dim3(blocks), dim3(256), 0, stream, n, R, src,
+                         static_cast<float*>(out), col_scale);
+    }
+    GLINT_LAUNCHED("k_convert");
+    return GLINT_OK;
+  };
+  if (in_dtype == GLINT_F64) return go(double{});
+  return go(float{});
+}
+
+}  // extern "C"
