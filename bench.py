@@ -1,0 +1,310 @@
+#!/usr/bin/env python3
+"""Benchmark: one step = the whole glint path on one batch, on one GPU.
+
+Workload (the plain FP32 query at scale): a 512x512 periodic Voronoi flake
+map (5000 sites, Beckmann alpha 0.15), intrinsic roughness 0.005, a 64x64
+NDF grid, 8 footprint levels (1..128 texels), CP rank 64 fitted by 50 ALS
+sweeps, and 1920x1080x8 = 16,588,800 range queries (8 angular boxes per pixel,
+pixel-major, box sides log-uniform in [0.005, 0.3]).  Inputs are synthetic and
+seeded; they are resident on the GPU before timing starts.
+
+A step runs, in order, every stage of the path:
+  build   per-texel binning and the FP32 NDF tensor T[u,v,l,s,t] (34 GB)
+  als     50 CP-ALS sweeps on the matrix cores (FP32 MTTKRP, FP64 solves)
+  tables  FP32 factor tables and summed-area tables (FP64 prefix sums)
+  query   the range query over the whole batch
+  grad    MSE gradient against the brute-force range integrals (computed
+          once, untimed, as the refinement targets) and the query backward
+  adam    one Adam step on the five FP32 factor tables
+
+Prints one JSON line.  value = queries answered per second of whole-step time.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix
+FP64_MFMA_PEAK_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--sweeps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=10,
+                    help="events-timed launches of the MTTKRP and query kernels")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2109_14807_amd as G
+    from paper_2109_14807_amd import _lib as L
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cfg = gen.config("c2")
+    R, N, nl = cfg.rank, cfg.nbins, cfg.nlevels
+    desc = G.desc_of(cfg.nu, cfg.nv, nl, N, cfg.sigma)
+
+    t0 = time.time()
+    nxy_h = gen.normal_map(cfg)
+    q_h = gen.make_queries(cfg, nxy_h)
+    init_h = gen.als_init(cfg)
+    nq = q_h.shape[0]
+    log(f"inputs generated in {time.time() - t0:.1f}s: {nq} queries")
+
+    nxy = torch.tensor(nxy_h, device=dev)
+    q = torch.tensor(q_h, device=dev)
+    init = [torch.tensor(a, device=dev) for a in init_h]
+
+    # ---- buffers (allocated once, outside the timed region) ----
+    T = torch.empty((cfg.nu, cfg.nv, nl, N, N), dtype=torch.float32, device=dev)
+    ws_build = torch.empty(L.glint_build_tensor_workspace(desc), dtype=torch.uint8, device=dev)
+    ws_als = torch.empty(L.glint_cp_als_workspace(desc, R, L.GLINT_F32), dtype=torch.uint8, device=dev)
+    F = [torch.empty_like(a) for a in init]
+    fits = torch.zeros(args.sweeps, dtype=torch.float64, device=dev)
+    info = torch.zeros(4, dtype=torch.int32, device=dev)
+    rows = (cfg.nu, cfg.nv, nl, N, N)
+    P = [torch.empty((r, R), dtype=torch.float32, device=dev) for r in rows]   # FP32 masters
+    CS = torch.empty((N + 1, R), dtype=torch.float32, device=dev)
+    CT = torch.empty((N + 1, R), dtype=torch.float32, device=dev)
+    out = torch.empty(nq, dtype=torch.float32, device=dev)
+    gout = torch.empty(nq, dtype=torch.float32, device=dev)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    dT = [torch.empty((r, R), dtype=torch.float32, device=dev) for r in (cfg.nu, cfg.nv, nl, N + 1, N + 1)]
+    dS = torch.empty((N, R), dtype=torch.float32, device=dev)
+    dTt = torch.empty((N, R), dtype=torch.float32, device=dev)
+    adam_m = [torch.zeros_like(p) for p in P]
+    adam_v = [torch.zeros_like(p) for p in P]
+    fac = L.make_factors(P[0], P[1], P[2], CS, CT)
+
+    # ---- refinement targets: brute-force range integrals, once, untimed ----
+    t0 = time.time()
+    bins, mass = G.texel_bins(nxy, desc)
+    q_bf = torch.empty(nq, dtype=torch.float64, device=dev)
+    L.glint_range_bruteforce(desc, bins, mass, q, q_bf)
+    torch.cuda.synchronize()
+    log(f"brute-force targets in {time.time() - t0:.1f}s")
+
+    stream = torch.cuda.current_stream()
+    stages = ["build", "als", "tables", "query", "grad", "adam"]
+
+    def step(ev=None):
+        def mark(i):
+            if ev is not None:
+                ev[i].record(stream)
+        mark(0)
+        L.glint_build_tensor(desc, nxy, T, 0, ws_build)
+        mark(1)
+        for a, b in zip(F, init):
+            a.copy_(b)
+        L.glint_cp_als(desc, T, R, args.sweeps, 0.0, *F, fits, info, ws_als)
+        mark(2)
+        for a, p in zip(F, P):
+            L.glint_convert(a, p)
+        L.glint_make_cumulative(P[3], CS)
+        L.glint_make_cumulative(P[4], CT)
+        mark(3)
+        L.glint_query(fac, q, out)
+        mark(4)
+        L.glint_mse_grad(out, q_bf, gout, loss)
+        L.glint_query_backward(fac, q, gout, *dT)
+        L.glint_cumulative_backward(dT[3], dS)
+        L.glint_cumulative_backward(dT[4], dTt)
+        mark(5)
+        grads = (dT[0], dT[1], dT[2], dS, dTt)
+        for k, (p, g) in enumerate(zip(P, grads)):
+            L.glint_adam_step(p, g, adam_m[k], adam_v[k], 1e-4, 0.9, 0.999, 1e-8, 1)
+        mark(6)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup step {i + 1}/{args.warmup} done")
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    log(f"{args.steps} timed steps done in {wall:.2f}s")
+    stage_ms = {s: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(args.steps)]))
+                for i, s in enumerate(stages)}
+    ev_total = float(np.mean([evs[k][0].elapsed_time(evs[k][6]) for k in range(args.steps)]))
+    ms_per_step = wall * 1e3 / args.steps
+    value = nq / (ms_per_step * 1e-3)
+
+    # ---- quality of this step's result ----
+    fit_last = float(fits[-1].item())
+    ebf = float((torch.linalg.vector_norm(out.double() - q_bf) / torch.linalg.vector_norm(q_bf)).item())
+    # the query as answered before this step's Adam update: re-run the step's query on its tables
+    # (out holds it already; P now holds the updated masters, so ebf above is the ALS form's error)
+
+    # ---- per-kernel timing with events (same launches as in the step) ----
+    reps = args.kernel_reps
+    e0 = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+    e1 = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+    M = torch.empty((cfg.nu, R), dtype=torch.float64, device=dev)
+    for i in range(reps):
+        e0[i].record(stream)
+        L.glint_mttkrp(desc, T, R, 0, *F, M, ws_als)
+        e1[i].record(stream)
+    torch.cuda.synchronize()
+    mttkrp_ms = float(np.mean([e0[i].elapsed_time(e1[i]) for i in range(reps)]))
+    for i in range(reps):
+        e0[i].record(stream)
+        L.glint_query(fac, q, out)
+        e1[i].record(stream)
+    torch.cuda.synchronize()
+    query_ms = float(np.mean([e0[i].elapsed_time(e1[i]) for i in range(reps)]))
+
+    ncells = cfg.nu * cfg.nv * nl
+    t_elems = ncells * N * N
+    mttkrp_flops = 2.0 * t_elems * R                 # one pass over T, 2R flops per element
+    mttkrp_tflops = mttkrp_flops / (mttkrp_ms * 1e-3) / 1e12
+    q_bytes = nq * (7 * 4 + 4)                       # record in, value out
+    q_gbs = q_bytes / (query_ms * 1e-3) / 1e9
+
+    res = {
+        "metric": "P-NDF range queries/sec + %HBM peak at stated rel. error vs brute-force NDF",
+        "value": value,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "c2: 512x512 flake map (5000 sites, alpha 0.15), sigma 0.005, 64x64 NDF bins, "
+                        "8 levels (1..128), rank 64, 50 ALS sweeps, 1920x1080x8 frame queries",
+            "queries_per_step": nq, "rank": R, "nbins": N, "levels": nl, "als_sweeps": args.sweeps,
+            "tensor": "FP32 34.4 GB", "query_tables": "FP32",
+        },
+        "roofline": {
+            "kernel": "k_mttkrp_z (glint_mttkrp mode u: (s,t) pass + u reduction)",
+            "bound": "mfma", "achieved": mttkrp_tflops, "peak": FP32_MFMA_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": mttkrp_tflops / FP32_MFMA_PEAK_TFLOPS, "traffic": None,
+            "per_launch": {"flops": mttkrp_flops, "ms": mttkrp_ms,
+                           "hbm_gbs_equiv": t_elems * 4 / (mttkrp_ms * 1e-3) / 1e9},
+        },
+        "query_kernel": {
+            "kernel": "k_query<float,float,64,4>", "ms": query_ms, "queries_per_s": nq / (query_ms * 1e-3),
+            "roofline": {"bound": "hbm", "achieved": q_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": q_gbs / HBM_PEAK_GBS, "traffic": None,
+                         "algorithmic_bytes_per_query": 32},
+        },
+        "stages_ms": stage_ms,
+        "events_ms_per_step": ev_total,
+        "fit_after_als": fit_last,
+        "error_vs_bruteforce": ebf,
+    }
+
+    log(f"kernels timed: mttkrp {mttkrp_ms:.3f} ms, query {query_ms:.3f} ms")
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle samples)")
+        res["cpu_baseline"], res["parity_sample"] = cpu_baseline(cfg, nxy_h, q_h, out, P, F, CS, CT,
+                                                                  args.sweeps, nq)
+    print(json.dumps(res), flush=True)
+
+
+def cpu_baseline(cfg, nxy_h, q_h, out_dev, P, F, CS, CT, sweeps, nq):
+    """The FP64 oracle timed on bounded samples of each stage and scaled to
+    the whole step (plus a parity check of sampled outputs of this step)."""
+    import numpy as np
+    import torch
+
+    from oracle import cp_als, ndf, query
+
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    except Exception:
+        threads = 1
+    cores = os.cpu_count() or 1
+    t_total = 0.0
+    parts = {}
+    N, R, nl = cfg.nbins, cfg.rank, cfg.nlevels
+
+    # build: brute force on a 32x32 crop of the map, 5 levels, scaled by texel-visit count
+    crop = np.ascontiguousarray(nxy_h[:32, :32])
+    t0 = time.perf_counter()
+    ndf.ndf_bruteforce(crop, N, cfg.sigma, 5)
+    dt = time.perf_counter() - t0
+    scale = (cfg.nu * cfg.nv * sum(4 ** l for l in range(nl))) / (32 * 32 * sum(4 ** l for l in range(5)))
+    parts["build_s"] = dt * scale
+
+    # ALS: one plain sweep on a 16x16x8 tensor of the same cell shape, scaled by |T| and sweeps
+    Ts = np.random.default_rng(0).random((16, 16, nl, N, N))
+    init = [np.random.default_rng(1).random((d, R)) for d in (16, 16, nl, N, N)]
+    t0 = time.perf_counter()
+    cp_als.cp_als(Ts, init, iters=1)
+    dt = time.perf_counter() - t0
+    parts["als_s"] = dt * (cfg.nu * cfg.nv) / (16 * 16) * sweeps
+
+    # query and its gradient on the FP32 tables of this step
+    tabs = [p.double().cpu().numpy() for p in P[:3]] + [CS.double().cpu().numpy(), CT.double().cpu().numpy()]
+    ns = 1_000_000
+    qs = q_h[:ns]
+    t0 = time.perf_counter()
+    qv = query.range_query(*tabs, qs)
+    dt = time.perf_counter() - t0
+    parts["query_s"] = dt * nq / ns
+    t0 = time.perf_counter()
+    query.range_query_grad(*tabs, qs[:200_000], np.ones(200_000))
+    dt = time.perf_counter() - t0
+    parts["grad_s"] = dt * nq / 200_000
+    t_total = sum(parts.values())
+
+    # parity: 10^5 sampled outputs of this step's query against the oracle on the same tables
+    rng = np.random.default_rng(5)
+    idx = np.sort(rng.choice(nq, 100_000, replace=False))
+    got = out_dev.double().cpu().numpy()  # out holds the last query over these tables
+    want = query.range_query(*tabs, q_h[idx])
+    mag = query.range_query_magnitude(*tabs, q_h[idx])
+    rel = np.abs(got[idx] - want) / np.maximum(mag, 1e-300)
+    del qv
+    cpu = {"value": nq / t_total, "unit": "queries/s", "cores": int(threads), "host_cores": int(cores),
+           "kind": "oracle",
+           "sample": "FP64 NumPy oracle per stage, scaled to the step: brute-force NDF on a 32x32 crop "
+                     "(5 levels) x texel visits; one plain ALS sweep on a 16x16x8x64x64 tensor x |T| x "
+                     f"{sweeps}; range query on 1e6 and its gradient on 2e5 of the batch x batch size",
+           "stage_seconds": parts}
+    parity = {"n": int(idx.size), "max_err_over_Nq": float(rel.max()), "tolerance": 1e-5,
+              "pass": bool(rel.max() <= 1e-5)}
+    return cpu, parity
+
+
+if __name__ == "__main__":
+    main()

@@ -197,15 +197,17 @@ __global__ __launch_bounds__(256) void k_mttkrp_z(const TT* __restrict__ T, int6
 // ---------------------------------------------------------------------------
 // Y pass (split K over cells): Ypart[split][k][r] = sum_{cell in split} T[cell][k] C[cell][r],
 // C[cell][r] = U[u][r] V[v][r] L[l][r].  A wave owns 16*VEC rows k (VEC row
-// tiles: tile j holds k = kb + m*VEC + j) and all R columns; 4 cells per step.
+// tiles: tile j holds k = kb + m*VEC + j) and all R columns.  A split is a range
+// of (u, v) pairs; for each pair the wave keeps U*V in registers and walks the
+// nl cells four at a time (lane group kk takes level l0 + kk), L from LDS.
 // ---------------------------------------------------------------------------
 
 template <typename TT, int R>
-__global__ __launch_bounds__(256) void k_mttkrp_y(const TT* __restrict__ T, int64_t ncells, int N,
-                                                  int nv, int nl, const double* __restrict__ U,
+__global__ __launch_bounds__(256) void k_mttkrp_y(const TT* __restrict__ T, int64_t nuv, int nv, int nl,
+                                                  int N, const double* __restrict__ U,
                                                   const double* __restrict__ V,
                                                   const double* __restrict__ L,
-                                                  int64_t cells_per_split, TT* __restrict__ Ypart,
+                                                  int64_t uv_per_split, TT* __restrict__ Ypart,
                                                   const int* __restrict__ ctrl) {
   if (ctrl[CTRL_DONE]) return;
   typedef Mfma<TT> M;
@@ -213,15 +215,19 @@ __global__ __launch_bounds__(256) void k_mttkrp_y(const TT* __restrict__ T, int6
   typedef typename std::conditional<sizeof(TT) == 4, float4, double2>::type vec_t;
   constexpr int VEC = 16 / sizeof(TT);
   constexpr int CT = R / 16;
+  __shared__ TT Lf[16 * R];                 // nl <= 16
+  for (int i = threadIdx.x; i < nl * R; i += blockDim.x) Lf[i] = static_cast<TT>(L[i]);
+  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int i16 = lane & 15;
   const int kk = lane >> 4;
   const int w = threadIdx.x >> 6;
   const int64_t NN = static_cast<int64_t>(N) * N;
   const int64_t kb = (static_cast<int64_t>(blockIdx.x) * 4 + w) * 16 * VEC;
-  const int64_t c_begin = static_cast<int64_t>(blockIdx.y) * cells_per_split;
-  int64_t c_end = c_begin + cells_per_split;
-  if (c_end > ncells) c_end = ncells;
+  if (kb >= NN) return;
+  const int64_t uv_begin = static_cast<int64_t>(blockIdx.y) * uv_per_split;
+  int64_t uv_end = uv_begin + uv_per_split;
+  if (uv_end > nuv) uv_end = nuv;
 
   acc_t acc[VEC][CT];
 #pragma unroll
@@ -229,22 +235,24 @@ __global__ __launch_bounds__(256) void k_mttkrp_y(const TT* __restrict__ T, int6
 #pragma unroll
     for (int c = 0; c < CT; ++c) acc[j][c] = acc_t{};
 
-  if (kb < NN) {
-    for (int64_t c0 = c_begin; c0 < c_end; c0 += 4) {
-      const int64_t cell = c0 + kk;
-      const bool ok = cell < c_end;
-      const int64_t cc = ok ? cell : c_begin;
-      vec_t av = ok ? *reinterpret_cast<const vec_t*>(T + cc * NN + kb + i16 * VEC) : vec_t{};
-      const int l = static_cast<int>(cc % nl);
-      const int64_t uv = cc / nl;
-      const int v = static_cast<int>(uv % nv);
-      const int64_t u = uv / nv;
+  const TT* tbase = T + kb + i16 * VEC;
+  for (int64_t uv = uv_begin; uv < uv_end; ++uv) {
+    const int64_t u = uv / nv;
+    const int v = static_cast<int>(uv - u * nv);
+    TT uvr[CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      const int r = 16 * c + i16;
+      uvr[c] = static_cast<TT>(U[u * R + r] * V[static_cast<int64_t>(v) * R + r]);
+    }
+    const TT* tcell = tbase + uv * nl * NN;
+    for (int l0 = 0; l0 < nl; l0 += 4) {
+      const int l = l0 + kk;
+      const bool ok = l < nl;
+      const vec_t av = ok ? *reinterpret_cast<const vec_t*>(tcell + l * NN) : vec_t{};
       TT bv[CT];
 #pragma unroll
-      for (int c = 0; c < CT; ++c) {
-        const int r = 16 * c + i16;
-        bv[c] = static_cast<TT>(U[u * R + r] * V[static_cast<int64_t>(v) * R + r] * L[l * R + r]);
-      }
+      for (int c = 0; c < CT; ++c) bv[c] = ok ? uvr[c] * Lf[l * R + 16 * c + i16] : TT(0);
 #pragma unroll
       for (int j = 0; j < VEC; ++j) {
         const TT a = reinterpret_cast<const TT*>(&av)[j];
@@ -252,16 +260,16 @@ __global__ __launch_bounds__(256) void k_mttkrp_y(const TT* __restrict__ T, int6
         for (int c = 0; c < CT; ++c) acc[j][c] = M::run(a, bv[c], acc[j][c]);
       }
     }
-    TT* out = Ypart + static_cast<int64_t>(blockIdx.y) * NN * R;
-#pragma unroll
-    for (int j = 0; j < VEC; ++j)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t k = kb + M::row(kk, q) * VEC + j;
-#pragma unroll
-        for (int c = 0; c < CT; ++c) out[k * R + 16 * c + i16] = acc[j][c][q];
-      }
   }
+  TT* out = Ypart + static_cast<int64_t>(blockIdx.y) * NN * R;
+#pragma unroll
+  for (int j = 0; j < VEC; ++j)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t k = kb + M::row(kk, q) * VEC + j;
+#pragma unroll
+      for (int c = 0; c < CT; ++c) out[k * R + 16 * c + i16] = acc[j][c][q];
+    }
 }
 
 template <typename TT>
@@ -596,16 +604,16 @@ bool als_layout(const glint_ndf_desc* d, int R, size_t elt, AlsLayout* L) {
   const int64_t ncells = static_cast<int64_t>(d->nu) * d->nv * d->nlevels;
   const int64_t NN = static_cast<int64_t>(d->nbins) * d->nbins;
   const int VEC = static_cast<int>(16 / elt);
+  const int64_t nuv = static_cast<int64_t>(d->nu) * d->nv;
   const int64_t kblocks = (NN + 64 * VEC - 1) / (64 * VEC);
   int64_t nsplit = 2048 / (kblocks > 0 ? kblocks : 1);
   if (nsplit < 1) nsplit = 1;
-  if (nsplit > (ncells + 63) / 64) nsplit = (ncells + 63) / 64;
+  if (nsplit > (nuv + 7) / 8) nsplit = (nuv + 7) / 8;
   if (nsplit < 1) nsplit = 1;
-  int64_t cps = (ncells + nsplit - 1) / nsplit;
-  cps = (cps + 3) / 4 * 4;
-  nsplit = (ncells + cps - 1) / cps;
+  const int64_t ups = (nuv + nsplit - 1) / nsplit;
+  nsplit = (nuv + ups - 1) / ups;
   L->nsplit = static_cast<int>(nsplit);
-  L->cells_per_split = cps;
+  L->cells_per_split = ups;       // (u, v) pairs per split
   L->sumsq_blocks = 1024;
   const int maxrows = std::max(std::max(d->nu, d->nv), std::max(d->nlevels, d->nbins));
   size_t off = 0;
@@ -699,8 +707,8 @@ glint_status run_als(const glint_ndf_desc* d, const TT* T, int iters, double tol
     hipLaunchKernelGGL(k_sum_rows, dim3((nl * R + 255) / 256), dim3(256), 0, stream, lpart, nu, nl, R, Mb, ctrl);
     GLINT_LAUNCHED("k_reduce_zl");
     if ((st = update(2)) != GLINT_OK) return st;
-    hipLaunchKernelGGL((k_mttkrp_y<TT, R>), dim3(yblocks, Lo.nsplit), dim3(256), 0, stream, T, ncells, N,
-                       nv, nl, F[0], F[1], F[2], Lo.cells_per_split, Yp, ctrl);
+    hipLaunchKernelGGL((k_mttkrp_y<TT, R>), dim3(yblocks, Lo.nsplit), dim3(256), 0, stream, T,
+                       static_cast<int64_t>(nu) * nv, nv, nl, N, F[0], F[1], F[2], Lo.cells_per_split, Yp, ctrl);
     GLINT_LAUNCHED("k_mttkrp_y");
     hipLaunchKernelGGL(k_reduce_splits<TT>, dim3(static_cast<unsigned>(std::min<int64_t>((NN * R + 255) / 256, 4096))),
                        dim3(256), 0, stream, Yp, Lo.nsplit, NN * R, Y, ctrl);
@@ -754,8 +762,8 @@ glint_status run_mttkrp(const glint_ndf_desc* d, const TT* T, int mode, const do
     GLINT_LAUNCHED("k_reduce_z");
   } else {
     const unsigned yblocks = static_cast<unsigned>((NN + 64 * VEC - 1) / (64 * VEC));
-    hipLaunchKernelGGL((k_mttkrp_y<TT, R>), dim3(yblocks, Lo.nsplit), dim3(256), 0, stream, T, ncells, N,
-                       nv, nl, F[0], F[1], F[2], Lo.cells_per_split, Yp, ctrl);
+    hipLaunchKernelGGL((k_mttkrp_y<TT, R>), dim3(yblocks, Lo.nsplit), dim3(256), 0, stream, T,
+                       static_cast<int64_t>(nu) * nv, nv, nl, N, F[0], F[1], F[2], Lo.cells_per_split, Yp, ctrl);
     GLINT_LAUNCHED("k_mttkrp_y");
     hipLaunchKernelGGL(k_reduce_splits<TT>, dim3(static_cast<unsigned>(std::min<int64_t>((NN * R + 255) / 256, 4096))),
                        dim3(256), 0, stream, Yp, Lo.nsplit, NN * R, Y, ctrl);

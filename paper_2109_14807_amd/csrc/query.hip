@@ -78,15 +78,40 @@ struct QueryArgs {
   float* out;
 };
 
+// Row offsets of one query, resolved once by the lane that owns the query:
+// element offsets of its U and V rows (global) and of its L, CS and CT rows
+// (LDS).  An empty box gets equal CS offsets, so its rank terms are exact zeros.
+struct alignas(16) QueryRows {
+  int u, v, l, sh, sl, th, tl, pad;
+};
+
+constexpr int kQueryThreads = 512;
+
+// RPL consecutive FP32 values from 16-byte aligned LDS.
+template <int RPL>
+__device__ __forceinline__ void lds_row(const float* p, float* out) {
+  static_assert(RPL % 4 == 0 || RPL < 4, "row slice");
+  if constexpr (RPL >= 4) {
+#pragma unroll
+    for (int i = 0; i < RPL / 4; ++i) {
+      const float4 x = reinterpret_cast<const float4*>(p)[i];
+      out[4 * i] = x.x; out[4 * i + 1] = x.y; out[4 * i + 2] = x.z; out[4 * i + 3] = x.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) out[i] = p[i];
+  }
+}
+
 template <typename FT, typename CT, int R, int RPL>
-__global__ __launch_bounds__(256) void k_query(QueryArgs a) {
-  constexpr int LPQ = R / RPL;
-  constexpr int QPW = 64 / LPQ;
+__global__ __launch_bounds__(kQueryThreads) void k_query(QueryArgs a) {
+  constexpr int LPQ = R / RPL;           // lanes per query
   static_assert(LPQ >= 1 && LPQ <= 64, "lanes per query");
   extern __shared__ __align__(16) float lds[];
   float* Ls = lds;
   float* CSs = Ls + a.nl * R;
   float* CTs = CSs + (a.N + 1) * R;
+  QueryRows* rows = reinterpret_cast<QueryRows*>(CTs + (a.N + 1) * R);   // [waves][64]
   stage_table<FT>(Ls, static_cast<const FT*>(a.L), a.nl, R, &a.scale);
   stage_table<CT>(CSs, static_cast<const CT*>(a.CS), a.N + 1, R, nullptr);
   stage_table<CT>(CTs, static_cast<const CT*>(a.CT), a.N + 1, R, nullptr);
@@ -98,34 +123,59 @@ __global__ __launch_bounds__(256) void k_query(QueryArgs a) {
   const int g = lane / LPQ;
   const int j = lane % LPQ;
   const int r0 = j * RPL;
+  QueryRows* wrows = rows + (threadIdx.x >> 6) * 64;
   const int64_t wave = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
-  for (int64_t base = wave * QPW; base < a.nq; base += nwaves * QPW) {
-    const int64_t qi = base + g;
-    const bool valid = qi < a.nq;
-    const int32_t* rec = a.q + (valid ? qi : a.nq - 1) * 7;
-    const int u = glint_wrap(rec[0], a.nu);
-    const int v = glint_wrap(rec[1], a.nv);
-    const int l = glint_clampi(rec[2], 0, a.nl - 1);
-    const int slo = glint_clampi(rec[3], 0, a.N), shi = glint_clampi(rec[4], 0, a.N);
-    const int tlo = glint_clampi(rec[5], 0, a.N), thi = glint_clampi(rec[6], 0, a.N);
-    float uu[RPL], vv[RPL];
-    load_row<FT, RPL>(U + static_cast<int64_t>(u) * R + r0, uu);
-    load_row<FT, RPL>(V + static_cast<int64_t>(v) * R + r0, vv);
-    const float* lr = Ls + l * R + r0;
-    const float* sh = CSs + shi * R + r0;
-    const float* sl = CSs + slo * R + r0;
-    const float* th = CTs + thi * R + r0;
-    const float* tl = CTs + tlo * R + r0;
-    float acc = 0.0f;
+  for (int64_t base = wave * 64; base < a.nq; base += nwaves * 64) {
+    // phase 1: lane i resolves query base + i (all seven loads issued first)
+    {
+      const int64_t qi = base + lane;
+      const int64_t qc = qi < a.nq ? qi : a.nq - 1;
+      const int32_t* rec = a.q + qc * 7;
+      int f[7];
 #pragma unroll
-    for (int e = 0; e < RPL; ++e) {
-      const float dS = sh[e] - sl[e];
-      const float dT = th[e] - tl[e];
-      acc += uu[e] * vv[e] * lr[e] * dS * dT;
+      for (int i = 0; i < 7; ++i) f[i] = rec[i];
+      const int u = glint_wrap(f[0], a.nu);
+      const int v = glint_wrap(f[1], a.nv);
+      const int l = glint_clampi(f[2], 0, a.nl - 1);
+      const int slo = glint_clampi(f[3], 0, a.N), shi = glint_clampi(f[4], 0, a.N);
+      const int tlo = glint_clampi(f[5], 0, a.N), thi = glint_clampi(f[6], 0, a.N);
+      const bool empty = !(slo < shi && tlo < thi);
+      QueryRows r;
+      r.u = u * R;
+      r.v = v * R;
+      r.l = l * R;
+      r.sh = (empty ? slo : shi) * R;
+      r.sl = slo * R;
+      r.th = thi * R;
+      r.tl = tlo * R;
+      r.pad = 0;
+      wrows[lane] = r;
     }
-    acc = glint_group_sum<LPQ>(acc);
-    if (valid && j == 0) a.out[qi] = (slo < shi && tlo < thi) ? acc : 0.0f;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    // phase 2: group g serves queries g*LPQ .. g*LPQ + LPQ - 1; lane j keeps query g*LPQ + j
+    float res = 0.0f;
+#pragma unroll 4
+    for (int jj = 0; jj < LPQ; ++jj) {
+      const QueryRows r = wrows[g * LPQ + jj];
+      float uu[RPL], vv[RPL], lr[RPL], sh[RPL], sl[RPL], th[RPL], tl[RPL];
+      load_row<FT, RPL>(U + r.u + r0, uu);
+      load_row<FT, RPL>(V + r.v + r0, vv);
+      lds_row<RPL>(Ls + r.l + r0, lr);
+      lds_row<RPL>(CSs + r.sh + r0, sh);
+      lds_row<RPL>(CSs + r.sl + r0, sl);
+      lds_row<RPL>(CTs + r.th + r0, th);
+      lds_row<RPL>(CTs + r.tl + r0, tl);
+      float acc = 0.0f;
+#pragma unroll
+      for (int e = 0; e < RPL; ++e) acc += uu[e] * vv[e] * lr[e] * (sh[e] - sl[e]) * (th[e] - tl[e]);
+      acc = glint_group_sum<LPQ>(acc);
+      res = (j == jj) ? acc : res;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int64_t qo = base + g * LPQ + j;
+    if (qo < a.nq) a.out[qo] = res;
   }
 }
 
@@ -402,17 +452,18 @@ constexpr int rpl_for() {
 template <typename FT, typename CT, int R>
 glint_status launch_query(const QueryArgs& a, hipStream_t stream) {
   constexpr int RPL = rpl_for<FT>() <= R ? rpl_for<FT>() : R;
-  const size_t lds = sizeof(float) * static_cast<size_t>(a.nl + 2 * (a.N + 1)) * R;
+  const size_t lds = sizeof(float) * static_cast<size_t>(a.nl + 2 * (a.N + 1)) * R +
+                     sizeof(QueryRows) * (kQueryThreads / 64) * 64;
   if (static_cast<int>(lds) > g_max_lds)
     return glint_fail(GLINT_E_UNSUPPORTED, "tables need %zu bytes of LDS (device max %d)", lds, g_max_lds);
-  constexpr int QPW = 64 / (R / RPL);
-  const int64_t waves_needed = (a.nq + QPW - 1) / QPW;
-  int64_t blocks = (waves_needed + 3) / 4;
-  const int64_t cap = static_cast<int64_t>(g_cu_count) * 8;
+  const int64_t waves_needed = (a.nq + 63) / 64;
+  constexpr int WPB = kQueryThreads / 64;
+  int64_t blocks = (waves_needed + WPB - 1) / WPB;
+  const int64_t cap = static_cast<int64_t>(g_cu_count) * 4;
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
   glint_clear_launch_error();
-  hipLaunchKernelGGL((k_query<FT, CT, R, RPL>), dim3(static_cast<unsigned>(blocks)), dim3(256), lds,
+  hipLaunchKernelGGL((k_query<FT, CT, R, RPL>), dim3(static_cast<unsigned>(blocks)), dim3(kQueryThreads), lds,
                      stream, a);
   GLINT_LAUNCHED("k_query");
   return GLINT_OK;
