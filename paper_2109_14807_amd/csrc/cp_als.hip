@@ -67,35 +67,20 @@ constexpr int kPad32 = 4;
 // ||T||^2
 // ---------------------------------------------------------------------------
 
-template <typename TT>
-__global__ __launch_bounds__(256) void k_sumsq(const TT* __restrict__ T, int64_t n,
-                                               double* __restrict__ part) {
-  double acc = 0.0;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const double x = static_cast<double>(T[i]);
-    acc += x * x;
-  }
-  __shared__ double sh[4];
-  acc = glint_wave_sum(acc);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+__global__ void k_als_init(int* __restrict__ ctrl, double* __restrict__ fitprev) {
+  if (threadIdx.x < CTRL_N) ctrl[threadIdx.x] = 0;
+  if (threadIdx.x == 0) fitprev[0] = 0.0;
 }
 
-__global__ void k_sum_parts(const double* __restrict__ part, int n, double* __restrict__ out,
-                            int* __restrict__ ctrl, double* __restrict__ fitprev) {
+// ||T||^2 from the per-wave partial sums of the first Z pass.
+__global__ void k_sum_norm(const double* __restrict__ part, int n, double* __restrict__ out) {
   __shared__ double sh[4];
   double acc = 0.0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) acc += part[i];
   acc = glint_wave_sum(acc);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    out[0] = sh[0] + sh[1] + sh[2] + sh[3];
-    for (int i = 0; i < CTRL_N; ++i) ctrl[i] = 0;
-    fitprev[0] = 0.0;
-  }
+  if (threadIdx.x == 0) out[0] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
 __global__ void k_ctrl_init(int* __restrict__ ctrl) {
@@ -112,7 +97,8 @@ template <typename TT, int R, int ROWT>
 __global__ __launch_bounds__(256) void k_mttkrp_z(const TT* __restrict__ T, int64_t ncells, int N,
                                                   const double* __restrict__ S,
                                                   const double* __restrict__ Tf,
-                                                  TT* __restrict__ Z, const int* __restrict__ ctrl) {
+                                                  TT* __restrict__ Z, double* __restrict__ sumsq,
+                                                  const int* __restrict__ ctrl) {
   if (ctrl[CTRL_DONE]) return;
   typedef Mfma<TT> M;
   typedef typename M::acc_t acc_t;
@@ -123,9 +109,11 @@ __global__ __launch_bounds__(256) void k_mttkrp_z(const TT* __restrict__ T, int6
   extern __shared__ __align__(16) unsigned char smem[];
   TT* TfT = reinterpret_cast<TT*>(smem);   // [R][N + PAD]
   const int ld = N + PAD;
+  TT* Ss = TfT + R * ld;                   // [N][R]
   for (int i = threadIdx.x; i < N * R; i += blockDim.x) {
     const int t = i / R, r = i - (i / R) * R;
     TfT[r * ld + t] = static_cast<TT>(Tf[i]);
+    Ss[i] = static_cast<TT>(S[i]);
   }
   __syncthreads();
 
@@ -144,42 +132,63 @@ __global__ __launch_bounds__(256) void k_mttkrp_z(const TT* __restrict__ T, int6
     for (int c = 0; c < CT; ++c) acc[rt][c] = acc_t{};
 
   const TT* rowp[ROWT];
-  bool rowok[ROWT];
 #pragma unroll
   for (int rt = 0; rt < ROWT; ++rt) {
-    const int64_t cell = cell0 + 16 * rt + i16;
-    rowok[rt] = cell < ncells;
-    rowp[rt] = T + (rowok[rt] ? cell : 0) * NN + kk * VEC;
+    int64_t cell = cell0 + 16 * rt + i16;
+    if (cell >= ncells) cell = ncells - 1;     // rows past the end load a valid row, never stored
+    rowp[rt] = T + cell * NN + kk * VEC;
   }
+  double ss = 0.0;                            // sum of squares of this lane's elements
+  const bool own_rows = sumsq != nullptr;
 
-  const int chunks = N / (4 * VEC);
-  for (int s = 0; s < N; ++s) {
-    TT sv[CT];
+  // flat loop over 4*VEC-wide chunks of k = s*N + t; the next chunk's loads are
+  // issued before this chunk's products
+  const int chunks_per_row = N / (4 * VEC);
+  const int nchunks = N * chunks_per_row;
+  vec_t nxt[ROWT];
 #pragma unroll
-    for (int c = 0; c < CT; ++c) sv[c] = static_cast<TT>(S[s * R + 16 * c + i16]);
-    for (int tb = 0; tb < chunks; ++tb) {
-      const int t0 = tb * 4 * VEC;
-      const int64_t k0 = static_cast<int64_t>(s) * N + t0;
-      vec_t av[ROWT];
+  for (int rt = 0; rt < ROWT; ++rt) nxt[rt] = *reinterpret_cast<const vec_t*>(rowp[rt]);
+  for (int ch = 0; ch < nchunks; ++ch) {
+    const int s = ch / chunks_per_row;
+    const int t0 = (ch - s * chunks_per_row) * 4 * VEC;
+    vec_t av[ROWT];
 #pragma unroll
-      for (int rt = 0; rt < ROWT; ++rt) {
-        av[rt] = rowok[rt] ? *reinterpret_cast<const vec_t*>(rowp[rt] + k0) : vec_t{};
-      }
+    for (int rt = 0; rt < ROWT; ++rt) av[rt] = nxt[rt];
+    if (ch + 1 < nchunks) {
+      const int s1 = (ch + 1) / chunks_per_row;
+      const int64_t k1 = static_cast<int64_t>(s1) * N + (ch + 1 - s1 * chunks_per_row) * 4 * VEC;
 #pragma unroll
-      for (int c = 0; c < CT; ++c) {
-        const vec_t tv = *reinterpret_cast<const vec_t*>(&TfT[(16 * c + i16) * ld + t0 + kk * VEC]);
-        const TT* tvp = reinterpret_cast<const TT*>(&tv);
+      for (int rt = 0; rt < ROWT; ++rt) nxt[rt] = *reinterpret_cast<const vec_t*>(rowp[rt] + k1);
+    }
+    if (own_rows) {
 #pragma unroll
-        for (int j = 0; j < VEC; ++j) {
-          const TT b = sv[c] * tvp[j];
+      for (int rt = 0; rt < ROWT; ++rt)
+        if (cell0 + 16 * rt + i16 < ncells)
 #pragma unroll
-          for (int rt = 0; rt < ROWT; ++rt) {
-            const TT a = reinterpret_cast<const TT*>(&av[rt])[j];
-            acc[rt][c] = M::run(a, b, acc[rt][c]);
+          for (int j = 0; j < VEC; ++j) {
+            const double x = static_cast<double>(reinterpret_cast<const TT*>(&av[rt])[j]);
+            ss += x * x;
           }
+    }
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      const TT sv = Ss[s * R + 16 * c + i16];
+      const vec_t tv = *reinterpret_cast<const vec_t*>(&TfT[(16 * c + i16) * ld + t0 + kk * VEC]);
+      const TT* tvp = reinterpret_cast<const TT*>(&tv);
+#pragma unroll
+      for (int j = 0; j < VEC; ++j) {
+        const TT b = sv * tvp[j];
+#pragma unroll
+        for (int rt = 0; rt < ROWT; ++rt) {
+          const TT a = reinterpret_cast<const TT*>(&av[rt])[j];
+          acc[rt][c] = M::run(a, b, acc[rt][c]);
         }
       }
     }
+  }
+  if (own_rows) {
+    ss = glint_wave_sum(ss);
+    if (lane == 0) sumsq[wave] = ss;
   }
   // D[m][n]: item q of this lane holds row M::row(lane/16, q), column lane%16
 #pragma unroll
@@ -196,18 +205,31 @@ __global__ __launch_bounds__(256) void k_mttkrp_z(const TT* __restrict__ T, int6
 
 // ---------------------------------------------------------------------------
 // Y pass (split K over cells): Ypart[split][k][r] = sum_{cell in split} T[cell][k] C[cell][r],
-// C[cell][r] = U[u][r] V[v][r] L[l][r].  A wave owns 16*VEC rows k (VEC row
-// tiles: tile j holds k = kb + m*VEC + j) and all R columns.  A split is a range
-// of (u, v) pairs; for each pair the wave keeps U*V in registers and walks the
-// nl cells four at a time (lane group kk takes level l0 + kk), L from LDS.
+// C[cell][r] = UV[u*nv+v][r] L[l][r] with UV = U*V precomputed per sweep.
+// A wave owns 16*VEC rows k (VEC row tiles: tile j holds k = kb + m*VEC + j)
+// and all R columns; it walks its split four cells per step (lane group kk
+// takes cell c0 + kk), issuing the next step's loads before this step's MFMAs.
 // ---------------------------------------------------------------------------
 
+template <typename TT>
+__global__ void k_uv_product(const double* __restrict__ U, const double* __restrict__ V, int nu,
+                             int nv, int R, TT* __restrict__ UV, const int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE]) return;
+  const int64_t n = static_cast<int64_t>(nu) * nv * R;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int r = static_cast<int>(i % R);
+    const int64_t uv = i / R;
+    const int64_t u = uv / nv, v = uv - u * nv;
+    UV[i] = static_cast<TT>(U[u * R + r] * V[v * R + r]);
+  }
+}
+
 template <typename TT, int R>
-__global__ __launch_bounds__(256) void k_mttkrp_y(const TT* __restrict__ T, int64_t nuv, int nv, int nl,
-                                                  int N, const double* __restrict__ U,
-                                                  const double* __restrict__ V,
+__global__ __launch_bounds__(256) void k_mttkrp_y(const TT* __restrict__ T, int64_t ncells, int nl,
+                                                  int N, const TT* __restrict__ UV,
                                                   const double* __restrict__ L,
-                                                  int64_t uv_per_split, TT* __restrict__ Ypart,
+                                                  int64_t cells_per_split, TT* __restrict__ Ypart,
                                                   const int* __restrict__ ctrl) {
   if (ctrl[CTRL_DONE]) return;
   typedef Mfma<TT> M;
@@ -225,9 +247,9 @@ __global__ __launch_bounds__(256) void k_mttkrp_y(const TT* __restrict__ T, int6
   const int64_t NN = static_cast<int64_t>(N) * N;
   const int64_t kb = (static_cast<int64_t>(blockIdx.x) * 4 + w) * 16 * VEC;
   if (kb >= NN) return;
-  const int64_t uv_begin = static_cast<int64_t>(blockIdx.y) * uv_per_split;
-  int64_t uv_end = uv_begin + uv_per_split;
-  if (uv_end > nuv) uv_end = nuv;
+  const int64_t c_begin = static_cast<int64_t>(blockIdx.y) * cells_per_split;
+  int64_t c_end = c_begin + cells_per_split;
+  if (c_end > ncells) c_end = ncells;
 
   acc_t acc[VEC][CT];
 #pragma unroll
@@ -235,30 +257,39 @@ __global__ __launch_bounds__(256) void k_mttkrp_y(const TT* __restrict__ T, int6
 #pragma unroll
     for (int c = 0; c < CT; ++c) acc[j][c] = acc_t{};
 
-  const TT* tbase = T + kb + i16 * VEC;
-  for (int64_t uv = uv_begin; uv < uv_end; ++uv) {
-    const int64_t u = uv / nv;
-    const int v = static_cast<int>(uv - u * nv);
-    TT uvr[CT];
+  const TT* tb = T + kb + i16 * VEC;
+  // this lane's cell c0 + kk as (uv, l), advanced by 4 cells per step
+  int64_t cell = c_begin + kk;
+  int64_t uv = cell / nl;
+  int l = static_cast<int>(cell - uv * nl);
+  auto load = [&](int64_t ce, int64_t uvv, vec_t& av, TT* uvr) {
+    const int64_t cc = ce < c_end ? ce : c_end - 1;
+    const int64_t uc = ce < c_end ? uvv : (c_end - 1) / nl;
+    av = *reinterpret_cast<const vec_t*>(tb + cc * NN);
 #pragma unroll
-    for (int c = 0; c < CT; ++c) {
-      const int r = 16 * c + i16;
-      uvr[c] = static_cast<TT>(U[u * R + r] * V[static_cast<int64_t>(v) * R + r]);
+    for (int c = 0; c < CT; ++c) uvr[c] = UV[uc * R + 16 * c + i16];
+  };
+  vec_t av_n;
+  TT uv_n[CT];
+  load(cell, uv, av_n, uv_n);
+  for (int64_t c0 = c_begin; c0 < c_end; c0 += 4) {
+    const vec_t av = av_n;
+    TT bv[CT];
+    const bool ok = cell < c_end;
+#pragma unroll
+    for (int c = 0; c < CT; ++c) bv[c] = ok ? uv_n[c] * Lf[l * R + 16 * c + i16] : TT(0);
+    cell += 4;
+    l += 4;
+    while (l >= nl) {
+      l -= nl;
+      ++uv;
     }
-    const TT* tcell = tbase + uv * nl * NN;
-    for (int l0 = 0; l0 < nl; l0 += 4) {
-      const int l = l0 + kk;
-      const bool ok = l < nl;
-      const vec_t av = ok ? *reinterpret_cast<const vec_t*>(tcell + l * NN) : vec_t{};
-      TT bv[CT];
+    if (c0 + 4 < c_end) load(cell, uv, av_n, uv_n);
 #pragma unroll
-      for (int c = 0; c < CT; ++c) bv[c] = ok ? uvr[c] * Lf[l * R + 16 * c + i16] : TT(0);
+    for (int j = 0; j < VEC; ++j) {
+      const TT a = reinterpret_cast<const TT*>(&av)[j];
 #pragma unroll
-      for (int j = 0; j < VEC; ++j) {
-        const TT a = reinterpret_cast<const TT*>(&av)[j];
-#pragma unroll
-        for (int c = 0; c < CT; ++c) acc[j][c] = M::run(a, bv[c], acc[j][c]);
-      }
+      for (int c = 0; c < CT; ++c) acc[j][c] = M::run(a, bv[c], acc[j][c]);
     }
   }
   TT* out = Ypart + static_cast<int64_t>(blockIdx.y) * NN * R;
@@ -300,102 +331,70 @@ __global__ void k_mttkrp_st(const double* __restrict__ Y, const double* __restri
 }
 
 // ---------------------------------------------------------------------------
-// Z reductions for modes u, v, l (FP64)
+// Z reductions for modes u, v, l (FP64): a block takes one row of the mode
+// and a chunk of one other index, reduces in registers and LDS, and adds R
+// partial sums into M with FP64 atomics (M cleared first).
+//   mode 0: M[u] += sum_{v in chunk, l} V[v] L[l] Z[u,v,l]      grid (nu, nv/kChunk)
+//   mode 1: M[v] += sum_{u in chunk, l} U[u] L[l] Z[u,v,l]      grid (nv, nu/kChunk)
+//   mode 2: M[l] += sum_{v in chunk}    U[u] V[v] Z[u,v,l]      grid (nu, nv/kChunk), all l
 // ---------------------------------------------------------------------------
 
-template <typename TT>
-__global__ __launch_bounds__(256) void k_reduce_zu(const TT* __restrict__ Z, int nv, int nl, int R,
-                                                   const double* __restrict__ V,
-                                                   const double* __restrict__ L,
-                                                   double* __restrict__ M, const int* __restrict__ ctrl) {
+constexpr int kChunk = 16;
+
+__global__ void k_zero(double* __restrict__ p, int64_t n, const int* __restrict__ ctrl) {
   if (ctrl[CTRL_DONE]) return;
-  __shared__ double sh[256];
-  const int u = blockIdx.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = 0.0;
+}
+
+template <typename TT, int MODE>
+__global__ __launch_bounds__(256) void k_reduce_z(const TT* __restrict__ Z, int nu, int nv, int nl, int R,
+                                                  const double* __restrict__ U,
+                                                  const double* __restrict__ V,
+                                                  const double* __restrict__ L,
+                                                  double* __restrict__ M, const int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE]) return;
+  __shared__ double sh[16 * 256];
   const int r = threadIdx.x % R;
   const int parts = blockDim.x / R;
   const int p = threadIdx.x / R;
+  const int row = blockIdx.x;                // u (modes 0, 2) or v (mode 1)
+  const int c0 = blockIdx.y * kChunk;        // chunk of v (modes 0, 2) or u (mode 1)
+  const int cn = min(kChunk, (MODE == 1 ? nu : nv) - c0);
+  if (MODE == 2)
+    for (int i = threadIdx.x; i < nl * 256; i += blockDim.x) sh[i] = 0.0;
   double acc = 0.0;
+  if (MODE == 2) __syncthreads();
   if (p < parts) {
-    const int64_t base = static_cast<int64_t>(u) * nv * nl;
-    for (int vl = p; vl < nv * nl; vl += parts) {
-      const int v = vl / nl, l = vl - (vl / nl) * nl;
-      acc += V[v * R + r] * L[l * R + r] * static_cast<double>(Z[(base + vl) * R + r]);
+    for (int o = p; o < cn; o += parts) {    // one (u, v) pair: nl contiguous cells
+      const int u = MODE == 1 ? c0 + o : row;
+      const int v = MODE == 1 ? row : c0 + o;
+      const TT* zc = Z + (static_cast<int64_t>(u) * nv + v) * nl * R + r;
+      if (MODE == 0) {
+        double t = 0.0;
+        for (int l = 0; l < nl; ++l) t += L[l * R + r] * static_cast<double>(zc[l * R]);
+        acc += V[static_cast<int64_t>(v) * R + r] * t;
+      } else if (MODE == 1) {
+        double t = 0.0;
+        for (int l = 0; l < nl; ++l) t += L[l * R + r] * static_cast<double>(zc[l * R]);
+        acc += U[static_cast<int64_t>(u) * R + r] * t;
+      } else {
+        const double w = U[static_cast<int64_t>(u) * R + r] * V[static_cast<int64_t>(v) * R + r];
+        for (int l = 0; l < nl; ++l) sh[l * 256 + threadIdx.x] += w * static_cast<double>(zc[l * R]);
+      }
     }
   }
-  sh[threadIdx.x] = acc;
+  if (MODE != 2) sh[threadIdx.x] = acc;
   __syncthreads();
-  if (threadIdx.x < R) {
-    double s = 0.0;
-    for (int q = 0; q < parts; ++q) s += sh[q * R + threadIdx.x];
-    M[u * R + threadIdx.x] = s;
+  const int nout = MODE == 2 ? nl : 1;
+  for (int idx = threadIdx.x; idx < nout * R; idx += blockDim.x) {
+    const int i = idx / R, rr = idx % R;
+    double t = 0.0;
+    for (int q = 0; q < parts; ++q) t += sh[i * 256 + q * R + rr];
+    const int orow = MODE == 2 ? i : row;
+    atomicAdd(&M[static_cast<int64_t>(orow) * R + rr], t);
   }
-}
-
-template <typename TT>
-__global__ __launch_bounds__(256) void k_reduce_zv(const TT* __restrict__ Z, int nu, int nv, int nl,
-                                                   int R, const double* __restrict__ U,
-                                                   const double* __restrict__ L,
-                                                   double* __restrict__ M, const int* __restrict__ ctrl) {
-  if (ctrl[CTRL_DONE]) return;
-  __shared__ double sh[256];
-  const int v = blockIdx.x;
-  const int r = threadIdx.x % R;
-  const int parts = blockDim.x / R;
-  const int p = threadIdx.x / R;
-  double acc = 0.0;
-  if (p < parts) {
-    for (int ul = p; ul < nu * nl; ul += parts) {
-      const int u = ul / nl, l = ul - (ul / nl) * nl;
-      const int64_t cell = (static_cast<int64_t>(u) * nv + v) * nl + l;
-      acc += U[u * R + r] * L[l * R + r] * static_cast<double>(Z[cell * R + r]);
-    }
-  }
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  if (threadIdx.x < R) {
-    double s = 0.0;
-    for (int q = 0; q < parts; ++q) s += sh[q * R + threadIdx.x];
-    M[v * R + threadIdx.x] = s;
-  }
-}
-
-// part[l][u][r] = sum_v U[u][r] V[v][r] Z[u,v,l][r]
-template <typename TT>
-__global__ __launch_bounds__(256) void k_reduce_zl(const TT* __restrict__ Z, int nu, int nv, int nl,
-                                                   int R, const double* __restrict__ U,
-                                                   const double* __restrict__ V,
-                                                   double* __restrict__ part, const int* __restrict__ ctrl) {
-  if (ctrl[CTRL_DONE]) return;
-  __shared__ double sh[256];
-  const int u = blockIdx.x, l = blockIdx.y;
-  const int r = threadIdx.x % R;
-  const int parts = blockDim.x / R;
-  const int p = threadIdx.x / R;
-  double acc = 0.0;
-  if (p < parts) {
-    for (int v = p; v < nv; v += parts) {
-      const int64_t cell = (static_cast<int64_t>(u) * nv + v) * nl + l;
-      acc += V[v * R + r] * static_cast<double>(Z[cell * R + r]);
-    }
-  }
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  if (threadIdx.x < R) {
-    double s = 0.0;
-    for (int q = 0; q < parts; ++q) s += sh[q * R + threadIdx.x];
-    part[(static_cast<int64_t>(l) * nu + u) * R + threadIdx.x] = U[u * R + threadIdx.x] * s;
-  }
-}
-
-__global__ void k_sum_rows(const double* __restrict__ part, int rows, int groups, int R,
-                           double* __restrict__ M, const int* __restrict__ ctrl) {
-  if (ctrl[CTRL_DONE]) return;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= groups * R) return;
-  const int gidx = idx / R, r = idx - (idx / R) * R;
-  double acc = 0.0;
-  for (int i = 0; i < rows; ++i) acc += part[(static_cast<int64_t>(gidx) * rows + i) * R + r];
-  M[idx] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -430,6 +429,10 @@ __global__ __launch_bounds__(1024) void k_cholesky(const double* __restrict__ gr
     if (i % (R + 1) == 0) diag0[i / (R + 1)] = g;
   }
   __syncthreads();
+  // Unscaled right-looking elimination: after step j the trailing block holds
+  // G - sum_{m<=j} c_m c_m^T / d_m with c_m the m-th column and d_m its pivot;
+  // the factor L[i][j] = c_j[i] / sqrt(d_j) is formed at the end.  One barrier
+  // per column.
   bool fail = false;
   for (int j = 0; j < R; ++j) {
     const double d = G[j * R + j];
@@ -438,15 +441,11 @@ __global__ __launch_bounds__(1024) void k_cholesky(const double* __restrict__ gr
       fail = true;
       break;
     }
-    const double ljj = sqrt(d);
-    __syncthreads();
-    for (int i = j + 1 + threadIdx.x; i < R; i += blockDim.x) G[i * R + j] /= ljj;
-    if (threadIdx.x == 0) G[j * R + j] = ljj;
-    __syncthreads();
+    const double inv = 1.0 / d;
     const int w = R - j - 1;
     for (int idx = threadIdx.x; idx < w * w; idx += blockDim.x) {
       const int i = j + 1 + idx / w, k = j + 1 + idx % w;
-      if (k <= i) G[i * R + k] -= G[i * R + j] * G[k * R + j];
+      if (k <= i) G[i * R + k] -= G[i * R + j] * G[k * R + j] * inv;
     }
     __syncthreads();
   }
@@ -455,6 +454,15 @@ __global__ __launch_bounds__(1024) void k_cholesky(const double* __restrict__ gr
     if (fail) ctrl[CTRL_FAILS] += 1;
   }
   if (fail) return;
+  for (int j = threadIdx.x; j < R; j += blockDim.x) diag0[j] = sqrt(G[j * R + j]);
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < RR; idx += blockDim.x) {
+    const int i = idx / R, k = idx % R;
+    if (k < i) G[idx] /= diag0[k];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < R; i += blockDim.x) G[i * R + i] = diag0[i];
+  __syncthreads();
   for (int idx = threadIdx.x; idx < RR; idx += blockDim.x) {
     const int i = idx / R, k = idx % R;
     const double x = k <= i ? G[idx] : 0.0;
@@ -465,12 +473,23 @@ __global__ __launch_bounds__(1024) void k_cholesky(const double* __restrict__ gr
 
 // One wave per row: x = m G^-1 with G = Lc Lc^T (forward then back substitution).
 template <int R>
-__global__ __launch_bounds__(256) void k_solve(const double* __restrict__ M, int rows,
-                                               const double* __restrict__ Lc,
-                                               const double* __restrict__ LcT,
+__global__ __launch_bounds__(1024) void k_solve(const double* __restrict__ M, int rows,
+                                               const double* Lc, const double* LcT,
                                                double* __restrict__ A, const int* __restrict__ ctrl) {
   if (ctrl[CTRL_DONE] || ctrl[CTRL_FAILNOW]) return;
   constexpr int E = (R + 63) / 64;
+  constexpr bool kStage = R <= 64;           // both factors fit in LDS (64 KB at R = 64)
+  __shared__ double sL[kStage ? R * R : 1];
+  __shared__ double sLT[kStage ? R * R : 1];
+  if constexpr (kStage) {
+    for (int i = threadIdx.x; i < R * R; i += blockDim.x) {
+      sL[i] = Lc[i];
+      sLT[i] = LcT[i];
+    }
+    __syncthreads();
+    Lc = sL;
+    LcT = sLT;
+  }
   const int lane = threadIdx.x & 63;
   const int row = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (row >= rows) return;
@@ -517,20 +536,66 @@ __global__ __launch_bounds__(256) void k_solve(const double* __restrict__ M, int
   }
 }
 
-__global__ void k_normalize(double* __restrict__ A, int rows, int R, double* __restrict__ lam,
-                            const int* __restrict__ ctrl) {
+// One workgroup: column norms lambda, unit columns, and the new Gram A^T A.
+__global__ __launch_bounds__(1024) void k_normalize_gram(double* __restrict__ A, int rows, int R,
+                                                         double* __restrict__ lam, double* __restrict__ G,
+                                                         const int* __restrict__ ctrl) {
   if (ctrl[CTRL_DONE] || ctrl[CTRL_FAILNOW]) return;
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= R) return;
-  double s = 0.0;
-  for (int i = 0; i < rows; ++i) {
-    const double x = A[static_cast<int64_t>(i) * R + r];
-    s += x * x;
+  __shared__ double sh[1024];
+  __shared__ double lr[256];
+  const int r = threadIdx.x % R;
+  const int parts = blockDim.x / R;
+  const int p = threadIdx.x / R;
+  double s2 = 0.0;
+  if (p < parts)
+    for (int i = p; i < rows; i += parts) {
+      const double x = A[static_cast<int64_t>(i) * R + r];
+      s2 += x * x;
+    }
+  sh[threadIdx.x] = s2;
+  __syncthreads();
+  if (threadIdx.x < R) {
+    double t = 0.0;
+    for (int q = 0; q < parts; ++q) t += sh[q * R + threadIdx.x];
+    const double nrm = sqrt(t);
+    lam[threadIdx.x] = nrm;
+    lr[threadIdx.x] = nrm;
   }
-  const double nrm = sqrt(s);
-  lam[r] = nrm;
-  if (nrm > 0.0)
-    for (int i = 0; i < rows; ++i) A[static_cast<int64_t>(i) * R + r] /= nrm;
+  __syncthreads();
+  const int64_t n = static_cast<int64_t>(rows) * R;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const double nrm = lr[i % R];
+    if (nrm > 0.0) A[i] /= nrm;
+  }
+  __syncthreads();
+  // Gram in row tiles staged through LDS (tile of kGramRows x R doubles)
+  constexpr int kGramRows = 4096 / 128;      // 32 rows of up to 128 columns = 32 KB
+  __shared__ double tile[kGramRows * 128];
+  constexpr int kMaxPer = 16;                // R*R / 1024 <= 16 for R <= 128
+  double acc[kMaxPer];
+#pragma unroll
+  for (int e = 0; e < kMaxPer; ++e) acc[e] = 0.0;
+  for (int k0 = 0; k0 < rows; k0 += kGramRows) {
+    const int kn = min(kGramRows, rows - k0);
+    for (int i = threadIdx.x; i < kn * R; i += blockDim.x) tile[i] = A[static_cast<int64_t>(k0) * R + i];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kMaxPer; ++e) {
+      const int idx = threadIdx.x + e * 1024;
+      if (idx < R * R) {
+        const int i = idx / R, j = idx % R;
+        double t = 0.0;
+        for (int k = 0; k < kn; ++k) t += tile[k * R + i] * tile[k * R + j];
+        acc[e] += t;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int e = 0; e < kMaxPer; ++e) {
+    const int idx = threadIdx.x + e * 1024;
+    if (idx < R * R) G[idx] = acc[e];
+  }
 }
 
 // fit = 1 - ||T - T^|| / ||T|| after the t update of sweep `it`.
@@ -594,7 +659,7 @@ __global__ void k_absorb(double* __restrict__ L, int nl, int R, const double* __
 // ---------------------------------------------------------------------------
 
 struct AlsLayout {
-  size_t z, ypart, y, m, lpart, grams, lc, lct, lam, sumsq, scal, ctrl, total;
+  size_t z, ypart, y, uv, m, grams, lc, lct, lam, sumsq, scal, ctrl, total;
   int nsplit;
   int64_t cells_per_split;
   int sumsq_blocks;
@@ -604,17 +669,17 @@ bool als_layout(const glint_ndf_desc* d, int R, size_t elt, AlsLayout* L) {
   const int64_t ncells = static_cast<int64_t>(d->nu) * d->nv * d->nlevels;
   const int64_t NN = static_cast<int64_t>(d->nbins) * d->nbins;
   const int VEC = static_cast<int>(16 / elt);
-  const int64_t nuv = static_cast<int64_t>(d->nu) * d->nv;
   const int64_t kblocks = (NN + 64 * VEC - 1) / (64 * VEC);
   int64_t nsplit = 2048 / (kblocks > 0 ? kblocks : 1);
   if (nsplit < 1) nsplit = 1;
-  if (nsplit > (nuv + 7) / 8) nsplit = (nuv + 7) / 8;
+  if (nsplit > (ncells + 63) / 64) nsplit = (ncells + 63) / 64;
   if (nsplit < 1) nsplit = 1;
-  const int64_t ups = (nuv + nsplit - 1) / nsplit;
-  nsplit = (nuv + ups - 1) / ups;
+  int64_t cps = (ncells + nsplit - 1) / nsplit;
+  cps = (cps + 3) / 4 * 4;
+  nsplit = (ncells + cps - 1) / cps;
   L->nsplit = static_cast<int>(nsplit);
-  L->cells_per_split = ups;       // (u, v) pairs per split
-  L->sumsq_blocks = 1024;
+  L->cells_per_split = cps;
+  L->sumsq_blocks = static_cast<int>((ncells + 15) / 16);   // one partial per Z-pass wave (16*ROWT >= 16 cells)
   const int maxrows = std::max(std::max(d->nu, d->nv), std::max(d->nlevels, d->nbins));
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -625,8 +690,8 @@ bool als_layout(const glint_ndf_desc* d, int R, size_t elt, AlsLayout* L) {
   L->z = take(elt * ncells * R);
   L->ypart = take(elt * nsplit * NN * R);
   L->y = take(sizeof(double) * NN * R);
+  L->uv = take(elt * static_cast<size_t>(d->nu) * d->nv * R);
   L->m = take(sizeof(double) * maxrows * R);
-  L->lpart = take(sizeof(double) * static_cast<size_t>(d->nlevels) * d->nu * R);
   L->grams = take(sizeof(double) * 5 * R * R);
   L->lc = take(sizeof(double) * R * R);
   L->lct = take(sizeof(double) * R * R);
@@ -636,6 +701,23 @@ bool als_layout(const glint_ndf_desc* d, int R, size_t elt, AlsLayout* L) {
   L->ctrl = take(sizeof(int) * CTRL_N);
   L->total = off;
   return true;
+}
+
+template <typename TT>
+glint_status reduce_z(int mode, const TT* Z, int nu, int nv, int nl, int R, const double* const F[5],
+                      double* M, const int* ctrl, hipStream_t stream) {
+  const int rows = mode == 0 ? nu : (mode == 1 ? nv : nl);
+  hipLaunchKernelGGL(k_zero, dim3((rows * R + 255) / 256), dim3(256), 0, stream, M,
+                     static_cast<int64_t>(rows) * R, ctrl);
+  const dim3 grid(mode == 1 ? nv : nu, ((mode == 1 ? nu : nv) + kChunk - 1) / kChunk);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_reduce_z<TT, 0>), grid, dim3(256), 0, stream, Z, nu, nv, nl, R, F[0], F[1], F[2], M, ctrl);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_reduce_z<TT, 1>), grid, dim3(256), 0, stream, Z, nu, nv, nl, R, F[0], F[1], F[2], M, ctrl);
+  else
+    hipLaunchKernelGGL((k_reduce_z<TT, 2>), grid, dim3(256), 0, stream, Z, nu, nv, nl, R, F[0], F[1], F[2], M, ctrl);
+  GLINT_LAUNCHED("k_reduce_z");
+  return GLINT_OK;
 }
 
 template <typename TT, int R>
@@ -650,7 +732,6 @@ glint_status run_als(const glint_ndf_desc* d, const TT* T, int iters, double tol
   TT* Yp = reinterpret_cast<TT*>(ws + Lo.ypart);
   double* Y = reinterpret_cast<double*>(ws + Lo.y);
   double* Mb = reinterpret_cast<double*>(ws + Lo.m);
-  double* lpart = reinterpret_cast<double*>(ws + Lo.lpart);
   double* grams = reinterpret_cast<double*>(ws + Lo.grams);
   double* Lc = reinterpret_cast<double*>(ws + Lo.lc);
   double* LcT = reinterpret_cast<double*>(ws + Lo.lct);
@@ -661,14 +742,13 @@ glint_status run_als(const glint_ndf_desc* d, const TT* T, int iters, double tol
 
   constexpr int ROWT = R <= 64 ? 2 : 1;
   constexpr int PAD = sizeof(TT) == 4 ? kPad32 : kPad64;
-  const size_t z_lds = sizeof(TT) * R * (N + PAD);
+  const size_t z_lds = sizeof(TT) * R * (2 * N + PAD);
   const size_t chol_lds = sizeof(double) * (R * R + R);
+  TT* UVt = reinterpret_cast<TT*>(ws + Lo.uv);
 
   glint_clear_launch_error();
-  hipLaunchKernelGGL(k_sumsq<TT>, dim3(Lo.sumsq_blocks), dim3(256), 0, stream, T, ncells * NN, sumsq);
-  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, stream, sumsq, Lo.sumsq_blocks, scal, ctrl,
-                     scal + 1);
-  GLINT_LAUNCHED("k_sumsq");
+  hipLaunchKernelGGL(k_als_init, dim3(1), dim3(64), 0, stream, ctrl, scal + 1);
+  GLINT_LAUNCHED("k_als_init");
   const dim3 gblk(16, 16), ggrid((R + 15) / 16, (R + 15) / 16);
   for (int m = 0; m < 5; ++m)
     hipLaunchKernelGGL(k_gram, ggrid, gblk, 0, stream, F[m], rows[m], R, grams + m * R * R, ctrl);
@@ -678,12 +758,11 @@ glint_status run_als(const glint_ndf_desc* d, const TT* T, int iters, double tol
     hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), chol_lds, stream, grams, n, R, Lc, LcT, ctrl);
     GLINT_LAUNCHED("k_cholesky");
     const int rws = rows[n];
-    hipLaunchKernelGGL((k_solve<R>), dim3((rws + 3) / 4), dim3(256), 0, stream, Mb, rws, Lc, LcT, F[n], ctrl);
+    hipLaunchKernelGGL((k_solve<R>), dim3((rws + 15) / 16), dim3(1024), 0, stream, Mb, rws, Lc, LcT, F[n], ctrl);
     GLINT_LAUNCHED("k_solve");
-    hipLaunchKernelGGL(k_normalize, dim3((R + 63) / 64), dim3(64), 0, stream, F[n], rws, R, lam, ctrl);
-    GLINT_LAUNCHED("k_normalize");
-    hipLaunchKernelGGL(k_gram, ggrid, gblk, 0, stream, F[n], rws, R, grams + n * R * R, ctrl);
-    GLINT_LAUNCHED("k_gram");
+    hipLaunchKernelGGL(k_normalize_gram, dim3(1), dim3(1024), 0, stream, F[n], rws, R, lam,
+                       grams + n * R * R, ctrl);
+    GLINT_LAUNCHED("k_normalize_gram");
     return GLINT_OK;
   };
 
@@ -693,22 +772,21 @@ glint_status run_als(const glint_ndf_desc* d, const TT* T, int iters, double tol
   const unsigned yblocks = static_cast<unsigned>((NN + 64 * VEC - 1) / (64 * VEC));
   for (int it = 0; it < iters; ++it) {
     hipLaunchKernelGGL((k_mttkrp_z<TT, R, ROWT>), dim3(zblocks), dim3(256), z_lds, stream, T, ncells,
-                       N, F[3], F[4], Z, ctrl);
+                       N, F[3], F[4], Z, it == 0 ? sumsq : nullptr, ctrl);
     GLINT_LAUNCHED("k_mttkrp_z");
-    hipLaunchKernelGGL(k_reduce_zu<TT>, dim3(nu), dim3(256), 0, stream, Z, nv, nl, R, F[1], F[2], Mb, ctrl);
-    GLINT_LAUNCHED("k_reduce_zu");
-    glint_status st = update(0);
-    if (st != GLINT_OK) return st;
-    hipLaunchKernelGGL(k_reduce_zv<TT>, dim3(nv), dim3(256), 0, stream, Z, nu, nv, nl, R, F[0], F[2], Mb, ctrl);
-    GLINT_LAUNCHED("k_reduce_zv");
+    if (it == 0) {
+      hipLaunchKernelGGL(k_sum_norm, dim3(1), dim3(256), 0, stream, sumsq, static_cast<int>(zwaves), scal);
+      GLINT_LAUNCHED("k_sum_norm");
+    }
+    glint_status st = reduce_z<TT>(0, Z, nu, nv, nl, R, F, Mb, ctrl, stream);
+    if (st != GLINT_OK || (st = update(0)) != GLINT_OK) return st;
+    if ((st = reduce_z<TT>(1, Z, nu, nv, nl, R, F, Mb, ctrl, stream)) != GLINT_OK) return st;
     if ((st = update(1)) != GLINT_OK) return st;
-    hipLaunchKernelGGL(k_reduce_zl<TT>, dim3(nu, nl), dim3(256), 0, stream, Z, nu, nv, nl, R, F[0], F[1],
-                       lpart, ctrl);
-    hipLaunchKernelGGL(k_sum_rows, dim3((nl * R + 255) / 256), dim3(256), 0, stream, lpart, nu, nl, R, Mb, ctrl);
-    GLINT_LAUNCHED("k_reduce_zl");
+    if ((st = reduce_z<TT>(2, Z, nu, nv, nl, R, F, Mb, ctrl, stream)) != GLINT_OK) return st;
     if ((st = update(2)) != GLINT_OK) return st;
-    hipLaunchKernelGGL((k_mttkrp_y<TT, R>), dim3(yblocks, Lo.nsplit), dim3(256), 0, stream, T,
-                       static_cast<int64_t>(nu) * nv, nv, nl, N, F[0], F[1], F[2], Lo.cells_per_split, Yp, ctrl);
+    hipLaunchKernelGGL(k_uv_product<TT>, dim3(2048), dim3(256), 0, stream, F[0], F[1], nu, nv, R, UVt, ctrl);
+    hipLaunchKernelGGL((k_mttkrp_y<TT, R>), dim3(yblocks, Lo.nsplit), dim3(256), 0, stream, T, ncells, nl, N,
+                       UVt, F[2], Lo.cells_per_split, Yp, ctrl);
     GLINT_LAUNCHED("k_mttkrp_y");
     hipLaunchKernelGGL(k_reduce_splits<TT>, dim3(static_cast<unsigned>(std::min<int64_t>((NN * R + 255) / 256, 4096))),
                        dim3(256), 0, stream, Yp, Lo.nsplit, NN * R, Y, ctrl);
@@ -737,7 +815,6 @@ glint_status run_mttkrp(const glint_ndf_desc* d, const TT* T, int mode, const do
   TT* Z = reinterpret_cast<TT*>(ws + Lo.z);
   TT* Yp = reinterpret_cast<TT*>(ws + Lo.ypart);
   double* Y = reinterpret_cast<double*>(ws + Lo.y);
-  double* lpart = reinterpret_cast<double*>(ws + Lo.lpart);
   int* ctrl = reinterpret_cast<int*>(ws + Lo.ctrl);
   constexpr int ROWT = R <= 64 ? 2 : 1;
   constexpr int PAD = sizeof(TT) == 4 ? kPad32 : kPad64;
@@ -748,22 +825,16 @@ glint_status run_mttkrp(const glint_ndf_desc* d, const TT* T, int mode, const do
   if (mode <= 2) {
     const int64_t zwaves = (ncells + 16 * ROWT - 1) / (16 * ROWT);
     hipLaunchKernelGGL((k_mttkrp_z<TT, R, ROWT>), dim3(static_cast<unsigned>((zwaves + 3) / 4)), dim3(256),
-                       sizeof(TT) * R * (N + PAD), stream, T, ncells, N, F[3], F[4], Z, ctrl);
+                       sizeof(TT) * R * (2 * N + PAD), stream, T, ncells, N, F[3], F[4], Z, nullptr, ctrl);
     GLINT_LAUNCHED("k_mttkrp_z");
-    if (mode == 0) {
-      hipLaunchKernelGGL(k_reduce_zu<TT>, dim3(nu), dim3(256), 0, stream, Z, nv, nl, R, F[1], F[2], M, ctrl);
-    } else if (mode == 1) {
-      hipLaunchKernelGGL(k_reduce_zv<TT>, dim3(nv), dim3(256), 0, stream, Z, nu, nv, nl, R, F[0], F[2], M, ctrl);
-    } else {
-      hipLaunchKernelGGL(k_reduce_zl<TT>, dim3(nu, nl), dim3(256), 0, stream, Z, nu, nv, nl, R, F[0], F[1],
-                         lpart, ctrl);
-      hipLaunchKernelGGL(k_sum_rows, dim3((nl * R + 255) / 256), dim3(256), 0, stream, lpart, nu, nl, R, M, ctrl);
-    }
-    GLINT_LAUNCHED("k_reduce_z");
+    glint_status st = reduce_z<TT>(mode, Z, nu, nv, nl, R, F, M, ctrl, stream);
+    if (st != GLINT_OK) return st;
   } else {
     const unsigned yblocks = static_cast<unsigned>((NN + 64 * VEC - 1) / (64 * VEC));
-    hipLaunchKernelGGL((k_mttkrp_y<TT, R>), dim3(yblocks, Lo.nsplit), dim3(256), 0, stream, T,
-                       static_cast<int64_t>(nu) * nv, nv, nl, N, F[0], F[1], F[2], Lo.cells_per_split, Yp, ctrl);
+    TT* UVt = reinterpret_cast<TT*>(ws + Lo.uv);
+    hipLaunchKernelGGL(k_uv_product<TT>, dim3(2048), dim3(256), 0, stream, F[0], F[1], nu, nv, R, UVt, ctrl);
+    hipLaunchKernelGGL((k_mttkrp_y<TT, R>), dim3(yblocks, Lo.nsplit), dim3(256), 0, stream, T, ncells, nl, N,
+                       UVt, F[2], Lo.cells_per_split, Yp, ctrl);
     GLINT_LAUNCHED("k_mttkrp_y");
     hipLaunchKernelGGL(k_reduce_splits<TT>, dim3(static_cast<unsigned>(std::min<int64_t>((NN * R + 255) / 256, 4096))),
                        dim3(256), 0, stream, Yp, Lo.nsplit, NN * R, Y, ctrl);
@@ -794,7 +865,7 @@ glint_status check_als_args(const glint_ndf_desc* desc, const void* T, glint_dty
   if (static_cast<size_t>(max_lds) < sizeof(double) * (R * R + R))
     return glint_fail(GLINT_E_UNSUPPORTED, "rank %d Gram does not fit in LDS (%d bytes)", R, max_lds);
   const size_t pad = T_dtype == GLINT_F32 ? kPad32 : kPad64;
-  if (static_cast<size_t>(max_lds) < glint_dtype_size(T_dtype) * R * (desc->nbins + pad))
+  if (static_cast<size_t>(max_lds) < glint_dtype_size(T_dtype) * R * (2 * desc->nbins + pad))
     return glint_fail(GLINT_E_UNSUPPORTED, "rank %d x %d bins factor block does not fit in LDS", R,
                       desc->nbins);
   return GLINT_OK;

@@ -246,27 +246,32 @@ __global__ __launch_bounds__(256) void k_query_grouped(GroupedArgs a) {
   }
 }
 
-// Backward: per query, lane j adds its ranks' partial derivatives.  dL, dCS
-// and dCT (few rows, heavily shared) accumulate in LDS and are flushed once
-// per workgroup; dU and dV go straight to global atomics.
+// Backward.  Phase 1 (one lane per query, as in the forward) resolves the
+// record and its upstream gradient (0 for empty boxes and padding, so those
+// contribute exact zeros).  Phase 2: lane group g walks its LPQ consecutive
+// queries; lane j owns ranks [j*RPL, (j+1)*RPL).  dU, dV, dL accumulate in
+// registers while (u, v, l) repeat and are flushed with one atomic per rank
+// when they change (consecutive boxes of one shading point share them); the
+// summed-area-table gradients go to LDS accumulators (few rows, heavily
+// shared) and are flushed once per block.
 template <typename FT, typename CT, int R, int RPL>
-__global__ __launch_bounds__(256) void k_query_backward(QueryArgs a, const float* __restrict__ gout,
-                                                        float* __restrict__ dU,
-                                                        float* __restrict__ dV,
-                                                        float* __restrict__ dL,
-                                                        float* __restrict__ dCS,
-                                                        float* __restrict__ dCT) {
+__global__ __launch_bounds__(kQueryThreads) void k_query_backward(QueryArgs a, const float* __restrict__ gout,
+                                                                  float* __restrict__ dU,
+                                                                  float* __restrict__ dV,
+                                                                  float* __restrict__ dL,
+                                                                  float* __restrict__ dCS,
+                                                                  float* __restrict__ dCT) {
   constexpr int LPQ = R / RPL;
-  constexpr int QPW = 64 / LPQ;
   extern __shared__ __align__(16) float lds[];
   const int nl = a.nl, N1 = a.N + 1;
   float* Ls = lds;                  // decoded L (no scale)
   float* CSs = Ls + nl * R;
   float* CTs = CSs + N1 * R;
-  float* sc = CTs + N1 * R;         // [R]
+  float* sc = CTs + N1 * R;         // [R] folded scale
   float* gL = sc + R;               // [nl][R]
   float* gCS = gL + nl * R;         // [N1][R]
   float* gCT = gCS + N1 * R;        // [N1][R]
+  QueryRows* rows = reinterpret_cast<QueryRows*>(gCT + N1 * R);
   stage_table<FT>(Ls, static_cast<const FT*>(a.L), nl, R, nullptr);
   stage_table<CT>(CSs, static_cast<const CT*>(a.CS), N1, R, nullptr);
   stage_table<CT>(CTs, static_cast<const CT*>(a.CT), N1, R, nullptr);
@@ -280,42 +285,93 @@ __global__ __launch_bounds__(256) void k_query_backward(QueryArgs a, const float
   const int g = lane / LPQ;
   const int j = lane % LPQ;
   const int r0 = j * RPL;
+  float scr[RPL];
+#pragma unroll
+  for (int e = 0; e < RPL; ++e) scr[e] = sc[r0 + e];
+  QueryRows* wrows = rows + (threadIdx.x >> 6) * 64;
   const int64_t wave = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
-  for (int64_t base = wave * QPW; base < a.nq; base += nwaves * QPW) {
-    const int64_t qi = base + g;
-    if (qi >= a.nq) break;          // no cross-lane operations below
-    const int32_t* rec = a.q + qi * 7;
-    const int u = glint_wrap(rec[0], a.nu);
-    const int v = glint_wrap(rec[1], a.nv);
-    const int l = glint_clampi(rec[2], 0, nl - 1);
-    const int slo = glint_clampi(rec[3], 0, a.N), shi = glint_clampi(rec[4], 0, a.N);
-    const int tlo = glint_clampi(rec[5], 0, a.N), thi = glint_clampi(rec[6], 0, a.N);
-    if (!(slo < shi && tlo < thi)) continue;
-    const float gq = gout[qi];
-    float uu[RPL], vv[RPL];
-    load_row<FT, RPL>(U + static_cast<int64_t>(u) * R + r0, uu);
-    load_row<FT, RPL>(V + static_cast<int64_t>(v) * R + r0, vv);
+  // running (u, v, l) of this group and its register accumulators
+  int cu = -1, cv = -1, cl = -1;
+  float aU[RPL], aV[RPL], aL[RPL];
 #pragma unroll
-    for (int e = 0; e < RPL; ++e) {
-      const int r = r0 + e;
-      const float s = sc[r] * gq;
-      const float ll = Ls[l * R + r];
-      const float dS = CSs[shi * R + r] - CSs[slo * R + r];
-      const float dT = CTs[thi * R + r] - CTs[tlo * R + r];
-      const float st = dS * dT;
-      const float uv = uu[e] * vv[e];
-      atomicAdd(&dU[static_cast<int64_t>(u) * R + r], s * vv[e] * ll * st);
-      atomicAdd(&dV[static_cast<int64_t>(v) * R + r], s * uu[e] * ll * st);
-      atomicAdd(&gL[l * R + r], s * uv * st);
-      const float wS = s * uv * ll * dT;
-      atomicAdd(&gCS[shi * R + r], wS);
-      atomicAdd(&gCS[slo * R + r], -wS);
-      const float wT = s * uv * ll * dS;
-      atomicAdd(&gCT[thi * R + r], wT);
-      atomicAdd(&gCT[tlo * R + r], -wT);
+  for (int e = 0; e < RPL; ++e) aU[e] = aV[e] = aL[e] = 0.0f;
+  auto flush = [&]() {
+    if (cu >= 0) {
+#pragma unroll
+      for (int e = 0; e < RPL; ++e) {
+        if (aU[e] != 0.0f) atomicAdd(&dU[cu + r0 + e], aU[e]);
+        if (aV[e] != 0.0f) atomicAdd(&dV[cv + r0 + e], aV[e]);
+        if (aL[e] != 0.0f) atomicAdd(&gL[cl + r0 + e], aL[e]);
+        aU[e] = aV[e] = aL[e] = 0.0f;
+      }
     }
+  };
+  for (int64_t base = wave * 64; base < a.nq; base += nwaves * 64) {
+    {
+      const int64_t qi = base + lane;
+      const int64_t qc = qi < a.nq ? qi : a.nq - 1;
+      const int32_t* rec = a.q + qc * 7;
+      int f[7];
+#pragma unroll
+      for (int i = 0; i < 7; ++i) f[i] = rec[i];
+      const float gq = gout[qc];
+      const int u = glint_wrap(f[0], a.nu);
+      const int v = glint_wrap(f[1], a.nv);
+      const int l = glint_clampi(f[2], 0, nl - 1);
+      const int slo = glint_clampi(f[3], 0, a.N), shi = glint_clampi(f[4], 0, a.N);
+      const int tlo = glint_clampi(f[5], 0, a.N), thi = glint_clampi(f[6], 0, a.N);
+      const bool live = qi < a.nq && slo < shi && tlo < thi;
+      QueryRows r;
+      r.u = u * R;
+      r.v = v * R;
+      r.l = l * R;
+      r.sh = shi * R;
+      r.sl = slo * R;
+      r.th = thi * R;
+      r.tl = tlo * R;
+      r.pad = __float_as_int(live ? gq : 0.0f);
+      wrows[lane] = r;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    for (int jj = 0; jj < LPQ; ++jj) {
+      const QueryRows r = wrows[g * LPQ + jj];
+      const float gq = __int_as_float(r.pad);
+      if (gq == 0.0f) continue;
+      if (r.u != cu || r.v != cv || r.l != cl) {
+        flush();
+        cu = r.u; cv = r.v; cl = r.l;
+      }
+      float uu[RPL], vv[RPL], lr[RPL], sh[RPL], sl[RPL], th[RPL], tl[RPL];
+      load_row<FT, RPL>(U + r.u + r0, uu);
+      load_row<FT, RPL>(V + r.v + r0, vv);
+      lds_row<RPL>(Ls + r.l + r0, lr);
+      lds_row<RPL>(CSs + r.sh + r0, sh);
+      lds_row<RPL>(CSs + r.sl + r0, sl);
+      lds_row<RPL>(CTs + r.th + r0, th);
+      lds_row<RPL>(CTs + r.tl + r0, tl);
+#pragma unroll
+      for (int e = 0; e < RPL; ++e) {
+        const float s = scr[e] * gq;
+        const float dS = sh[e] - sl[e];
+        const float dT = th[e] - tl[e];
+        const float st = dS * dT;
+        const float uv = uu[e] * vv[e];
+        aU[e] += s * vv[e] * lr[e] * st;
+        aV[e] += s * uu[e] * lr[e] * st;
+        aL[e] += s * uv * st;
+        const float wS = s * uv * lr[e] * dT;
+        atomicAdd(&gCS[r.sh + r0 + e], wS);
+        atomicAdd(&gCS[r.sl + r0 + e], -wS);
+        const float wT = s * uv * lr[e] * dS;
+        atomicAdd(&gCT[r.th + r0 + e], wT);
+        atomicAdd(&gCT[r.tl + r0 + e], -wT);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
   }
+  flush();
   __syncthreads();
   for (int i = threadIdx.x; i < nl * R; i += blockDim.x)
     if (gL[i] != 0.0f) atomicAdd(&dL[i], gL[i]);
@@ -492,18 +548,19 @@ template <typename FT, typename CT, int R>
 glint_status launch_backward(const QueryArgs& a, const float* gout, float* dU, float* dV,
                              float* dL, float* dCS, float* dCT, hipStream_t stream) {
   constexpr int RPL = rpl_for<FT>() <= R ? rpl_for<FT>() : R;
-  const size_t lds = sizeof(float) * (2 * static_cast<size_t>(a.nl + 2 * (a.N + 1)) * R + R);
+  const size_t lds = sizeof(float) * (2 * static_cast<size_t>(a.nl + 2 * (a.N + 1)) * R + R) +
+                     sizeof(QueryRows) * (kQueryThreads / 64) * 64;
   if (static_cast<int>(lds) > g_max_lds)
     return glint_fail(GLINT_E_UNSUPPORTED, "backward needs %zu bytes of LDS (device max %d)", lds, g_max_lds);
-  constexpr int QPW = 64 / (R / RPL);
-  const int64_t waves_needed = (a.nq + QPW - 1) / QPW;
-  int64_t blocks = (waves_needed + 3) / 4;
-  const int64_t cap = static_cast<int64_t>(g_cu_count) * 4;
+  const int64_t waves_needed = (a.nq + 63) / 64;
+  constexpr int WPB = kQueryThreads / 64;
+  int64_t blocks = (waves_needed + WPB - 1) / WPB;
+  const int64_t cap = static_cast<int64_t>(g_cu_count) * 2;
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
   glint_clear_launch_error();
   hipLaunchKernelGGL((k_query_backward<FT, CT, R, RPL>), dim3(static_cast<unsigned>(blocks)),
-                     dim3(256), lds, stream, a, gout, dU, dV, dL, dCS, dCT);
+                     dim3(kQueryThreads), lds, stream, a, gout, dU, dV, dL, dCS, dCT);
   GLINT_LAUNCHED("k_query_backward");
   return GLINT_OK;
 }
