@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=10,
                     help="events-timed launches of the MTTKRP and query kernels")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 2 GiB device copy (read 2 GiB, write 2 GiB) after the "
+                         "steps, the reference for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE")
     return ap.parse_args()
 
 
@@ -232,6 +235,13 @@ def main():
     }
 
     log(f"kernels timed: mttkrp {mttkrp_ms:.3f} ms, query {query_ms:.3f} ms")
+    if args.copy_calibration:
+        src = torch.ones(1 << 29, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration done (2 GiB read, 2 GiB written)")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle samples)")
         res["cpu_baseline"], res["parity_sample"] = cpu_baseline(cfg, nxy_h, q_h, out, P, F, CS, CT,

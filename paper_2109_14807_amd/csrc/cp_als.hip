@@ -93,7 +93,7 @@ __global__ void k_ctrl_init(int* __restrict__ ctrl) {
 // loads VEC consecutive k of cell i; MFMA sub-step j takes k = k0 + kk*VEC + j.
 // ---------------------------------------------------------------------------
 
-template <typename TT, int R, int ROWT>
+template <typename TT, int R, int ROWT, int H>
 __global__ __launch_bounds__(256) void k_mttkrp_z(const TT* __restrict__ T, int64_t ncells, int N,
                                                   const double* __restrict__ S,
                                                   const double* __restrict__ Tf,
@@ -136,52 +136,68 @@ __global__ __launch_bounds__(256) void k_mttkrp_z(const TT* __restrict__ T, int6
   for (int rt = 0; rt < ROWT; ++rt) {
     int64_t cell = cell0 + 16 * rt + i16;
     if (cell >= ncells) cell = ncells - 1;     // rows past the end load a valid row, never stored
-    rowp[rt] = T + cell * NN + kk * VEC;
+    rowp[rt] = T + cell * NN + kk * VEC;   // + h*4*VEC for the second vector of a chunk
   }
   double ss = 0.0;                            // sum of squares of this lane's elements
   const bool own_rows = sumsq != nullptr;
 
-  // flat loop over 4*VEC-wide chunks of k = s*N + t; the next chunk's loads are
+  // flat loop over H*4*VEC-wide chunks of k = s*N + t: with H = 2 the four
+  // lanes of a row read one whole 128-byte line per chunk (two 16-byte
+  // vectors each, at kk*VEC and 4*VEC + kk*VEC); the next chunk's loads are
   // issued before this chunk's products
-  const int chunks_per_row = N / (4 * VEC);
+  constexpr int CW = H * 4 * VEC;            // k per chunk; N is a multiple
+  const int chunks_per_row = N / CW;
   const int nchunks = N * chunks_per_row;
-  vec_t nxt[ROWT];
+  vec_t nxt[ROWT][H];
 #pragma unroll
-  for (int rt = 0; rt < ROWT; ++rt) nxt[rt] = *reinterpret_cast<const vec_t*>(rowp[rt]);
+  for (int rt = 0; rt < ROWT; ++rt)
+#pragma unroll
+    for (int h = 0; h < H; ++h) nxt[rt][h] = *reinterpret_cast<const vec_t*>(rowp[rt] + h * 4 * VEC);
   for (int ch = 0; ch < nchunks; ++ch) {
     const int s = ch / chunks_per_row;
-    const int t0 = (ch - s * chunks_per_row) * 4 * VEC;
-    vec_t av[ROWT];
+    const int t0 = (ch - s * chunks_per_row) * CW;
+    vec_t av[ROWT][H];
 #pragma unroll
-    for (int rt = 0; rt < ROWT; ++rt) av[rt] = nxt[rt];
+    for (int rt = 0; rt < ROWT; ++rt)
+#pragma unroll
+      for (int h = 0; h < H; ++h) av[rt][h] = nxt[rt][h];
     if (ch + 1 < nchunks) {
       const int s1 = (ch + 1) / chunks_per_row;
-      const int64_t k1 = static_cast<int64_t>(s1) * N + (ch + 1 - s1 * chunks_per_row) * 4 * VEC;
+      const int64_t k1 = static_cast<int64_t>(s1) * N + (ch + 1 - s1 * chunks_per_row) * CW;
 #pragma unroll
-      for (int rt = 0; rt < ROWT; ++rt) nxt[rt] = *reinterpret_cast<const vec_t*>(rowp[rt] + k1);
+      for (int rt = 0; rt < ROWT; ++rt)
+#pragma unroll
+        for (int h = 0; h < H; ++h)
+          nxt[rt][h] = *reinterpret_cast<const vec_t*>(rowp[rt] + k1 + h * 4 * VEC);
     }
     if (own_rows) {
 #pragma unroll
       for (int rt = 0; rt < ROWT; ++rt)
         if (cell0 + 16 * rt + i16 < ncells)
 #pragma unroll
-          for (int j = 0; j < VEC; ++j) {
-            const double x = static_cast<double>(reinterpret_cast<const TT*>(&av[rt])[j]);
-            ss += x * x;
-          }
+          for (int h = 0; h < H; ++h)
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+              const double x = static_cast<double>(reinterpret_cast<const TT*>(&av[rt][h])[j]);
+              ss += x * x;
+            }
     }
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
       const TT sv = Ss[s * R + 16 * c + i16];
-      const vec_t tv = *reinterpret_cast<const vec_t*>(&TfT[(16 * c + i16) * ld + t0 + kk * VEC]);
-      const TT* tvp = reinterpret_cast<const TT*>(&tv);
 #pragma unroll
-      for (int j = 0; j < VEC; ++j) {
-        const TT b = sv * tvp[j];
+      for (int h = 0; h < H; ++h) {
+        const vec_t tv =
+            *reinterpret_cast<const vec_t*>(&TfT[(16 * c + i16) * ld + t0 + h * 4 * VEC + kk * VEC]);
+        const TT* tvp = reinterpret_cast<const TT*>(&tv);
 #pragma unroll
-        for (int rt = 0; rt < ROWT; ++rt) {
-          const TT a = reinterpret_cast<const TT*>(&av[rt])[j];
-          acc[rt][c] = M::run(a, b, acc[rt][c]);
+        for (int j = 0; j < VEC; ++j) {
+          const TT b = sv * tvp[j];
+#pragma unroll
+          for (int rt = 0; rt < ROWT; ++rt) {
+            const TT a = reinterpret_cast<const TT*>(&av[rt][h])[j];
+            acc[rt][c] = M::run(a, b, acc[rt][c]);
+          }
         }
       }
     }
@@ -225,8 +241,10 @@ __global__ void k_uv_product(const double* __restrict__ U, const double* __restr
   }
 }
 
+constexpr int kYWaves = 8;                   // waves per Y-pass block: adjacent k-slices of the same cells
+
 template <typename TT, int R>
-__global__ __launch_bounds__(256) void k_mttkrp_y(const TT* __restrict__ T, int64_t ncells, int nl,
+__global__ __launch_bounds__(64 * kYWaves) void k_mttkrp_y(const TT* __restrict__ T, int64_t ncells, int nl,
                                                   int N, const TT* __restrict__ UV,
                                                   const double* __restrict__ L,
                                                   int64_t cells_per_split, TT* __restrict__ Ypart,
@@ -245,7 +263,7 @@ __global__ __launch_bounds__(256) void k_mttkrp_y(const TT* __restrict__ T, int6
   const int kk = lane >> 4;
   const int w = threadIdx.x >> 6;
   const int64_t NN = static_cast<int64_t>(N) * N;
-  const int64_t kb = (static_cast<int64_t>(blockIdx.x) * 4 + w) * 16 * VEC;
+  const int64_t kb = (static_cast<int64_t>(blockIdx.x) * kYWaves + w) * 16 * VEC;
   if (kb >= NN) return;
   const int64_t c_begin = static_cast<int64_t>(blockIdx.y) * cells_per_split;
   int64_t c_end = c_begin + cells_per_split;
@@ -258,39 +276,60 @@ __global__ __launch_bounds__(256) void k_mttkrp_y(const TT* __restrict__ T, int6
     for (int c = 0; c < CT; ++c) acc[j][c] = acc_t{};
 
   const TT* tb = T + kb + i16 * VEC;
-  // this lane's cell c0 + kk as (uv, l), advanced by 4 cells per step
-  int64_t cell = c_begin + kk;
-  int64_t uv = cell / nl;
-  int l = static_cast<int>(cell - uv * nl);
-  auto load = [&](int64_t ce, int64_t uvv, vec_t& av, TT* uvr) {
-    const int64_t cc = ce < c_end ? ce : c_end - 1;
-    const int64_t uc = ce < c_end ? uvv : (c_end - 1) / nl;
+  // Two quads per step: lane group kk takes cells c0 + kk and c0 + 4 + kk,
+  // tracked as (uv, l) and advanced by 8 cells per step without division.
+  const int adv_uv = 8 / nl, adv_l = 8 - (8 / nl) * nl;
+  const int64_t last = c_end - 1;
+  const int64_t uv_last = last / nl;
+  int64_t cell[2] = {c_begin + kk, c_begin + 4 + kk};
+  int64_t uv[2];
+  int l[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    uv[h] = cell[h] / nl;
+    l[h] = static_cast<int>(cell[h] - uv[h] * nl);
+  }
+  auto load = [&](int h, vec_t& av, TT* uvr) {
+    const bool in = cell[h] < c_end;
+    const int64_t cc = in ? cell[h] : last;       // clamped rows are loaded, then zeroed
+    const int64_t uc = in ? uv[h] : uv_last;
     av = *reinterpret_cast<const vec_t*>(tb + cc * NN);
 #pragma unroll
     for (int c = 0; c < CT; ++c) uvr[c] = UV[uc * R + 16 * c + i16];
   };
-  vec_t av_n;
-  TT uv_n[CT];
-  load(cell, uv, av_n, uv_n);
-  for (int64_t c0 = c_begin; c0 < c_end; c0 += 4) {
-    const vec_t av = av_n;
-    TT bv[CT];
-    const bool ok = cell < c_end;
+  vec_t av_n[2];
+  TT uv_n[2][CT];
 #pragma unroll
-    for (int c = 0; c < CT; ++c) bv[c] = ok ? uv_n[c] * Lf[l * R + 16 * c + i16] : TT(0);
-    cell += 4;
-    l += 4;
-    while (l >= nl) {
-      l -= nl;
-      ++uv;
+  for (int h = 0; h < 2; ++h) load(h, av_n[h], uv_n[h]);
+  for (int64_t c0 = c_begin; c0 < c_end; c0 += 8) {
+    vec_t av[2];
+    TT bv[2][CT];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      av[h] = av_n[h];
+      const TT keep = cell[h] < c_end ? TT(1) : TT(0);
+      const TT* lrow = Lf + l[h] * R + i16;
+#pragma unroll
+      for (int c = 0; c < CT; ++c) bv[h][c] = uv_n[h][c] * lrow[16 * c] * keep;
+      cell[h] += 8;
+      l[h] += adv_l;
+      uv[h] += adv_uv;
+      const bool wrap = l[h] >= nl;
+      l[h] = wrap ? l[h] - nl : l[h];
+      uv[h] = wrap ? uv[h] + 1 : uv[h];
     }
-    if (c0 + 4 < c_end) load(cell, uv, av_n, uv_n);
+    if (c0 + 8 < c_end) {
 #pragma unroll
-    for (int j = 0; j < VEC; ++j) {
-      const TT a = reinterpret_cast<const TT*>(&av)[j];
-#pragma unroll
-      for (int c = 0; c < CT; ++c) acc[j][c] = M::run(a, bv[c], acc[j][c]);
+      for (int h = 0; h < 2; ++h) load(h, av_n[h], uv_n[h]);
     }
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int j = 0; j < VEC; ++j) {
+        const TT a = reinterpret_cast<const TT*>(&av[h])[j];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[j][c] = M::run(a, bv[h][c], acc[j][c]);
+      }
   }
   TT* out = Ypart + static_cast<int64_t>(blockIdx.y) * NN * R;
 #pragma unroll
@@ -669,13 +708,13 @@ bool als_layout(const glint_ndf_desc* d, int R, size_t elt, AlsLayout* L) {
   const int64_t ncells = static_cast<int64_t>(d->nu) * d->nv * d->nlevels;
   const int64_t NN = static_cast<int64_t>(d->nbins) * d->nbins;
   const int VEC = static_cast<int>(16 / elt);
-  const int64_t kblocks = (NN + 64 * VEC - 1) / (64 * VEC);
-  int64_t nsplit = 2048 / (kblocks > 0 ? kblocks : 1);
+  const int64_t kblocks = (NN + 16 * kYWaves * VEC - 1) / (16 * kYWaves * VEC);
+  int64_t nsplit = 1024 / (kblocks > 0 ? kblocks : 1);
   if (nsplit < 1) nsplit = 1;
   if (nsplit > (ncells + 63) / 64) nsplit = (ncells + 63) / 64;
   if (nsplit < 1) nsplit = 1;
   int64_t cps = (ncells + nsplit - 1) / nsplit;
-  cps = (cps + 3) / 4 * 4;
+  cps = (cps + 7) / 8 * 8;
   nsplit = (ncells + cps - 1) / cps;
   L->nsplit = static_cast<int>(nsplit);
   L->cells_per_split = cps;
@@ -769,10 +808,14 @@ glint_status run_als(const glint_ndf_desc* d, const TT* T, int iters, double tol
   const int64_t zwaves = (ncells + 16 * ROWT - 1) / (16 * ROWT);
   const unsigned zblocks = static_cast<unsigned>((zwaves + 3) / 4);
   const int VEC = 16 / sizeof(TT);
-  const unsigned yblocks = static_cast<unsigned>((NN + 64 * VEC - 1) / (64 * VEC));
+  const unsigned yblocks = static_cast<unsigned>((NN + 16 * kYWaves * VEC - 1) / (16 * kYWaves * VEC));
   for (int it = 0; it < iters; ++it) {
-    hipLaunchKernelGGL((k_mttkrp_z<TT, R, ROWT>), dim3(zblocks), dim3(256), z_lds, stream, T, ncells,
-                       N, F[3], F[4], Z, it == 0 ? sumsq : nullptr, ctrl);
+    if (N >= 8 * VEC)
+      hipLaunchKernelGGL((k_mttkrp_z<TT, R, ROWT, 2>), dim3(zblocks), dim3(256), z_lds, stream, T, ncells,
+                         N, F[3], F[4], Z, it == 0 ? sumsq : nullptr, ctrl);
+    else
+      hipLaunchKernelGGL((k_mttkrp_z<TT, R, ROWT, 1>), dim3(zblocks), dim3(256), z_lds, stream, T, ncells,
+                         N, F[3], F[4], Z, it == 0 ? sumsq : nullptr, ctrl);
     GLINT_LAUNCHED("k_mttkrp_z");
     if (it == 0) {
       hipLaunchKernelGGL(k_sum_norm, dim3(1), dim3(256), 0, stream, sumsq, static_cast<int>(zwaves), scal);
@@ -785,7 +828,7 @@ glint_status run_als(const glint_ndf_desc* d, const TT* T, int iters, double tol
     if ((st = reduce_z<TT>(2, Z, nu, nv, nl, R, F, Mb, ctrl, stream)) != GLINT_OK) return st;
     if ((st = update(2)) != GLINT_OK) return st;
     hipLaunchKernelGGL(k_uv_product<TT>, dim3(2048), dim3(256), 0, stream, F[0], F[1], nu, nv, R, UVt, ctrl);
-    hipLaunchKernelGGL((k_mttkrp_y<TT, R>), dim3(yblocks, Lo.nsplit), dim3(256), 0, stream, T, ncells, nl, N,
+    hipLaunchKernelGGL((k_mttkrp_y<TT, R>), dim3(yblocks, Lo.nsplit), dim3(64 * kYWaves), 0, stream, T, ncells, nl, N,
                        UVt, F[2], Lo.cells_per_split, Yp, ctrl);
     GLINT_LAUNCHED("k_mttkrp_y");
     hipLaunchKernelGGL(k_reduce_splits<TT>, dim3(static_cast<unsigned>(std::min<int64_t>((NN * R + 255) / 256, 4096))),
@@ -824,16 +867,20 @@ glint_status run_mttkrp(const glint_ndf_desc* d, const TT* T, int mode, const do
   GLINT_LAUNCHED("k_ctrl_init");
   if (mode <= 2) {
     const int64_t zwaves = (ncells + 16 * ROWT - 1) / (16 * ROWT);
-    hipLaunchKernelGGL((k_mttkrp_z<TT, R, ROWT>), dim3(static_cast<unsigned>((zwaves + 3) / 4)), dim3(256),
-                       sizeof(TT) * R * (2 * N + PAD), stream, T, ncells, N, F[3], F[4], Z, nullptr, ctrl);
+    if (N >= 8 * VEC)
+      hipLaunchKernelGGL((k_mttkrp_z<TT, R, ROWT, 2>), dim3(static_cast<unsigned>((zwaves + 3) / 4)), dim3(256),
+                         sizeof(TT) * R * (2 * N + PAD), stream, T, ncells, N, F[3], F[4], Z, nullptr, ctrl);
+    else
+      hipLaunchKernelGGL((k_mttkrp_z<TT, R, ROWT, 1>), dim3(static_cast<unsigned>((zwaves + 3) / 4)), dim3(256),
+                         sizeof(TT) * R * (2 * N + PAD), stream, T, ncells, N, F[3], F[4], Z, nullptr, ctrl);
     GLINT_LAUNCHED("k_mttkrp_z");
     glint_status st = reduce_z<TT>(mode, Z, nu, nv, nl, R, F, M, ctrl, stream);
     if (st != GLINT_OK) return st;
   } else {
-    const unsigned yblocks = static_cast<unsigned>((NN + 64 * VEC - 1) / (64 * VEC));
+    const unsigned yblocks = static_cast<unsigned>((NN + 16 * kYWaves * VEC - 1) / (16 * kYWaves * VEC));
     TT* UVt = reinterpret_cast<TT*>(ws + Lo.uv);
     hipLaunchKernelGGL(k_uv_product<TT>, dim3(2048), dim3(256), 0, stream, F[0], F[1], nu, nv, R, UVt, ctrl);
-    hipLaunchKernelGGL((k_mttkrp_y<TT, R>), dim3(yblocks, Lo.nsplit), dim3(256), 0, stream, T, ncells, nl, N,
+    hipLaunchKernelGGL((k_mttkrp_y<TT, R>), dim3(yblocks, Lo.nsplit), dim3(64 * kYWaves), 0, stream, T, ncells, nl, N,
                        UVt, F[2], Lo.cells_per_split, Yp, ctrl);
     GLINT_LAUNCHED("k_mttkrp_y");
     hipLaunchKernelGGL(k_reduce_splits<TT>, dim3(static_cast<unsigned>(std::min<int64_t>((NN * R + 255) / 256, 4096))),
