@@ -34,6 +34,27 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix
 FP64_MFMA_PEAK_TFLOPS = 78.6
 
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE on this workload,
+# scaled by the counters' reading for a plain 2 GiB copy (fetch x2.0, write x1.0);
+# see profiles/<kernel>_c2_hbm_traffic.md.  Valid only for the kernel source they
+# were taken with (sha1); otherwise traffic is reported as null.
+MEASURED_TRAFFIC = {
+    "k_mttkrp_y": ("paper_2109_14807_amd/csrc/cp_als.hip", "6bc43108b7361ad691fe0ed4aac5d1adfde6b3ae", 36600865606),
+    "k_mttkrp_z": ("paper_2109_14807_amd/csrc/cp_als.hip", "6bc43108b7361ad691fe0ed4aac5d1adfde6b3ae", 34933118562),
+    "k_query": ("paper_2109_14807_amd/csrc/query.hip", "8d39398c02180271b4eb751a57a7a66729819dc2", 535143394),
+}
+
+
+def measured_traffic(kernel):
+    import hashlib
+    src, sha, nbytes = MEASURED_TRAFFIC[kernel]
+    try:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            cur = hashlib.sha1(f.read()).hexdigest()
+    except OSError:
+        return None
+    return nbytes if cur == sha else None
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -175,26 +196,31 @@ def main():
     reps = args.kernel_reps
     e0 = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
     e1 = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
-    M = torch.empty((cfg.nu, R), dtype=torch.float64, device=dev)
-    for i in range(reps):
-        e0[i].record(stream)
-        L.glint_mttkrp(desc, T, R, 0, *F, M, ws_als)
-        e1[i].record(stream)
-    torch.cuda.synchronize()
-    mttkrp_ms = float(np.mean([e0[i].elapsed_time(e1[i]) for i in range(reps)]))
-    for i in range(reps):
-        e0[i].record(stream)
-        L.glint_query(fac, q, out)
-        e1[i].record(stream)
-    torch.cuda.synchronize()
-    query_ms = float(np.mean([e0[i].elapsed_time(e1[i]) for i in range(reps)]))
+
+    def timed(fn):
+        for i in range(reps):
+            e0[i].record(stream)
+            fn()
+            e1[i].record(stream)
+        torch.cuda.synchronize()
+        return float(np.mean([e0[i].elapsed_time(e1[i]) for i in range(reps)]))
+
+    M_u = torch.empty((cfg.nu, R), dtype=torch.float64, device=dev)
+    M_s = torch.empty((N, R), dtype=torch.float64, device=dev)
+    # mode s: U*V table + cell pass (k_mttkrp_y) + split reduction + (s) contraction
+    mttkrp_y_ms = timed(lambda: L.glint_mttkrp(desc, T, R, 3, *F, M_s, ws_als))
+    # mode u: (s,t) pass (k_mttkrp_z) + u reduction
+    mttkrp_z_ms = timed(lambda: L.glint_mttkrp(desc, T, R, 0, *F, M_u, ws_als))
+    query_ms = timed(lambda: L.glint_query(fac, q, out))
 
     ncells = cfg.nu * cfg.nv * nl
     t_elems = ncells * N * N
     mttkrp_flops = 2.0 * t_elems * R                 # one pass over T, 2R flops per element
-    mttkrp_tflops = mttkrp_flops / (mttkrp_ms * 1e-3) / 1e12
+    y_tflops = mttkrp_flops / (mttkrp_y_ms * 1e-3) / 1e12
+    z_tflops = mttkrp_flops / (mttkrp_z_ms * 1e-3) / 1e12
     q_bytes = nq * (7 * 4 + 4)                       # record in, value out
     q_gbs = q_bytes / (query_ms * 1e-3) / 1e9
+    mttkrp_ms = mttkrp_y_ms
 
     res = {
         "metric": "P-NDF range queries/sec + %HBM peak at stated rel. error vs brute-force NDF",
@@ -216,16 +242,23 @@ def main():
             "tensor": "FP32 34.4 GB", "query_tables": "FP32",
         },
         "roofline": {
-            "kernel": "k_mttkrp_z (glint_mttkrp mode u: (s,t) pass + u reduction)",
-            "bound": "mfma", "achieved": mttkrp_tflops, "peak": FP32_MFMA_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": mttkrp_tflops / FP32_MFMA_PEAK_TFLOPS, "traffic": None,
-            "per_launch": {"flops": mttkrp_flops, "ms": mttkrp_ms,
-                           "hbm_gbs_equiv": t_elems * 4 / (mttkrp_ms * 1e-3) / 1e9},
+            "kernel": "k_mttkrp_y, the ALS cell-contraction pass (timed as glint_mttkrp mode s: "
+                      "U*V table + k_mttkrp_y + split reduction + s contraction)",
+            "bound": "mfma", "achieved": y_tflops, "peak": FP32_MFMA_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": y_tflops / FP32_MFMA_PEAK_TFLOPS,
+            "traffic": measured_traffic("k_mttkrp_y"),
+            "per_launch": {"flops": mttkrp_flops, "ms": mttkrp_y_ms, "algorithmic_bytes": t_elems * 4,
+                           "launches_per_step": args.sweeps},
+        },
+        "mttkrp_z": {
+            "kernel": "k_mttkrp_z, the ALS (s,t)-contraction pass (timed as glint_mttkrp mode u)",
+            "ms": mttkrp_z_ms, "achieved_tflops": z_tflops, "frac": z_tflops / FP32_MFMA_PEAK_TFLOPS,
+            "traffic": measured_traffic("k_mttkrp_z"), "launches_per_step": args.sweeps,
         },
         "query_kernel": {
             "kernel": "k_query<float,float,64,4>", "ms": query_ms, "queries_per_s": nq / (query_ms * 1e-3),
             "roofline": {"bound": "hbm", "achieved": q_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": q_gbs / HBM_PEAK_GBS, "traffic": None,
+                         "frac": q_gbs / HBM_PEAK_GBS, "traffic": measured_traffic("k_query"),
                          "algorithmic_bytes_per_query": 32},
         },
         "stages_ms": stage_ms,
@@ -234,7 +267,8 @@ def main():
         "error_vs_bruteforce": ebf,
     }
 
-    log(f"kernels timed: mttkrp {mttkrp_ms:.3f} ms, query {query_ms:.3f} ms")
+    log(f"kernels timed: mttkrp cell pass {mttkrp_y_ms:.3f} ms, (s,t) pass {mttkrp_z_ms:.3f} ms, "
+        f"query {query_ms:.3f} ms")
     if args.copy_calibration:
         src = torch.ones(1 << 29, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
