@@ -255,8 +255,11 @@ __global__ __launch_bounds__(64 * kYWaves) void k_mttkrp_y(const TT* __restrict_
   typedef typename std::conditional<sizeof(TT) == 4, float4, double2>::type vec_t;
   constexpr int VEC = 16 / sizeof(TT);
   constexpr int CT = R / 16;
-  __shared__ TT Lf[16 * R];                 // nl <= 16
-  for (int i = threadIdx.x; i < nl * R; i += blockDim.x) Lf[i] = static_cast<TT>(L[i]);
+  // L rows padded by 16 elements: the four lane groups usually read four
+  // consecutive levels, which then start on different LDS banks
+  constexpr int LD = R + 16;
+  __shared__ TT Lf[16 * LD];                // nl <= 16
+  for (int i = threadIdx.x; i < nl * R; i += blockDim.x) Lf[(i / R) * LD + i % R] = static_cast<TT>(L[i]);
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int i16 = lane & 15;
@@ -308,7 +311,7 @@ __global__ __launch_bounds__(64 * kYWaves) void k_mttkrp_y(const TT* __restrict_
     for (int h = 0; h < 2; ++h) {
       av[h] = av_n[h];
       const TT keep = cell[h] < c_end ? TT(1) : TT(0);
-      const TT* lrow = Lf + l[h] * R + i16;
+      const TT* lrow = Lf + l[h] * LD + i16;
 #pragma unroll
       for (int c = 0; c < CT; ++c) bv[h][c] = uv_n[h][c] * lrow[16 * c] * keep;
       cell[h] += 8;

@@ -103,18 +103,71 @@ __device__ __forceinline__ void lds_row(const float* p, float* out) {
   }
 }
 
+// Summed-area tables stay in LDS in BF16 when stored in BF16 (half the LDS
+// bytes per gathered row; decoding is exact), otherwise as FP32.
+template <typename CT>
+struct LdsCum {
+  typedef float type;
+};
+template <>
+struct LdsCum<uint16_t> {
+  typedef uint16_t type;
+};
+
+template <typename CT, typename LT>
+__device__ void stage_cum(LT* __restrict__ dst, const CT* __restrict__ src, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    if constexpr (std::is_same<LT, uint16_t>::value) dst[i] = src[i];
+    else dst[i] = dec<CT>(src[i]);
+  }
+}
+
+// RPL consecutive values of an LDS row (16-byte aligned for RPL*elt >= 16) as FP32.
+template <typename LT, int RPL>
+__device__ __forceinline__ void lds_cum_row(const LT* p, float* out) {
+  if constexpr (std::is_same<LT, float>::value) {
+    lds_row<RPL>(p, out);
+  } else {
+    static_assert(RPL % 2 == 0, "bf16 pairs");
+    if constexpr (RPL >= 8) {
+#pragma unroll
+      for (int i = 0; i < RPL / 8; ++i) {
+        const uint4 w = reinterpret_cast<const uint4*>(p)[i];
+        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          out[8 * i + 2 * k] = __uint_as_float(ws[k] << 16);
+          out[8 * i + 2 * k + 1] = __uint_as_float(ws[k] & 0xffff0000u);
+        }
+      }
+    } else if constexpr (RPL == 4) {
+      const uint2 w = *reinterpret_cast<const uint2*>(p);
+      out[0] = __uint_as_float(w.x << 16);
+      out[1] = __uint_as_float(w.x & 0xffff0000u);
+      out[2] = __uint_as_float(w.y << 16);
+      out[3] = __uint_as_float(w.y & 0xffff0000u);
+    } else {
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) out[i] = glint_bf16_to_f32(p[i]);
+    }
+  }
+}
+
 template <typename FT, typename CT, int R, int RPL>
 __global__ __launch_bounds__(kQueryThreads) void k_query(QueryArgs a) {
   constexpr int LPQ = R / RPL;           // lanes per query
   static_assert(LPQ >= 1 && LPQ <= 64, "lanes per query");
+  typedef typename LdsCum<CT>::type LT;
   extern __shared__ __align__(16) float lds[];
   float* Ls = lds;
-  float* CSs = Ls + a.nl * R;
-  float* CTs = CSs + (a.N + 1) * R;
-  QueryRows* rows = reinterpret_cast<QueryRows*>(CTs + (a.N + 1) * R);   // [waves][64]
+  LT* CSs = reinterpret_cast<LT*>(Ls + a.nl * R);
+  LT* CTs = CSs + (a.N + 1) * R;
+  QueryRows* rows = reinterpret_cast<QueryRows*>(
+      reinterpret_cast<unsigned char*>(lds) +
+      glint_round_up(sizeof(float) * a.nl * R + 2 * sizeof(LT) * (a.N + 1) * R, 16));   // [waves][64]
   stage_table<FT>(Ls, static_cast<const FT*>(a.L), a.nl, R, &a.scale);
-  stage_table<CT>(CSs, static_cast<const CT*>(a.CS), a.N + 1, R, nullptr);
-  stage_table<CT>(CTs, static_cast<const CT*>(a.CT), a.N + 1, R, nullptr);
+  stage_cum<CT, LT>(CSs, static_cast<const CT*>(a.CS), (a.N + 1) * R);
+  stage_cum<CT, LT>(CTs, static_cast<const CT*>(a.CT), (a.N + 1) * R);
   __syncthreads();
 
   const FT* __restrict__ U = static_cast<const FT*>(a.U);
@@ -123,7 +176,11 @@ __global__ __launch_bounds__(kQueryThreads) void k_query(QueryArgs a) {
   const int g = lane / LPQ;
   const int j = lane % LPQ;
   const int r0 = j * RPL;
-  QueryRows* wrows = rows + (threadIdx.x >> 6) * 64;
+  // record slots: query g*LPQ + jj sits at g*(LPQ+1) + jj, so the groups' slots
+  // do not share LDS banks when read back
+  constexpr int kSlots = 64 + 64 / LPQ;
+  QueryRows* wrows = rows + (threadIdx.x >> 6) * kSlots;
+  const int my_slot = lane + lane / LPQ;
   const int64_t wave = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
   for (int64_t base = wave * 64; base < a.nq; base += nwaves * 64) {
@@ -150,26 +207,36 @@ __global__ __launch_bounds__(kQueryThreads) void k_query(QueryArgs a) {
       r.th = thi * R;
       r.tl = tlo * R;
       r.pad = 0;
-      wrows[lane] = r;
+      wrows[my_slot] = r;
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    // phase 2: group g serves queries g*LPQ .. g*LPQ + LPQ - 1; lane j keeps query g*LPQ + j
+    // phase 2: group g serves queries g*LPQ .. g*LPQ + LPQ - 1; lane j keeps query
+    // g*LPQ + j.  The footprint product W = U*V*L is reused while consecutive
+    // queries share (u, v, l) (several angular boxes of one shading point).
     float res = 0.0f;
-#pragma unroll 4
+    int pu = -1, pv = -1, pl = -1;
+    float W[RPL];
+#pragma unroll 2
     for (int jj = 0; jj < LPQ; ++jj) {
-      const QueryRows r = wrows[g * LPQ + jj];
-      float uu[RPL], vv[RPL], lr[RPL], sh[RPL], sl[RPL], th[RPL], tl[RPL];
-      load_row<FT, RPL>(U + r.u + r0, uu);
-      load_row<FT, RPL>(V + r.v + r0, vv);
-      lds_row<RPL>(Ls + r.l + r0, lr);
-      lds_row<RPL>(CSs + r.sh + r0, sh);
-      lds_row<RPL>(CSs + r.sl + r0, sl);
-      lds_row<RPL>(CTs + r.th + r0, th);
-      lds_row<RPL>(CTs + r.tl + r0, tl);
+      const QueryRows r = wrows[g * (LPQ + 1) + jj];
+      if (r.u != pu || r.v != pv || r.l != pl) {
+        float uu[RPL], vv[RPL], lr[RPL];
+        load_row<FT, RPL>(U + r.u + r0, uu);
+        load_row<FT, RPL>(V + r.v + r0, vv);
+        lds_row<RPL>(Ls + r.l + r0, lr);
+#pragma unroll
+        for (int e = 0; e < RPL; ++e) W[e] = uu[e] * vv[e] * lr[e];
+        pu = r.u; pv = r.v; pl = r.l;
+      }
+      float sh[RPL], sl[RPL], th[RPL], tl[RPL];
+      lds_cum_row<LT, RPL>(CSs + r.sh + r0, sh);
+      lds_cum_row<LT, RPL>(CSs + r.sl + r0, sl);
+      lds_cum_row<LT, RPL>(CTs + r.th + r0, th);
+      lds_cum_row<LT, RPL>(CTs + r.tl + r0, tl);
       float acc = 0.0f;
 #pragma unroll
-      for (int e = 0; e < RPL; ++e) acc += uu[e] * vv[e] * lr[e] * (sh[e] - sl[e]) * (th[e] - tl[e]);
+      for (int e = 0; e < RPL; ++e) acc += W[e] * (sh[e] - sl[e]) * (th[e] - tl[e]);
       acc = glint_group_sum<LPQ>(acc);
       res = (j == jj) ? acc : res;
     }
@@ -193,17 +260,25 @@ struct GroupedArgs {
   float* out;
 };
 
+// Grouped query: lane i of a wave resolves shading point base + i to row
+// offsets; lane group g then takes points g*LPQ .. g*LPQ + LPQ - 1 one by one,
+// forms W = U*V*L once per point and walks its K boxes, only the summed-area
+// rows changing per box.  Lane j keeps the result of box b with b % LPQ == j,
+// so LPQ consecutive results leave as one contiguous store.
 template <typename FT, typename CT, int R, int RPL>
-__global__ __launch_bounds__(256) void k_query_grouped(GroupedArgs a) {
+__global__ __launch_bounds__(kQueryThreads) void k_query_grouped(GroupedArgs a) {
   constexpr int LPQ = R / RPL;
-  constexpr int QPW = 64 / LPQ;
+  typedef typename LdsCum<CT>::type LT;
   extern __shared__ __align__(16) float lds[];
   float* Ls = lds;
-  float* CSs = Ls + a.nl * R;
-  float* CTs = CSs + (a.N + 1) * R;
+  LT* CSs = reinterpret_cast<LT*>(Ls + a.nl * R);
+  LT* CTs = CSs + (a.N + 1) * R;
+  int4* pts = reinterpret_cast<int4*>(
+      reinterpret_cast<unsigned char*>(lds) +
+      glint_round_up(sizeof(float) * a.nl * R + 2 * sizeof(LT) * (a.N + 1) * R, 16));   // [waves][64]
   stage_table<FT>(Ls, static_cast<const FT*>(a.L), a.nl, R, &a.scale);
-  stage_table<CT>(CSs, static_cast<const CT*>(a.CS), a.N + 1, R, nullptr);
-  stage_table<CT>(CTs, static_cast<const CT*>(a.CT), a.N + 1, R, nullptr);
+  stage_cum<CT, LT>(CSs, static_cast<const CT*>(a.CS), (a.N + 1) * R);
+  stage_cum<CT, LT>(CTs, static_cast<const CT*>(a.CT), (a.N + 1) * R);
   __syncthreads();
 
   const FT* __restrict__ U = static_cast<const FT*>(a.U);
@@ -212,37 +287,59 @@ __global__ __launch_bounds__(256) void k_query_grouped(GroupedArgs a) {
   const int g = lane / LPQ;
   const int j = lane % LPQ;
   const int r0 = j * RPL;
+  const int K = a.K;
+  int4* wpts = pts + (threadIdx.x >> 6) * 64;
   const int64_t wave = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
-  for (int64_t base = wave * QPW; base < a.npts; base += nwaves * QPW) {
-    const int64_t pi = base + g;
-    const bool valid = pi < a.npts;
-    const int64_t pc = valid ? pi : a.npts - 1;
-    const int32_t* rec = a.uvl + pc * 3;
-    const int u = glint_wrap(rec[0], a.nu);
-    const int v = glint_wrap(rec[1], a.nv);
-    const int l = glint_clampi(rec[2], 0, a.nl - 1);
-    float w[RPL], vv[RPL];
-    load_row<FT, RPL>(U + static_cast<int64_t>(u) * R + r0, w);
-    load_row<FT, RPL>(V + static_cast<int64_t>(v) * R + r0, vv);
-    const float* lr = Ls + l * R + r0;
-#pragma unroll
-    for (int e = 0; e < RPL; ++e) w[e] = w[e] * vv[e] * lr[e];
-    const int4* bx = reinterpret_cast<const int4*>(a.boxes) + pc * a.K;
-    for (int b = 0; b < a.K; ++b) {
-      const int4 box = bx[b];
-      const int slo = glint_clampi(box.x, 0, a.N), shi = glint_clampi(box.y, 0, a.N);
-      const int tlo = glint_clampi(box.z, 0, a.N), thi = glint_clampi(box.w, 0, a.N);
-      const float* sh = CSs + shi * R + r0;
-      const float* sl = CSs + slo * R + r0;
-      const float* th = CTs + thi * R + r0;
-      const float* tl = CTs + tlo * R + r0;
-      float acc = 0.0f;
-#pragma unroll
-      for (int e = 0; e < RPL; ++e) acc += w[e] * (sh[e] - sl[e]) * (th[e] - tl[e]);
-      acc = glint_group_sum<LPQ>(acc);
-      if (valid && j == 0) a.out[pi * a.K + b] = (slo < shi && tlo < thi) ? acc : 0.0f;
+  for (int64_t base = wave * 64; base < a.npts; base += nwaves * 64) {
+    {
+      const int64_t pi = base + lane;
+      const int64_t pc = pi < a.npts ? pi : a.npts - 1;
+      const int32_t* rec = a.uvl + pc * 3;
+      const int f0 = rec[0], f1 = rec[1], f2 = rec[2];
+      wpts[lane] = make_int4(glint_wrap(f0, a.nu) * R, glint_wrap(f1, a.nv) * R,
+                             glint_clampi(f2, 0, a.nl - 1) * R, 0);
     }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    for (int jj = 0; jj < LPQ; ++jj) {
+      const int64_t pi = base + g * LPQ + jj;
+      if (pi >= a.npts) break;                // group-uniform: no cross-group operations follow
+      const int4 pr = wpts[g * LPQ + jj];
+      float W[RPL];
+      {
+        float uu[RPL], vv[RPL], lr[RPL];
+        load_row<FT, RPL>(U + pr.x + r0, uu);
+        load_row<FT, RPL>(V + pr.y + r0, vv);
+        lds_row<RPL>(Ls + pr.z + r0, lr);
+#pragma unroll
+        for (int e = 0; e < RPL; ++e) W[e] = uu[e] * vv[e] * lr[e];
+      }
+      const int4* bx = reinterpret_cast<const int4*>(a.boxes) + pi * K;
+      float* out = a.out + pi * K;
+      float res = 0.0f;
+      for (int b = 0; b < K; ++b) {
+        const int4 box = bx[b];
+        const int slo = glint_clampi(box.x, 0, a.N), shi0 = glint_clampi(box.y, 0, a.N);
+        const int tlo = glint_clampi(box.z, 0, a.N), thi = glint_clampi(box.w, 0, a.N);
+        const int shi = (slo < shi0 && tlo < thi) ? shi0 : slo;     // empty box: exact zeros
+        float sh[RPL], sl[RPL], th[RPL], tl[RPL];
+        lds_cum_row<LT, RPL>(CSs + shi * R + r0, sh);
+        lds_cum_row<LT, RPL>(CSs + slo * R + r0, sl);
+        lds_cum_row<LT, RPL>(CTs + thi * R + r0, th);
+        lds_cum_row<LT, RPL>(CTs + tlo * R + r0, tl);
+        float acc = 0.0f;
+#pragma unroll
+        for (int e = 0; e < RPL; ++e) acc += W[e] * (sh[e] - sl[e]) * (th[e] - tl[e]);
+        acc = glint_group_sum<LPQ>(acc);
+        const int bj = b % LPQ;
+        res = (j == bj) ? acc : res;
+        if (bj == LPQ - 1 || b == K - 1) {
+          if (j <= bj) out[b - bj + j] = res;
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -505,11 +602,16 @@ constexpr int rpl_for() {
   return 16 / static_cast<int>(sizeof(FT));
 }
 
+template <typename CT>
+size_t cum_lds_bytes(int N1, int R) {
+  return 2 * sizeof(typename LdsCum<CT>::type) * static_cast<size_t>(N1) * R;
+}
+
 template <typename FT, typename CT, int R>
 glint_status launch_query(const QueryArgs& a, hipStream_t stream) {
   constexpr int RPL = rpl_for<FT>() <= R ? rpl_for<FT>() : R;
-  const size_t lds = sizeof(float) * static_cast<size_t>(a.nl + 2 * (a.N + 1)) * R +
-                     sizeof(QueryRows) * (kQueryThreads / 64) * 64;
+  const size_t lds = glint_round_up(sizeof(float) * static_cast<size_t>(a.nl) * R + cum_lds_bytes<CT>(a.N + 1, R), 16) +
+                     sizeof(QueryRows) * (kQueryThreads / 64) * (64 + 64 / (R / RPL));
   if (static_cast<int>(lds) > g_max_lds)
     return glint_fail(GLINT_E_UNSUPPORTED, "tables need %zu bytes of LDS (device max %d)", lds, g_max_lds);
   const int64_t waves_needed = (a.nq + 63) / 64;
@@ -528,18 +630,19 @@ glint_status launch_query(const QueryArgs& a, hipStream_t stream) {
 template <typename FT, typename CT, int R>
 glint_status launch_grouped(const GroupedArgs& a, hipStream_t stream) {
   constexpr int RPL = rpl_for<FT>() <= R ? rpl_for<FT>() : R;
-  const size_t lds = sizeof(float) * static_cast<size_t>(a.nl + 2 * (a.N + 1)) * R;
+  const size_t lds = glint_round_up(sizeof(float) * static_cast<size_t>(a.nl) * R + cum_lds_bytes<CT>(a.N + 1, R), 16) +
+                     sizeof(int4) * (kQueryThreads / 64) * 64;
   if (static_cast<int>(lds) > g_max_lds)
     return glint_fail(GLINT_E_UNSUPPORTED, "tables need %zu bytes of LDS (device max %d)", lds, g_max_lds);
-  constexpr int QPW = 64 / (R / RPL);
-  const int64_t waves_needed = (a.npts + QPW - 1) / QPW;
-  int64_t blocks = (waves_needed + 3) / 4;
-  const int64_t cap = static_cast<int64_t>(g_cu_count) * 8;
+  const int64_t waves_needed = (a.npts + 63) / 64;
+  constexpr int WPB = kQueryThreads / 64;
+  int64_t blocks = (waves_needed + WPB - 1) / WPB;
+  const int64_t cap = static_cast<int64_t>(g_cu_count) * 4;
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
   glint_clear_launch_error();
   hipLaunchKernelGGL((k_query_grouped<FT, CT, R, RPL>), dim3(static_cast<unsigned>(blocks)),
-                     dim3(256), lds, stream, a);
+                     dim3(kQueryThreads), lds, stream, a);
   GLINT_LAUNCHED("k_query_grouped");
   return GLINT_OK;
 }
