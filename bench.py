@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=10,
                     help="events-timed launches of the MTTKRP and query kernels")
+    ap.add_argument("--refine-steps", type=int, default=100,
+                    help="Adam steps of the BF16 refinement report (0 to skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 2 GiB device copy (read 2 GiB, write 2 GiB) after the "
                          "steps, the reference for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE")
@@ -269,6 +271,9 @@ def main():
 
     log(f"kernels timed: mttkrp cell pass {mttkrp_y_ms:.3f} ms, (s,t) pass {mttkrp_z_ms:.3f} ms, "
         f"query {query_ms:.3f} ms")
+    if args.refine_steps > 0:
+        res["refinement"] = refine_report(cfg, nxy_h, desc, F, q, q_bf, args.refine_steps, timed)
+        log(f"refinement report done: {res['refinement']}")
     if args.copy_calibration:
         src = torch.ones(1 << 29, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -281,6 +286,54 @@ def main():
         res["cpu_baseline"], res["parity_sample"] = cpu_baseline(cfg, nxy_h, q_h, out, P, F, CS, CT,
                                                                   args.sweeps, nq)
     print(json.dumps(res), flush=True)
+
+
+def refine_report(cfg, nxy_h, desc, F, q, q_bf, steps, timed):
+    """BF16 straight-through refinement of this step's ALS factors against the
+    brute-force range integrals of the batch, evaluated on a held-out batch:
+    error against brute force and query throughput, plain FP32 vs refined BF16."""
+    import torch
+
+    import gen
+    import paper_2109_14807_amd as G
+    from paper_2109_14807_amd import _lib as L
+
+    dev = q.device
+    q_ev_h = gen.make_queries(cfg, nxy_h, nq=1 << 21, seed=gen.query_seed(cfg) + 7, shuffle=True)
+    q_ev = torch.tensor(q_ev_h, device=dev)
+    bins, mass = G.texel_bins(torch.tensor(nxy_h, device=dev), desc)
+    bf_ev = torch.empty(q_ev.shape[0], dtype=torch.float64, device=dev)
+    L.glint_range_bruteforce(desc, bins, mass, q_ev, bf_ev)
+
+    def ebf(tables):
+        out = G.query(tables, q_ev)
+        return float((torch.linalg.vector_norm(out.double() - bf_ev) / torch.linalg.vector_norm(bf_ev)).item())
+
+    masters = [f.float() for f in F]
+    plain = G.make_tables(*masters, dtype="f32", cum_dtype="f32")
+    rms = float(torch.sqrt(torch.mean(torch.cat([m.flatten() for m in masters]) ** 2)).item())
+    lr = 1e-3 * rms
+    t0 = time.perf_counter()
+    refined, losses = G.refine(*masters, q, q_bf, steps=steps, lr=lr, dtype="bf16")
+    torch.cuda.synchronize()
+    t_ref = time.perf_counter() - t0
+    bf16 = G.make_tables(*refined, dtype="bf16", cum_dtype="bf16")
+    out = torch.empty(q.shape[0], dtype=torch.float32, device=dev)
+    f_plain, f_bf16 = plain.factors(), bf16.factors()
+    ms_plain = timed(lambda: L.glint_query(f_plain, q, out))
+    ms_bf16 = timed(lambda: L.glint_query(f_bf16, q, out))
+    e_plain, e_bf16 = ebf(plain), ebf(bf16)
+    ls = losses.cpu().numpy()
+    return {
+        "adam_steps": steps, "lr": lr, "seconds": t_ref,
+        "train_loss_first_last": [float(ls[0]), float(ls[-1])],
+        "heldout_queries": int(q_ev.shape[0]),
+        "error_vs_bruteforce_plain_f32": e_plain,
+        "error_vs_bruteforce_refined_bf16": e_bf16,
+        "query_ms_plain_f32": ms_plain, "query_ms_refined_bf16": ms_bf16,
+        "speedup_bf16_over_f32": ms_plain / ms_bf16,
+        "equal_or_lower_error": bool(e_bf16 <= e_plain),
+    }
 
 
 def cpu_baseline(cfg, nxy_h, q_h, out_dev, P, F, CS, CT, sweeps, nq):
