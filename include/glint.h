@@ -172,6 +172,38 @@ glint_status glint_mttkrp(const glint_ndf_desc* desc, const void* T, glint_dtype
                           const double* L, const double* S, const double* Tf, double* M,
                           void* workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* Texel-space forms of the two calls above, for maps whose tensor T does not
+ * fit in memory.  T (Sec. 4.1, Eq. geom with the box footprints of
+ * Sec. 4.3) is the footprint average of per-texel outer products of the s-
+ * and t-bin masses, so each MTTKRP is evaluated from the per-texel bin
+ * windows of glint_texel_bins and window sums of U and V over the footprint
+ * pyramid; T is never formed.  The results equal those of glint_mttkrp /
+ * glint_cp_als on the materialised FP64 T up to FP64 rounding order.
+ * nxy: float [nu][nv][2] normal map (as for glint_build_tensor).  All
+ * arithmetic FP64.  R in {16, 32, 64, 128, 256}; any valid desc.
+ * Workspace: glint_cp_als_texel_workspace bytes, 256-byte aligned; it holds
+ * three FP64 [nu*nv][R] texel arrays, so it grows with the map, not with
+ * the tensor. */
+size_t glint_cp_als_texel_workspace(const glint_ndf_desc* desc, int32_t R);
+
+/* Texel-space MTTKRP of one mode (0 u, 1 v, 2 l, 3 s, 4 t); M FP64
+ * [rows of the mode][R]; factors FP64 [rows][R]. */
+glint_status glint_mttkrp_texel(const glint_ndf_desc* desc, const float* nxy, int32_t R,
+                                int32_t mode, const double* U, const double* V,
+                                const double* L, const double* S, const double* Tf,
+                                double* M, void* workspace, size_t workspace_bytes,
+                                hipStream_t stream);
+
+/* Texel-space CP-ALS: same sweep order, update rule, breakdown rule, factor
+ * normalisation and outputs as glint_cp_als.  ||T||^2 is not computable
+ * without T, so the caller supplies normT2 (host double); if normT2 <= 0 the
+ * fit history is NaN and tol must be 0. */
+glint_status glint_cp_als_texel(const glint_ndf_desc* desc, const float* nxy, int32_t R,
+                                int32_t iters, double tol, double normT2,
+                                double* U, double* V, double* L, double* S, double* Tf,
+                                double* fit_hist, int32_t* info,
+                                void* workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* ---- step 4: summed-area tables and storage types (Sec. 4.4) ------------ */
 
 /* C[j][r] = sum_{s<j} S[s][r] for j = 0..n, accumulated in FP64 and then

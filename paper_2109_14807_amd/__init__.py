@@ -10,7 +10,8 @@ from . import _lib  # noqa: F401
 from ._lib import GlintError, NdfDesc  # noqa: F401
 from .api import (  # noqa: F401
     AlsResult, QueryTables, build_tensor, convert, cp_als, cumulative, cumulative_backward,
-    desc_of, make_tables, mttkrp, query, query_backward, query_grouped, range_bruteforce, texel_bins,
+    cp_als_texel, desc_of, make_tables, mttkrp, mttkrp_texel, query, query_backward, query_grouped,
+    range_bruteforce, texel_bins, texel_workspace,
 )
 from .autograd import GlintQuery, glint_query_fn  # noqa: F401
 from .refine import refine  # noqa: F401

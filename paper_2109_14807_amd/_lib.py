@@ -78,6 +78,10 @@ _SIGS = {
     "glint_cp_als_workspace": (_SZ, [_DESC, _I32, _I32]),
     "glint_cp_als": (_I32, [_DESC, _P, _I32, _I32, _I32, _F64, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     "glint_mttkrp": (_I32, [_DESC, _P, _I32, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "glint_cp_als_texel_workspace": (_SZ, [_DESC, _I32]),
+    "glint_mttkrp_texel": (_I32, [_DESC, _P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "glint_cp_als_texel": (_I32, [_DESC, _P, _I32, _I32, _F64, _F64, _P, _P, _P, _P, _P, _P, _P,
+                                  _P, _SZ, _P]),
     "glint_make_cumulative": (_I32, [_I32, _I32, _P, _I32, _P, _I32, _P, _P]),
     "glint_convert": (_I32, [_I64, _I32, _P, _I32, _P, _I32, _P, _P]),
     "glint_query": (_I32, [_FAC, _I64, _P, _P, _P]),
@@ -204,6 +208,30 @@ def glint_mttkrp(desc, T, R, mode, U, V, L, S, Tf, M, workspace, stream=None):
         _ptr(U, f64, "U"), _ptr(V, f64, "V"), _ptr(L, f64, "L"), _ptr(S, f64, "S"),
         _ptr(Tf, f64, "Tf"), _ptr(M, f64, "M"), _ptr(workspace, torch.uint8, "workspace"),
         workspace.numel(), _stream(stream)))
+
+
+def glint_cp_als_texel_workspace(desc, R) -> int:
+    return int(lib().glint_cp_als_texel_workspace(ctypes.byref(desc), int(R)))
+
+
+def glint_mttkrp_texel(desc, nxy, R, mode, U, V, L, S, Tf, M, workspace, stream=None):
+    f64 = torch.float64
+    _check("glint_mttkrp_texel", lib().glint_mttkrp_texel(
+        ctypes.byref(desc), _ptr(nxy, torch.float32, "nxy"), int(R), int(mode),
+        _ptr(U, f64, "U"), _ptr(V, f64, "V"), _ptr(L, f64, "L"), _ptr(S, f64, "S"),
+        _ptr(Tf, f64, "Tf"), _ptr(M, f64, "M"), _ptr(workspace, torch.uint8, "workspace"),
+        workspace.numel(), _stream(stream)))
+
+
+def glint_cp_als_texel(desc, nxy, R, iters, tol, normT2, U, V, L, S, Tf, fit_hist, info,
+                       workspace, stream=None):
+    f64 = torch.float64
+    _check("glint_cp_als_texel", lib().glint_cp_als_texel(
+        ctypes.byref(desc), _ptr(nxy, torch.float32, "nxy"), int(R), int(iters), float(tol),
+        float(normT2), _ptr(U, f64, "U"), _ptr(V, f64, "V"), _ptr(L, f64, "L"),
+        _ptr(S, f64, "S"), _ptr(Tf, f64, "Tf"), _ptr(fit_hist, f64, "fit_hist"),
+        _ptr(info, torch.int32, "info") if info is not None else None,
+        _ptr(workspace, torch.uint8, "workspace"), workspace.numel(), _stream(stream)))
 
 
 def glint_make_cumulative(S, C, col_scale=None, stream=None):

@@ -93,6 +93,36 @@ def mttkrp(T: torch.Tensor, desc: NdfDesc, factors, mode: int, workspace=None):
     return M
 
 
+def texel_workspace(desc: NdfDesc, R: int) -> torch.Tensor:
+    n = L.glint_cp_als_texel_workspace(desc, R)
+    if n == 0:
+        raise ValueError("unsupported texel-space ALS configuration")
+    return torch.empty(n, dtype=torch.uint8, device=_DEV)
+
+
+def mttkrp_texel(nxy, desc: NdfDesc, factors, mode: int, workspace=None):
+    """MTTKRP of one mode evaluated from the normal map (T never formed)."""
+    R = int(factors[0].shape[1])
+    F = tuple(_dev(a, torch.float64) for a in factors)
+    rows = (desc.nu, desc.nv, desc.nlevels, desc.nbins, desc.nbins)[mode]
+    M = torch.empty((rows, R), dtype=torch.float64, device=_DEV)
+    ws = texel_workspace(desc, R) if workspace is None else workspace
+    L.glint_mttkrp_texel(desc, _dev(nxy, torch.float32), R, mode, *F, M, ws)
+    return M
+
+
+def cp_als_texel(nxy, desc: NdfDesc, init, iters: int, tol: float = 0.0, normT2: float = 0.0,
+                 workspace=None) -> AlsResult:
+    """CP-ALS from the normal map; fits are NaN unless ||T||^2 is supplied."""
+    R = int(init[0].shape[1])
+    F = tuple(_dev(a, torch.float64).clone() for a in init)
+    fits = torch.zeros(iters, dtype=torch.float64, device=_DEV)
+    info = torch.zeros(4, dtype=torch.int32, device=_DEV)
+    ws = texel_workspace(desc, R) if workspace is None else workspace
+    L.glint_cp_als_texel(desc, _dev(nxy, torch.float32), R, iters, tol, normT2, *F, fits, info, ws)
+    return AlsResult(F, fits, info)
+
+
 # ----------------------------------------------------------------------------
 # query tables
 # ----------------------------------------------------------------------------

@@ -72,6 +72,8 @@ __global__ void k_als_init(int* __restrict__ ctrl, double* __restrict__ fitprev)
   if (threadIdx.x == 0) fitprev[0] = 0.0;
 }
 
+__global__ void k_fill_scalar(double* __restrict__ p, double v) { p[0] = v; }
+
 // ||T||^2 from the per-wave partial sums of the first Z pass.
 __global__ void k_sum_norm(const double* __restrict__ part, int n, double* __restrict__ out) {
   __shared__ double sh[4];
@@ -609,6 +611,7 @@ __global__ __launch_bounds__(1024) void k_normalize_gram(double* __restrict__ A,
     const double nrm = lr[i % R];
     if (nrm > 0.0) A[i] /= nrm;
   }
+  if (G == nullptr) return;
   __syncthreads();
   // Gram in row tiles staged through LDS (tile of kGramRows x R doubles)
   constexpr int kGramRows = 4096 / 128;      // 32 rows of up to 128 columns = 32 KB
@@ -676,7 +679,7 @@ __global__ __launch_bounds__(256) void k_fit(const double* __restrict__ grams, c
     const double t2 = normT2[0];
     double res2 = t2 - 2.0 * in + nh;
     if (res2 < 0.0) res2 = 0.0;
-    const double fit = 1.0 - sqrt(res2) / sqrt(t2);
+    const double fit = t2 > 0.0 ? 1.0 - sqrt(res2) / sqrt(t2) : __builtin_nan("");
     fit_hist[it] = fit;
     ctrl[CTRL_SWEEPS] = it + 1;
     if (tol > 0.0 && it > 0 && fabs(fit - fitprev[0]) < tol) ctrl[CTRL_DONE] = 1;
@@ -921,6 +924,480 @@ glint_status check_als_args(const glint_ndf_desc* desc, const void* T, glint_dty
   return GLINT_OK;
 }
 
+
+// ===========================================================================
+// Texel-space MTTKRP and ALS: the same contractions for the tensor built from
+// per-texel bin windows (T[u,v,l] = k^-2 sum_{footprint} m_s (x) m_t), evaluated
+// without forming T, so maps whose tensor exceeds HBM can be decomposed.
+// With gs = S-contracted s-windows, gt = T-contracted t-windows, P = gs*gt and
+// Ubar_l[x] = sum_{u : x in W_l(u)} U[u] (likewise Vbar):
+//   M_U[u] = sum_l L[l]/k^2 sum_{x in W_l(u)} sum_y Vbar_l[y] P[x,y]
+//   M_V[v] = sum_l L[l]/k^2 sum_{y in W_l(v)} sum_x Ubar_l[x] P[x,y]
+//   M_L[l] = k^-2 sum_{x,y} Ubar_l[x] Vbar_l[y] P[x,y]
+//   M_S[s] = sum_{x,y} m_s[x,y][s] gt[x,y] sum_l L[l]/k^2 Ubar_l[x] Vbar_l[y]   (M_T alike)
+// All FP64.
+// ===========================================================================
+
+// gamma[tex][r] = sum_j mass[tex][axis][j] F[i0 - K + j][r]  (times mul[tex][r] if given)
+__global__ void k_texel_gamma(const int32_t* __restrict__ bins, const double* __restrict__ mass,
+                              int64_t ntex, int axis, int K, int N, const double* __restrict__ F, int R,
+                              const double* __restrict__ mul, double* __restrict__ out,
+                              const int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE]) return;
+  const int P = 2 * K + 1;
+  const int64_t n = ntex * R;
+  for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < n;
+       idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t tex = idx / R;
+    const int r = static_cast<int>(idx - tex * R);
+    const int i0 = bins[2 * tex + axis] - K;
+    const double* m = mass + (2 * tex + axis) * P;
+    double acc = 0.0;
+    for (int j = 0; j < P; ++j) {
+      const int i = i0 + j;
+      if (i >= 0 && i < N) acc += m[j] * F[i * R + r];
+    }
+    out[idx] = mul ? acc * mul[idx] : acc;
+  }
+}
+
+// C[g][j][r] = sum_{i<j} X[g][i][r], j = 0..n, for `groups` stacked [n][R] blocks.
+__global__ void k_prefix_rows(const double* __restrict__ X, int groups, int n, int R,
+                              double* __restrict__ C, const int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE]) return;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= groups * R) return;
+  const int gi = idx / R, r = idx % R;
+  const double* x = X + static_cast<int64_t>(gi) * n * R + r;
+  double* c = C + static_cast<int64_t>(gi) * (n + 1) * R + r;
+  double acc = 0.0;
+  c[0] = 0.0;
+  for (int i = 0; i < n; ++i) {
+    acc += x[static_cast<int64_t>(i) * R];
+    c[static_cast<int64_t>(i + 1) * R] = acc;
+  }
+}
+
+// Sum of X[m mod n] over the integer range [lo, hi) (|lo|, |hi| < 2n), from its prefix table C.
+__device__ __forceinline__ double wrap_range_sum(const double* C, int n, int R, int lo, int hi) {
+  auto pf = [&](int m) {
+    const int w = m >= 0 ? m / n : -((-m + n - 1) / n);
+    const int rr = m - w * n;
+    return static_cast<double>(w) * C[static_cast<int64_t>(n) * R] + C[static_cast<int64_t>(rr) * R];
+  };
+  return pf(hi) - pf(lo);
+}
+
+// out[l][x][r] = sum of F[c][r] over the centres c whose level-l footprint covers x,
+// i.e. c in [x + h - k + 1, x + h] (k = 2^l, h = k/2), wrapping.
+__global__ void k_window_sums(const double* __restrict__ Cpref, int n, int R, int nl,
+                              double* __restrict__ out, const int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE]) return;
+  const int64_t total = static_cast<int64_t>(nl) * n * R;
+  for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < total;
+       idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int r = static_cast<int>(idx % R);
+    const int64_t t = idx / R;
+    const int x = static_cast<int>(t % n), l = static_cast<int>(t / n);
+    const int k = 1 << l, h = k >> 1;
+    out[idx] = wrap_range_sum(Cpref + r, n, R, x + h - k + 1, x + h + 1);
+  }
+}
+
+// M[c][r] = sum_l L[l][r]/k^2 * sum_{x in W_l(c)} H[l][x][r], W_l(c) = [c - h, c - h + k).
+__global__ void k_window_apply(const double* __restrict__ Hpref, int n, int R, int nl,
+                               const double* __restrict__ L, double* __restrict__ M,
+                               const int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE]) return;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * R) return;
+  const int c = idx / R, r = idx % R;
+  double acc = 0.0;
+  for (int l = 0; l < nl; ++l) {
+    const int k = 1 << l, h = k >> 1;
+    const double s = wrap_range_sum(Hpref + static_cast<int64_t>(l) * (n + 1) * R + r, n, R, c - h, c - h + k);
+    acc += L[l * R + r] / (static_cast<double>(k) * k) * s;
+  }
+  M[idx] = acc;
+}
+
+// H[l][x][r] = sum_y W[l][y][r] P[x][y][r]   (rows = true: one thread per (x, r))
+// H[l][y][r] = sum_x W[l][x][r] P[x][y][r]   (rows = false: one thread per (y, r))
+template <bool ROWS>
+__global__ void k_window_contract(const double* __restrict__ Pm, const double* __restrict__ W, int nu,
+                                  int nv, int nl, int R, double* __restrict__ H,
+                                  const int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE]) return;
+  const int outer = ROWS ? nu : nv, inner = ROWS ? nv : nu;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= outer * R) return;
+  const int o = idx / R, r = idx % R;
+  double acc[16];
+#pragma unroll
+  for (int l = 0; l < 16; ++l) acc[l] = 0.0;
+  for (int i = 0; i < inner; ++i) {
+    const int64_t tex = ROWS ? static_cast<int64_t>(o) * nv + i : static_cast<int64_t>(i) * nv + o;
+    const double pv = Pm[tex * R + r];
+#pragma unroll
+    for (int l = 0; l < 16; ++l)
+      if (l < nl) acc[l] += W[(static_cast<int64_t>(l) * inner + i) * R + r] * pv;
+  }
+#pragma unroll
+  for (int l = 0; l < 16; ++l)
+    if (l < nl) H[(static_cast<int64_t>(l) * outer + o) * R + r] = acc[l];
+}
+
+// M_L[l][r] += k^-2 sum_y Ubar[l][x][r] Vbar[l][y][r] P[x][y][r], one thread per (x, r).
+__global__ void k_texel_ml(const double* __restrict__ Pm, const double* __restrict__ Ub,
+                           const double* __restrict__ Vb, int nu, int nv, int nl, int R,
+                           double* __restrict__ M, const int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE]) return;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nu * R) return;
+  const int x = idx / R, r = idx % R;
+  double acc[16];
+#pragma unroll
+  for (int l = 0; l < 16; ++l) acc[l] = 0.0;
+  for (int y = 0; y < nv; ++y) {
+    const double pv = Pm[(static_cast<int64_t>(x) * nv + y) * R + r];
+#pragma unroll
+    for (int l = 0; l < 16; ++l)
+      if (l < nl) acc[l] += Vb[(static_cast<int64_t>(l) * nv + y) * R + r] * pv;
+  }
+#pragma unroll
+  for (int l = 0; l < 16; ++l)
+    if (l < nl) {
+      const double k = static_cast<double>(1 << l);
+      atomicAdd(&M[l * R + r], acc[l] * Ub[(static_cast<int64_t>(l) * nu + x) * R + r] / (k * k));
+    }
+}
+
+// M_S (axis 0, G = gt) or M_T (axis 1, G = gs): sum over texels of the texel's
+// bin-window masses times G[x,y][r] sum_l L[l]/k^2 Ubar_l[x] Vbar_l[y].  A block
+// takes a chunk of texels and a tile of kRT ranks, accumulates into LDS
+// [N][kRT] with LDS atomics and adds the tile to M once.
+constexpr int kRT = 32;
+constexpr int kTexChunk = 8192;
+
+__global__ __launch_bounds__(256) void k_texel_scatter(const int32_t* __restrict__ bins,
+                                                       const double* __restrict__ mass, int axis, int K,
+                                                       int N, const double* __restrict__ G,
+                                                       const double* __restrict__ Ub,
+                                                       const double* __restrict__ Vb,
+                                                       const double* __restrict__ L, int nu, int nv,
+                                                       int nl, int R, double* __restrict__ M,
+                                                       const int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE]) return;
+  extern __shared__ __align__(16) double acc_lds[];   // [N][kRT]
+  for (int i = threadIdx.x; i < N * kRT; i += blockDim.x) acc_lds[i] = 0.0;
+  __syncthreads();
+  const int rr = threadIdx.x % kRT;
+  const int r = blockIdx.x * kRT + rr;
+  const int sub = threadIdx.x / kRT;
+  const int subs = blockDim.x / kRT;
+  const int P = 2 * K + 1;
+  const int64_t ntex = static_cast<int64_t>(nu) * nv;
+  const int64_t t0 = static_cast<int64_t>(blockIdx.y) * kTexChunk;
+  const int64_t t1 = t0 + kTexChunk < ntex ? t0 + kTexChunk : ntex;
+  if (r < R) {
+    for (int64_t tex = t0 + sub; tex < t1; tex += subs) {
+      const int x = static_cast<int>(tex / nv), y = static_cast<int>(tex - static_cast<int64_t>(x) * nv);
+      double w = 0.0;
+      for (int l = 0; l < nl; ++l) {
+        const double k = static_cast<double>(1 << l);
+        w += L[l * R + r] / (k * k) * Ub[(static_cast<int64_t>(l) * nu + x) * R + r] *
+             Vb[(static_cast<int64_t>(l) * nv + y) * R + r];
+      }
+      const double q = G[tex * R + r] * w;
+      const int i0 = bins[2 * tex + axis] - K;
+      const double* m = mass + (2 * tex + axis) * P;
+      for (int j = 0; j < P; ++j) {
+        const int i = i0 + j;
+        if (i >= 0 && i < N && m[j] != 0.0) atomicAdd(&acc_lds[i * kRT + rr], m[j] * q);
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < N * kRT; i += blockDim.x) {
+    const int ri = blockIdx.x * kRT + i % kRT;
+    if (ri < R && acc_lds[i] != 0.0) atomicAdd(&M[(i / kRT) * R + ri], acc_lds[i]);
+  }
+}
+
+// Cholesky in global memory (ranks whose Gram does not fit in LDS); same
+// algorithm and breakdown rule as k_cholesky.
+__global__ __launch_bounds__(1024) void k_cholesky_global(const double* __restrict__ grams, int n, int R,
+                                                          double* __restrict__ G, double* __restrict__ Lc,
+                                                          double* __restrict__ LcT, int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE]) return;
+  double* diag0 = G + R * R;
+  const int RR = R * R;
+  for (int i = threadIdx.x; i < RR; i += blockDim.x) {
+    double g = 1.0;
+    for (int m = 0; m < 5; ++m)
+      if (m != n) g *= grams[static_cast<int64_t>(m) * RR + i];
+    G[i] = g;
+    if (i % (R + 1) == 0) diag0[i / (R + 1)] = g;
+  }
+  __syncthreads();
+  bool fail = false;
+  for (int j = 0; j < R; ++j) {
+    const double d = G[j * R + j];
+    if (!(d > kPivotRtol * diag0[j])) {
+      fail = true;
+      break;
+    }
+    const double inv = 1.0 / d;
+    const int w = R - j - 1;
+    for (int idx = threadIdx.x; idx < w * w; idx += blockDim.x) {
+      const int i = j + 1 + idx / w, k = j + 1 + idx % w;
+      if (k <= i) G[i * R + k] -= G[i * R + j] * G[k * R + j] * inv;
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    ctrl[CTRL_FAILNOW] = fail ? 1 : 0;
+    if (fail) ctrl[CTRL_FAILS] += 1;
+  }
+  if (fail) return;
+  for (int idx = threadIdx.x; idx < RR; idx += blockDim.x) {
+    const int i = idx / R, k = idx % R;
+    const double x = k < i ? G[idx] / sqrt(G[k * R + k]) : (k == i ? sqrt(G[idx]) : 0.0);
+    Lc[idx] = x;
+    LcT[k * R + i] = x;
+  }
+}
+
+struct TexelLayout {
+  size_t bins, mass, gs, gt, pm, ub, vb, hb, hpref, cpre, m, grams, lc, lct, cholg, lam, scal, ctrl, total;
+};
+
+void texel_layout(const glint_ndf_desc* d, int R, TexelLayout* L) {
+  const size_t ntex = static_cast<size_t>(d->nu) * d->nv;
+  const int K = glint_window_k(d);
+  const size_t P = 2 * K + 1;
+  const size_t nmax = std::max(d->nu, d->nv);
+  const size_t rows = std::max<size_t>(nmax, std::max(d->nlevels, d->nbins));
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += glint_round_up(bytes, 256);
+    return at;
+  };
+  L->bins = take(sizeof(int32_t) * 2 * ntex);
+  L->mass = take(sizeof(double) * 2 * ntex * P);
+  L->gs = take(sizeof(double) * ntex * R);
+  L->gt = take(sizeof(double) * ntex * R);
+  L->pm = take(sizeof(double) * ntex * R);
+  L->ub = take(sizeof(double) * d->nlevels * d->nu * R);
+  L->vb = take(sizeof(double) * d->nlevels * d->nv * R);
+  L->hb = take(sizeof(double) * d->nlevels * nmax * R);
+  L->hpref = take(sizeof(double) * d->nlevels * (nmax + 1) * R);
+  L->cpre = take(sizeof(double) * (nmax + 1) * R);
+  L->m = take(sizeof(double) * rows * R);
+  L->grams = take(sizeof(double) * 5 * R * R);
+  L->lc = take(sizeof(double) * R * R);
+  L->lct = take(sizeof(double) * R * R);
+  L->cholg = take(sizeof(double) * (R * R + R));
+  L->lam = take(sizeof(double) * R);
+  L->scal = take(sizeof(double) * 4);
+  L->ctrl = take(sizeof(int) * CTRL_N);
+  L->total = off;
+}
+
+// The texel-space contraction of one mode into M (FP64 [rows][R]); requires the
+// window tables the mode reads: gs/gt/P current, Ubar/Vbar current.
+struct TexelCtx {
+  const glint_ndf_desc* d;
+  int R, K;
+  int32_t* bins;
+  double *mass, *gs, *gt, *pm, *ub, *vb, *hb, *hpref, *cpre, *M;
+  int* ctrl;
+  hipStream_t stream;
+};
+
+glint_status texel_gammas(const TexelCtx& c, const double* S, const double* Tf, bool make_p) {
+  const int64_t ntex = static_cast<int64_t>(c.d->nu) * c.d->nv;
+  const unsigned blocks = static_cast<unsigned>(std::min<int64_t>((ntex * c.R + 255) / 256, 1 << 16));
+  if (S) hipLaunchKernelGGL(k_texel_gamma, dim3(blocks), dim3(256), 0, c.stream, c.bins, c.mass, ntex, 0, c.K,
+                            c.d->nbins, S, c.R, static_cast<const double*>(nullptr), c.gs, c.ctrl);
+  if (Tf) hipLaunchKernelGGL(k_texel_gamma, dim3(blocks), dim3(256), 0, c.stream, c.bins, c.mass, ntex, 1, c.K,
+                             c.d->nbins, Tf, c.R, static_cast<const double*>(nullptr), c.gt, c.ctrl);
+  if (make_p)   // P = gs * gt: gamma of T again with gs as the multiplier
+    hipLaunchKernelGGL(k_texel_gamma, dim3(blocks), dim3(256), 0, c.stream, c.bins, c.mass, ntex, 1, c.K,
+                       c.d->nbins, Tf, c.R, c.gs, c.pm, c.ctrl);
+  GLINT_LAUNCHED("k_texel_gamma");
+  return GLINT_OK;
+}
+
+glint_status texel_window(const TexelCtx& c, const double* F, int n, double* out) {
+  const int R = c.R, nl = c.d->nlevels;
+  hipLaunchKernelGGL(k_prefix_rows, dim3((R + 63) / 64), dim3(64), 0, c.stream, F, 1, n, R, c.cpre, c.ctrl);
+  const int64_t total = static_cast<int64_t>(nl) * n * R;
+  hipLaunchKernelGGL(k_window_sums, dim3(static_cast<unsigned>(std::min<int64_t>((total + 255) / 256, 1 << 16))),
+                     dim3(256), 0, c.stream, c.cpre, n, R, nl, out, c.ctrl);
+  GLINT_LAUNCHED("k_window_sums");
+  return GLINT_OK;
+}
+
+glint_status texel_mode(const TexelCtx& c, int mode, const double* L) {
+  const glint_ndf_desc* d = c.d;
+  const int R = c.R, nu = d->nu, nv = d->nv, nl = d->nlevels, N = d->nbins;
+  hipStream_t st = c.stream;
+  if (mode == 0 || mode == 1) {
+    const int n = mode == 0 ? nu : nv;
+    if (mode == 0)
+      hipLaunchKernelGGL(k_window_contract<true>, dim3((nu * R + 255) / 256), dim3(256), 0, st, c.pm, c.vb, nu,
+                         nv, nl, R, c.hb, c.ctrl);
+    else
+      hipLaunchKernelGGL(k_window_contract<false>, dim3((nv * R + 255) / 256), dim3(256), 0, st, c.pm, c.ub, nu,
+                         nv, nl, R, c.hb, c.ctrl);
+    hipLaunchKernelGGL(k_prefix_rows, dim3((nl * R + 63) / 64), dim3(64), 0, st, c.hb, nl, n, R, c.hpref, c.ctrl);
+    hipLaunchKernelGGL(k_window_apply, dim3((n * R + 255) / 256), dim3(256), 0, st, c.hpref, n, R, nl, L, c.M,
+                       c.ctrl);
+    GLINT_LAUNCHED("texel mode u/v");
+    return GLINT_OK;
+  }
+  const int rows = mode == 2 ? nl : N;
+  hipLaunchKernelGGL(k_zero, dim3((rows * R + 255) / 256), dim3(256), 0, st, c.M, static_cast<int64_t>(rows) * R,
+                     c.ctrl);
+  if (mode == 2) {
+    hipLaunchKernelGGL(k_texel_ml, dim3((nu * R + 255) / 256), dim3(256), 0, st, c.pm, c.ub, c.vb, nu, nv, nl, R,
+                       c.M, c.ctrl);
+  } else {
+    const int64_t ntex = static_cast<int64_t>(nu) * nv;
+    const dim3 grid((R + kRT - 1) / kRT, static_cast<unsigned>((ntex + kTexChunk - 1) / kTexChunk));
+    hipLaunchKernelGGL(k_texel_scatter, grid, dim3(256), sizeof(double) * N * kRT, st, c.bins, c.mass,
+                       mode == 3 ? 0 : 1, c.K, N, mode == 3 ? c.gt : c.gs, c.ub, c.vb, L, nu, nv, nl, R, c.M,
+                       c.ctrl);
+  }
+  GLINT_LAUNCHED("texel mode l/s/t");
+  return GLINT_OK;
+}
+
+template <int R>
+glint_status run_texel_als(const glint_ndf_desc* d, const float* nxy, int iters, double tol, double normT2,
+                           double* F[5], double* fit_hist, int32_t* info, unsigned char* ws,
+                           const TexelLayout& Lo, hipStream_t stream) {
+  const int nu = d->nu, nv = d->nv, nl = d->nlevels, N = d->nbins;
+  const int rows[5] = {nu, nv, nl, N, N};
+  TexelCtx c;
+  c.d = d; c.R = R; c.K = glint_window_k(d); c.stream = stream;
+  c.bins = reinterpret_cast<int32_t*>(ws + Lo.bins);
+  c.mass = reinterpret_cast<double*>(ws + Lo.mass);
+  c.gs = reinterpret_cast<double*>(ws + Lo.gs);
+  c.gt = reinterpret_cast<double*>(ws + Lo.gt);
+  c.pm = reinterpret_cast<double*>(ws + Lo.pm);
+  c.ub = reinterpret_cast<double*>(ws + Lo.ub);
+  c.vb = reinterpret_cast<double*>(ws + Lo.vb);
+  c.hb = reinterpret_cast<double*>(ws + Lo.hb);
+  c.hpref = reinterpret_cast<double*>(ws + Lo.hpref);
+  c.cpre = reinterpret_cast<double*>(ws + Lo.cpre);
+  c.M = reinterpret_cast<double*>(ws + Lo.m);
+  c.ctrl = reinterpret_cast<int*>(ws + Lo.ctrl);
+  double* grams = reinterpret_cast<double*>(ws + Lo.grams);
+  double* Lc = reinterpret_cast<double*>(ws + Lo.lc);
+  double* LcT = reinterpret_cast<double*>(ws + Lo.lct);
+  double* cholg = reinterpret_cast<double*>(ws + Lo.cholg);
+  double* lam = reinterpret_cast<double*>(ws + Lo.lam);
+  double* scal = reinterpret_cast<double*>(ws + Lo.scal);
+  glint_status st = glint_texel_bins(d, nxy, c.bins, c.mass, stream);
+  if (st != GLINT_OK) return st;
+  glint_clear_launch_error();
+  hipLaunchKernelGGL(k_als_init, dim3(1), dim3(64), 0, stream, c.ctrl, scal + 1);
+  hipLaunchKernelGGL(k_fill_scalar, dim3(1), dim3(1), 0, stream, scal, normT2);
+  const dim3 gblk(16, 16), ggrid((R + 15) / 16, (R + 15) / 16);
+  for (int m = 0; m < 5; ++m)
+    hipLaunchKernelGGL(k_gram, ggrid, gblk, 0, stream, F[m], rows[m], R, grams + m * R * R, c.ctrl);
+  GLINT_LAUNCHED("texel ALS init");
+  constexpr bool kLdsChol = R <= 128;
+  auto update = [&](int n) -> glint_status {
+    if constexpr (kLdsChol)
+      hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), sizeof(double) * (R * R + R), stream, grams, n, R, Lc,
+                         LcT, c.ctrl);
+    else
+      hipLaunchKernelGGL(k_cholesky_global, dim3(1), dim3(1024), 0, stream, grams, n, R, cholg, Lc, LcT, c.ctrl);
+    GLINT_LAUNCHED("k_cholesky");
+    hipLaunchKernelGGL((k_solve<R>), dim3((rows[n] + 15) / 16), dim3(1024), 0, stream, c.M, rows[n], Lc, LcT,
+                       F[n], c.ctrl);
+    GLINT_LAUNCHED("k_solve");
+    if constexpr (R <= 128) {
+      hipLaunchKernelGGL(k_normalize_gram, dim3(1), dim3(1024), 0, stream, F[n], rows[n], R, lam,
+                         grams + n * R * R, c.ctrl);
+    } else {
+      hipLaunchKernelGGL(k_normalize_gram, dim3(1), dim3(1024), 0, stream, F[n], rows[n], R, lam,
+                         static_cast<double*>(nullptr), c.ctrl);
+      hipLaunchKernelGGL(k_gram, ggrid, gblk, 0, stream, F[n], rows[n], R, grams + n * R * R, c.ctrl);
+    }
+    GLINT_LAUNCHED("k_normalize_gram");
+    return GLINT_OK;
+  };
+  for (int it = 0; it < iters; ++it) {
+    if ((st = texel_gammas(c, F[3], F[4], true)) != GLINT_OK) return st;
+    if ((st = texel_window(c, F[1], nv, c.vb)) != GLINT_OK) return st;
+    if ((st = texel_mode(c, 0, F[2])) != GLINT_OK || (st = update(0)) != GLINT_OK) return st;
+    if ((st = texel_window(c, F[0], nu, c.ub)) != GLINT_OK) return st;
+    if ((st = texel_mode(c, 1, F[2])) != GLINT_OK || (st = update(1)) != GLINT_OK) return st;
+    if ((st = texel_window(c, F[1], nv, c.vb)) != GLINT_OK) return st;
+    if ((st = texel_mode(c, 2, F[2])) != GLINT_OK || (st = update(2)) != GLINT_OK) return st;
+    if ((st = texel_mode(c, 3, F[2])) != GLINT_OK || (st = update(3)) != GLINT_OK) return st;
+    if ((st = texel_gammas(c, F[3], nullptr, false)) != GLINT_OK) return st;
+    if ((st = texel_mode(c, 4, F[2])) != GLINT_OK || (st = update(4)) != GLINT_OK) return st;
+    hipLaunchKernelGGL(k_fit, dim3(1), dim3(256), 0, stream, grams, lam, c.M, F[4], N, R, scal, it, tol, fit_hist,
+                       scal + 1, c.ctrl);
+    GLINT_LAUNCHED("k_fit");
+  }
+  hipLaunchKernelGGL(k_absorb, dim3((nl * R + 255) / 256), dim3(256), 0, stream, F[2], nl, R, lam, c.ctrl, info);
+  GLINT_LAUNCHED("k_absorb");
+  return GLINT_OK;
+}
+
+glint_status texel_mttkrp(const glint_ndf_desc* d, const float* nxy, int R, int mode, const double* const F[5],
+                          double* M, unsigned char* ws, const TexelLayout& Lo, hipStream_t stream) {
+  TexelCtx c;
+  c.d = d; c.R = R; c.K = glint_window_k(d); c.stream = stream;
+  c.bins = reinterpret_cast<int32_t*>(ws + Lo.bins);
+  c.mass = reinterpret_cast<double*>(ws + Lo.mass);
+  c.gs = reinterpret_cast<double*>(ws + Lo.gs);
+  c.gt = reinterpret_cast<double*>(ws + Lo.gt);
+  c.pm = reinterpret_cast<double*>(ws + Lo.pm);
+  c.ub = reinterpret_cast<double*>(ws + Lo.ub);
+  c.vb = reinterpret_cast<double*>(ws + Lo.vb);
+  c.hb = reinterpret_cast<double*>(ws + Lo.hb);
+  c.hpref = reinterpret_cast<double*>(ws + Lo.hpref);
+  c.cpre = reinterpret_cast<double*>(ws + Lo.cpre);
+  c.M = M;
+  c.ctrl = reinterpret_cast<int*>(ws + Lo.ctrl);
+  glint_status st = glint_texel_bins(d, nxy, c.bins, c.mass, stream);
+  if (st != GLINT_OK) return st;
+  glint_clear_launch_error();
+  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, stream, c.ctrl);
+  if ((st = texel_gammas(c, F[3], F[4], true)) != GLINT_OK) return st;
+  if ((st = texel_window(c, F[0], d->nu, c.ub)) != GLINT_OK) return st;
+  if ((st = texel_window(c, F[1], d->nv, c.vb)) != GLINT_OK) return st;
+  return texel_mode(c, mode, F[2]);
+}
+
+glint_status check_texel_args(const glint_ndf_desc* d, const float* nxy, int R, void* ws, size_t ws_bytes,
+                              TexelLayout* Lo) {
+  glint_status st = glint_check_desc(d);
+  if (st != GLINT_OK) return st;
+  GLINT_REQUIRE(nxy && ws, "null pointer argument");
+  GLINT_SUPPORT(R == 16 || R == 32 || R == 64 || R == 128 || R == 256, "rank %d not in {16,32,64,128,256}", R);
+  GLINT_REQUIRE(glint_aligned(ws, 256), "workspace must be 256-byte aligned");
+  texel_layout(d, R, Lo);
+  if (ws_bytes < Lo->total)
+    return glint_fail(GLINT_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, Lo->total);
+  int dev = 0, max_lds = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return glint_fail(GLINT_E_HIP, "hipDeviceGetAttribute failed");
+  if (R <= 128 && static_cast<size_t>(max_lds) < sizeof(double) * (R * R + R))
+    return glint_fail(GLINT_E_UNSUPPORTED, "rank %d Gram does not fit in LDS (%d bytes)", R, max_lds);
+  return GLINT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -983,6 +1460,49 @@ glint_status glint_cp_als(const glint_ndf_desc* desc, const void* T, glint_dtype
   };
   if (T_dtype == GLINT_F64) return go(double{});
   return go(float{});
+}
+
+size_t glint_cp_als_texel_workspace(const glint_ndf_desc* desc, int32_t R) {
+  if (glint_check_desc(desc) != GLINT_OK) return 0;
+  if (!(R == 16 || R == 32 || R == 64 || R == 128 || R == 256)) return 0;
+  TexelLayout L;
+  texel_layout(desc, R, &L);
+  return L.total;
+}
+
+glint_status glint_mttkrp_texel(const glint_ndf_desc* desc, const float* nxy, int32_t R, int32_t mode,
+                                const double* U, const double* V, const double* L, const double* S,
+                                const double* Tf, double* M, void* workspace, size_t workspace_bytes,
+                                hipStream_t stream) {
+  TexelLayout Lo;
+  glint_status st = check_texel_args(desc, nxy, R, workspace, workspace_bytes, &Lo);
+  if (st != GLINT_OK) return st;
+  GLINT_REQUIRE(mode >= 0 && mode <= 4, "mode %d outside 0..4", mode);
+  GLINT_REQUIRE(U && V && L && S && Tf && M, "null pointer argument");
+  const double* F[5] = {U, V, L, S, Tf};
+  return texel_mttkrp(desc, nxy, R, mode, F, M, static_cast<unsigned char*>(workspace), Lo, stream);
+}
+
+glint_status glint_cp_als_texel(const glint_ndf_desc* desc, const float* nxy, int32_t R, int32_t iters,
+                                double tol, double normT2, double* U, double* V, double* L, double* S,
+                                double* Tf, double* fit_hist, int32_t* info, void* workspace,
+                                size_t workspace_bytes, hipStream_t stream) {
+  TexelLayout Lo;
+  glint_status st = check_texel_args(desc, nxy, R, workspace, workspace_bytes, &Lo);
+  if (st != GLINT_OK) return st;
+  GLINT_REQUIRE(U && V && L && S && Tf && fit_hist, "null pointer argument");
+  GLINT_REQUIRE(iters >= 1, "iters must be >= 1");
+  GLINT_REQUIRE(tol >= 0.0, "tol must be >= 0");
+  GLINT_REQUIRE(tol == 0.0 || normT2 > 0.0, "tol > 0 needs normT2 > 0");
+  double* F[5] = {U, V, L, S, Tf};
+  unsigned char* ws = static_cast<unsigned char*>(workspace);
+  switch (R) {
+    case 16: return run_texel_als<16>(desc, nxy, iters, tol, normT2, F, fit_hist, info, ws, Lo, stream);
+    case 32: return run_texel_als<32>(desc, nxy, iters, tol, normT2, F, fit_hist, info, ws, Lo, stream);
+    case 64: return run_texel_als<64>(desc, nxy, iters, tol, normT2, F, fit_hist, info, ws, Lo, stream);
+    case 128: return run_texel_als<128>(desc, nxy, iters, tol, normT2, F, fit_hist, info, ws, Lo, stream);
+    default: return run_texel_als<256>(desc, nxy, iters, tol, normT2, F, fit_hist, info, ws, Lo, stream);
+  }
 }
 
 }  // extern "C"

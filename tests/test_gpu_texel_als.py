@@ -1,0 +1,119 @@
+"""GPU parity: the texel-space MTTKRP and CP-ALS (T never formed) against the
+FP64 oracle on the materialised tensor, and against the dense GPU path."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+from oracle import cp_als, ndf
+
+pytestmark = pytest.mark.gpu
+
+import paper_2109_14807_amd as G  # noqa: E402
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _signed_factors(dims, R, seed):
+    rng = np.random.default_rng(seed)
+    nu, nv, nl, N = dims
+    return [rng.standard_normal((n, R)) for n in (nu, nv, nl, N, N)]
+
+
+@pytest.mark.parametrize("R", [16, 256])
+def test_mttkrp_texel_every_mode_matches_oracle(R):
+    """24 x 20 map (footprints wrap on both axes), 5 levels, N = 16, signed factors."""
+    nu, nv, nl, N, sigma = 24, 20, 5, 16, 0.03
+    nxy = gen.flake_map(nu, nv, 15, 0.2, 31)
+    T = ndf.ndf_bruteforce(nxy, N, sigma, nl)
+    A = _signed_factors((nu, nv, nl, N), R, 32 + R)
+    d = G.desc_of(nu, nv, nl, N, sigma)
+    ws = G.texel_workspace(d, R)
+    for mode in range(5):
+        print(f"mttkrp_texel R={R} mode={mode}", flush=True)
+        got = G.mttkrp_texel(nxy, d, A, mode, workspace=ws).cpu().numpy()
+        want = cp_als.mttkrp(T, A, mode)
+        assert _rel(got, want) < 1e-12, (R, mode, _rel(got, want))
+
+
+def test_mttkrp_texel_equals_dense_gpu_c1():
+    """The 64 x 64, N = 32, 5-level workload: texel form against the matrix-core
+    passes over the built FP64 tensor."""
+    cfg = gen.config("c1")
+    nxy = gen.normal_map(cfg)
+    d = G.desc_of(cfg.nu, cfg.nv, cfg.nlevels, cfg.nbins, cfg.sigma)
+    T = G.build_tensor(nxy, d, dtype=torch.float64)
+    A = gen.als_init(cfg)
+    for mode in range(5):
+        dense = G.mttkrp(T, d, A, mode).cpu().numpy()
+        tex = G.mttkrp_texel(nxy, d, A, mode).cpu().numpy()
+        assert _rel(tex, dense) < 1e-12, (mode, _rel(tex, dense))
+
+
+def test_cp_als_texel_two_sweeps_match_oracle():
+    cfg = gen.config("c1")
+    nxy = gen.normal_map(cfg)
+    T = ndf.ndf_bruteforce(nxy, cfg.nbins, cfg.sigma, cfg.nlevels)
+    init = gen.als_init(cfg)
+    d = G.desc_of(cfg.nu, cfg.nv, cfg.nlevels, cfg.nbins, cfg.sigma)
+    for iters in (1, 2):
+        ref = cp_als.cp_als(T, init, iters=iters)
+        res = G.cp_als_texel(nxy, d, init, iters, normT2=float(np.sum(T * T)))
+        F = [f.cpu().numpy() for f in res.factors]
+        for m in range(5):
+            assert _rel(F[m], ref["factors"][m]) < 1e-10, (iters, m)
+        assert np.max(np.abs(res.fits.cpu().numpy() - ref["fits"])) < 1e-10
+        info = res.info.cpu().numpy()
+        assert info[0] == iters and info[1] == 0
+
+
+def test_cp_als_texel_fifty_sweeps_match_dense_gpu():
+    """32 x 32 flake map, N = 16, 4 levels, rank 16: fit histories of the texel
+    and dense GPU paths over 50 sweeps, and the stopping rule."""
+    nxy = gen.flake_map(32, 32, 60, 0.15, 77)
+    d = G.desc_of(32, 32, 4, 16, 0.02)
+    T = G.build_tensor(nxy, d, dtype=torch.float64)
+    normT2 = float((T * T).sum())
+    init = gen.als_init((32, 32, 4, 16), rank=16, seed=78)
+    dense = G.cp_als(T, d, init, 50).fits.cpu().numpy()
+    tex = G.cp_als_texel(nxy, d, init, 50, normT2=normT2).fits.cpu().numpy()
+    assert np.max(np.abs(tex - dense)) < 1e-9
+    # a tolerance between two consecutive fit changes, so that the stop is early
+    # and not decided by rounding
+    step = np.abs(np.diff(dense))
+    k = int(np.argmax(step < 0.5 * step[0]))
+    assert k > 0
+    tol = float(np.sqrt(step[k] * step[k - 1]))     # step[k] < tol < step[k - 1]
+    stop_d = G.cp_als(T, d, init, 50, tol=tol)
+    stop_t = G.cp_als_texel(nxy, d, init, 50, tol=tol, normT2=normT2)
+    assert int(stop_t.info[0]) == int(stop_d.info[0]) < 50
+
+
+def test_cp_als_texel_without_norm_gives_nan_fits():
+    nxy = gen.flake_map(16, 16, 10, 0.2, 3)
+    d = G.desc_of(16, 16, 3, 16, 0.03)
+    init = gen.als_init((16, 16, 3, 16), rank=16, seed=4)
+    res = G.cp_als_texel(nxy, d, init, 2)
+    assert np.all(np.isnan(res.fits.cpu().numpy()))
+    with pytest.raises(G.GlintError):
+        G.cp_als_texel(nxy, d, init, 2, tol=1e-3)
+
+
+def test_cp_als_texel_rank256_global_cholesky():
+    """Rank 256 takes the Cholesky in global memory: one sweep against the oracle
+    (fit and reconstruction; the factors of so wide a rank are ill-conditioned)."""
+    nu, nv, nl, N, sigma = 32, 32, 4, 32, 0.02
+    nxy = gen.flake_map(nu, nv, 40, 0.2, 256)
+    T = ndf.ndf_bruteforce(nxy, N, sigma, nl)
+    init = gen.als_init((nu, nv, nl, N), rank=256, seed=257)
+    ref = cp_als.cp_als(T, init, iters=1)
+    d = G.desc_of(nu, nv, nl, N, sigma)
+    res = G.cp_als_texel(nxy, d, init, 1, normT2=float(np.sum(T * T)))
+    info = res.info.cpu().numpy()
+    assert info[1] == ref["fallbacks"]
+    assert abs(float(res.fits[0]) - ref["fits"][0]) < 1e-8
+    rec = cp_als.reconstruct(*[f.cpu().numpy() for f in res.factors])
+    rec_ref = cp_als.reconstruct(*ref["factors"])
+    assert _rel(rec, rec_ref) < 1e-6
