@@ -157,16 +157,19 @@ def scratch_map(nu: int, nv: int, nscratch: int, seed: int,
         tt, oo = np.meshgrid(ts, os_, indexing="ij")
         cx = np.floor(x0[i] + tt * dx + oo * px).astype(np.int64).ravel()
         cy = np.floor(y0[i] + tt * dy + oo * py).astype(np.int64).ravel()
-        cand = np.unique(np.stack([cx, cy], axis=1), axis=0)
+        # distinct candidates through one int64 key (|cx|, |cy| < 2^20 here)
+        key = np.unique((cx + (1 << 20)) * (1 << 21) + (cy + (1 << 20)))
+        cand_x = key // (1 << 21) - (1 << 20)
+        cand_y = key % (1 << 21) - (1 << 20)
         # exact test: distance from the texel centre to the segment <= half width
-        rx = cand[:, 0] + 0.5 - x0[i]
-        ry = cand[:, 1] + 0.5 - y0[i]
+        rx = cand_x + 0.5 - x0[i]
+        ry = cand_y + 0.5 - y0[i]
         along = np.clip(rx * dx + ry * dy, 0.0, length[i])
         ex = rx - along * dx
         ey = ry - along * dy
         keep = ex * ex + ey * ey <= half * half
-        cu = np.mod(cand[keep, 0], nu)
-        cv = np.mod(cand[keep, 1], nv)
+        cu = np.mod(cand_x[keep], nu)
+        cv = np.mod(cand_y[keep], nv)
         s = math.sin(tilt[i])
         out[cu, cv, 0] = np.float32(s * px)
         out[cu, cv, 1] = np.float32(s * py)

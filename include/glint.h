@@ -179,8 +179,10 @@ glint_status glint_mttkrp(const glint_ndf_desc* desc, const void* T, glint_dtype
  * windows of glint_texel_bins and window sums of U and V over the footprint
  * pyramid; T is never formed.  The results equal those of glint_mttkrp /
  * glint_cp_als on the materialised FP64 T up to FP64 rounding order.
- * nxy: float [nu][nv][2] normal map (as for glint_build_tensor).  All
- * arithmetic FP64.  R in {16, 32, 64, 128, 256}; any valid desc.
+ * nxy: float [nu][nv][2] normal map (as for glint_build_tensor), 8-byte
+ * aligned.  All arithmetic FP64.  R in {16, 32, 64, 128, 256}; nbins <= 128
+ * when R >= 64 (two [nbins][64] FP64 tiles must fit in one block's LDS),
+ * else any valid desc.
  * Workspace: glint_cp_als_texel_workspace bytes, 256-byte aligned; it holds
  * three FP64 [nu*nv][R] texel arrays, so it grows with the map, not with
  * the tensor. */

@@ -67,9 +67,12 @@ constexpr int kPad32 = 4;
 // ||T||^2
 // ---------------------------------------------------------------------------
 
-__global__ void k_als_init(int* __restrict__ ctrl, double* __restrict__ fitprev) {
+// Clears the control words and the previous fit, and sets the column weights
+// to 1: if no mode update succeeds, the initial factors are returned as given.
+__global__ void k_als_init(int* __restrict__ ctrl, double* __restrict__ fitprev, double* __restrict__ lam, int R) {
   if (threadIdx.x < CTRL_N) ctrl[threadIdx.x] = 0;
   if (threadIdx.x == 0) fitprev[0] = 0.0;
+  for (int r = threadIdx.x; r < R; r += blockDim.x) lam[r] = 1.0;
 }
 
 __global__ void k_fill_scalar(double* __restrict__ p, double v) { p[0] = v; }
@@ -792,7 +795,7 @@ glint_status run_als(const glint_ndf_desc* d, const TT* T, int iters, double tol
   TT* UVt = reinterpret_cast<TT*>(ws + Lo.uv);
 
   glint_clear_launch_error();
-  hipLaunchKernelGGL(k_als_init, dim3(1), dim3(64), 0, stream, ctrl, scal + 1);
+  hipLaunchKernelGGL(k_als_init, dim3(1), dim3(64), 0, stream, ctrl, scal + 1, lam, R);
   GLINT_LAUNCHED("k_als_init");
   const dim3 gblk(16, 16), ggrid((R + 15) / 16, (R + 15) / 16);
   for (int m = 0; m < 5; ++m)
@@ -929,56 +932,393 @@ glint_status check_als_args(const glint_ndf_desc* desc, const void* T, glint_dty
 // Texel-space MTTKRP and ALS: the same contractions for the tensor built from
 // per-texel bin windows (T[u,v,l] = k^-2 sum_{footprint} m_s (x) m_t), evaluated
 // without forming T, so maps whose tensor exceeds HBM can be decomposed.
-// With gs = S-contracted s-windows, gt = T-contracted t-windows, P = gs*gt and
-// Ubar_l[x] = sum_{u : x in W_l(u)} U[u] (likewise Vbar):
+// With gs = S contracted with each texel's s-window, gt likewise for t,
+// P = gs * gt and Ubar_l[x] = sum_{u : x in W_l(u)} U[u] (likewise Vbar):
 //   M_U[u] = sum_l L[l]/k^2 sum_{x in W_l(u)} sum_y Vbar_l[y] P[x,y]
 //   M_V[v] = sum_l L[l]/k^2 sum_{y in W_l(v)} sum_x Ubar_l[x] P[x,y]
 //   M_L[l] = k^-2 sum_{x,y} Ubar_l[x] Vbar_l[y] P[x,y]
-//   M_S[s] = sum_{x,y} m_s[x,y][s] gt[x,y] sum_l L[l]/k^2 Ubar_l[x] Vbar_l[y]   (M_T alike)
-// All FP64.
+//   M_S[s] = sum_{x,y} m_s[x,y][s] gt[x,y] W[x,y],  W = sum_l L[l]/k^2 Ubar_l[x] Vbar_l[y]
+//   M_T[t] = sum_{x,y} m_t[x,y][t] gs[x,y] W[x,y]
+// (elementwise in the rank r).  One [texels][R] FP64 array holds P during the
+// u, v, l updates and W during the s, t updates; gs and gt are recomputed
+// where they are needed from factor tiles in LDS.  All FP64.
 // ===========================================================================
 
-// gamma[tex][r] = sum_j mass[tex][axis][j] F[i0 - K + j][r]  (times mul[tex][r] if given)
-__global__ void k_texel_gamma(const int32_t* __restrict__ bins, const double* __restrict__ mass,
-                              int64_t ntex, int axis, int K, int N, const double* __restrict__ F, int R,
-                              const double* __restrict__ mul, double* __restrict__ out,
-                              const int* __restrict__ ctrl) {
+constexpr int kTexThreads = 1024;    // one block shares its LDS factor tiles among 16 wavefronts
+constexpr int kMaxLevels = 16;
+
+template <int R>
+struct TexTile {
+  static constexpr int RT = R < 64 ? R : 64;             // ranks per block (lanes per texel)
+  static constexpr int TPW = 64 / RT;                    // texels per wavefront step
+  static constexpr int WAVES = kTexThreads / 64;
+};
+
+// rows [0, N) x ranks [r0, r0 + RT) of a [N][R] factor into LDS [N][RT]
+template <int R>
+__device__ __forceinline__ void stage_rank_tile(const double* __restrict__ F, int N, int r0, double* tile) {
+  constexpr int RT = TexTile<R>::RT;
+  for (int i = threadIdx.x; i < N * RT; i += blockDim.x) tile[i] = F[(i / RT) * R + r0 + i % RT];
+}
+
+// sum_j m[j] F[i0 + j][r] over a texel's bin window.  The window masses of bins
+// outside [0, N) are zero, so the row is clamped rather than tested.
+template <int RT>
+__device__ __forceinline__ double window_dot(const double* __restrict__ m, int i0, int P, int N,
+                                             const double* tile, int rr) {
+  double acc = 0.0;
+  for (int j = 0; j < P; ++j) acc += m[j] * tile[glint_clampi(i0 + j, 0, N - 1) * RT + rr];
+  return acc;
+}
+
+// The texels [w0, w1) one wavefront walks: a contiguous share of the block's
+// chunk, so that runs of texels with one normal (equal bins and window masses)
+// stay together.  With 64 or more ranks each step is one texel, the same for
+// the whole wavefront.
+struct WaveRange {
+  int64_t w0, w1;
+};
+template <int R>
+__device__ __forceinline__ WaveRange wave_range(int64_t ntex, int64_t chunk) {
+  constexpr int TPW = TexTile<R>::TPW, WAVES = TexTile<R>::WAVES;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t t0 = static_cast<int64_t>(blockIdx.y) * chunk;
+  const int64_t t1 = t0 + chunk < ntex ? t0 + chunk : ntex;
+  const int64_t per = ((chunk + WAVES - 1) / WAVES + TPW - 1) / TPW * TPW;
+  const int64_t w0 = t0 + wave * per;
+  return {w0 < t1 ? w0 : t1, w0 + per < t1 ? w0 + per : t1};
+}
+
+__device__ __forceinline__ bool same_normal(float2 a, float2 b) { return a.x == b.x && a.y == b.y; }
+
+// lane k's value of a wavefront-wide register
+__device__ __forceinline__ float lane_f(float v, int k) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), k));
+}
+
+// Pm[tex][r] = gs[tex][r] * gt[tex][r]
+template <int R>
+__global__ __launch_bounds__(kTexThreads) void k_texel_p(const float2* __restrict__ nxy,
+                                                         const int32_t* __restrict__ bins,
+                                                         const double* __restrict__ mass, int64_t ntex,
+                                                         int K, int N, int64_t chunk,
+                                                         const double* __restrict__ S,
+                                                         const double* __restrict__ Tf,
+                                                         double* __restrict__ Pm, const int* __restrict__ ctrl) {
   if (ctrl[CTRL_DONE]) return;
+  constexpr int RT = TexTile<R>::RT, TPW = TexTile<R>::TPW;
+  extern __shared__ __align__(16) double tex_lds[];
+  double* sS = tex_lds;
+  double* sT = tex_lds + N * RT;
+  const int r0 = blockIdx.x * RT;
+  stage_rank_tile<R>(S, N, r0, sS);
+  stage_rank_tile<R>(Tf, N, r0, sT);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, rr = lane % RT, tsub = lane / RT;
   const int P = 2 * K + 1;
-  const int64_t n = ntex * R;
-  for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < n;
-       idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int64_t tex = idx / R;
-    const int r = static_cast<int>(idx - tex * R);
-    const int i0 = bins[2 * tex + axis] - K;
-    const double* m = mass + (2 * tex + axis) * P;
-    double acc = 0.0;
+  const WaveRange wr = wave_range<R>(ntex, chunk);
+  const int2* b2 = reinterpret_cast<const int2*>(bins);
+  float2 prev = make_float2(__builtin_nanf(""), 0.0f);
+  double val = 0.0;
+  if constexpr (TPW == 1) {
+    // one texel per step for the whole wavefront: the normals and bins of 64
+    // texels come in one vector load and are read out lane by lane
+    for (int64_t tb = wr.w0; tb < wr.w1; tb += 64) {
+      const int nb = static_cast<int>(wr.w1 - tb < 64 ? wr.w1 - tb : 64);
+      const float2 nm = lane < nb ? nxy[tb + lane] : make_float2(0.0f, 0.0f);
+      const int2 bm = lane < nb ? b2[tb + lane] : make_int2(0, 0);
+      for (int k = 0; k < nb; ++k) {
+        const float2 n = make_float2(lane_f(nm.x, k), lane_f(nm.y, k));
+        const int64_t tex = tb + k;
+        if (!same_normal(n, prev)) {
+          const int bx = __builtin_amdgcn_readlane(bm.x, k), by = __builtin_amdgcn_readlane(bm.y, k);
+          const double* ms = mass + tex * 2 * P;
+          val = window_dot<RT>(ms, bx - K, P, N, sS, rr) * window_dot<RT>(ms + P, by - K, P, N, sT, rr);
+          prev = n;
+        }
+        Pm[tex * R + r0 + rr] = val;
+      }
+    }
+  } else {
+    for (int64_t tb = wr.w0; tb < wr.w1; tb += TPW) {
+      const int64_t tex = tb + tsub;
+      if (tex < wr.w1) {
+        const float2 n = nxy[tex];
+        if (!same_normal(n, prev)) {
+          const int2 b = b2[tex];
+          const double* ms = mass + tex * 2 * P;
+          val = window_dot<RT>(ms, b.x - K, P, N, sS, rr) * window_dot<RT>(ms + P, b.y - K, P, N, sT, rr);
+          prev = n;
+        }
+        Pm[tex * R + r0 + rr] = val;
+      }
+    }
+  }
+}
+
+// Window contraction over the inner texel axis, XT outer rows per thread and
+// the inner axis split over gridDim.y:
+//   ROWS:  H[l][x][r] = sum_y Wb[l][y][r] Pm[x][y][r]      (outer x, inner y)
+//   !ROWS: H[l][y][r] = sum_x Wb[l][x][r] Pm[x][y][r]      (outer y, inner x)
+//   ML (with ROWS): M[l][r] += k^-2 sum_x Ub[l][x][r] H[l][x][r] in place of H.
+// NL is the level count rounded up to a multiple of 4; the window sums are
+// zero on the padding levels, which are not stored.  The P and window-sum
+// values of the next inner step are loaded while the current one is used.
+// The destination must be zero on entry when gridDim.y > 1 or ML.
+template <int R, int XT, int NL, bool ROWS, bool ML>
+__global__ __launch_bounds__(256) void k_texel_contract(const double* __restrict__ Pm,
+                                                        const double* __restrict__ Wb,
+                                                        const double* __restrict__ Ub, int nu, int nv,
+                                                        int nl, int ichunk, double* __restrict__ H,
+                                                        const int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE]) return;
+  const int outer = ROWS ? nu : nv, inner = ROWS ? nv : nu;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int r = static_cast<int>(idx % R);
+  const int o0 = static_cast<int>(idx / R) * XT;
+  if (o0 >= outer) return;
+  const int i0 = blockIdx.y * ichunk;
+  const int i1 = min(i0 + ichunk, inner);
+  if (i0 >= i1) return;
+  // P[o][i] at pp[o] + i * istep
+  const double* pp[XT];
+#pragma unroll
+  for (int xt = 0; xt < XT; ++xt) {
+    const int o = min(o0 + xt, outer - 1);
+    pp[xt] = Pm + (ROWS ? static_cast<int64_t>(o) * nv : o) * R + r;
+  }
+  const int64_t istep = ROWS ? R : static_cast<int64_t>(nv) * R;
+  const double* wp = Wb + r;
+  const int64_t lstride = static_cast<int64_t>(inner) * R;
+  double acc[XT][NL];
+#pragma unroll
+  for (int xt = 0; xt < XT; ++xt)
+#pragma unroll
+    for (int l = 0; l < NL; ++l) acc[xt][l] = 0.0;
+  double pn[XT], wn[NL];
+#pragma unroll
+  for (int xt = 0; xt < XT; ++xt) pn[xt] = pp[xt][i0 * istep];
+#pragma unroll
+  for (int l = 0; l < NL; ++l) wn[l] = wp[l * lstride + static_cast<int64_t>(i0) * R];
+  for (int i = i0; i < i1; ++i) {
+    double p[XT], w[NL];
+#pragma unroll
+    for (int xt = 0; xt < XT; ++xt) p[xt] = pn[xt];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) w[l] = wn[l];
+    const int in = i + 1 < i1 ? i + 1 : i;
+#pragma unroll
+    for (int xt = 0; xt < XT; ++xt) pn[xt] = pp[xt][in * istep];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) wn[l] = wp[l * lstride + static_cast<int64_t>(in) * R];
+#pragma unroll
+    for (int l = 0; l < NL; ++l)
+#pragma unroll
+      for (int xt = 0; xt < XT; ++xt) acc[xt][l] += w[l] * p[xt];
+  }
+  if constexpr (ML) {
+#pragma unroll
+    for (int l = 0; l < NL; ++l)
+      if (l < nl) {
+        double sum = 0.0;
+#pragma unroll
+        for (int xt = 0; xt < XT; ++xt)
+          if (o0 + xt < outer) sum += acc[xt][l] * Ub[(static_cast<int64_t>(l) * nu + o0 + xt) * R + r];
+        const double k = static_cast<double>(1 << l);
+        atomicAdd(&H[l * R + r], sum / (k * k));
+      }
+  } else {
+#pragma unroll
+    for (int xt = 0; xt < XT; ++xt)
+      if (o0 + xt < outer)
+#pragma unroll
+        for (int l = 0; l < NL; ++l)
+          if (l < nl) {
+            double* dst = &H[(static_cast<int64_t>(l) * outer + o0 + xt) * R + r];
+            if (gridDim.y > 1) atomicAdd(dst, acc[xt][l]);
+            else *dst = acc[xt][l];
+          }
+  }
+}
+
+// Wt[x][y][r] = sum_l L[l][r] / k^2 Ub[l][x][r] Vb[l][y][r], XT rows x per
+// thread, y split over gridDim.y, the next y's window sums loaded ahead.
+template <int R, int XT, int NL>
+__global__ __launch_bounds__(256) void k_texel_w(const double* __restrict__ Ub, const double* __restrict__ Vb,
+                                                 const double* __restrict__ L, int nu, int nv, int nl,
+                                                 int ychunk, double* __restrict__ Wt,
+                                                 const int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE]) return;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int r = static_cast<int>(idx % R);
+  const int x0 = static_cast<int>(idx / R) * XT;
+  if (x0 >= nu) return;
+  const int y0 = blockIdx.y * ychunk;
+  const int y1 = min(y0 + ychunk, nv);
+  if (y0 >= y1) return;
+  double a[XT][NL];
+#pragma unroll
+  for (int l = 0; l < NL; ++l) {
+    const double k = static_cast<double>(1 << l);
+    const double c = l < nl ? L[l * R + r] / (k * k) : 0.0;
+#pragma unroll
+    for (int xt = 0; xt < XT; ++xt)
+      a[xt][l] = c * Ub[(static_cast<int64_t>(l) * nu + min(x0 + xt, nu - 1)) * R + r];
+  }
+  const int64_t lstride = static_cast<int64_t>(nv) * R;
+  const double* vp = Vb + r;
+  double* wp[XT];
+#pragma unroll
+  for (int xt = 0; xt < XT; ++xt) wp[xt] = Wt + static_cast<int64_t>(min(x0 + xt, nu - 1)) * nv * R + r;
+  double vn[NL];
+#pragma unroll
+  for (int l = 0; l < NL; ++l) vn[l] = vp[l * lstride + static_cast<int64_t>(y0) * R];
+  for (int y = y0; y < y1; ++y) {
+    double v[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) v[l] = vn[l];
+    const int yn = y + 1 < y1 ? y + 1 : y;
+#pragma unroll
+    for (int l = 0; l < NL; ++l) vn[l] = vp[l * lstride + static_cast<int64_t>(yn) * R];
+    double w[XT];
+#pragma unroll
+    for (int xt = 0; xt < XT; ++xt) w[xt] = 0.0;
+#pragma unroll
+    for (int l = 0; l < NL; ++l)
+#pragma unroll
+      for (int xt = 0; xt < XT; ++xt) w[xt] += a[xt][l] * v[l];
+#pragma unroll
+    for (int xt = 0; xt < XT; ++xt)
+      if (x0 + xt < nu) wp[xt][static_cast<int64_t>(y) * R] = w[xt];
+  }
+}
+
+// Mode s (AXIS 0) or t (AXIS 1): every texel adds its AXIS bin-window masses
+// times q = g * Wt[tex][r] to the rows of its window, g being the contraction
+// of the other axis' window with that axis' factor F.  A run of texels with
+// one normal shares g and the masses, so it adds g * (sum of its Wt) once.  A
+// block sums a chunk of texels for RT ranks in LDS and stores the tile in its
+// slot of parts[chunk][N][R]; the slots are summed afterwards (fixed order).
+template <int R, int AXIS>
+__global__ __launch_bounds__(kTexThreads) void k_texel_scatter(const float2* __restrict__ nxy,
+                                                               const int32_t* __restrict__ bins,
+                                                               const double* __restrict__ mass, int64_t ntex,
+                                                               int K, int N, int64_t chunk,
+                                                               const double* __restrict__ F,
+                                                               const double* __restrict__ Wt,
+                                                               double* __restrict__ parts,
+                                                               const int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE]) return;
+  constexpr int RT = TexTile<R>::RT, TPW = TexTile<R>::TPW;
+  extern __shared__ __align__(16) double tex_lds[];
+  double* acc = tex_lds;             // [N][RT]
+  double* sF = tex_lds + N * RT;     // [N][RT]
+  const int r0 = blockIdx.x * RT;
+  for (int i = threadIdx.x; i < N * RT; i += blockDim.x) acc[i] = 0.0;
+  stage_rank_tile<R>(F, N, r0, sF);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, rr = lane % RT, tsub = lane / RT;
+  const int P = 2 * K + 1;
+  const WaveRange wr = wave_range<R>(ntex, chunk);
+  const int2* b2 = reinterpret_cast<const int2*>(bins);
+  float2 prev = make_float2(__builtin_nanf(""), 0.0f);
+  const double* mo = nullptr;
+  int i0 = 0;
+  double g = 0.0, wsum = 0.0;
+  auto flush = [&]() {
+    if (mo == nullptr) return;
+    const double q = g * wsum;
     for (int j = 0; j < P; ++j) {
       const int i = i0 + j;
-      if (i >= 0 && i < N) acc += m[j] * F[i * R + r];
+      if (i >= 0 && i < N) atomicAdd(&acc[i * RT + rr], mo[j] * q);
     }
-    out[idx] = mul ? acc * mul[idx] : acc;
+  };
+  auto start_run = [&](int64_t tex, float2 n, int bx, int by) {
+    flush();
+    mo = mass + (2 * tex + AXIS) * P;
+    i0 = (AXIS ? by : bx) - K;
+    g = window_dot<RT>(mass + (2 * tex + (1 - AXIS)) * P, (AXIS ? bx : by) - K, P, N, sF, rr);
+    wsum = 0.0;
+    prev = n;
+  };
+  if constexpr (TPW == 1) {
+    // one texel per step for the whole wavefront; normals and bins of 64
+    // texels per vector load, the Wt rows of the next 8 texels in flight
+    constexpr int kG = 8;
+    const double* wrow = Wt + r0 + rr;
+    for (int64_t tb = wr.w0; tb < wr.w1; tb += 64) {
+      const int nb = static_cast<int>(wr.w1 - tb < 64 ? wr.w1 - tb : 64);
+      const float2 nm = lane < nb ? nxy[tb + lane] : make_float2(0.0f, 0.0f);
+      const int2 bm = lane < nb ? b2[tb + lane] : make_int2(0, 0);
+      double wa[kG], wb[kG];
+#pragma unroll
+      for (int j = 0; j < kG; ++j) wa[j] = wrow[(tb + min(j, nb - 1)) * R];
+      for (int k0 = 0; k0 < nb; k0 += kG) {
+#pragma unroll
+        for (int j = 0; j < kG; ++j) wb[j] = wrow[(tb + min(k0 + kG + j, nb - 1)) * R];
+#pragma unroll
+        for (int j = 0; j < kG; ++j) {
+          const int k = k0 + j;
+          if (k < nb) {
+            const float2 n = make_float2(lane_f(nm.x, k), lane_f(nm.y, k));
+            if (!same_normal(n, prev))
+              start_run(tb + k, n, __builtin_amdgcn_readlane(bm.x, k), __builtin_amdgcn_readlane(bm.y, k));
+            wsum += wa[j];
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < kG; ++j) wa[j] = wb[j];
+      }
+    }
+  } else {
+    for (int64_t tb = wr.w0; tb < wr.w1; tb += TPW) {
+      const int64_t tex = tb + tsub;
+      if (tex < wr.w1) {
+        const float2 n = nxy[tex];
+        if (!same_normal(n, prev)) {
+          const int2 b = b2[tex];
+          start_run(tex, n, b.x, b.y);
+        }
+        wsum += Wt[tex * R + r0 + rr];
+      }
+    }
   }
+  flush();
+  __syncthreads();
+  double* dst = parts + static_cast<int64_t>(blockIdx.y) * N * R;
+  for (int i = threadIdx.x; i < N * RT; i += blockDim.x) dst[(i / RT) * R + r0 + i % RT] = acc[i];
 }
 
-// C[g][j][r] = sum_{i<j} X[g][i][r], j = 0..n, for `groups` stacked [n][R] blocks.
-__global__ void k_prefix_rows(const double* __restrict__ X, int groups, int n, int R,
-                              double* __restrict__ C, const int* __restrict__ ctrl) {
+// C[g][j][r] = sum_{i<j} X[g][i][r], j = 0..n, for `groups` stacked [n][R]
+// blocks: one block per (group, tile of up to 64 ranks), the rows cut into
+// segments summed in parallel.
+__global__ __launch_bounds__(1024) void k_prefix_rows(const double* __restrict__ X, int n, int R,
+                                                      double* __restrict__ C, const int* __restrict__ ctrl) {
   if (ctrl[CTRL_DONE]) return;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= groups * R) return;
-  const int gi = idx / R, r = idx % R;
-  const double* x = X + static_cast<int64_t>(gi) * n * R + r;
-  double* c = C + static_cast<int64_t>(gi) * (n + 1) * R + r;
-  double acc = 0.0;
-  c[0] = 0.0;
-  for (int i = 0; i < n; ++i) {
-    acc += x[static_cast<int64_t>(i) * R];
-    c[static_cast<int64_t>(i + 1) * R] = acc;
+  __shared__ double seg[1024];
+  const int RB = R < 64 ? R : 64;
+  const int parts = blockDim.x / RB;
+  const int rr = threadIdx.x % RB, part = threadIdx.x / RB;
+  const int r = blockIdx.x * RB + rr;
+  const double* x = X + static_cast<int64_t>(blockIdx.y) * n * R + r;
+  double* c = C + static_cast<int64_t>(blockIdx.y) * (n + 1) * R + r;
+  const int len = (n + parts - 1) / parts;
+  const int a = min(part * len, n), e = min(a + len, n);
+  double s = 0.0;
+  for (int i = a; i < e; ++i) s += x[static_cast<int64_t>(i) * R];
+  seg[threadIdx.x] = s;
+  __syncthreads();
+  double off = 0.0;
+  for (int p = 0; p < part; ++p) off += seg[p * RB + rr];
+  if (part == 0) c[0] = 0.0;
+  for (int i = a; i < e; ++i) {
+    off += x[static_cast<int64_t>(i) * R];
+    c[static_cast<int64_t>(i + 1) * R] = off;
   }
 }
 
-// Sum of X[m mod n] over the integer range [lo, hi) (|lo|, |hi| < 2n), from its prefix table C.
+// Sum of X[m mod n] over the integer range [lo, hi), from its prefix table C
+// (C[j] = sum_{i<j} X[i], j = 0..n).
 __device__ __forceinline__ double wrap_range_sum(const double* C, int n, int R, int lo, int hi) {
   auto pf = [&](int m) {
     const int w = m >= 0 ? m / n : -((-m + n - 1) / n);
@@ -1021,107 +1361,29 @@ __global__ void k_window_apply(const double* __restrict__ Hpref, int n, int R, i
   M[idx] = acc;
 }
 
-// H[l][x][r] = sum_y W[l][y][r] P[x][y][r]   (rows = true: one thread per (x, r))
-// H[l][y][r] = sum_x W[l][x][r] P[x][y][r]   (rows = false: one thread per (y, r))
-template <bool ROWS>
-__global__ void k_window_contract(const double* __restrict__ Pm, const double* __restrict__ W, int nu,
-                                  int nv, int nl, int R, double* __restrict__ H,
-                                  const int* __restrict__ ctrl) {
-  if (ctrl[CTRL_DONE]) return;
-  const int outer = ROWS ? nu : nv, inner = ROWS ? nv : nu;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= outer * R) return;
-  const int o = idx / R, r = idx % R;
-  double acc[16];
-#pragma unroll
-  for (int l = 0; l < 16; ++l) acc[l] = 0.0;
-  for (int i = 0; i < inner; ++i) {
-    const int64_t tex = ROWS ? static_cast<int64_t>(o) * nv + i : static_cast<int64_t>(i) * nv + o;
-    const double pv = Pm[tex * R + r];
-#pragma unroll
-    for (int l = 0; l < 16; ++l)
-      if (l < nl) acc[l] += W[(static_cast<int64_t>(l) * inner + i) * R + r] * pv;
-  }
-#pragma unroll
-  for (int l = 0; l < 16; ++l)
-    if (l < nl) H[(static_cast<int64_t>(l) * outer + o) * R + r] = acc[l];
-}
-
-// M_L[l][r] += k^-2 sum_y Ubar[l][x][r] Vbar[l][y][r] P[x][y][r], one thread per (x, r).
-__global__ void k_texel_ml(const double* __restrict__ Pm, const double* __restrict__ Ub,
-                           const double* __restrict__ Vb, int nu, int nv, int nl, int R,
-                           double* __restrict__ M, const int* __restrict__ ctrl) {
-  if (ctrl[CTRL_DONE]) return;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nu * R) return;
-  const int x = idx / R, r = idx % R;
-  double acc[16];
-#pragma unroll
-  for (int l = 0; l < 16; ++l) acc[l] = 0.0;
-  for (int y = 0; y < nv; ++y) {
-    const double pv = Pm[(static_cast<int64_t>(x) * nv + y) * R + r];
-#pragma unroll
-    for (int l = 0; l < 16; ++l)
-      if (l < nl) acc[l] += Vb[(static_cast<int64_t>(l) * nv + y) * R + r] * pv;
-  }
-#pragma unroll
-  for (int l = 0; l < 16; ++l)
-    if (l < nl) {
-      const double k = static_cast<double>(1 << l);
-      atomicAdd(&M[l * R + r], acc[l] * Ub[(static_cast<int64_t>(l) * nu + x) * R + r] / (k * k));
+// G = A^T A over a chunk of rows per blockIdx.z, into parts[z][R][R]: 16 x 16
+// output tiles, rows staged through LDS.
+__global__ __launch_bounds__(256) void k_gram_parts(const double* __restrict__ A, int rows, int R, int rchunk,
+                                                    double* __restrict__ parts, const int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE] || ctrl[CTRL_FAILNOW]) return;
+  __shared__ double ai[32][17], aj[32][17];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int i = blockIdx.y * 16 + ty, j = blockIdx.x * 16 + tx;
+  const int k0 = blockIdx.z * rchunk, k1 = min(k0 + rchunk, rows);
+  double acc = 0.0;
+  for (int kb = k0; kb < k1; kb += 32) {
+    for (int e = threadIdx.x; e < 32 * 16; e += 256) {
+      const int kk = e / 16, c = e % 16;
+      const bool in = kb + kk < k1;
+      ai[kk][c] = in ? A[static_cast<int64_t>(kb + kk) * R + blockIdx.y * 16 + c] : 0.0;
+      aj[kk][c] = in ? A[static_cast<int64_t>(kb + kk) * R + blockIdx.x * 16 + c] : 0.0;
     }
-}
-
-// M_S (axis 0, G = gt) or M_T (axis 1, G = gs): sum over texels of the texel's
-// bin-window masses times G[x,y][r] sum_l L[l]/k^2 Ubar_l[x] Vbar_l[y].  A block
-// takes a chunk of texels and a tile of kRT ranks, accumulates into LDS
-// [N][kRT] with LDS atomics and adds the tile to M once.
-constexpr int kRT = 32;
-constexpr int kTexChunk = 8192;
-
-__global__ __launch_bounds__(256) void k_texel_scatter(const int32_t* __restrict__ bins,
-                                                       const double* __restrict__ mass, int axis, int K,
-                                                       int N, const double* __restrict__ G,
-                                                       const double* __restrict__ Ub,
-                                                       const double* __restrict__ Vb,
-                                                       const double* __restrict__ L, int nu, int nv,
-                                                       int nl, int R, double* __restrict__ M,
-                                                       const int* __restrict__ ctrl) {
-  if (ctrl[CTRL_DONE]) return;
-  extern __shared__ __align__(16) double acc_lds[];   // [N][kRT]
-  for (int i = threadIdx.x; i < N * kRT; i += blockDim.x) acc_lds[i] = 0.0;
-  __syncthreads();
-  const int rr = threadIdx.x % kRT;
-  const int r = blockIdx.x * kRT + rr;
-  const int sub = threadIdx.x / kRT;
-  const int subs = blockDim.x / kRT;
-  const int P = 2 * K + 1;
-  const int64_t ntex = static_cast<int64_t>(nu) * nv;
-  const int64_t t0 = static_cast<int64_t>(blockIdx.y) * kTexChunk;
-  const int64_t t1 = t0 + kTexChunk < ntex ? t0 + kTexChunk : ntex;
-  if (r < R) {
-    for (int64_t tex = t0 + sub; tex < t1; tex += subs) {
-      const int x = static_cast<int>(tex / nv), y = static_cast<int>(tex - static_cast<int64_t>(x) * nv);
-      double w = 0.0;
-      for (int l = 0; l < nl; ++l) {
-        const double k = static_cast<double>(1 << l);
-        w += L[l * R + r] / (k * k) * Ub[(static_cast<int64_t>(l) * nu + x) * R + r] *
-             Vb[(static_cast<int64_t>(l) * nv + y) * R + r];
-      }
-      const double q = G[tex * R + r] * w;
-      const int i0 = bins[2 * tex + axis] - K;
-      const double* m = mass + (2 * tex + axis) * P;
-      for (int j = 0; j < P; ++j) {
-        const int i = i0 + j;
-        if (i >= 0 && i < N && m[j] != 0.0) atomicAdd(&acc_lds[i * kRT + rr], m[j] * q);
-      }
-    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < 32; ++kk) acc += ai[kk][ty] * aj[kk][tx];
+    __syncthreads();
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < N * kRT; i += blockDim.x) {
-    const int ri = blockIdx.x * kRT + i % kRT;
-    if (ri < R && acc_lds[i] != 0.0) atomicAdd(&M[(i / kRT) * R + ri], acc_lds[i]);
-  }
+  parts[static_cast<int64_t>(blockIdx.z) * R * R + i * R + j] = acc;
 }
 
 // Cholesky in global memory (ranks whose Gram does not fit in LDS); same
@@ -1153,7 +1415,6 @@ __global__ __launch_bounds__(1024) void k_cholesky_global(const double* __restri
       const int i = j + 1 + idx / w, k = j + 1 + idx % w;
       if (k <= i) G[i * R + k] -= G[i * R + j] * G[k * R + j] * inv;
     }
-    __threadfence_block();
     __syncthreads();
   }
   if (threadIdx.x == 0) {
@@ -1170,15 +1431,27 @@ __global__ __launch_bounds__(1024) void k_cholesky_global(const double* __restri
 }
 
 struct TexelLayout {
-  size_t bins, mass, gs, gt, pm, ub, vb, hb, hpref, cpre, m, grams, lc, lct, cholg, lam, scal, ctrl, total;
+  size_t bins, mass, pm, ub, vb, hb, hpref, cpre, parts, gparts, m, grams, lc, lct, cholg, lam, scal, ctrl, total;
+  int64_t chunk_p, chunk_s, nchunk_s;
+  int gsplit;
 };
 
+constexpr int kGramRowsPerSplit = 256;
+
 void texel_layout(const glint_ndf_desc* d, int R, TexelLayout* L) {
-  const size_t ntex = static_cast<size_t>(d->nu) * d->nv;
+  const int64_t ntex = static_cast<int64_t>(d->nu) * d->nv;
   const int K = glint_window_k(d);
   const size_t P = 2 * K + 1;
   const size_t nmax = std::max(d->nu, d->nv);
   const size_t rows = std::max<size_t>(nmax, std::max(d->nlevels, d->nbins));
+  const int RT = R < 64 ? R : 64;
+  // chunks of the texel kernels: >= 4096 texels per block for the P pass, about
+  // 2048 blocks for the scatter passes (whose per-chunk tiles are summed later)
+  L->chunk_p = std::max<int64_t>(4096, (ntex + 65534) / 65535);
+  const int64_t want = std::max<int64_t>(1, 2048 / (R / RT));
+  L->chunk_s = std::max<int64_t>(512, (ntex + want - 1) / want);
+  L->nchunk_s = (ntex + L->chunk_s - 1) / L->chunk_s;
+  L->gsplit = static_cast<int>((rows + kGramRowsPerSplit - 1) / kGramRowsPerSplit);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t at = off;
@@ -1187,14 +1460,15 @@ void texel_layout(const glint_ndf_desc* d, int R, TexelLayout* L) {
   };
   L->bins = take(sizeof(int32_t) * 2 * ntex);
   L->mass = take(sizeof(double) * 2 * ntex * P);
-  L->gs = take(sizeof(double) * ntex * R);
-  L->gt = take(sizeof(double) * ntex * R);
   L->pm = take(sizeof(double) * ntex * R);
-  L->ub = take(sizeof(double) * d->nlevels * d->nu * R);
-  L->vb = take(sizeof(double) * d->nlevels * d->nv * R);
+  const int nlp = (d->nlevels + 3) / 4 * 4;   // levels padded to a multiple of 4
+  L->ub = take(sizeof(double) * nlp * d->nu * R);
+  L->vb = take(sizeof(double) * nlp * d->nv * R);
   L->hb = take(sizeof(double) * d->nlevels * nmax * R);
   L->hpref = take(sizeof(double) * d->nlevels * (nmax + 1) * R);
   L->cpre = take(sizeof(double) * (nmax + 1) * R);
+  L->parts = take(sizeof(double) * L->nchunk_s * d->nbins * R);
+  L->gparts = take(sizeof(double) * L->gsplit * R * R);
   L->m = take(sizeof(double) * rows * R);
   L->grams = take(sizeof(double) * 5 * R * R);
   L->lc = take(sizeof(double) * R * R);
@@ -1206,74 +1480,192 @@ void texel_layout(const glint_ndf_desc* d, int R, TexelLayout* L) {
   L->total = off;
 }
 
-// The texel-space contraction of one mode into M (FP64 [rows][R]); requires the
-// window tables the mode reads: gs/gt/P current, Ubar/Vbar current.
 struct TexelCtx {
   const glint_ndf_desc* d;
-  int R, K;
+  const float2* nxy;
+  int R;
+  const TexelLayout* lo;
+  int K;
   int32_t* bins;
-  double *mass, *gs, *gt, *pm, *ub, *vb, *hb, *hpref, *cpre, *M;
+  double *mass, *pm, *ub, *vb, *hb, *hpref, *cpre, *parts, *gparts, *M;
   int* ctrl;
   hipStream_t stream;
 };
 
-glint_status texel_gammas(const TexelCtx& c, const double* S, const double* Tf, bool make_p) {
-  const int64_t ntex = static_cast<int64_t>(c.d->nu) * c.d->nv;
-  const unsigned blocks = static_cast<unsigned>(std::min<int64_t>((ntex * c.R + 255) / 256, 1 << 16));
-  if (S) hipLaunchKernelGGL(k_texel_gamma, dim3(blocks), dim3(256), 0, c.stream, c.bins, c.mass, ntex, 0, c.K,
-                            c.d->nbins, S, c.R, static_cast<const double*>(nullptr), c.gs, c.ctrl);
-  if (Tf) hipLaunchKernelGGL(k_texel_gamma, dim3(blocks), dim3(256), 0, c.stream, c.bins, c.mass, ntex, 1, c.K,
-                             c.d->nbins, Tf, c.R, static_cast<const double*>(nullptr), c.gt, c.ctrl);
-  if (make_p)   // P = gs * gt: gamma of T again with gs as the multiplier
-    hipLaunchKernelGGL(k_texel_gamma, dim3(blocks), dim3(256), 0, c.stream, c.bins, c.mass, ntex, 1, c.K,
-                       c.d->nbins, Tf, c.R, c.gs, c.pm, c.ctrl);
-  GLINT_LAUNCHED("k_texel_gamma");
-  return GLINT_OK;
+// the window-sum levels beyond nlevels (padding to a multiple of 4) are read
+// as zeros by the contraction kernels
+void texel_zero_padding(const TexelCtx& c) {
+  const int nl = c.d->nlevels, nlp = (nl + 3) / 4 * 4;
+  if (nlp == nl) return;
+  const int R = c.R;
+  const int64_t nu_pad = static_cast<int64_t>(nlp - nl) * c.d->nu * R;
+  const int64_t nv_pad = static_cast<int64_t>(nlp - nl) * c.d->nv * R;
+  hipLaunchKernelGGL(k_zero, dim3(static_cast<unsigned>(std::min<int64_t>((nu_pad + 255) / 256, 4096))), dim3(256),
+                     0, c.stream, c.ub + static_cast<int64_t>(nl) * c.d->nu * R, nu_pad, c.ctrl);
+  hipLaunchKernelGGL(k_zero, dim3(static_cast<unsigned>(std::min<int64_t>((nv_pad + 255) / 256, 4096))), dim3(256),
+                     0, c.stream, c.vb + static_cast<int64_t>(nl) * c.d->nv * R, nv_pad, c.ctrl);
 }
 
-glint_status texel_window(const TexelCtx& c, const double* F, int n, double* out) {
-  const int R = c.R, nl = c.d->nlevels;
-  hipLaunchKernelGGL(k_prefix_rows, dim3((R + 63) / 64), dim3(64), 0, c.stream, F, 1, n, R, c.cpre, c.ctrl);
+void texel_ctx(const glint_ndf_desc* d, const float* nxy, const TexelLayout& Lo, unsigned char* ws, double* M,
+               hipStream_t stream, TexelCtx* c) {
+  c->d = d;
+  c->nxy = reinterpret_cast<const float2*>(nxy);
+  c->R = 0;
+  c->lo = &Lo;
+  c->K = glint_window_k(d);
+  c->stream = stream;
+  c->bins = reinterpret_cast<int32_t*>(ws + Lo.bins);
+  c->mass = reinterpret_cast<double*>(ws + Lo.mass);
+  c->pm = reinterpret_cast<double*>(ws + Lo.pm);
+  c->ub = reinterpret_cast<double*>(ws + Lo.ub);
+  c->vb = reinterpret_cast<double*>(ws + Lo.vb);
+  c->hb = reinterpret_cast<double*>(ws + Lo.hb);
+  c->hpref = reinterpret_cast<double*>(ws + Lo.hpref);
+  c->cpre = reinterpret_cast<double*>(ws + Lo.cpre);
+  c->parts = reinterpret_cast<double*>(ws + Lo.parts);
+  c->gparts = reinterpret_cast<double*>(ws + Lo.gparts);
+  c->M = M ? M : reinterpret_cast<double*>(ws + Lo.m);
+  c->ctrl = reinterpret_cast<int*>(ws + Lo.ctrl);
+}
+
+// outer rows per thread and inner split of the contraction kernels: about
+// 2^17 threads, at least 32 inner steps per thread
+constexpr int kTexXT = 8;
+inline int inner_split(int outer, int inner, int R) {
+  const int64_t threads = static_cast<int64_t>((outer + kTexXT - 1) / kTexXT) * R;
+  int64_t s = ((int64_t{1} << 17) + threads - 1) / threads;
+  s = std::min<int64_t>(s, std::max(1, inner / 32));
+  return static_cast<int>(std::max<int64_t>(s, 1));
+}
+
+template <int R>
+void texel_p(const TexelCtx& c, const double* S, const double* Tf) {
+  constexpr int RT = TexTile<R>::RT;
+  const int64_t ntex = static_cast<int64_t>(c.d->nu) * c.d->nv;
+  const dim3 grid(R / RT, static_cast<unsigned>((ntex + c.lo->chunk_p - 1) / c.lo->chunk_p));
+  hipLaunchKernelGGL((k_texel_p<R>), grid, dim3(kTexThreads), sizeof(double) * 2 * c.d->nbins * RT, c.stream,
+                     c.nxy, c.bins, c.mass, ntex, c.K, c.d->nbins, c.lo->chunk_p, S, Tf, c.pm, c.ctrl);
+}
+
+template <int R>
+void texel_window(const TexelCtx& c, const double* F, int n, double* out) {
+  const int nl = c.d->nlevels;
+  const int RB = R < 64 ? R : 64;
+  hipLaunchKernelGGL(k_prefix_rows, dim3(R / RB, 1), dim3(1024), 0, c.stream, F, n, R, c.cpre, c.ctrl);
   const int64_t total = static_cast<int64_t>(nl) * n * R;
   hipLaunchKernelGGL(k_window_sums, dim3(static_cast<unsigned>(std::min<int64_t>((total + 255) / 256, 1 << 16))),
                      dim3(256), 0, c.stream, c.cpre, n, R, nl, out, c.ctrl);
-  GLINT_LAUNCHED("k_window_sums");
+}
+
+template <int R, int NL>
+void texel_w_nl(const TexelCtx& c, const double* L, dim3 grid, int ychunk) {
+  hipLaunchKernelGGL((k_texel_w<R, kTexXT, NL>), grid, dim3(256), 0, c.stream, c.ub, c.vb, L, c.d->nu, c.d->nv,
+                     c.d->nlevels, ychunk, c.pm, c.ctrl);
+}
+
+template <int R>
+void texel_w(const TexelCtx& c, const double* L) {
+  const int nu = c.d->nu, nv = c.d->nv;
+  const int split = inner_split(nu, nv, R);
+  const int ychunk = (nv + split - 1) / split;
+  const int64_t threads = static_cast<int64_t>((nu + kTexXT - 1) / kTexXT) * R;
+  const dim3 grid(static_cast<unsigned>((threads + 255) / 256), static_cast<unsigned>((nv + ychunk - 1) / ychunk));
+  switch ((c.d->nlevels + 3) / 4) {
+    case 1: texel_w_nl<R, 4>(c, L, grid, ychunk); break;
+    case 2: texel_w_nl<R, 8>(c, L, grid, ychunk); break;
+    case 3: texel_w_nl<R, 12>(c, L, grid, ychunk); break;
+    default: texel_w_nl<R, 16>(c, L, grid, ychunk); break;
+  }
+}
+
+template <int R, int NL>
+void texel_contract_nl(const TexelCtx& c, int mode, dim3 grid, int ichunk, double* dst) {
+  const int nu = c.d->nu, nv = c.d->nv, nl = c.d->nlevels;
+  hipStream_t st = c.stream;
+  if (mode == 0)
+    hipLaunchKernelGGL((k_texel_contract<R, kTexXT, NL, true, false>), grid, dim3(256), 0, st, c.pm, c.vb,
+                       static_cast<const double*>(nullptr), nu, nv, nl, ichunk, dst, c.ctrl);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_texel_contract<R, kTexXT, NL, false, false>), grid, dim3(256), 0, st, c.pm, c.ub,
+                       static_cast<const double*>(nullptr), nu, nv, nl, ichunk, dst, c.ctrl);
+  else
+    hipLaunchKernelGGL((k_texel_contract<R, kTexXT, NL, true, true>), grid, dim3(256), 0, st, c.pm, c.vb, c.ub,
+                       nu, nv, nl, ichunk, dst, c.ctrl);
+}
+
+// The contraction of one mode into c.M.  Requires: modes u, v, l: P in c.pm and
+// the window sums of the other spatial factor(s) current; modes s, t: W in c.pm.
+template <int R>
+glint_status texel_mode(const TexelCtx& c, int mode, const double* L, const double* S, const double* Tf) {
+  const glint_ndf_desc* d = c.d;
+  const int nu = d->nu, nv = d->nv, nl = d->nlevels, N = d->nbins;
+  hipStream_t st = c.stream;
+  if (mode <= 2) {
+    const bool rows = mode != 1;
+    const int outer = rows ? nu : nv, inner = rows ? nv : nu;
+    const int split = inner_split(outer, inner, R);
+    const int ichunk = (inner + split - 1) / split;
+    const int64_t threads = static_cast<int64_t>((outer + kTexXT - 1) / kTexXT) * R;
+    const dim3 grid(static_cast<unsigned>((threads + 255) / 256),
+                    static_cast<unsigned>((inner + ichunk - 1) / ichunk));
+    double* dst = mode == 2 ? c.M : c.hb;
+    const int64_t n = mode == 2 ? static_cast<int64_t>(nl) * R : static_cast<int64_t>(nl) * outer * R;
+    if (mode == 2 || grid.y > 1)
+      hipLaunchKernelGGL(k_zero, dim3(static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 4096))), dim3(256),
+                         0, st, dst, n, c.ctrl);
+    switch ((nl + 3) / 4) {
+      case 1: texel_contract_nl<R, 4>(c, mode, grid, ichunk, dst); break;
+      case 2: texel_contract_nl<R, 8>(c, mode, grid, ichunk, dst); break;
+      case 3: texel_contract_nl<R, 12>(c, mode, grid, ichunk, dst); break;
+      default: texel_contract_nl<R, 16>(c, mode, grid, ichunk, dst); break;
+    }
+    if (mode <= 1) {
+      const int RB = R < 64 ? R : 64;
+      hipLaunchKernelGGL(k_prefix_rows, dim3(R / RB, nl), dim3(1024), 0, st, c.hb, outer, R, c.hpref, c.ctrl);
+      hipLaunchKernelGGL(k_window_apply, dim3((outer * R + 255) / 256), dim3(256), 0, st, c.hpref, outer, R, nl,
+                         L, c.M, c.ctrl);
+    }
+    GLINT_LAUNCHED("texel modes u, v, l");
+    return GLINT_OK;
+  }
+  constexpr int RT = TexTile<R>::RT;
+  const int64_t ntex = static_cast<int64_t>(nu) * nv;
+  const dim3 grid(R / RT, static_cast<unsigned>(c.lo->nchunk_s));
+  const size_t lds = sizeof(double) * 2 * N * RT;
+  if (mode == 3)
+    hipLaunchKernelGGL((k_texel_scatter<R, 0>), grid, dim3(kTexThreads), lds, st, c.nxy, c.bins, c.mass, ntex, c.K,
+                       N, c.lo->chunk_s, Tf, c.pm, c.parts, c.ctrl);
+  else
+    hipLaunchKernelGGL((k_texel_scatter<R, 1>), grid, dim3(kTexThreads), lds, st, c.nxy, c.bins, c.mass, ntex, c.K,
+                       N, c.lo->chunk_s, S, c.pm, c.parts, c.ctrl);
+  const int64_t n = static_cast<int64_t>(N) * R;
+  hipLaunchKernelGGL(k_reduce_splits<double>, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st,
+                     c.parts, static_cast<int>(c.lo->nchunk_s), n, c.M, c.ctrl);
+  GLINT_LAUNCHED("texel modes s, t");
   return GLINT_OK;
 }
 
-glint_status texel_mode(const TexelCtx& c, int mode, const double* L) {
-  const glint_ndf_desc* d = c.d;
-  const int R = c.R, nu = d->nu, nv = d->nv, nl = d->nlevels, N = d->nbins;
-  hipStream_t st = c.stream;
-  if (mode == 0 || mode == 1) {
-    const int n = mode == 0 ? nu : nv;
-    if (mode == 0)
-      hipLaunchKernelGGL(k_window_contract<true>, dim3((nu * R + 255) / 256), dim3(256), 0, st, c.pm, c.vb, nu,
-                         nv, nl, R, c.hb, c.ctrl);
-    else
-      hipLaunchKernelGGL(k_window_contract<false>, dim3((nv * R + 255) / 256), dim3(256), 0, st, c.pm, c.ub, nu,
-                         nv, nl, R, c.hb, c.ctrl);
-    hipLaunchKernelGGL(k_prefix_rows, dim3((nl * R + 63) / 64), dim3(64), 0, st, c.hb, nl, n, R, c.hpref, c.ctrl);
-    hipLaunchKernelGGL(k_window_apply, dim3((n * R + 255) / 256), dim3(256), 0, st, c.hpref, n, R, nl, L, c.M,
-                       c.ctrl);
-    GLINT_LAUNCHED("texel mode u/v");
-    return GLINT_OK;
+// G = sum of the row-chunk partial Grams (skipped, like the partials, when the
+// mode update was not applied)
+__global__ void k_gram_reduce(const double* __restrict__ parts, int nsplit, int64_t n, double* __restrict__ G,
+                              const int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE] || ctrl[CTRL_FAILNOW]) return;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    double acc = 0.0;
+    for (int p = 0; p < nsplit; ++p) acc += parts[p * n + i];
+    G[i] = acc;
   }
-  const int rows = mode == 2 ? nl : N;
-  hipLaunchKernelGGL(k_zero, dim3((rows * R + 255) / 256), dim3(256), 0, st, c.M, static_cast<int64_t>(rows) * R,
-                     c.ctrl);
-  if (mode == 2) {
-    hipLaunchKernelGGL(k_texel_ml, dim3((nu * R + 255) / 256), dim3(256), 0, st, c.pm, c.ub, c.vb, nu, nv, nl, R,
-                       c.M, c.ctrl);
-  } else {
-    const int64_t ntex = static_cast<int64_t>(nu) * nv;
-    const dim3 grid((R + kRT - 1) / kRT, static_cast<unsigned>((ntex + kTexChunk - 1) / kTexChunk));
-    hipLaunchKernelGGL(k_texel_scatter, grid, dim3(256), sizeof(double) * N * kRT, st, c.bins, c.mass,
-                       mode == 3 ? 0 : 1, c.K, N, mode == 3 ? c.gt : c.gs, c.ub, c.vb, L, nu, nv, nl, R, c.M,
-                       c.ctrl);
-  }
-  GLINT_LAUNCHED("texel mode l/s/t");
-  return GLINT_OK;
+}
+
+template <int R>
+void texel_gram(const TexelCtx& c, const double* A, int rows, double* G) {
+  const int split = (rows + kGramRowsPerSplit - 1) / kGramRowsPerSplit;
+  hipLaunchKernelGGL(k_gram_parts, dim3(R / 16, R / 16, split), dim3(256), 0, c.stream, A, rows, R,
+                     kGramRowsPerSplit, c.gparts, c.ctrl);
+  const int64_t n = static_cast<int64_t>(R) * R;
+  hipLaunchKernelGGL(k_gram_reduce, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, c.stream,
+                     c.gparts, split, n, G, c.ctrl);
 }
 
 template <int R>
@@ -1283,19 +1675,7 @@ glint_status run_texel_als(const glint_ndf_desc* d, const float* nxy, int iters,
   const int nu = d->nu, nv = d->nv, nl = d->nlevels, N = d->nbins;
   const int rows[5] = {nu, nv, nl, N, N};
   TexelCtx c;
-  c.d = d; c.R = R; c.K = glint_window_k(d); c.stream = stream;
-  c.bins = reinterpret_cast<int32_t*>(ws + Lo.bins);
-  c.mass = reinterpret_cast<double*>(ws + Lo.mass);
-  c.gs = reinterpret_cast<double*>(ws + Lo.gs);
-  c.gt = reinterpret_cast<double*>(ws + Lo.gt);
-  c.pm = reinterpret_cast<double*>(ws + Lo.pm);
-  c.ub = reinterpret_cast<double*>(ws + Lo.ub);
-  c.vb = reinterpret_cast<double*>(ws + Lo.vb);
-  c.hb = reinterpret_cast<double*>(ws + Lo.hb);
-  c.hpref = reinterpret_cast<double*>(ws + Lo.hpref);
-  c.cpre = reinterpret_cast<double*>(ws + Lo.cpre);
-  c.M = reinterpret_cast<double*>(ws + Lo.m);
-  c.ctrl = reinterpret_cast<int*>(ws + Lo.ctrl);
+  texel_ctx(d, nxy, Lo, ws, nullptr, stream, &c);
   double* grams = reinterpret_cast<double*>(ws + Lo.grams);
   double* Lc = reinterpret_cast<double*>(ws + Lo.lc);
   double* LcT = reinterpret_cast<double*>(ws + Lo.lct);
@@ -1305,45 +1685,37 @@ glint_status run_texel_als(const glint_ndf_desc* d, const float* nxy, int iters,
   glint_status st = glint_texel_bins(d, nxy, c.bins, c.mass, stream);
   if (st != GLINT_OK) return st;
   glint_clear_launch_error();
-  hipLaunchKernelGGL(k_als_init, dim3(1), dim3(64), 0, stream, c.ctrl, scal + 1);
+  hipLaunchKernelGGL(k_als_init, dim3(1), dim3(64), 0, stream, c.ctrl, scal + 1, lam, R);
   hipLaunchKernelGGL(k_fill_scalar, dim3(1), dim3(1), 0, stream, scal, normT2);
-  const dim3 gblk(16, 16), ggrid((R + 15) / 16, (R + 15) / 16);
-  for (int m = 0; m < 5; ++m)
-    hipLaunchKernelGGL(k_gram, ggrid, gblk, 0, stream, F[m], rows[m], R, grams + m * R * R, c.ctrl);
+  c.R = R;
+  texel_zero_padding(c);
+  for (int m = 0; m < 5; ++m) texel_gram<R>(c, F[m], rows[m], grams + m * R * R);
   GLINT_LAUNCHED("texel ALS init");
-  constexpr bool kLdsChol = R <= 128;
   auto update = [&](int n) -> glint_status {
-    if constexpr (kLdsChol)
+    if constexpr (R <= 128)
       hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), sizeof(double) * (R * R + R), stream, grams, n, R, Lc,
                          LcT, c.ctrl);
     else
       hipLaunchKernelGGL(k_cholesky_global, dim3(1), dim3(1024), 0, stream, grams, n, R, cholg, Lc, LcT, c.ctrl);
-    GLINT_LAUNCHED("k_cholesky");
     hipLaunchKernelGGL((k_solve<R>), dim3((rows[n] + 15) / 16), dim3(1024), 0, stream, c.M, rows[n], Lc, LcT,
                        F[n], c.ctrl);
-    GLINT_LAUNCHED("k_solve");
-    if constexpr (R <= 128) {
-      hipLaunchKernelGGL(k_normalize_gram, dim3(1), dim3(1024), 0, stream, F[n], rows[n], R, lam,
-                         grams + n * R * R, c.ctrl);
-    } else {
-      hipLaunchKernelGGL(k_normalize_gram, dim3(1), dim3(1024), 0, stream, F[n], rows[n], R, lam,
-                         static_cast<double*>(nullptr), c.ctrl);
-      hipLaunchKernelGGL(k_gram, ggrid, gblk, 0, stream, F[n], rows[n], R, grams + n * R * R, c.ctrl);
-    }
-    GLINT_LAUNCHED("k_normalize_gram");
+    hipLaunchKernelGGL(k_normalize_gram, dim3(1), dim3(1024), 0, stream, F[n], rows[n], R, lam,
+                       static_cast<double*>(nullptr), c.ctrl);
+    texel_gram<R>(c, F[n], rows[n], grams + n * R * R);
+    GLINT_LAUNCHED("texel ALS update");
     return GLINT_OK;
   };
   for (int it = 0; it < iters; ++it) {
-    if ((st = texel_gammas(c, F[3], F[4], true)) != GLINT_OK) return st;
-    if ((st = texel_window(c, F[1], nv, c.vb)) != GLINT_OK) return st;
-    if ((st = texel_mode(c, 0, F[2])) != GLINT_OK || (st = update(0)) != GLINT_OK) return st;
-    if ((st = texel_window(c, F[0], nu, c.ub)) != GLINT_OK) return st;
-    if ((st = texel_mode(c, 1, F[2])) != GLINT_OK || (st = update(1)) != GLINT_OK) return st;
-    if ((st = texel_window(c, F[1], nv, c.vb)) != GLINT_OK) return st;
-    if ((st = texel_mode(c, 2, F[2])) != GLINT_OK || (st = update(2)) != GLINT_OK) return st;
-    if ((st = texel_mode(c, 3, F[2])) != GLINT_OK || (st = update(3)) != GLINT_OK) return st;
-    if ((st = texel_gammas(c, F[3], nullptr, false)) != GLINT_OK) return st;
-    if ((st = texel_mode(c, 4, F[2])) != GLINT_OK || (st = update(4)) != GLINT_OK) return st;
+    texel_p<R>(c, F[3], F[4]);
+    texel_window<R>(c, F[1], nv, c.vb);
+    if ((st = texel_mode<R>(c, 0, F[2], F[3], F[4])) != GLINT_OK || (st = update(0)) != GLINT_OK) return st;
+    texel_window<R>(c, F[0], nu, c.ub);
+    if ((st = texel_mode<R>(c, 1, F[2], F[3], F[4])) != GLINT_OK || (st = update(1)) != GLINT_OK) return st;
+    texel_window<R>(c, F[1], nv, c.vb);
+    if ((st = texel_mode<R>(c, 2, F[2], F[3], F[4])) != GLINT_OK || (st = update(2)) != GLINT_OK) return st;
+    texel_w<R>(c, F[2]);
+    if ((st = texel_mode<R>(c, 3, F[2], F[3], F[4])) != GLINT_OK || (st = update(3)) != GLINT_OK) return st;
+    if ((st = texel_mode<R>(c, 4, F[2], F[3], F[4])) != GLINT_OK || (st = update(4)) != GLINT_OK) return st;
     hipLaunchKernelGGL(k_fit, dim3(1), dim3(256), 0, stream, grams, lam, c.M, F[4], N, R, scal, it, tol, fit_hist,
                        scal + 1, c.ctrl);
     GLINT_LAUNCHED("k_fit");
@@ -1353,30 +1725,23 @@ glint_status run_texel_als(const glint_ndf_desc* d, const float* nxy, int iters,
   return GLINT_OK;
 }
 
-glint_status texel_mttkrp(const glint_ndf_desc* d, const float* nxy, int R, int mode, const double* const F[5],
-                          double* M, unsigned char* ws, const TexelLayout& Lo, hipStream_t stream) {
+template <int R>
+glint_status texel_mttkrp(const glint_ndf_desc* d, const float* nxy, int mode, const double* const F[5], double* M,
+                          unsigned char* ws, const TexelLayout& Lo, hipStream_t stream) {
   TexelCtx c;
-  c.d = d; c.R = R; c.K = glint_window_k(d); c.stream = stream;
-  c.bins = reinterpret_cast<int32_t*>(ws + Lo.bins);
-  c.mass = reinterpret_cast<double*>(ws + Lo.mass);
-  c.gs = reinterpret_cast<double*>(ws + Lo.gs);
-  c.gt = reinterpret_cast<double*>(ws + Lo.gt);
-  c.pm = reinterpret_cast<double*>(ws + Lo.pm);
-  c.ub = reinterpret_cast<double*>(ws + Lo.ub);
-  c.vb = reinterpret_cast<double*>(ws + Lo.vb);
-  c.hb = reinterpret_cast<double*>(ws + Lo.hb);
-  c.hpref = reinterpret_cast<double*>(ws + Lo.hpref);
-  c.cpre = reinterpret_cast<double*>(ws + Lo.cpre);
-  c.M = M;
-  c.ctrl = reinterpret_cast<int*>(ws + Lo.ctrl);
+  texel_ctx(d, nxy, Lo, ws, M, stream, &c);
   glint_status st = glint_texel_bins(d, nxy, c.bins, c.mass, stream);
   if (st != GLINT_OK) return st;
   glint_clear_launch_error();
   hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, stream, c.ctrl);
-  if ((st = texel_gammas(c, F[3], F[4], true)) != GLINT_OK) return st;
-  if ((st = texel_window(c, F[0], d->nu, c.ub)) != GLINT_OK) return st;
-  if ((st = texel_window(c, F[1], d->nv, c.vb)) != GLINT_OK) return st;
-  return texel_mode(c, mode, F[2]);
+  c.R = R;
+  texel_zero_padding(c);
+  texel_window<R>(c, F[0], d->nu, c.ub);
+  texel_window<R>(c, F[1], d->nv, c.vb);
+  if (mode <= 2) texel_p<R>(c, F[3], F[4]);
+  else texel_w<R>(c, F[2]);
+  GLINT_LAUNCHED("texel MTTKRP set-up");
+  return texel_mode<R>(c, mode, F[2], F[3], F[4]);
 }
 
 glint_status check_texel_args(const glint_ndf_desc* d, const float* nxy, int R, void* ws, size_t ws_bytes,
@@ -1386,6 +1751,7 @@ glint_status check_texel_args(const glint_ndf_desc* d, const float* nxy, int R, 
   GLINT_REQUIRE(nxy && ws, "null pointer argument");
   GLINT_SUPPORT(R == 16 || R == 32 || R == 64 || R == 128 || R == 256, "rank %d not in {16,32,64,128,256}", R);
   GLINT_REQUIRE(glint_aligned(ws, 256), "workspace must be 256-byte aligned");
+  GLINT_REQUIRE(glint_aligned(nxy, 8), "nxy must be 8-byte aligned");
   texel_layout(d, R, Lo);
   if (ws_bytes < Lo->total)
     return glint_fail(GLINT_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, Lo->total);
@@ -1393,6 +1759,9 @@ glint_status check_texel_args(const glint_ndf_desc* d, const float* nxy, int R, 
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
     return glint_fail(GLINT_E_HIP, "hipDeviceGetAttribute failed");
+  const int RT = R < 64 ? R : 64;
+  if (static_cast<size_t>(max_lds) < sizeof(double) * 2 * d->nbins * RT)
+    return glint_fail(GLINT_E_UNSUPPORTED, "texel tiles of %d bins do not fit in LDS (%d bytes)", d->nbins, max_lds);
   if (R <= 128 && static_cast<size_t>(max_lds) < sizeof(double) * (R * R + R))
     return glint_fail(GLINT_E_UNSUPPORTED, "rank %d Gram does not fit in LDS (%d bytes)", R, max_lds);
   return GLINT_OK;
@@ -1480,7 +1849,14 @@ glint_status glint_mttkrp_texel(const glint_ndf_desc* desc, const float* nxy, in
   GLINT_REQUIRE(mode >= 0 && mode <= 4, "mode %d outside 0..4", mode);
   GLINT_REQUIRE(U && V && L && S && Tf && M, "null pointer argument");
   const double* F[5] = {U, V, L, S, Tf};
-  return texel_mttkrp(desc, nxy, R, mode, F, M, static_cast<unsigned char*>(workspace), Lo, stream);
+  unsigned char* ws = static_cast<unsigned char*>(workspace);
+  switch (R) {
+    case 16: return texel_mttkrp<16>(desc, nxy, mode, F, M, ws, Lo, stream);
+    case 32: return texel_mttkrp<32>(desc, nxy, mode, F, M, ws, Lo, stream);
+    case 64: return texel_mttkrp<64>(desc, nxy, mode, F, M, ws, Lo, stream);
+    case 128: return texel_mttkrp<128>(desc, nxy, mode, F, M, ws, Lo, stream);
+    default: return texel_mttkrp<256>(desc, nxy, mode, F, M, ws, Lo, stream);
+  }
 }
 
 glint_status glint_cp_als_texel(const glint_ndf_desc* desc, const float* nxy, int32_t R, int32_t iters,

@@ -119,6 +119,11 @@ def test_non_positive_definite_gram_is_reported():
     F, fits, info = _run(T, (16, 16, 2, 16), init, 1)
     assert info[1] > 0
     assert all(np.all(np.isfinite(f)) for f in F)
+    # every Hadamard Gram holds two equal rows, so every update fails and the
+    # initial factors come back unchanged (unit column weights)
+    assert info[1] == 5
+    for a, b in zip(F, init):
+        assert np.array_equal(a, b)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])

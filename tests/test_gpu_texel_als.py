@@ -117,3 +117,21 @@ def test_cp_als_texel_rank256_global_cholesky():
     rec = cp_als.reconstruct(*[f.cpu().numpy() for f in res.factors])
     rec_ref = cp_als.reconstruct(*ref["factors"])
     assert _rel(rec, rec_ref) < 1e-6
+
+
+def test_cp_als_texel_breakdown_rule_matches_dense_gpu():
+    """Duplicate initial columns make every Hadamard Gram singular: both paths
+    report all ten updates as failed and return the initial factors."""
+    nxy = gen.flake_map(16, 16, 9, 0.25, 5)
+    d = G.desc_of(16, 16, 2, 16, 0.05)
+    rng = np.random.default_rng(4)
+    init = [rng.random((n, 16)) for n in (16, 16, 2, 16, 16)]
+    for a in init:
+        a[:, 1] = a[:, 0]
+    T = G.build_tensor(nxy, d, dtype=torch.float64)
+    dense = G.cp_als(T, d, init, 2)
+    tex = G.cp_als_texel(nxy, d, init, 2, normT2=float((T * T).sum()))
+    assert int(tex.info[1]) == int(dense.info[1]) == 10
+    for a, b, c in zip(tex.factors, dense.factors, init):
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+        assert np.array_equal(a, c) and np.array_equal(b, c)
