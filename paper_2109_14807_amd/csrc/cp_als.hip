@@ -461,61 +461,106 @@ __global__ void k_gram(const double* __restrict__ A, int rows, int R, double* __
 
 // One workgroup: G = Hadamard product of the Grams of the modes other than n,
 // lower Cholesky factor in place (LDS), written as Lc and its transpose LcT.
-__global__ __launch_bounds__(1024) void k_cholesky(const double* __restrict__ grams, int n, int R,
+// Cholesky factor of the Hadamard product of the four Grams other than mode n,
+// held in registers: a GD x GD grid of threads, thread (a, b) owning the
+// entries (a + GD e, b + GD f) of the lower triangle (f <= e).  Unscaled
+// right-looking elimination: after step j the trailing block holds
+// G - sum_{m<=j} c_m c_m^T / d_m with c_m the m-th column and d_m its pivot,
+// and the factor L[i][j] = c_j[i] / sqrt(d_j) is formed at the end.  Column j
+// goes through LDS (double-buffered, one barrier per column).  Breakdown: a
+// pivot not above kPivotRtol times the original diagonal entry.
+template <int R>
+__global__ __launch_bounds__(1024) void k_cholesky(const double* __restrict__ grams, int n,
                                                    double* __restrict__ Lc, double* __restrict__ LcT,
                                                    int* __restrict__ ctrl) {
   if (ctrl[CTRL_DONE]) return;
-  extern __shared__ __align__(16) double G[];   // [R*R] matrix, then [R] original diagonal
-  double* diag0 = G + R * R;
-  const int RR = R * R;
-  for (int i = threadIdx.x; i < RR; i += blockDim.x) {
-    double g = 1.0;
-    for (int m = 0; m < 5; ++m)
-      if (m != n) g *= grams[static_cast<int64_t>(m) * RR + i];
-    G[i] = g;
-    if (i % (R + 1) == 0) diag0[i / (R + 1)] = g;
-  }
+  constexpr int GD = R < 32 ? R : 32;
+  constexpr int E = R / GD;
+  constexpr int RR = R * R;
+  __shared__ double col[2][R];
+  __shared__ double diag0[R];
+  const int t = threadIdx.x;
+  const bool active = t < GD * GD;
+  const int a = t / GD, b = t % GD;
+  double g[E][E];
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+#pragma unroll
+    for (int f = 0; f <= e; ++f) {
+      g[e][f] = 0.0;
+      if (active) {
+        const int idx = (a + GD * e) * R + b + GD * f;
+        double v = 1.0;
+        for (int m = 0; m < 5; ++m)
+          if (m != n) v *= grams[static_cast<int64_t>(m) * RR + idx];
+        g[e][f] = v;
+      }
+    }
+  if (active && a == b)
+#pragma unroll
+    for (int e = 0; e < E; ++e) diag0[a + GD * e] = g[e][e];
   __syncthreads();
-  // Unscaled right-looking elimination: after step j the trailing block holds
-  // G - sum_{m<=j} c_m c_m^T / d_m with c_m the m-th column and d_m its pivot;
-  // the factor L[i][j] = c_j[i] / sqrt(d_j) is formed at the end.  One barrier
-  // per column.
   bool fail = false;
   for (int j = 0; j < R; ++j) {
-    const double d = G[j * R + j];
-    // breakdown: a pivot not above kPivotRtol times the original diagonal entry
+    const int buf = j & 1;
+    const int jb = j % GD, jf = j / GD;
+    if (active && b == jb) {
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+#pragma unroll
+        for (int f = 0; f <= e; ++f)
+          if (f == jf && a + GD * e >= j) col[buf][a + GD * e] = g[e][f];
+    }
+    __syncthreads();
+    const double d = col[buf][j];
     if (!(d > kPivotRtol * diag0[j])) {
       fail = true;
       break;
     }
     const double inv = 1.0 / d;
-    const int w = R - j - 1;
-    for (int idx = threadIdx.x; idx < w * w; idx += blockDim.x) {
-      const int i = j + 1 + idx / w, k = j + 1 + idx % w;
-      if (k <= i) G[i * R + k] -= G[i * R + j] * G[k * R + j] * inv;
+    if (active) {
+      double ci[E], ck[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int i = a + GD * e, k = b + GD * e;
+        ci[e] = i > j ? col[buf][i] : 0.0;
+        ck[e] = k > j ? col[buf][k] : 0.0;
+      }
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+#pragma unroll
+        for (int f = 0; f <= e; ++f) {
+          const int i = a + GD * e, k = b + GD * f;
+          if (k > j && i >= k) g[e][f] -= ci[e] * ck[f] * inv;
+        }
     }
-    __syncthreads();
   }
-  if (threadIdx.x == 0) {
+  if (t == 0) {
     ctrl[CTRL_FAILNOW] = fail ? 1 : 0;
     if (fail) ctrl[CTRL_FAILS] += 1;
   }
   if (fail) return;
-  for (int j = threadIdx.x; j < R; j += blockDim.x) diag0[j] = sqrt(G[j * R + j]);
+  // sqrt of the final pivots through LDS (a second array: diag0 may still be
+  // read by threads finishing the last step), then L and L^T
+  __shared__ double dsq[R];
+  if (active && a == b)
+#pragma unroll
+    for (int e = 0; e < E; ++e) dsq[a + GD * e] = sqrt(g[e][e]);
   __syncthreads();
-  for (int idx = threadIdx.x; idx < RR; idx += blockDim.x) {
-    const int i = idx / R, k = idx % R;
-    if (k < i) G[idx] /= diag0[k];
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < R; i += blockDim.x) G[i * R + i] = diag0[i];
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < RR; idx += blockDim.x) {
-    const int i = idx / R, k = idx % R;
-    const double x = k <= i ? G[idx] : 0.0;
-    Lc[idx] = x;
-    LcT[k * R + i] = x;
-  }
+  if (!active) return;
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+#pragma unroll
+    for (int f = 0; f < E; ++f) {
+      const int i = a + GD * e, k = b + GD * f;
+      double x = 0.0;
+      if (f <= e) {
+        if (k < i) x = g[e][f] / dsq[k];
+        else if (k == i) x = dsq[i];
+      }
+      Lc[i * R + k] = x;
+      LcT[k * R + i] = x;
+    }
 }
 
 // One wave per row: x = m G^-1 with G = Lc Lc^T (forward then back substitution).
@@ -791,7 +836,6 @@ glint_status run_als(const glint_ndf_desc* d, const TT* T, int iters, double tol
   constexpr int ROWT = R <= 64 ? 2 : 1;
   constexpr int PAD = sizeof(TT) == 4 ? kPad32 : kPad64;
   const size_t z_lds = sizeof(TT) * R * (2 * N + PAD);
-  const size_t chol_lds = sizeof(double) * (R * R + R);
   TT* UVt = reinterpret_cast<TT*>(ws + Lo.uv);
 
   glint_clear_launch_error();
@@ -803,7 +847,7 @@ glint_status run_als(const glint_ndf_desc* d, const TT* T, int iters, double tol
   GLINT_LAUNCHED("k_gram");
 
   auto update = [&](int n) -> glint_status {
-    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), chol_lds, stream, grams, n, R, Lc, LcT, ctrl);
+    hipLaunchKernelGGL((k_cholesky<R>), dim3(1), dim3(1024), 0, stream, grams, n, Lc, LcT, ctrl);
     GLINT_LAUNCHED("k_cholesky");
     const int rws = rows[n];
     hipLaunchKernelGGL((k_solve<R>), dim3((rws + 15) / 16), dim3(1024), 0, stream, Mb, rws, Lc, LcT, F[n], ctrl);
@@ -918,8 +962,6 @@ glint_status check_als_args(const glint_ndf_desc* desc, const void* T, glint_dty
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
     return glint_fail(GLINT_E_HIP, "hipDeviceGetAttribute failed");
-  if (static_cast<size_t>(max_lds) < sizeof(double) * (R * R + R))
-    return glint_fail(GLINT_E_UNSUPPORTED, "rank %d Gram does not fit in LDS (%d bytes)", R, max_lds);
   const size_t pad = T_dtype == GLINT_F32 ? kPad32 : kPad64;
   if (static_cast<size_t>(max_lds) < glint_dtype_size(T_dtype) * R * (2 * desc->nbins + pad))
     return glint_fail(GLINT_E_UNSUPPORTED, "rank %d x %d bins factor block does not fit in LDS", R,
@@ -944,6 +986,7 @@ glint_status check_als_args(const glint_ndf_desc* desc, const void* T, glint_dty
 // where they are needed from factor tiles in LDS.  All FP64.
 // ===========================================================================
 
+constexpr int kMassPad = 16;        // largest unrolled bin window
 constexpr int kTexThreads = 1024;    // one block shares its LDS factor tiles among 16 wavefronts
 constexpr int kMaxLevels = 16;
 
@@ -961,13 +1004,27 @@ __device__ __forceinline__ void stage_rank_tile(const double* __restrict__ F, in
   for (int i = threadIdx.x; i < N * RT; i += blockDim.x) tile[i] = F[(i / RT) * R + r0 + i % RT];
 }
 
-// sum_j m[j] F[i0 + j][r] over a texel's bin window.  The window masses of bins
-// outside [0, N) are zero, so the row is clamped rather than tested.
-template <int RT>
+// sum_j m[j] F[i0 + j][r] over a texel's bin window of P = 2K + 1 bins.  The
+// window masses of bins outside [0, N) are zero, so the row is clamped rather
+// than tested.  With PMAX > 0 (P <= PMAX) the loop is unrolled to PMAX with
+// all loads issued first; the mass array is padded so that reading PMAX
+// entries stays inside it, and entries past P are discarded by a select.
+template <int RT, int PMAX>
 __device__ __forceinline__ double window_dot(const double* __restrict__ m, int i0, int P, int N,
                                              const double* tile, int rr) {
   double acc = 0.0;
-  for (int j = 0; j < P; ++j) acc += m[j] * tile[glint_clampi(i0 + j, 0, N - 1) * RT + rr];
+  if constexpr (PMAX > 0) {
+    double mv[PMAX], tv[PMAX];
+#pragma unroll
+    for (int j = 0; j < PMAX; ++j) {
+      mv[j] = m[j];
+      tv[j] = tile[glint_clampi(i0 + j, 0, N - 1) * RT + rr];
+    }
+#pragma unroll
+    for (int j = 0; j < PMAX; ++j) acc += (j < P ? mv[j] : 0.0) * tv[j];
+  } else {
+    for (int j = 0; j < P; ++j) acc += m[j] * tile[glint_clampi(i0 + j, 0, N - 1) * RT + rr];
+  }
   return acc;
 }
 
@@ -997,7 +1054,7 @@ __device__ __forceinline__ float lane_f(float v, int k) {
 }
 
 // Pm[tex][r] = gs[tex][r] * gt[tex][r]
-template <int R>
+template <int R, int PMAX>
 __global__ __launch_bounds__(kTexThreads) void k_texel_p(const float2* __restrict__ nxy,
                                                          const int32_t* __restrict__ bins,
                                                          const double* __restrict__ mass, int64_t ntex,
@@ -1033,7 +1090,7 @@ __global__ __launch_bounds__(kTexThreads) void k_texel_p(const float2* __restric
         if (!same_normal(n, prev)) {
           const int bx = __builtin_amdgcn_readlane(bm.x, k), by = __builtin_amdgcn_readlane(bm.y, k);
           const double* ms = mass + tex * 2 * P;
-          val = window_dot<RT>(ms, bx - K, P, N, sS, rr) * window_dot<RT>(ms + P, by - K, P, N, sT, rr);
+          val = window_dot<RT, PMAX>(ms, bx - K, P, N, sS, rr) * window_dot<RT, PMAX>(ms + P, by - K, P, N, sT, rr);
           prev = n;
         }
         Pm[tex * R + r0 + rr] = val;
@@ -1047,7 +1104,8 @@ __global__ __launch_bounds__(kTexThreads) void k_texel_p(const float2* __restric
         if (!same_normal(n, prev)) {
           const int2 b = b2[tex];
           const double* ms = mass + tex * 2 * P;
-          val = window_dot<RT>(ms, b.x - K, P, N, sS, rr) * window_dot<RT>(ms + P, b.y - K, P, N, sT, rr);
+          val = window_dot<RT, PMAX>(ms, b.x - K, P, N, sS, rr) *
+                window_dot<RT, PMAX>(ms + P, b.y - K, P, N, sT, rr);
           prev = n;
         }
         Pm[tex * R + r0 + rr] = val;
@@ -1199,7 +1257,7 @@ __global__ __launch_bounds__(256) void k_texel_w(const double* __restrict__ Ub, 
 // one normal shares g and the masses, so it adds g * (sum of its Wt) once.  A
 // block sums a chunk of texels for RT ranks in LDS and stores the tile in its
 // slot of parts[chunk][N][R]; the slots are summed afterwards (fixed order).
-template <int R, int AXIS>
+template <int R, int AXIS, int PMAX>
 __global__ __launch_bounds__(kTexThreads) void k_texel_scatter(const float2* __restrict__ nxy,
                                                                const int32_t* __restrict__ bins,
                                                                const double* __restrict__ mass, int64_t ntex,
@@ -1228,16 +1286,27 @@ __global__ __launch_bounds__(kTexThreads) void k_texel_scatter(const float2* __r
   auto flush = [&]() {
     if (mo == nullptr) return;
     const double q = g * wsum;
-    for (int j = 0; j < P; ++j) {
-      const int i = i0 + j;
-      if (i >= 0 && i < N) atomicAdd(&acc[i * RT + rr], mo[j] * q);
+    if constexpr (PMAX > 0) {
+      double mv[PMAX];
+#pragma unroll
+      for (int j = 0; j < PMAX; ++j) mv[j] = mo[j];
+#pragma unroll
+      for (int j = 0; j < PMAX; ++j) {
+        const int i = i0 + j;
+        if (j < P && i >= 0 && i < N) atomicAdd(&acc[i * RT + rr], mv[j] * q);
+      }
+    } else {
+      for (int j = 0; j < P; ++j) {
+        const int i = i0 + j;
+        if (i >= 0 && i < N) atomicAdd(&acc[i * RT + rr], mo[j] * q);
+      }
     }
   };
   auto start_run = [&](int64_t tex, float2 n, int bx, int by) {
     flush();
     mo = mass + (2 * tex + AXIS) * P;
     i0 = (AXIS ? by : bx) - K;
-    g = window_dot<RT>(mass + (2 * tex + (1 - AXIS)) * P, (AXIS ? bx : by) - K, P, N, sF, rr);
+    g = window_dot<RT, PMAX>(mass + (2 * tex + (1 - AXIS)) * P, (AXIS ? bx : by) - K, P, N, sF, rr);
     wsum = 0.0;
     prev = n;
   };
@@ -1386,52 +1455,8 @@ __global__ __launch_bounds__(256) void k_gram_parts(const double* __restrict__ A
   parts[static_cast<int64_t>(blockIdx.z) * R * R + i * R + j] = acc;
 }
 
-// Cholesky in global memory (ranks whose Gram does not fit in LDS); same
-// algorithm and breakdown rule as k_cholesky.
-__global__ __launch_bounds__(1024) void k_cholesky_global(const double* __restrict__ grams, int n, int R,
-                                                          double* __restrict__ G, double* __restrict__ Lc,
-                                                          double* __restrict__ LcT, int* __restrict__ ctrl) {
-  if (ctrl[CTRL_DONE]) return;
-  double* diag0 = G + R * R;
-  const int RR = R * R;
-  for (int i = threadIdx.x; i < RR; i += blockDim.x) {
-    double g = 1.0;
-    for (int m = 0; m < 5; ++m)
-      if (m != n) g *= grams[static_cast<int64_t>(m) * RR + i];
-    G[i] = g;
-    if (i % (R + 1) == 0) diag0[i / (R + 1)] = g;
-  }
-  __syncthreads();
-  bool fail = false;
-  for (int j = 0; j < R; ++j) {
-    const double d = G[j * R + j];
-    if (!(d > kPivotRtol * diag0[j])) {
-      fail = true;
-      break;
-    }
-    const double inv = 1.0 / d;
-    const int w = R - j - 1;
-    for (int idx = threadIdx.x; idx < w * w; idx += blockDim.x) {
-      const int i = j + 1 + idx / w, k = j + 1 + idx % w;
-      if (k <= i) G[i * R + k] -= G[i * R + j] * G[k * R + j] * inv;
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    ctrl[CTRL_FAILNOW] = fail ? 1 : 0;
-    if (fail) ctrl[CTRL_FAILS] += 1;
-  }
-  if (fail) return;
-  for (int idx = threadIdx.x; idx < RR; idx += blockDim.x) {
-    const int i = idx / R, k = idx % R;
-    const double x = k < i ? G[idx] / sqrt(G[k * R + k]) : (k == i ? sqrt(G[idx]) : 0.0);
-    Lc[idx] = x;
-    LcT[k * R + i] = x;
-  }
-}
-
 struct TexelLayout {
-  size_t bins, mass, pm, ub, vb, hb, hpref, cpre, parts, gparts, m, grams, lc, lct, cholg, lam, scal, ctrl, total;
+  size_t bins, mass, pm, ub, vb, hb, hpref, cpre, parts, gparts, m, grams, lc, lct, lam, scal, ctrl, total;
   int64_t chunk_p, chunk_s, nchunk_s;
   int gsplit;
 };
@@ -1459,7 +1484,7 @@ void texel_layout(const glint_ndf_desc* d, int R, TexelLayout* L) {
     return at;
   };
   L->bins = take(sizeof(int32_t) * 2 * ntex);
-  L->mass = take(sizeof(double) * 2 * ntex * P);
+  L->mass = take(sizeof(double) * (2 * ntex * P + kMassPad));   // padded for the unrolled window reads
   L->pm = take(sizeof(double) * ntex * R);
   const int nlp = (d->nlevels + 3) / 4 * 4;   // levels padded to a multiple of 4
   L->ub = take(sizeof(double) * nlp * d->nu * R);
@@ -1473,7 +1498,6 @@ void texel_layout(const glint_ndf_desc* d, int R, TexelLayout* L) {
   L->grams = take(sizeof(double) * 5 * R * R);
   L->lc = take(sizeof(double) * R * R);
   L->lct = take(sizeof(double) * R * R);
-  L->cholg = take(sizeof(double) * (R * R + R));
   L->lam = take(sizeof(double) * R);
   L->scal = take(sizeof(double) * 4);
   L->ctrl = take(sizeof(int) * CTRL_N);
@@ -1538,13 +1562,41 @@ inline int inner_split(int outer, int inner, int R) {
   return static_cast<int>(std::max<int64_t>(s, 1));
 }
 
-template <int R>
-void texel_p(const TexelCtx& c, const double* S, const double* Tf) {
+// the unrolled bin-window bound for a window of P bins (0: not unrolled)
+inline int window_pmax(int P) { return P <= 8 ? 8 : (P <= kMassPad ? kMassPad : 0); }
+
+template <int R, int PMAX>
+void texel_p_pm(const TexelCtx& c, const double* S, const double* Tf) {
   constexpr int RT = TexTile<R>::RT;
   const int64_t ntex = static_cast<int64_t>(c.d->nu) * c.d->nv;
   const dim3 grid(R / RT, static_cast<unsigned>((ntex + c.lo->chunk_p - 1) / c.lo->chunk_p));
-  hipLaunchKernelGGL((k_texel_p<R>), grid, dim3(kTexThreads), sizeof(double) * 2 * c.d->nbins * RT, c.stream,
-                     c.nxy, c.bins, c.mass, ntex, c.K, c.d->nbins, c.lo->chunk_p, S, Tf, c.pm, c.ctrl);
+  hipLaunchKernelGGL((k_texel_p<R, PMAX>), grid, dim3(kTexThreads), sizeof(double) * 2 * c.d->nbins * RT,
+                     c.stream, c.nxy, c.bins, c.mass, ntex, c.K, c.d->nbins, c.lo->chunk_p, S, Tf, c.pm, c.ctrl);
+}
+
+template <int R>
+void texel_p(const TexelCtx& c, const double* S, const double* Tf) {
+  switch (window_pmax(2 * c.K + 1)) {
+    case 8: texel_p_pm<R, 8>(c, S, Tf); break;
+    case kMassPad: texel_p_pm<R, kMassPad>(c, S, Tf); break;
+    default: texel_p_pm<R, 0>(c, S, Tf); break;
+  }
+}
+
+template <int R, int AXIS, int PMAX>
+void texel_scatter_pm(const TexelCtx& c, const double* F, dim3 grid, size_t lds) {
+  const int64_t ntex = static_cast<int64_t>(c.d->nu) * c.d->nv;
+  hipLaunchKernelGGL((k_texel_scatter<R, AXIS, PMAX>), grid, dim3(kTexThreads), lds, c.stream, c.nxy, c.bins,
+                     c.mass, ntex, c.K, c.d->nbins, c.lo->chunk_s, F, c.pm, c.parts, c.ctrl);
+}
+
+template <int R, int AXIS>
+void texel_scatter(const TexelCtx& c, const double* F, dim3 grid, size_t lds) {
+  switch (window_pmax(2 * c.K + 1)) {
+    case 8: texel_scatter_pm<R, AXIS, 8>(c, F, grid, lds); break;
+    case kMassPad: texel_scatter_pm<R, AXIS, kMassPad>(c, F, grid, lds); break;
+    default: texel_scatter_pm<R, AXIS, 0>(c, F, grid, lds); break;
+  }
 }
 
 template <int R>
@@ -1632,12 +1684,8 @@ glint_status texel_mode(const TexelCtx& c, int mode, const double* L, const doub
   const int64_t ntex = static_cast<int64_t>(nu) * nv;
   const dim3 grid(R / RT, static_cast<unsigned>(c.lo->nchunk_s));
   const size_t lds = sizeof(double) * 2 * N * RT;
-  if (mode == 3)
-    hipLaunchKernelGGL((k_texel_scatter<R, 0>), grid, dim3(kTexThreads), lds, st, c.nxy, c.bins, c.mass, ntex, c.K,
-                       N, c.lo->chunk_s, Tf, c.pm, c.parts, c.ctrl);
-  else
-    hipLaunchKernelGGL((k_texel_scatter<R, 1>), grid, dim3(kTexThreads), lds, st, c.nxy, c.bins, c.mass, ntex, c.K,
-                       N, c.lo->chunk_s, S, c.pm, c.parts, c.ctrl);
+  if (mode == 3) texel_scatter<R, 0>(c, Tf, grid, lds);
+  else texel_scatter<R, 1>(c, S, grid, lds);
   const int64_t n = static_cast<int64_t>(N) * R;
   hipLaunchKernelGGL(k_reduce_splits<double>, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st,
                      c.parts, static_cast<int>(c.lo->nchunk_s), n, c.M, c.ctrl);
@@ -1679,7 +1727,6 @@ glint_status run_texel_als(const glint_ndf_desc* d, const float* nxy, int iters,
   double* grams = reinterpret_cast<double*>(ws + Lo.grams);
   double* Lc = reinterpret_cast<double*>(ws + Lo.lc);
   double* LcT = reinterpret_cast<double*>(ws + Lo.lct);
-  double* cholg = reinterpret_cast<double*>(ws + Lo.cholg);
   double* lam = reinterpret_cast<double*>(ws + Lo.lam);
   double* scal = reinterpret_cast<double*>(ws + Lo.scal);
   glint_status st = glint_texel_bins(d, nxy, c.bins, c.mass, stream);
@@ -1692,11 +1739,7 @@ glint_status run_texel_als(const glint_ndf_desc* d, const float* nxy, int iters,
   for (int m = 0; m < 5; ++m) texel_gram<R>(c, F[m], rows[m], grams + m * R * R);
   GLINT_LAUNCHED("texel ALS init");
   auto update = [&](int n) -> glint_status {
-    if constexpr (R <= 128)
-      hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), sizeof(double) * (R * R + R), stream, grams, n, R, Lc,
-                         LcT, c.ctrl);
-    else
-      hipLaunchKernelGGL(k_cholesky_global, dim3(1), dim3(1024), 0, stream, grams, n, R, cholg, Lc, LcT, c.ctrl);
+    hipLaunchKernelGGL((k_cholesky<R>), dim3(1), dim3(1024), 0, stream, grams, n, Lc, LcT, c.ctrl);
     hipLaunchKernelGGL((k_solve<R>), dim3((rows[n] + 15) / 16), dim3(1024), 0, stream, c.M, rows[n], Lc, LcT,
                        F[n], c.ctrl);
     hipLaunchKernelGGL(k_normalize_gram, dim3(1), dim3(1024), 0, stream, F[n], rows[n], R, lam,
@@ -1762,8 +1805,6 @@ glint_status check_texel_args(const glint_ndf_desc* d, const float* nxy, int R, 
   const int RT = R < 64 ? R : 64;
   if (static_cast<size_t>(max_lds) < sizeof(double) * 2 * d->nbins * RT)
     return glint_fail(GLINT_E_UNSUPPORTED, "texel tiles of %d bins do not fit in LDS (%d bytes)", d->nbins, max_lds);
-  if (R <= 128 && static_cast<size_t>(max_lds) < sizeof(double) * (R * R + R))
-    return glint_fail(GLINT_E_UNSUPPORTED, "rank %d Gram does not fit in LDS (%d bytes)", R, max_lds);
   return GLINT_OK;
 }
 
