@@ -111,3 +111,69 @@ def test_refinement_lowers_the_loss():
     _, losses = G.refine(*noisy, q, target, steps=60, lr=3e-3)
     losses = losses.cpu().numpy()
     assert losses[-1] < 0.5 * losses[0]
+
+
+def test_backward_c4_full_batch_sparse_gout():
+    """The 2048x2048, N = 64, 10-level, rank-128 FP32 shape with the whole
+    2^24-record batch in one backward launch; gout is zero except on 10^4
+    sampled records, so by linearity the gradients equal the oracle gradient
+    of those records alone."""
+    import gen
+    cfg = gen.config("c4")
+    nxy = gen.normal_map(cfg)
+    q = gen.make_queries(cfg, nxy)
+    rng = np.random.default_rng(44)
+    F = _rand(rng, cfg.nu, cfg.nv, cfg.nlevels, cfg.nbins, cfg.rank)
+    idx = np.sort(rng.choice(q.shape[0], 10_000, replace=False))
+    g = np.zeros(q.shape[0], dtype=np.float32)
+    g[idx] = rng.standard_normal(idx.size).astype(np.float32)
+    Ft = [torch.tensor(x, dtype=torch.float32, device="cuda") for x in F]
+    tabs = G.make_tables(*Ft)
+    got = G.query_backward(tabs, torch.tensor(q, device="cuda"), torch.tensor(g, device="cuda"))
+    F32 = [np.asarray(x, dtype=np.float32).astype(np.float64) for x in F]
+    CS, CT = (np.float32(query.cumulative(x)).astype(np.float64) for x in F32[3:])
+    want = query.range_query_grad(F32[0], F32[1], F32[2], CS, CT, q[idx], g[idx].astype(np.float64))
+    for a, w, name in zip(got, want, ("dU", "dV", "dL", "dCS", "dCT")):
+        _close(a.cpu().numpy(), w, name)
+
+
+def test_backward_c4_finite_differences_fp64():
+    """FD check on 64 random factor entries at the 2048x2048, N = 64, 10-level,
+    rank-128 shape: the GPU gradient of sum_i g_i q_i (10^4 records with
+    nonzero g inside the 2^24 batch) against FP64 central differences of the
+    oracle query.  The query is linear in each single entry, so the difference
+    quotient is exact up to rounding; S and T enter through their summed-area
+    tables (chain rule by glint_cumulative_backward)."""
+    import gen
+    cfg = gen.config("c4")
+    nxy = gen.normal_map(cfg)
+    q = gen.make_queries(cfg, nxy)
+    rng = np.random.default_rng(4004)
+    F = [np.asarray(x, dtype=np.float32).astype(np.float64)
+         for x in _rand(rng, cfg.nu, cfg.nv, cfg.nlevels, cfg.nbins, cfg.rank)]
+    idx = np.sort(rng.choice(q.shape[0], 10_000, replace=False))
+    g = np.zeros(q.shape[0], dtype=np.float32)
+    g[idx] = rng.standard_normal(idx.size).astype(np.float32)
+    tabs = G.make_tables(*[torch.tensor(x, dtype=torch.float32, device="cuda") for x in F])
+    dU, dV, dL, dCS, dCT = G.query_backward(tabs, torch.tensor(q, device="cuda"), torch.tensor(g, device="cuda"))
+    grads = [dU.cpu().numpy(), dV.cpu().numpy(), dL.cpu().numpy(),
+             G.cumulative_backward(dCS).cpu().numpy(), G.cumulative_backward(dCT).cpu().numpy()]
+    qs, gs = q[idx], g[idx].astype(np.float64)
+
+    def loss(Fx):
+        CS, CT = query.cumulative(Fx[3]), query.cumulative(Fx[4])
+        return float(np.dot(gs, query.range_query(Fx[0], Fx[1], Fx[2], CS, CT, qs)))
+
+    scale = max(float(np.max(np.abs(x))) for x in grads)
+    worst = 0.0
+    for _ in range(64):
+        m = int(rng.integers(0, 5))
+        i, r = int(rng.integers(0, F[m].shape[0])), int(rng.integers(0, F[m].shape[1]))
+        h = 1e-3 * max(abs(F[m][i, r]), 1.0)
+        Fp = [x.copy() for x in F]
+        Fm = [x.copy() for x in F]
+        Fp[m][i, r] += h
+        Fm[m][i, r] -= h
+        fd = (loss(Fp) - loss(Fm)) / (2 * h)
+        worst = max(worst, abs(grads[m][i, r] - fd) / scale)
+    assert worst <= 1e-5, worst

@@ -207,3 +207,45 @@ def test_query_c2_full_batch_sampled():
     idx[-1] = q.shape[0] - 1
     want, mag = _oracle(F, q[idx], "f32", "f32")
     _check(got[idx], want, mag)
+
+
+def test_query_c3_bf16_full_batch_sampled():
+    """The 2048x2048, N = 64, 10-level, rank-128 shape with BF16 factors and
+    BF16 summed-area tables, the whole 6.4e7-record footprint batch in one
+    launch; 10^5 outputs (and the last) against the oracle on the stored values."""
+    cfg = gen.config("c3")
+    nxy = gen.normal_map(cfg)
+    print(f"c3: generating {cfg.nqueries} records", flush=True)
+    q = gen.make_queries(cfg, nxy)
+    rng = np.random.default_rng(33)
+    F = _rand_factors(rng, cfg.nu, cfg.nv, cfg.nlevels, cfg.nbins, cfg.rank)
+    tabs = G.make_tables(*[torch.tensor(x, device="cuda") for x in F], dtype="bf16", cum_dtype="bf16")
+    got = G.query(tabs, torch.tensor(q, device="cuda")).cpu().numpy()
+    idx = np.sort(rng.choice(q.shape[0], 100_000, replace=False))
+    idx[-1] = q.shape[0] - 1
+    want, mag = _oracle(F, q[idx], "bf16", "bf16")
+    _check(got[idx], want, mag)
+    print(f"c3 bf16: max |err| / N_q = {np.max(np.abs(got[idx] - want) / np.maximum(mag, 1e-300)):.2e}")
+
+
+def test_grouped_c5_fp8_full_batch_sampled():
+    """The 4096x4096 scratch shape, N = 128, 12 levels, rank 256, FP8 factors with
+    per-column scales and BF16 tables: 2^20 shading points x 32 boxes in one
+    grouped launch; 10^5 outputs against the oracle on the stored values."""
+    cfg = gen.config("c5")
+    nxy = gen.normal_map(cfg)
+    print("c5: generating 2^20 x 32 boxes", flush=True)
+    uvl, boxes = gen.make_grouped_queries(cfg, nxy)
+    rng = np.random.default_rng(55)
+    F = _rand_factors(rng, cfg.nu, cfg.nv, cfg.nlevels, cfg.nbins, cfg.rank)
+    tabs = G.make_tables(*[torch.tensor(x, device="cuda") for x in F], dtype="fp8", cum_dtype="bf16")
+    got = G.query_grouped(tabs, torch.tensor(uvl, device="cuda"), torch.tensor(boxes, device="cuda"))
+    got = got.cpu().numpy().reshape(-1)
+    npts, K = boxes.shape[:2]
+    idx = np.sort(rng.choice(npts * K, 100_000, replace=False))
+    idx[-1] = npts * K - 1
+    p, k = idx // K, idx % K
+    flat = np.concatenate([uvl[p], boxes[p, k]], axis=1).astype(np.int32)
+    want, mag = _oracle(F, flat, "fp8", "bf16")
+    _check(got[idx], want, mag)
+    print(f"c5 fp8/bf16: max |err| / N_q = {np.max(np.abs(got[idx] - want) / np.maximum(mag, 1e-300)):.2e}")
