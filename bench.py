@@ -67,6 +67,9 @@ def parse():
                     help="events-timed launches of the MTTKRP and query kernels")
     ap.add_argument("--refine-steps", type=int, default=100,
                     help="Adam steps of the BF16 refinement report (0 to skip)")
+    ap.add_argument("--configs", default="",
+                    help="comma-separated extra workloads (c1, c3, c4, c5) run end to end on their own "
+                         "ALS factors after the step, reported under 'configs'")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 2 GiB device copy (read 2 GiB, write 2 GiB) after the "
                          "steps, the reference for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE")
@@ -274,6 +277,13 @@ def main():
     if args.refine_steps > 0:
         res["refinement"] = refine_report(cfg, nxy_h, desc, F, q, q_bf, args.refine_steps, timed)
         log(f"refinement report done: {res['refinement']}")
+    if args.configs:
+        res["configs"] = {}
+        for name in [c.strip() for c in args.configs.split(",") if c.strip()]:
+            log(f"workload {name}")
+            res["configs"][name] = config_report(name, args.sweeps, timed)
+            log(f"workload {name}: {res['configs'][name]}")
+            torch.cuda.empty_cache()
     if args.copy_calibration:
         src = torch.ones(1 << 29, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -334,6 +344,119 @@ def refine_report(cfg, nxy_h, desc, F, q, q_bf, steps, timed):
         "speedup_bf16_over_f32": ms_plain / ms_bf16,
         "equal_or_lower_error": bool(e_bf16 <= e_plain),
     }
+
+
+def config_report(name, sweeps, timed):
+    """One workload end to end on its own inputs: CP-ALS (dense FP64 tensor for
+    the 64x64 map, texel-space ALS for the maps whose tensor does not fit),
+    query tables in the workload's storage types, the batch's query time, and
+    the relative L2 error against brute-force range integrals on a sample of
+    the batch (the FP32 tables' error beside it).  The 2048x2048 FP32 workload
+    adds Adam refinement of the factors over its 2^24-record batch."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2109_14807_amd as G
+    from paper_2109_14807_amd import _lib as L
+
+    dev = torch.device("cuda:0")
+    cfg = gen.config(name)
+    t0 = time.time()
+    nxy_h = gen.normal_map(cfg)
+    nxy = torch.tensor(nxy_h, device=dev)
+    desc = G.desc_of(cfg.nu, cfg.nv, cfg.nlevels, cfg.nbins, cfg.sigma)
+    grouped = cfg.query_kind == "sg_grouped"
+    if grouped:
+        uvl_h, boxes_h = gen.make_grouped_queries(cfg, nxy_h)
+        uvl, boxes = torch.tensor(uvl_h, device=dev), torch.tensor(boxes_h, device=dev)
+        nq = boxes_h.shape[0] * boxes_h.shape[1]
+    else:
+        q_h = gen.make_queries(cfg, nxy_h)
+        q = torch.tensor(q_h, device=dev)
+        nq = q_h.shape[0]
+    rep = {"inputs_s": time.time() - t0, "queries": nq, "rank": cfg.rank, "sweeps": sweeps,
+           "storage": f"{cfg.dtype}/{cfg.cum_dtype}"}
+    log(f"  {name}: inputs ready ({nq} queries)")
+    init = [torch.tensor(a, device=dev) for a in gen.als_init(cfg)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if cfg.nu * cfg.nv <= 64 * 64:
+        T = G.build_tensor(nxy, desc, dtype=torch.float64)
+        res = G.cp_als(T, desc, init, sweeps)
+        rep["als"] = "dense FP64"
+        torch.cuda.synchronize()
+        rep["fit"] = float(res.fits[-1])
+        del T
+    else:
+        res = G.cp_als_texel(nxy, desc, init, sweeps)
+        rep["als"] = "texel-space FP64"
+        torch.cuda.synchronize()
+        rep["fit"] = None
+    rep["als_s"] = time.perf_counter() - t0
+    F = res.factors
+    log(f"  {name}: ALS done in {rep['als_s']:.2f}s")
+
+    # brute-force sample of the batch
+    rng = np.random.default_rng(11)
+    ns = min(nq, 1 << 18)
+    idx = torch.tensor(np.sort(rng.choice(nq, ns, replace=False)), device=dev)
+    if grouped:
+        K = boxes.shape[1]
+        flat = torch.cat([uvl[idx // K], boxes.reshape(-1, 4)[idx]], dim=1).contiguous()
+    else:
+        flat = q[idx].contiguous()
+    bins, mass = G.texel_bins(nxy, desc)
+    bf = torch.empty(ns, dtype=torch.float64, device=dev)
+    L.glint_range_bruteforce(desc, bins, mass, flat, bf)
+
+    def ebf(tables):
+        out = G.query(tables, flat)
+        return float((torch.linalg.vector_norm(out.double() - bf) / torch.linalg.vector_norm(bf)).item())
+
+    tabs = G.make_tables(*F, dtype=cfg.dtype, cum_dtype=cfg.cum_dtype)
+    f32 = G.make_tables(*F)
+    rep["error_vs_bruteforce"] = ebf(tabs)
+    rep["error_vs_bruteforce_f32_tables"] = ebf(f32)
+    fac = tabs.factors()
+    if grouped:
+        out = torch.empty(boxes.shape[:2], dtype=torch.float32, device=dev)
+        ms = timed(lambda: L.glint_query_grouped(fac, uvl, boxes, out))
+    else:
+        out = torch.empty(nq, dtype=torch.float32, device=dev)
+        ms = timed(lambda: L.glint_query(fac, q, out))
+    rep["query_ms"] = ms
+    rep["queries_per_s"] = nq / (ms * 1e-3)
+    if name == "c4":
+        # Adam refinement of the FP32 factors over the whole batch, against its
+        # brute-force integrals; error on a held-out batch of the same recipe
+        t0 = time.time()
+        tgt = torch.empty(nq, dtype=torch.float64, device=dev)
+        L.glint_range_bruteforce(desc, bins, mass, q, tgt)
+        q_ev = torch.tensor(gen.make_queries(cfg, nxy_h, nq=1 << 18, seed=gen.query_seed(cfg) + 7,
+                                             shuffle=True), device=dev)
+        bf_ev = torch.empty(q_ev.shape[0], dtype=torch.float64, device=dev)
+        L.glint_range_bruteforce(desc, bins, mass, q_ev, bf_ev)
+        torch.cuda.synchronize()
+        rep["refine_targets_s"] = time.time() - t0
+        log(f"  {name}: brute-force targets in {rep['refine_targets_s']:.1f}s; refining")
+        masters = [f.float() for f in F]
+        rms = float(torch.sqrt(torch.mean(torch.cat([m.flatten() for m in masters]) ** 2)).item())
+        steps = 200
+        t0 = time.perf_counter()
+        refined, losses = G.refine(*masters, q, tgt, steps=steps, lr=1e-3 * rms, dtype="f32")
+        torch.cuda.synchronize()
+        rep["refine_ms_per_step"] = (time.perf_counter() - t0) * 1e3 / steps
+
+        def ebf_ev(tables):
+            o = G.query(tables, q_ev)
+            return float((torch.linalg.vector_norm(o.double() - bf_ev) / torch.linalg.vector_norm(bf_ev)).item())
+
+        rep["heldout_error_before"] = ebf_ev(f32)
+        rep["heldout_error_after_200_adam"] = ebf_ev(G.make_tables(*refined))
+        ls = losses.cpu().numpy()
+        rep["train_loss_first_last"] = [float(ls[0]), float(ls[-1])]
+    return rep
 
 
 def cpu_baseline(cfg, nxy_h, q_h, out_dev, P, F, CS, CT, sweeps, nq):

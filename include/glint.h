@@ -229,8 +229,9 @@ glint_status glint_convert(int64_t rows, int32_t R, const void* in, glint_dtype 
 
 /* out[i] for each record q[i] (int32 [nq][7], see the header comment), FP32
  * arithmetic on values decoded exactly from their storage types.
- * nq = 0 is a no-op.  Requires f->nbins in 4..256 and the tables to fit the
- * kernel's on-chip staging (L, CS, CT together at most 96 KiB as FP32). */
+ * nq = 0 is a no-op.  Requires f->nbins in 4..256.  L is staged in LDS as
+ * FP32 (nl * R * 4 bytes); CS and CT are staged there too (as BF16 when so
+ * stored, else FP32) when they fit, and otherwise read from global memory. */
 glint_status glint_query(const glint_factors* f, int64_t nq, const int32_t* q,
                          float* out, hipStream_t stream);
 
@@ -247,7 +248,10 @@ glint_status glint_query_grouped(const glint_factors* f, int64_t npts, int32_t K
  * V, L, CS and CT (FP32, overwritten: the call clears them first).  f->dtype
  * and f->cum_dtype must be F32 or BF16.  dU [nu][R], dV [nv][R], dL [nl][R],
  * dCS, dCT [N+1][R].  Accumulation uses atomics, so the summation order (and
- * the last bits) vary between runs. */
+ * the last bits) vary between runs.  L, CS, CT and their gradient
+ * accumulators are held in LDS: 8 (nl + 2 (N + 1)) R + 4 R bytes plus 16 KiB
+ * of record slots must fit (e.g. rank 128 with N = 64 and 10 levels);
+ * larger tables return GLINT_E_UNSUPPORTED. */
 glint_status glint_query_backward(const glint_factors* f, int64_t nq, const int32_t* q,
                                   const float* gout, float* dU, float* dV, float* dL,
                                   float* dCS, float* dCT, hipStream_t stream);

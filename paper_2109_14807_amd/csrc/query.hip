@@ -40,6 +40,25 @@ __device__ __forceinline__ void load_row(const FT* __restrict__ p, float* out) {
   for (int i = 0; i < RPL; ++i) out[i] = dec<FT>(e[i]);
 }
 
+// Load RPL consecutive stored elements of a summed-area table row from
+// global memory (aligned to the slice size) and decode them to FP32: whole
+// 16-byte words where the slice allows, else one 8-, 4- or 2-byte word.
+template <typename CT, int RPL>
+__device__ __forceinline__ void load_cum_row(const CT* __restrict__ p, float* out) {
+  constexpr int BYTES = RPL * static_cast<int>(sizeof(CT));
+  if constexpr (BYTES % 16 == 0) {
+    load_row<CT, RPL>(p, out);
+  } else {
+    static_assert(BYTES == 8 || BYTES == 4 || BYTES == 2, "row slice");
+    typedef typename std::conditional<BYTES == 8, uint2,
+            typename std::conditional<BYTES == 4, uint32_t, uint16_t>::type>::type W;
+    const W w = *reinterpret_cast<const W*>(p);
+    const CT* e = reinterpret_cast<const CT*>(&w);
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) out[i] = dec<CT>(e[i]);
+  }
+}
+
 struct Scales {
   const float* s[5];   // U, V, L, CS, CT; NULL = 1
 };
@@ -153,7 +172,16 @@ __device__ __forceinline__ void lds_cum_row(const LT* p, float* out) {
   }
 }
 
-template <typename FT, typename CT, int R, int RPL>
+// One summed-area row slice as FP32, from LDS or (GC) from global memory.
+template <bool GC, typename CT, typename LT, int RPL>
+__device__ __forceinline__ void cum_row(const LT* lds_tab, const CT* __restrict__ glob_tab, int off, float* out) {
+  if constexpr (GC) load_cum_row<CT, RPL>(glob_tab + off, out);
+  else lds_cum_row<LT, RPL>(lds_tab + off, out);
+}
+
+// GC: the summed-area tables are too large for LDS and are read from global
+// memory (L2-resident); L stays in LDS.
+template <typename FT, typename CT, int R, int RPL, bool GC>
 __global__ __launch_bounds__(kQueryThreads) void k_query(QueryArgs a) {
   constexpr int LPQ = R / RPL;           // lanes per query
   static_assert(LPQ >= 1 && LPQ <= 64, "lanes per query");
@@ -162,12 +190,16 @@ __global__ __launch_bounds__(kQueryThreads) void k_query(QueryArgs a) {
   float* Ls = lds;
   LT* CSs = reinterpret_cast<LT*>(Ls + a.nl * R);
   LT* CTs = CSs + (a.N + 1) * R;
+  const size_t cum_bytes = GC ? 0 : 2 * sizeof(LT) * (a.N + 1) * R;
   QueryRows* rows = reinterpret_cast<QueryRows*>(
-      reinterpret_cast<unsigned char*>(lds) +
-      glint_round_up(sizeof(float) * a.nl * R + 2 * sizeof(LT) * (a.N + 1) * R, 16));   // [waves][64]
+      reinterpret_cast<unsigned char*>(lds) + glint_round_up(sizeof(float) * a.nl * R + cum_bytes, 16));
+  const CT* CSg = static_cast<const CT*>(a.CS);
+  const CT* CTg = static_cast<const CT*>(a.CT);
   stage_table<FT>(Ls, static_cast<const FT*>(a.L), a.nl, R, &a.scale);
-  stage_cum<CT, LT>(CSs, static_cast<const CT*>(a.CS), (a.N + 1) * R);
-  stage_cum<CT, LT>(CTs, static_cast<const CT*>(a.CT), (a.N + 1) * R);
+  if constexpr (!GC) {
+    stage_cum<CT, LT>(CSs, CSg, (a.N + 1) * R);
+    stage_cum<CT, LT>(CTs, CTg, (a.N + 1) * R);
+  }
   __syncthreads();
 
   const FT* __restrict__ U = static_cast<const FT*>(a.U);
@@ -230,10 +262,10 @@ __global__ __launch_bounds__(kQueryThreads) void k_query(QueryArgs a) {
         pu = r.u; pv = r.v; pl = r.l;
       }
       float sh[RPL], sl[RPL], th[RPL], tl[RPL];
-      lds_cum_row<LT, RPL>(CSs + r.sh + r0, sh);
-      lds_cum_row<LT, RPL>(CSs + r.sl + r0, sl);
-      lds_cum_row<LT, RPL>(CTs + r.th + r0, th);
-      lds_cum_row<LT, RPL>(CTs + r.tl + r0, tl);
+      cum_row<GC, CT, LT, RPL>(CSs, CSg, r.sh + r0, sh);
+      cum_row<GC, CT, LT, RPL>(CSs, CSg, r.sl + r0, sl);
+      cum_row<GC, CT, LT, RPL>(CTs, CTg, r.th + r0, th);
+      cum_row<GC, CT, LT, RPL>(CTs, CTg, r.tl + r0, tl);
       float acc = 0.0f;
 #pragma unroll
       for (int e = 0; e < RPL; ++e) acc += W[e] * (sh[e] - sl[e]) * (th[e] - tl[e]);
@@ -265,7 +297,7 @@ struct GroupedArgs {
 // forms W = U*V*L once per point and walks its K boxes, only the summed-area
 // rows changing per box.  Lane j keeps the result of box b with b % LPQ == j,
 // so LPQ consecutive results leave as one contiguous store.
-template <typename FT, typename CT, int R, int RPL>
+template <typename FT, typename CT, int R, int RPL, bool GC>
 __global__ __launch_bounds__(kQueryThreads) void k_query_grouped(GroupedArgs a) {
   constexpr int LPQ = R / RPL;
   typedef typename LdsCum<CT>::type LT;
@@ -273,12 +305,16 @@ __global__ __launch_bounds__(kQueryThreads) void k_query_grouped(GroupedArgs a) 
   float* Ls = lds;
   LT* CSs = reinterpret_cast<LT*>(Ls + a.nl * R);
   LT* CTs = CSs + (a.N + 1) * R;
+  const size_t cum_bytes = GC ? 0 : 2 * sizeof(LT) * (a.N + 1) * R;
   int4* pts = reinterpret_cast<int4*>(
-      reinterpret_cast<unsigned char*>(lds) +
-      glint_round_up(sizeof(float) * a.nl * R + 2 * sizeof(LT) * (a.N + 1) * R, 16));   // [waves][64]
+      reinterpret_cast<unsigned char*>(lds) + glint_round_up(sizeof(float) * a.nl * R + cum_bytes, 16));
+  const CT* CSg = static_cast<const CT*>(a.CS);
+  const CT* CTg = static_cast<const CT*>(a.CT);
   stage_table<FT>(Ls, static_cast<const FT*>(a.L), a.nl, R, &a.scale);
-  stage_cum<CT, LT>(CSs, static_cast<const CT*>(a.CS), (a.N + 1) * R);
-  stage_cum<CT, LT>(CTs, static_cast<const CT*>(a.CT), (a.N + 1) * R);
+  if constexpr (!GC) {
+    stage_cum<CT, LT>(CSs, CSg, (a.N + 1) * R);
+    stage_cum<CT, LT>(CTs, CTg, (a.N + 1) * R);
+  }
   __syncthreads();
 
   const FT* __restrict__ U = static_cast<const FT*>(a.U);
@@ -324,10 +360,10 @@ __global__ __launch_bounds__(kQueryThreads) void k_query_grouped(GroupedArgs a) 
         const int tlo = glint_clampi(box.z, 0, a.N), thi = glint_clampi(box.w, 0, a.N);
         const int shi = (slo < shi0 && tlo < thi) ? shi0 : slo;     // empty box: exact zeros
         float sh[RPL], sl[RPL], th[RPL], tl[RPL];
-        lds_cum_row<LT, RPL>(CSs + shi * R + r0, sh);
-        lds_cum_row<LT, RPL>(CSs + slo * R + r0, sl);
-        lds_cum_row<LT, RPL>(CTs + thi * R + r0, th);
-        lds_cum_row<LT, RPL>(CTs + tlo * R + r0, tl);
+        cum_row<GC, CT, LT, RPL>(CSs, CSg, shi * R + r0, sh);
+        cum_row<GC, CT, LT, RPL>(CSs, CSg, slo * R + r0, sl);
+        cum_row<GC, CT, LT, RPL>(CTs, CTg, thi * R + r0, th);
+        cum_row<GC, CT, LT, RPL>(CTs, CTg, tlo * R + r0, tl);
         float acc = 0.0f;
 #pragma unroll
         for (int e = 0; e < RPL; ++e) acc += W[e] * (sh[e] - sl[e]) * (th[e] - tl[e]);
@@ -607,13 +643,22 @@ size_t cum_lds_bytes(int N1, int R) {
   return 2 * sizeof(typename LdsCum<CT>::type) * static_cast<size_t>(N1) * R;
 }
 
+// LDS bytes of a query launch: L (FP32), the summed-area tables unless they
+// are read from global memory, and the per-wave record slots.
+template <typename CT, int R>
+size_t query_lds_bytes(int nl, int N, bool global_cum, size_t slot_bytes) {
+  return glint_round_up(sizeof(float) * static_cast<size_t>(nl) * R + (global_cum ? 0 : cum_lds_bytes<CT>(N + 1, R)),
+                        16) + slot_bytes;
+}
+
 template <typename FT, typename CT, int R>
 glint_status launch_query(const QueryArgs& a, hipStream_t stream) {
   constexpr int RPL = rpl_for<FT>() <= R ? rpl_for<FT>() : R;
-  const size_t lds = glint_round_up(sizeof(float) * static_cast<size_t>(a.nl) * R + cum_lds_bytes<CT>(a.N + 1, R), 16) +
-                     sizeof(QueryRows) * (kQueryThreads / 64) * (64 + 64 / (R / RPL));
+  const size_t slots = sizeof(QueryRows) * (kQueryThreads / 64) * (64 + 64 / (R / RPL));
+  const bool gc = static_cast<int>(query_lds_bytes<CT, R>(a.nl, a.N, false, slots)) > g_max_lds;
+  const size_t lds = query_lds_bytes<CT, R>(a.nl, a.N, gc, slots);
   if (static_cast<int>(lds) > g_max_lds)
-    return glint_fail(GLINT_E_UNSUPPORTED, "tables need %zu bytes of LDS (device max %d)", lds, g_max_lds);
+    return glint_fail(GLINT_E_UNSUPPORTED, "L needs %zu bytes of LDS (device max %d)", lds, g_max_lds);
   const int64_t waves_needed = (a.nq + 63) / 64;
   constexpr int WPB = kQueryThreads / 64;
   int64_t blocks = (waves_needed + WPB - 1) / WPB;
@@ -621,8 +666,12 @@ glint_status launch_query(const QueryArgs& a, hipStream_t stream) {
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
   glint_clear_launch_error();
-  hipLaunchKernelGGL((k_query<FT, CT, R, RPL>), dim3(static_cast<unsigned>(blocks)), dim3(kQueryThreads), lds,
-                     stream, a);
+  if (gc)
+    hipLaunchKernelGGL((k_query<FT, CT, R, RPL, true>), dim3(static_cast<unsigned>(blocks)), dim3(kQueryThreads),
+                       lds, stream, a);
+  else
+    hipLaunchKernelGGL((k_query<FT, CT, R, RPL, false>), dim3(static_cast<unsigned>(blocks)), dim3(kQueryThreads),
+                       lds, stream, a);
   GLINT_LAUNCHED("k_query");
   return GLINT_OK;
 }
@@ -630,10 +679,11 @@ glint_status launch_query(const QueryArgs& a, hipStream_t stream) {
 template <typename FT, typename CT, int R>
 glint_status launch_grouped(const GroupedArgs& a, hipStream_t stream) {
   constexpr int RPL = rpl_for<FT>() <= R ? rpl_for<FT>() : R;
-  const size_t lds = glint_round_up(sizeof(float) * static_cast<size_t>(a.nl) * R + cum_lds_bytes<CT>(a.N + 1, R), 16) +
-                     sizeof(int4) * (kQueryThreads / 64) * 64;
+  const size_t slots = sizeof(int4) * (kQueryThreads / 64) * 64;
+  const bool gc = static_cast<int>(query_lds_bytes<CT, R>(a.nl, a.N, false, slots)) > g_max_lds;
+  const size_t lds = query_lds_bytes<CT, R>(a.nl, a.N, gc, slots);
   if (static_cast<int>(lds) > g_max_lds)
-    return glint_fail(GLINT_E_UNSUPPORTED, "tables need %zu bytes of LDS (device max %d)", lds, g_max_lds);
+    return glint_fail(GLINT_E_UNSUPPORTED, "L needs %zu bytes of LDS (device max %d)", lds, g_max_lds);
   const int64_t waves_needed = (a.npts + 63) / 64;
   constexpr int WPB = kQueryThreads / 64;
   int64_t blocks = (waves_needed + WPB - 1) / WPB;
@@ -641,8 +691,12 @@ glint_status launch_grouped(const GroupedArgs& a, hipStream_t stream) {
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
   glint_clear_launch_error();
-  hipLaunchKernelGGL((k_query_grouped<FT, CT, R, RPL>), dim3(static_cast<unsigned>(blocks)),
-                     dim3(kQueryThreads), lds, stream, a);
+  if (gc)
+    hipLaunchKernelGGL((k_query_grouped<FT, CT, R, RPL, true>), dim3(static_cast<unsigned>(blocks)),
+                       dim3(kQueryThreads), lds, stream, a);
+  else
+    hipLaunchKernelGGL((k_query_grouped<FT, CT, R, RPL, false>), dim3(static_cast<unsigned>(blocks)),
+                       dim3(kQueryThreads), lds, stream, a);
   GLINT_LAUNCHED("k_query_grouped");
   return GLINT_OK;
 }

@@ -159,6 +159,33 @@ def test_query_matches_oracle(dtype, cum_dtype, R):
     assert empty.any() and np.all(got[empty] == 0.0)
 
 
+GLOBAL_CUM_CASES = [("f32", "f32", 256, 128), ("f32", "bf16", 256, 256), ("f32", "fp8", 128, 256),
+                    ("fp8", "f32", 256, 128), ("bf16", "fp8", 128, 256)]
+
+
+@pytest.mark.parametrize("dtype,cum_dtype,R,N", GLOBAL_CUM_CASES)
+def test_query_tables_beyond_lds(dtype, cum_dtype, R, N):
+    """Summed-area tables too large for LDS are read from global memory (8-,
+    4- and 16-byte row slices among these cases): flat and grouped queries."""
+    print(f"global-table query dtype={dtype} cum={cum_dtype} R={R} N={N}", flush=True)
+    rng = np.random.default_rng(R + N)
+    nu, nv, nl = 29, 41, 6
+    F = _rand_factors(rng, nu, nv, nl, N, R)
+    q = _rand_queries(rng, 8009, nu, nv, nl, N, wild=True)
+    tabs = G.make_tables(*[torch.tensor(x, device="cuda") for x in F], dtype=dtype, cum_dtype=cum_dtype)
+    got = G.query(tabs, q).cpu().numpy()
+    want, mag = _oracle(F, q, dtype, cum_dtype)
+    _check(got, want, mag)
+    npts, K = 257, 8
+    uvl = np.stack([rng.integers(0, nu, npts), rng.integers(0, nv, npts),
+                    rng.integers(0, nl, npts)], axis=1).astype(np.int32)
+    boxes = _rand_queries(rng, npts * K, nu, nv, nl, N)[:, 3:7].reshape(npts, K, 4)
+    gotg = G.query_grouped(tabs, uvl, boxes).cpu().numpy().reshape(-1)
+    flat = np.concatenate([np.repeat(uvl, K, axis=0), boxes.reshape(-1, 4)], axis=1).astype(np.int32)
+    want, mag = _oracle(F, flat, dtype, cum_dtype)
+    _check(gotg, want, mag)
+
+
 @pytest.mark.parametrize("nq", [0, 1, 3, 63, 65, 1000003])
 def test_query_sizes(nq):
     rng = np.random.default_rng(nq + 5)
