@@ -39,21 +39,33 @@ FP64_MFMA_PEAK_TFLOPS = 78.6
 # see profiles/<kernel>_c2_hbm_traffic.md.  Valid only for the kernel source they
 # were taken with (sha1); otherwise traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "k_mttkrp_y": ("paper_2109_14807_amd/csrc/cp_als.hip", "6bc43108b7361ad691fe0ed4aac5d1adfde6b3ae", 36600865606),
-    "k_mttkrp_z": ("paper_2109_14807_amd/csrc/cp_als.hip", "6bc43108b7361ad691fe0ed4aac5d1adfde6b3ae", 34933118562),
-    "k_query": ("paper_2109_14807_amd/csrc/query.hip", "8d39398c02180271b4eb751a57a7a66729819dc2", 535143394),
+    "k_mttkrp_y": ("paper_2109_14807_amd/csrc/cp_als.hip", "8f0b96faef3d3d8b25d17ae8ac059a47a899a204", 36579418647),
+    "k_mttkrp_z": ("paper_2109_14807_amd/csrc/cp_als.hip", "6c0880d3ad452058f93ed40f598a5a613a43b374", 34936220934),
+    "k_query": ("paper_2109_14807_amd/csrc/query.hip", "32ebcc8307719c734e263434761ea01a29ff291d", 534671702),
 }
 
 
-def measured_traffic(kernel):
+def kernel_source_sha(path, name):
+    """SHA-1 of a kernel's definition text: from the template line before
+    `void <name>(` to the first line that closes it at column 0."""
     import hashlib
+    with open(os.path.join(ROOT, path)) as f:
+        lines = f.read().split("\n")
+    at = next(i for i, l in enumerate(lines) if f"void {name}(" in l)
+    start = at - 1 if at > 0 and lines[at - 1].startswith("template") else at
+    end = next(i for i in range(at, len(lines)) if lines[i] == "}")
+    return hashlib.sha1("\n".join(lines[start:end + 1]).encode()).hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed counter runs, or None once the
+    kernel's source has changed since they were taken."""
     src, sha, nbytes = MEASURED_TRAFFIC[kernel]
     try:
-        with open(os.path.join(ROOT, src), "rb") as f:
-            cur = hashlib.sha1(f.read()).hexdigest()
-    except OSError:
+        cur = kernel_source_sha(src, kernel)
+    except (OSError, StopIteration):
         return None
-    return nbytes if cur == sha else None
+    return nbytes if cur == sha and nbytes > 0 else None
 
 
 def parse():
@@ -70,6 +82,10 @@ def parse():
     ap.add_argument("--configs", default="",
                     help="comma-separated extra workloads (c1, c3, c4, c5) run end to end on their own "
                          "ALS factors after the step, reported under 'configs'")
+    ap.add_argument("--als-only", default="",
+                    help="instead of the step: run only the named workload's CP-ALS (--sweeps sweeps, "
+                         "texel-space for maps whose tensor does not fit) and print its timing; "
+                         "used to profile the ALS kernels at that shape")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 2 GiB device copy (read 2 GiB, write 2 GiB) after the "
                          "steps, the reference for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE")
@@ -97,6 +113,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.als_only:
+        print(json.dumps(als_only(args.als_only, args.sweeps)), flush=True)
+        return
     cfg = gen.config("c2")
     R, N, nl = cfg.rank, cfg.nbins, cfg.nlevels
     desc = G.desc_of(cfg.nu, cfg.nv, nl, N, cfg.sigma)
@@ -369,6 +388,38 @@ def refine_report(cfg, nxy_h, desc, F, q, q_bf, steps, timed):
         "speedup_bf16_over_f32": ms_plain / ms_bf16,
         "equal_or_lower_error": bool(e_bf16 <= e_plain),
     }
+
+
+def als_only(name, sweeps):
+    """CP-ALS of one workload alone (one untimed warm-up run of 1 sweep first)."""
+    import torch
+
+    import gen
+    import paper_2109_14807_amd as G
+
+    dev = torch.device("cuda:0")
+    cfg = gen.config(name)
+    nxy = torch.tensor(gen.normal_map(cfg), device=dev)
+    desc = G.desc_of(cfg.nu, cfg.nv, cfg.nlevels, cfg.nbins, cfg.sigma)
+    init = [torch.tensor(a, device=dev) for a in gen.als_init(cfg)]
+    dense = cfg.nu * cfg.nv <= 64 * 64
+    if dense:
+        T = G.build_tensor(nxy, desc, dtype=torch.float64)
+        ws = G.als_workspace(desc, cfg.rank, T.dtype)
+        run = lambda k: G.cp_als(T, desc, init, k, workspace=ws)
+    else:
+        ws = G.texel_workspace(desc, cfg.rank)
+        run = lambda k: G.cp_als_texel(nxy, desc, init, k, workspace=ws)
+    run(1)
+    torch.cuda.synchronize()
+    log(f"{name}: warm-up done; {sweeps} sweeps")
+    t0 = time.perf_counter()
+    res = run(sweeps)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    return {"workload": name, "als": "dense FP64" if dense else "texel-space FP64", "rank": cfg.rank,
+            "sweeps": sweeps, "ms": ms, "ms_per_sweep": ms / sweeps, "workspace_bytes": int(ws.numel()),
+            "info": res.info.cpu().tolist()}
 
 
 def config_report(name, sweeps, timed):
