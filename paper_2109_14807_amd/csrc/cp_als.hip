@@ -469,12 +469,16 @@ __global__ void k_gram(const double* __restrict__ A, int rows, int R, double* __
 // and the factor L[i][j] = c_j[i] / sqrt(d_j) is formed at the end.  Column j
 // goes through LDS (double-buffered, one barrier per column).  Breakdown: a
 // pivot not above kPivotRtol times the original diagonal entry.
+// side of the thread grid of k_cholesky (launched with its square as the block size):
+// 16 x 16 up to rank 64 (fewer wavefronts per column barrier), else 32 x 32
+constexpr int cholesky_grid(int R) { return R <= 16 ? R : (R <= 64 ? 16 : 32); }
+
 template <int R>
 __global__ __launch_bounds__(1024) void k_cholesky(const double* __restrict__ grams, int n,
                                                    double* __restrict__ Lc, double* __restrict__ LcT,
                                                    int* __restrict__ ctrl) {
   if (ctrl[CTRL_DONE]) return;
-  constexpr int GD = R < 32 ? R : 32;
+  constexpr int GD = cholesky_grid(R);
   constexpr int E = R / GD;
   constexpr int RR = R * R;
   __shared__ double col[2][R];
@@ -563,24 +567,35 @@ __global__ __launch_bounds__(1024) void k_cholesky(const double* __restrict__ gr
     }
 }
 
-// One wave per row: x = m G^-1 with G = Lc Lc^T (forward then back substitution).
+// One wave per row: x = m G^-1 with G = Lc Lc^T (forward then back
+// substitution).  For R <= 128 the factor is staged once per block in LDS
+// with row stride R + 1 (dynamic LDS of solve_lds_bytes(R)), so both the
+// column walk of the forward pass and the row walk of the back pass are
+// served without bank conflicts; larger ranks read it from global memory.
+template <int R>
+constexpr size_t solve_lds_bytes() {
+  return R <= 128 ? sizeof(double) * R * (R + 1) : 0;
+}
+
 template <int R>
 __global__ __launch_bounds__(1024) void k_solve(const double* __restrict__ M, int rows,
                                                const double* Lc, const double* LcT,
                                                double* __restrict__ A, const int* __restrict__ ctrl) {
   if (ctrl[CTRL_DONE] || ctrl[CTRL_FAILNOW]) return;
   constexpr int E = (R + 63) / 64;
-  constexpr bool kStage = R <= 64;           // both factors fit in LDS (64 KB at R = 64)
-  __shared__ double sL[kStage ? R * R : 1];
-  __shared__ double sLT[kStage ? R * R : 1];
+  constexpr bool kStage = R <= 128;
+  constexpr int LD = kStage ? R + 1 : R;
+  extern __shared__ __align__(16) double sL[];
+  const double* Lf;   // L[i][k] at Lf[i * LD + k]
   if constexpr (kStage) {
-    for (int i = threadIdx.x; i < R * R; i += blockDim.x) {
-      sL[i] = Lc[i];
-      sLT[i] = LcT[i];
+    for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) {
+      const int i = idx / R, k = idx % R;
+      if (k <= i) sL[i * LD + k] = Lc[idx];
     }
     __syncthreads();
-    Lc = sL;
-    LcT = sLT;
+    Lf = sL;
+  } else {
+    Lf = Lc;
   }
   const int lane = threadIdx.x & 63;
   const int row = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -591,34 +606,34 @@ __global__ __launch_bounds__(1024) void k_solve(const double* __restrict__ M, in
     const int e = lane + 64 * t;
     w[t] = e < R ? M[static_cast<int64_t>(row) * R + e] : 0.0;
   }
-  // forward: L y = m
+  // forward: L y = m (column j of L: L[e][j], e > j)
   for (int j = 0; j < R; ++j) {
     const int slot = j >> 6, owner = j & 63;
     double wj = 0.0;
 #pragma unroll
     for (int t = 0; t < E; ++t)
       if (t == slot) wj = w[t];
-    const double yj = __shfl(wj, owner) / Lc[j * R + j];
+    const double yj = __shfl(wj, owner) / Lf[j * LD + j];
 #pragma unroll
     for (int t = 0; t < E; ++t) {
       const int e = lane + 64 * t;
       if (e == j) w[t] = yj;
-      else if (e > j && e < R) w[t] -= LcT[j * R + e] * yj;
+      else if (e > j && e < R) w[t] -= (kStage ? Lf[e * LD + j] : LcT[j * R + e]) * yj;
     }
   }
-  // back: L^T x = y
+  // back: L^T x = y (row j of L: L[j][e], e < j)
   for (int j = R - 1; j >= 0; --j) {
     const int slot = j >> 6, owner = j & 63;
     double wj = 0.0;
 #pragma unroll
     for (int t = 0; t < E; ++t)
       if (t == slot) wj = w[t];
-    const double xj = __shfl(wj, owner) / Lc[j * R + j];
+    const double xj = __shfl(wj, owner) / Lf[j * LD + j];
 #pragma unroll
     for (int t = 0; t < E; ++t) {
       const int e = lane + 64 * t;
       if (e == j) w[t] = xj;
-      else if (e < j) w[t] -= Lc[j * R + e] * xj;
+      else if (e < j) w[t] -= Lf[j * LD + e] * xj;
     }
   }
 #pragma unroll
@@ -847,10 +862,12 @@ glint_status run_als(const glint_ndf_desc* d, const TT* T, int iters, double tol
   GLINT_LAUNCHED("k_gram");
 
   auto update = [&](int n) -> glint_status {
-    hipLaunchKernelGGL((k_cholesky<R>), dim3(1), dim3(1024), 0, stream, grams, n, Lc, LcT, ctrl);
+    hipLaunchKernelGGL((k_cholesky<R>), dim3(1), dim3(cholesky_grid(R) * cholesky_grid(R)), 0, stream, grams, n, Lc,
+                       LcT, ctrl);
     GLINT_LAUNCHED("k_cholesky");
     const int rws = rows[n];
-    hipLaunchKernelGGL((k_solve<R>), dim3((rws + 15) / 16), dim3(1024), 0, stream, Mb, rws, Lc, LcT, F[n], ctrl);
+    hipLaunchKernelGGL((k_solve<R>), dim3((rws + 15) / 16), dim3(1024), solve_lds_bytes<R>(), stream, Mb, rws, Lc,
+                       LcT, F[n], ctrl);
     GLINT_LAUNCHED("k_solve");
     hipLaunchKernelGGL(k_normalize_gram, dim3(1), dim3(1024), 0, stream, F[n], rws, R, lam,
                        grams + n * R * R, ctrl);
@@ -1455,6 +1472,31 @@ __global__ __launch_bounds__(256) void k_gram_parts(const double* __restrict__ A
   parts[static_cast<int64_t>(blockIdx.z) * R * R + i * R + j] = acc;
 }
 
+// Fixed-order sum of the per-chunk partial tiles parts[p][n] in two levels:
+// each group of kPartGroup consecutive tiles is summed into its first tile,
+// then the group heads into out.
+constexpr int kPartGroup = 32;
+__global__ void k_sum_part_groups(double* __restrict__ parts, int nparts, int64_t n, const int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE]) return;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int p0 = blockIdx.y * kPartGroup;
+  const int p1 = min(p0 + kPartGroup, nparts);
+  double acc = 0.0;
+  for (int p = p0; p < p1; ++p) acc += parts[p * n + i];
+  parts[p0 * n + i] = acc;
+}
+
+__global__ void k_sum_group_heads(const double* __restrict__ parts, int groups, int64_t n, double* __restrict__ out,
+                                  const int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE]) return;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int g = 0; g < groups; ++g) acc += parts[static_cast<int64_t>(g) * kPartGroup * n + i];
+  out[i] = acc;
+}
+
 struct TexelLayout {
   size_t bins, mass, pm, ub, vb, hb, hpref, cpre, parts, gparts, m, grams, lc, lct, lam, scal, ctrl, total;
   int64_t chunk_p, chunk_s, nchunk_s;
@@ -1687,8 +1729,12 @@ glint_status texel_mode(const TexelCtx& c, int mode, const double* L, const doub
   if (mode == 3) texel_scatter<R, 0>(c, Tf, grid, lds);
   else texel_scatter<R, 1>(c, S, grid, lds);
   const int64_t n = static_cast<int64_t>(N) * R;
-  hipLaunchKernelGGL(k_reduce_splits<double>, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st,
-                     c.parts, static_cast<int>(c.lo->nchunk_s), n, c.M, c.ctrl);
+  const int nparts = static_cast<int>(c.lo->nchunk_s);
+  const int groups = (nparts + kPartGroup - 1) / kPartGroup;
+  hipLaunchKernelGGL(k_sum_part_groups, dim3(static_cast<unsigned>((n + 255) / 256), groups), dim3(256), 0, st,
+                     c.parts, nparts, n, c.ctrl);
+  hipLaunchKernelGGL(k_sum_group_heads, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, c.parts,
+                     groups, n, c.M, c.ctrl);
   GLINT_LAUNCHED("texel modes s, t");
   return GLINT_OK;
 }
@@ -1739,8 +1785,10 @@ glint_status run_texel_als(const glint_ndf_desc* d, const float* nxy, int iters,
   for (int m = 0; m < 5; ++m) texel_gram<R>(c, F[m], rows[m], grams + m * R * R);
   GLINT_LAUNCHED("texel ALS init");
   auto update = [&](int n) -> glint_status {
-    hipLaunchKernelGGL((k_cholesky<R>), dim3(1), dim3(1024), 0, stream, grams, n, Lc, LcT, c.ctrl);
-    hipLaunchKernelGGL((k_solve<R>), dim3((rows[n] + 15) / 16), dim3(1024), 0, stream, c.M, rows[n], Lc, LcT,
+    hipLaunchKernelGGL((k_cholesky<R>), dim3(1), dim3(cholesky_grid(R) * cholesky_grid(R)), 0, stream, grams, n, Lc,
+                       LcT, c.ctrl);
+    hipLaunchKernelGGL((k_solve<R>), dim3((rows[n] + 15) / 16), dim3(1024), solve_lds_bytes<R>(), stream, c.M,
+                       rows[n], Lc, LcT,
                        F[n], c.ctrl);
     hipLaunchKernelGGL(k_normalize_gram, dim3(1), dim3(1024), 0, stream, F[n], rows[n], R, lam,
                        static_cast<double*>(nullptr), c.ctrl);
