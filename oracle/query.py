@@ -16,6 +16,8 @@ Readings:
     sum / ((s_hi - s_lo) (t_hi - t_lo)).
   * Boundary rules: u, v wrap; l clamps to [0, nl-1]; bin bounds clamp to
     [0, N]; an empty box (lo >= hi on either axis) gives exactly 0.
+  * Off-grid footprints: trilinear blend of the eight surrounding
+    precomputed footprints' range queries (see range_query_trilinear).
 """
 from __future__ import annotations
 
@@ -53,6 +55,55 @@ def range_query(U, V, L, CS, CT, q, scale=None) -> np.ndarray:
     out = P.sum(axis=1)
     empty = (slo >= shi) | (tlo >= thi)
     out[empty] = 0.0
+    return out
+
+
+# Off-grid footprints (Sec. 4.1 and Sec. 4.3): a footprint between the
+# precomputed centres and levels takes the trilinear blend of the NDF values
+# of the eight surrounding precomputed footprints.  Coordinates are in index
+# units: x, y continuous footprint centres (u = floor(x) wraps, fraction
+# x - floor(x)); lam a continuous level clamped to [0, nl - 1].  Reading: a
+# non-finite coordinate counts as 0, and |x|, |y| are clamped to 2^24 (where
+# FP32 has no fraction left).
+COORD_LIMIT = float(1 << 24)
+
+
+def trilinear_corners(xyl, nu, nv, nl):
+    """Corner indices [n][8][3] (u, v, l) and blend weights [n][8] (FP64)."""
+    xyl = np.asarray(xyl, dtype=np.float32).astype(np.float64)
+    xyl = np.where(np.isfinite(xyl), xyl, 0.0)
+    x = np.clip(xyl[:, 0], -COORD_LIMIT, COORD_LIMIT)
+    y = np.clip(xyl[:, 1], -COORD_LIMIT, COORD_LIMIT)
+    lam = np.clip(xyl[:, 2], 0.0, nl - 1.0)
+    fx0, fy0, fl0 = np.floor(x), np.floor(y), np.floor(lam)
+    fx, fy, fl = x - fx0, y - fy0, lam - fl0
+    u0, v0, l0 = fx0.astype(np.int64), fy0.astype(np.int64), fl0.astype(np.int64)
+    corners = np.empty((x.shape[0], 8, 3), dtype=np.int64)
+    weights = np.empty((x.shape[0], 8))
+    c = 0
+    for a in (0, 1):
+        for b in (0, 1):
+            for d in (0, 1):
+                corners[:, c, 0] = np.mod(u0 + a, nu)
+                corners[:, c, 1] = np.mod(v0 + b, nv)
+                corners[:, c, 2] = np.minimum(l0 + d, nl - 1)
+                weights[:, c] = (fx if a else 1.0 - fx) * (fy if b else 1.0 - fy) * (fl if d else 1.0 - fl)
+                c += 1
+    return corners, weights
+
+
+def range_query_trilinear(U, V, L, CS, CT, xyl, boxes, scale=None, magnitude=False) -> np.ndarray:
+    """Trilinear blend over the 8 surrounding footprints of the range query of
+    each box (boxes [n][4] = s_lo, s_hi, t_lo, t_hi); FP64.  With
+    ``magnitude`` the blend of the corners' condition magnitudes instead."""
+    nu, nv, nl = U.shape[0], V.shape[0], L.shape[0]
+    corners, w = trilinear_corners(xyl, nu, nv, nl)
+    boxes = np.asarray(boxes, dtype=np.int64)
+    fn = range_query_magnitude if magnitude else range_query
+    out = np.zeros(corners.shape[0])
+    for c in range(8):
+        rec = np.concatenate([corners[:, c, :], boxes], axis=1)
+        out += w[:, c] * fn(U, V, L, CS, CT, rec, scale=scale)
     return out
 
 

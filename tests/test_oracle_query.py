@@ -202,3 +202,84 @@ def test_mse_gradient():
     loss, g = query.mse_loss(qv, t)
     assert loss == (0.25 + 0 + 4) / 3
     assert np.allclose(g, [1 / 3, 0, -4 / 3])
+
+
+def _rand_coords(rng, n, nu, nv, nl):
+    return np.stack([rng.uniform(-nu, 2 * nu, n), rng.uniform(-nv, 2 * nv, n),
+                     rng.uniform(-0.5, nl - 0.5, n)], axis=1).astype(np.float32)
+
+
+def test_trilinear_at_grid_points_is_the_plain_query():
+    rng = np.random.default_rng(31)
+    dims = (6, 5, 4, 8, 8)
+    U, V, L, S, Tf = _rand_factors(rng, dims, 5)
+    CS, CT = query.cumulative(S), query.cumulative(Tf)
+    q = _rand_queries(rng, 200, 6, 5, 4, 8)
+    xyl = q[:, :3].astype(np.float32)
+    got = query.range_query_trilinear(U, V, L, CS, CT, xyl, q[:, 3:])
+    assert np.array_equal(got, query.range_query(U, V, L, CS, CT, q))
+
+
+def test_trilinear_equals_linear_interpolation_of_the_tensor():
+    """Against scipy's order-1 interpolation of the reconstructed tensor over
+    (u, v, l), with u, v extended periodically and l clamped, then box sums."""
+    from scipy.ndimage import map_coordinates
+    rng = np.random.default_rng(32)
+    nu, nv, nl, N = 5, 4, 3, 6
+    U, V, L, S, Tf = _rand_factors(rng, (nu, nv, nl, N, N), 3)
+    T = cp_als.reconstruct(U, V, L, S, Tf)
+    Tp = np.concatenate([T, T[:1]], axis=0)          # u = nu wraps to 0
+    Tp = np.concatenate([Tp, Tp[:, :1]], axis=1)      # v = nv wraps to 0
+    xyl = _rand_coords(rng, 60, nu, nv, nl)
+    boxes = _rand_queries(rng, 60, nu, nv, nl, N)[:, 3:]
+    got = query.range_query_trilinear(U, V, L, query.cumulative(S), query.cumulative(Tf), xyl, boxes)
+    s_idx, t_idx = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    for i in range(xyl.shape[0]):
+        x, y, lam = (float(c) for c in xyl[i])
+        coords = np.stack([np.full((N, N), x % nu), np.full((N, N), y % nv),
+                           np.full((N, N), min(max(lam, 0.0), nl - 1.0)), s_idx, t_idx])
+        sl = map_coordinates(Tp, coords.reshape(5, -1), order=1, mode="nearest").reshape(N, N)
+        slo, shi, tlo, thi = boxes[i]
+        want = sl[slo:shi, tlo:thi].sum()
+        assert abs(got[i] - want) <= 1e-11 * max(1.0, abs(want)), (i, got[i], want)
+
+
+def test_trilinear_blend_equals_interpolated_factor_rows():
+    """The CP reconstruction is multilinear, so the blend of the eight corner
+    queries equals one query with linearly interpolated U, V and L rows (the
+    form the GPU evaluates)."""
+    rng = np.random.default_rng(33)
+    nu, nv, nl, N, R = 7, 6, 5, 16, 8
+    U, V, L, S, Tf = _rand_factors(rng, (nu, nv, nl, N, N), R)
+    CS, CT = query.cumulative(S), query.cumulative(Tf)
+    xyl = _rand_coords(rng, 500, nu, nv, nl)
+    boxes = _rand_queries(rng, 500, nu, nv, nl, N)[:, 3:]
+    got = query.range_query_trilinear(U, V, L, CS, CT, xyl, boxes)
+    x, y = xyl[:, 0].astype(np.float64), xyl[:, 1].astype(np.float64)
+    lam = np.clip(xyl[:, 2].astype(np.float64), 0, nl - 1)
+    u0, v0, l0 = np.floor(x).astype(int), np.floor(y).astype(int), np.floor(lam).astype(int)
+    fx, fy, fl = (x - u0)[:, None], (y - v0)[:, None], (lam - l0)[:, None]
+    Ui = (1 - fx) * U[u0 % nu] + fx * U[(u0 + 1) % nu]
+    Vi = (1 - fy) * V[v0 % nv] + fy * V[(v0 + 1) % nv]
+    Li = (1 - fl) * L[l0] + fl * L[np.minimum(l0 + 1, nl - 1)]
+    slo, shi, tlo, thi = boxes.T
+    want = np.sum(Ui * Vi * Li * (CS[shi] - CS[slo]) * (CT[thi] - CT[tlo]), axis=1)
+    want[(slo >= shi) | (tlo >= thi)] = 0.0
+    assert np.max(np.abs(got - want)) <= 1e-12 * max(1.0, np.abs(want).max())
+
+
+def test_trilinear_boundary_rules():
+    rng = np.random.default_rng(34)
+    nu, nv, nl, N = 4, 6, 3, 8
+    U, V, L, S, Tf = _rand_factors(rng, (nu, nv, nl, N, N), 4)
+    CS, CT = query.cumulative(S), query.cumulative(Tf)
+    box = np.array([[1, 5, 2, 7]])
+    f = lambda c: query.range_query_trilinear(U, V, L, CS, CT, np.array([c], dtype=np.float32), box)[0]
+    assert f([1.25, 2.5, 0.75]) == pytest.approx(f([1.25 + 3 * nu, 2.5 - 2 * nv, 0.75]), rel=1e-12)
+    assert f([1.0, 2.0, -3.0]) == f([1.0, 2.0, 0.0])
+    assert f([1.0, 2.0, 9.0]) == f([1.0, 2.0, nl - 1.0])
+    assert f([np.nan, 2.0, 1.0]) == f([0.0, 2.0, 1.0])
+    assert f([1.0, np.inf, 1.0]) == f([1.0, 0.0, 1.0])
+    # the level weight is linear between two levels
+    a, b, m = f([1.0, 2.0, 1.0]), f([1.0, 2.0, 2.0]), f([1.0, 2.0, 1.25])
+    assert m == pytest.approx(0.75 * a + 0.25 * b, rel=1e-12)
