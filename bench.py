@@ -236,6 +236,12 @@ def main():
     # mode u: (s,t) pass (k_mttkrp_z) + u reduction
     mttkrp_z_ms = timed(lambda: L.glint_mttkrp(desc, T, R, 0, *F, M_u, ws_als))
     query_ms = timed(lambda: L.glint_query(fac, q, out))
+    # off-grid footprints: the same records at fractional centres and levels
+    frac = torch.tensor([0.37, 0.61, 0.25], dtype=torch.float32, device=dev)
+    xyl = (q[:, :3].float() + frac).contiguous()
+    boxes = q[:, 3:7].contiguous()
+    tri_ms = timed(lambda: L.glint_query_trilinear(fac, xyl, boxes, out))
+    del xyl, boxes
 
     ncells = cfg.nu * cfg.nv * nl
     t_elems = ncells * N * N
@@ -284,6 +290,11 @@ def main():
             "roofline": {"bound": "hbm", "achieved": q_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": q_gbs / HBM_PEAK_GBS, "traffic": measured_traffic("k_query"),
                          "algorithmic_bytes_per_query": 32},
+        },
+        "query_trilinear_kernel": {
+            "kernel": "k_query_trilinear<float,float,64,4>: the batch at fractional centres and levels "
+                      "(eight-footprint trilinear blend, two rows per factor)",
+            "ms": tri_ms, "queries_per_s": nq / (tri_ms * 1e-3),
         },
         "stages_ms": stage_ms,
         "events_ms_per_step": ev_total,

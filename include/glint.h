@@ -242,6 +242,19 @@ glint_status glint_query_grouped(const glint_factors* f, int64_t npts, int32_t K
                                  const int32_t* uvl, const int32_t* boxes,
                                  float* out, hipStream_t stream);
 
+/* Off-grid footprints (Sec. 4.1 and Sec. 4.3): the trilinear blend of the
+ * range queries of the eight precomputed footprints around a continuous
+ * centre and level.  xyl: float [nq][3] = (x, y, lam) in index units (the
+ * corners are floor(x) and floor(x)+1, wrapping; likewise y; floor(lam) and
+ * floor(lam)+1 with lam clamped to [0, nl-1]); a non-finite coordinate
+ * counts as 0 and |x|, |y| are clamped to 2^24.  boxes: int32 [nq][4] =
+ * (s_lo, s_hi, t_lo, t_hi) with the clamping and empty-box rules of
+ * glint_query.  Evaluated as one query with linearly interpolated U, V and
+ * L rows (the reconstruction is multilinear, so this equals the blend),
+ * FP32 arithmetic; same table limits as glint_query. */
+glint_status glint_query_trilinear(const glint_factors* f, int64_t nq, const float* xyl,
+                                   const int32_t* boxes, float* out, hipStream_t stream);
+
 /* ---- step 6: gradient of the query (not in the paper) -------------------- */
 
 /* Gradients of sum_i gout[i] * q[i] with respect to the stored values of U,

@@ -10,7 +10,7 @@ from . import _lib  # noqa: F401
 from ._lib import GlintError, NdfDesc  # noqa: F401
 from .api import (  # noqa: F401
     AlsResult, QueryTables, als_workspace, build_tensor, convert, cp_als, cumulative, cumulative_backward,
-    cp_als_texel, desc_of, make_tables, mttkrp, mttkrp_texel, query, query_backward, query_grouped,
+    cp_als_texel, desc_of, make_tables, mttkrp, mttkrp_texel, query, query_backward, query_grouped, query_trilinear,
     range_bruteforce, texel_bins, texel_workspace,
 )
 from .autograd import GlintQuery, glint_query_fn  # noqa: F401

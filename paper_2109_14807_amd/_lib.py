@@ -86,6 +86,7 @@ _SIGS = {
     "glint_convert": (_I32, [_I64, _I32, _P, _I32, _P, _I32, _P, _P]),
     "glint_query": (_I32, [_FAC, _I64, _P, _P, _P]),
     "glint_query_grouped": (_I32, [_FAC, _I64, _I32, _P, _P, _P, _P]),
+    "glint_query_trilinear": (_I32, [_FAC, _I64, _P, _P, _P, _P]),
     "glint_query_backward": (_I32, [_FAC, _I64, _P, _P, _P, _P, _P, _P, _P, _P]),
     "glint_cumulative_backward": (_I32, [_I32, _I32, _P, _P, _P]),
     "glint_mse_grad": (_I32, [_I64, _P, _P, _P, _P, _P]),
@@ -286,6 +287,15 @@ def glint_query_grouped(f: Factors, uvl, boxes, out, stream=None):
     npts, K = boxes.shape[0], boxes.shape[1]
     _check("glint_query_grouped", lib().glint_query_grouped(
         ctypes.byref(f), npts, K, _ptr(uvl, torch.int32, "uvl"), _ptr(boxes, torch.int32, "boxes"),
+        _ptr(out, torch.float32, "out"), _stream(stream)))
+
+
+def glint_query_trilinear(f: Factors, xyl, boxes, out, stream=None):
+    nq = xyl.shape[0]
+    if tuple(boxes.shape) != (nq, 4) or tuple(xyl.shape) != (nq, 3):
+        raise ValueError("xyl must be [nq][3] and boxes [nq][4]")
+    _check("glint_query_trilinear", lib().glint_query_trilinear(
+        ctypes.byref(f), nq, _ptr(xyl, torch.float32, "xyl"), _ptr(boxes, torch.int32, "boxes"),
         _ptr(out, torch.float32, "out"), _stream(stream)))
 
 

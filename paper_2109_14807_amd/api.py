@@ -197,6 +197,15 @@ def query_grouped(tables: QueryTables, uvl, boxes, out=None):
     return out
 
 
+def query_trilinear(tables: QueryTables, xyl, boxes, out=None):
+    """Trilinear off-grid footprints: xyl float [nq][3] (x, y, level), boxes int [nq][4]."""
+    xyl = _dev(xyl, torch.float32)
+    boxes = _dev(boxes, torch.int32)
+    out = torch.empty(xyl.shape[0], dtype=torch.float32, device=_DEV) if out is None else out
+    L.glint_query_trilinear(tables.factors(), xyl, boxes, out)
+    return out
+
+
 def query_backward(tables: QueryTables, q, gout):
     """Gradients (dU, dV, dL, dCS, dCT) of sum gout * q w.r.t. the stored tables."""
     R = tables.R

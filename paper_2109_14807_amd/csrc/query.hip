@@ -379,6 +379,134 @@ __global__ __launch_bounds__(kQueryThreads) void k_query_grouped(GroupedArgs a) 
   }
 }
 
+// Off-grid footprints (Sec. 4.1, Sec. 4.3): the trilinear blend of the range
+// queries of the eight precomputed footprints around a continuous centre
+// (x, y) and level lam.  The reconstruction is multilinear in the U, V and L
+// rows, so the blend equals one query with linearly interpolated rows: two
+// U, two V (global) and two L (LDS) rows per record instead of one each.
+// Coordinates are in index units; a non-finite coordinate counts as 0,
+// |x|, |y| are clamped to 2^24, x and y wrap, lam clamps to [0, nl - 1].
+struct TriArgs {
+  const void* U;
+  const void* V;
+  const void* L;
+  const void* CS;
+  const void* CT;
+  Scales scale;
+  int nu, nv, nl, N;
+  int64_t nq;
+  const float* xyl;
+  const int32_t* boxes;
+  float* out;
+};
+
+struct alignas(16) TriRows {
+  int u0, u1, v0, v1, l0, l1, sh, sl, th, tl;
+  float wx, wy, wl;
+  int pad[3];
+};
+
+constexpr float kCoordLimit = 16777216.0f;
+
+__device__ __forceinline__ float finite_or_zero(float x) { return __builtin_isfinite(x) ? x : 0.0f; }
+
+template <typename FT, typename CT, int R, int RPL, bool GC>
+__global__ __launch_bounds__(kQueryThreads) void k_query_trilinear(TriArgs a) {
+  constexpr int LPQ = R / RPL;
+  typedef typename LdsCum<CT>::type LT;
+  extern __shared__ __align__(16) float lds[];
+  float* Ls = lds;
+  LT* CSs = reinterpret_cast<LT*>(Ls + a.nl * R);
+  LT* CTs = CSs + (a.N + 1) * R;
+  const size_t cum_bytes = GC ? 0 : 2 * sizeof(LT) * (a.N + 1) * R;
+  TriRows* rows = reinterpret_cast<TriRows*>(
+      reinterpret_cast<unsigned char*>(lds) + glint_round_up(sizeof(float) * a.nl * R + cum_bytes, 16));
+  const CT* CSg = static_cast<const CT*>(a.CS);
+  const CT* CTg = static_cast<const CT*>(a.CT);
+  stage_table<FT>(Ls, static_cast<const FT*>(a.L), a.nl, R, &a.scale);
+  if constexpr (!GC) {
+    stage_cum<CT, LT>(CSs, CSg, (a.N + 1) * R);
+    stage_cum<CT, LT>(CTs, CTg, (a.N + 1) * R);
+  }
+  __syncthreads();
+
+  const FT* __restrict__ U = static_cast<const FT*>(a.U);
+  const FT* __restrict__ V = static_cast<const FT*>(a.V);
+  const int lane = threadIdx.x & 63;
+  const int g = lane / LPQ;
+  const int j = lane % LPQ;
+  const int r0 = j * RPL;
+  constexpr int kSlots = 64 + 64 / LPQ;
+  TriRows* wrows = rows + (threadIdx.x >> 6) * kSlots;
+  const int my_slot = lane + lane / LPQ;
+  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
+  for (int64_t base = wave * 64; base < a.nq; base += nwaves * 64) {
+    {
+      const int64_t qi = base + lane;
+      const int64_t qc = qi < a.nq ? qi : a.nq - 1;
+      const float* c = a.xyl + qc * 3;
+      const int32_t* bx = a.boxes + qc * 4;
+      float x = finite_or_zero(c[0]), y = finite_or_zero(c[1]), lam = finite_or_zero(c[2]);
+      const int b0 = bx[0], b1 = bx[1], b2 = bx[2], b3 = bx[3];
+      x = fminf(fmaxf(x, -kCoordLimit), kCoordLimit);
+      y = fminf(fmaxf(y, -kCoordLimit), kCoordLimit);
+      lam = fminf(fmaxf(lam, 0.0f), static_cast<float>(a.nl - 1));
+      const float fx = floorf(x), fy = floorf(y), fl = floorf(lam);
+      const int ix = static_cast<int>(fx), iy = static_cast<int>(fy), il = static_cast<int>(fl);
+      const int slo = glint_clampi(b0, 0, a.N), shi = glint_clampi(b1, 0, a.N);
+      const int tlo = glint_clampi(b2, 0, a.N), thi = glint_clampi(b3, 0, a.N);
+      const bool empty = !(slo < shi && tlo < thi);
+      TriRows r;
+      r.u0 = glint_wrap(ix, a.nu) * R;
+      r.u1 = glint_wrap(ix + 1, a.nu) * R;
+      r.v0 = glint_wrap(iy, a.nv) * R;
+      r.v1 = glint_wrap(iy + 1, a.nv) * R;
+      r.l0 = il * R;
+      r.l1 = min(il + 1, a.nl - 1) * R;
+      r.sh = (empty ? slo : shi) * R;
+      r.sl = slo * R;
+      r.th = thi * R;
+      r.tl = tlo * R;
+      r.wx = x - fx;
+      r.wy = y - fy;
+      r.wl = lam - fl;
+      r.pad[0] = r.pad[1] = r.pad[2] = 0;
+      wrows[my_slot] = r;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    float res = 0.0f;
+    for (int jj = 0; jj < LPQ; ++jj) {
+      const TriRows r = wrows[g * (LPQ + 1) + jj];
+      float ua[RPL], ub[RPL], va[RPL], vb[RPL], la[RPL], lb[RPL];
+      load_row<FT, RPL>(U + r.u0 + r0, ua);
+      load_row<FT, RPL>(U + r.u1 + r0, ub);
+      load_row<FT, RPL>(V + r.v0 + r0, va);
+      load_row<FT, RPL>(V + r.v1 + r0, vb);
+      lds_row<RPL>(Ls + r.l0 + r0, la);
+      lds_row<RPL>(Ls + r.l1 + r0, lb);
+      float sh[RPL], sl[RPL], th[RPL], tl[RPL];
+      cum_row<GC, CT, LT, RPL>(CSs, CSg, r.sh + r0, sh);
+      cum_row<GC, CT, LT, RPL>(CSs, CSg, r.sl + r0, sl);
+      cum_row<GC, CT, LT, RPL>(CTs, CTg, r.th + r0, th);
+      cum_row<GC, CT, LT, RPL>(CTs, CTg, r.tl + r0, tl);
+      float acc = 0.0f;
+#pragma unroll
+      for (int e = 0; e < RPL; ++e) {
+        const float w = (ua[e] + r.wx * (ub[e] - ua[e])) * (va[e] + r.wy * (vb[e] - va[e])) *
+                        (la[e] + r.wl * (lb[e] - la[e]));
+        acc += w * (sh[e] - sl[e]) * (th[e] - tl[e]);
+      }
+      acc = glint_group_sum<LPQ>(acc);
+      res = (j == jj) ? acc : res;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int64_t qo = base + g * LPQ + j;
+    if (qo < a.nq) a.out[qo] = res;
+  }
+}
+
 // Backward.  Phase 1 (one lane per query, as in the forward) resolves the
 // record and its upstream gradient (0 for empty boxes and padding, so those
 // contribute exact zeros).  Phase 2: lane group g walks its LPQ consecutive
@@ -702,6 +830,31 @@ glint_status launch_grouped(const GroupedArgs& a, hipStream_t stream) {
 }
 
 template <typename FT, typename CT, int R>
+glint_status launch_trilinear(const TriArgs& a, hipStream_t stream) {
+  constexpr int RPL = rpl_for<FT>() <= R ? rpl_for<FT>() : R;
+  const size_t slots = sizeof(TriRows) * (kQueryThreads / 64) * (64 + 64 / (R / RPL));
+  const bool gc = static_cast<int>(query_lds_bytes<CT, R>(a.nl, a.N, false, slots)) > g_max_lds;
+  const size_t lds = query_lds_bytes<CT, R>(a.nl, a.N, gc, slots);
+  if (static_cast<int>(lds) > g_max_lds)
+    return glint_fail(GLINT_E_UNSUPPORTED, "L needs %zu bytes of LDS (device max %d)", lds, g_max_lds);
+  const int64_t waves_needed = (a.nq + 63) / 64;
+  constexpr int WPB = kQueryThreads / 64;
+  int64_t blocks = (waves_needed + WPB - 1) / WPB;
+  const int64_t cap = static_cast<int64_t>(g_cu_count) * 4;
+  if (blocks > cap) blocks = cap;
+  if (blocks < 1) blocks = 1;
+  glint_clear_launch_error();
+  if (gc)
+    hipLaunchKernelGGL((k_query_trilinear<FT, CT, R, RPL, true>), dim3(static_cast<unsigned>(blocks)),
+                       dim3(kQueryThreads), lds, stream, a);
+  else
+    hipLaunchKernelGGL((k_query_trilinear<FT, CT, R, RPL, false>), dim3(static_cast<unsigned>(blocks)),
+                       dim3(kQueryThreads), lds, stream, a);
+  GLINT_LAUNCHED("k_query_trilinear");
+  return GLINT_OK;
+}
+
+template <typename FT, typename CT, int R>
 glint_status launch_backward(const QueryArgs& a, const float* gout, float* dU, float* dV,
                              float* dL, float* dCS, float* dCT, hipStream_t stream) {
   constexpr int RPL = rpl_for<FT>() <= R ? rpl_for<FT>() : R;
@@ -800,6 +953,26 @@ glint_status glint_query(const glint_factors* f, int64_t nq, const int32_t* q, f
     using CT = decltype(ct);
     return by_rank<FT, CT>(f->R, [&](auto rr) -> glint_status {
       return launch_query<FT, CT, decltype(rr)::value>(a, stream);
+    });
+  });
+}
+
+glint_status glint_query_trilinear(const glint_factors* f, int64_t nq, const float* xyl, const int32_t* boxes,
+                                   float* out, hipStream_t stream) {
+  glint_status st = check_factors(f);
+  if (st != GLINT_OK) return st;
+  GLINT_REQUIRE(nq >= 0, "nq must be >= 0");
+  if (nq == 0) return GLINT_OK;
+  GLINT_REQUIRE(xyl && boxes && out, "null pointer argument");
+  TriArgs a;
+  a.U = f->U; a.V = f->V; a.L = f->L; a.CS = f->CS; a.CT = f->CT; a.scale = scales_of(f);
+  a.nu = f->nu; a.nv = f->nv; a.nl = f->nl; a.N = f->nbins;
+  a.nq = nq; a.xyl = xyl; a.boxes = boxes; a.out = out;
+  return by_types(f->dtype, f->cum_dtype, [&](auto ft, auto ct) -> glint_status {
+    using FT = decltype(ft);
+    using CT = decltype(ct);
+    return by_rank<FT, CT>(f->R, [&](auto rr) -> glint_status {
+      return launch_trilinear<FT, CT, decltype(rr)::value>(a, stream);
     });
   });
 }

@@ -276,3 +276,49 @@ def test_grouped_c5_fp8_full_batch_sampled():
     want, mag = _oracle(F, flat, "fp8", "bf16")
     _check(got[idx], want, mag)
     print(f"c5 fp8/bf16: max |err| / N_q = {np.max(np.abs(got[idx] - want) / np.maximum(mag, 1e-300)):.2e}")
+
+
+def _oracle_trilinear(F, xyl, boxes, dtype, cum_dtype):
+    U, V, L, S, Tf = F
+    vals, scales = [], []
+    for x in (U, V, L):
+        v, s = _stored(x, dtype)
+        vals.append(v); scales.append(s)
+    for x in (S, Tf):
+        v, s = _stored(query.cumulative(x), cum_dtype)
+        vals.append(v); scales.append(s)
+    scale = np.ones(U.shape[1])
+    for s in scales:
+        if s is not None:
+            scale = scale * s.astype(np.float64)
+    return (query.range_query_trilinear(*vals, xyl, boxes, scale=scale),
+            query.range_query_trilinear(*vals, xyl, boxes, scale=scale, magnitude=True))
+
+
+@pytest.mark.parametrize("dtype,cum_dtype,R,N", [("f32", "f32", 16, 32), ("f32", "f32", 64, 64),
+                                                 ("bf16", "bf16", 128, 64), ("fp8", "bf16", 256, 128),
+                                                 ("f32", "f32", 256, 128)])
+def test_trilinear_query_matches_oracle(dtype, cum_dtype, R, N):
+    """Off-grid footprints: continuous centres and levels (including negative,
+    wrapped, non-finite and out-of-range coordinates, and empty boxes) against
+    the oracle's blend of the eight corner queries."""
+    print(f"trilinear dtype={dtype} cum={cum_dtype} R={R} N={N}", flush=True)
+    rng = np.random.default_rng(R * 3 + N)
+    nu, nv, nl = 37, 29, 7
+    F = _rand_factors(rng, nu, nv, nl, N, R)
+    n = 20011
+    xyl = np.stack([rng.uniform(-2 * nu, 3 * nu, n), rng.uniform(-nv, 2 * nv, n),
+                    rng.uniform(-1.0, nl + 1.0, n)], axis=1).astype(np.float32)
+    xyl[:50, 0] = np.nan
+    xyl[50:100, 1] = np.inf
+    xyl[100:150, 2] = -np.inf
+    xyl[150:200, 0] = 3e9
+    xyl[200:250] = np.round(xyl[200:250])          # grid points
+    boxes = _rand_queries(rng, n, nu, nv, nl, N, wild=True)[:, 3:7].copy()
+    tabs = G.make_tables(*[torch.tensor(x, device="cuda") for x in F], dtype=dtype, cum_dtype=cum_dtype)
+    got = G.query_trilinear(tabs, xyl, boxes).cpu().numpy()
+    want, mag = _oracle_trilinear(F, xyl, boxes, dtype, cum_dtype)
+    _check(got, want, mag)
+    c = np.clip(boxes, 0, N)
+    empty = (c[:, 0] >= c[:, 1]) | (c[:, 2] >= c[:, 3])
+    assert empty.any() and np.all(got[empty] == 0.0)
