@@ -19,6 +19,7 @@ query   summed-area (cumulative) tables (Sec. 4.4), point query (Sec. 4.3,
         Eq. decompress), range query (Sec. 4.4, Eq. rangeDecom and the
         Appendix proposition), its gradient, and the query conditioning
         magnitude used by the tolerances.
+sampling  hierarchical NDF importance sampling by range queries (Sec. 5.2).
 quant   BF16 and FP8 (OCP E4M3FN) rounding with per-column scales.
 adam    one Adam step (refinement of the factors; not in the paper).
 
