@@ -242,6 +242,16 @@ def main():
     boxes = q[:, 3:7].contiguous()
     tri_ms = timed(lambda: L.glint_query_trilinear(fac, xyl, boxes, out))
     del xyl, boxes
+    # hierarchical importance sampling: one sample per pixel footprint of the frame
+    npix = nq // cfg.boxes_per_point
+    s_uvl = q[::cfg.boxes_per_point, :3].contiguous()
+    levels = N.bit_length() - 1
+    s_rnd = torch.rand((npix, levels + 2), device=dev, generator=torch.Generator(device=dev).manual_seed(5))
+    s_h = torch.empty((npix, 2), dtype=torch.float32, device=dev)
+    s_pdf = torch.empty(npix, dtype=torch.float32, device=dev)
+    s_bins = torch.empty((npix, 2), dtype=torch.int32, device=dev)
+    sample_ms = timed(lambda: L.glint_sample(fac, s_uvl, s_rnd, s_h, s_pdf, s_bins))
+    del s_uvl, s_rnd, s_h, s_pdf, s_bins
 
     ncells = cfg.nu * cfg.nv * nl
     t_elems = ncells * N * N
@@ -295,6 +305,11 @@ def main():
             "kernel": "k_query_trilinear<float,float,64,4>: the batch at fractional centres and levels "
                       "(eight-footprint trilinear blend, two rows per factor)",
             "ms": tri_ms, "queries_per_s": nq / (tri_ms * 1e-3),
+        },
+        "sample_kernel": {
+            "kernel": f"k_sample<float,float,64,4>: one hierarchical NDF importance sample ({levels} levels of "
+                      "four-quad range queries) per pixel footprint of the frame",
+            "samples": npix, "ms": sample_ms, "samples_per_s": npix / (sample_ms * 1e-3),
         },
         "stages_ms": stage_ms,
         "events_ms_per_step": ev_total,

@@ -255,6 +255,24 @@ glint_status glint_query_grouped(const glint_factors* f, int64_t npts, int32_t K
 glint_status glint_query_trilinear(const glint_factors* f, int64_t nq, const float* xyl,
                                    const int32_t* boxes, float* out, hipStream_t stream);
 
+/* Hierarchical importance sampling of a footprint's NDF image by range
+ * queries (Sec. 5.2).  For each record uvl[i] = (u, v, l) (wrapped/clamped
+ * as in glint_query): the N x N image is split into four quads, ordered
+ * (s low, t low), (s low, t high), (s high, t low), (s high, t high); quad
+ * masses are range queries, negative ones count as zero; the draw
+ * rnd[i][k] in [0, 1) picks the first quad whose running mass sum exceeds
+ * rnd * total; this repeats for log2(N) levels, then
+ * h[i] = (-1 + (s + rnd[i][L]) * 2/N, -1 + (t + rnd[i][L+1]) * 2/N) with
+ * L = log2(N) and (s, t) = bins[i] the final bin; pdf[i] = P(bin) / (2/N)^2,
+ * P(bin) the product of the chosen quads' probabilities (the normalised
+ * NDF mass of the bin when no mass is negative).  A record whose quads hold
+ * no positive mass at some level gets bins (-1, -1), pdf 0, h (0, 0).
+ * rnd: float [n][L + 2] (the caller's uniform draws); h: float [n][2];
+ * pdf: float [n]; bins: int32 [n][2].  FP32 arithmetic; same table limits
+ * as glint_query. */
+glint_status glint_sample(const glint_factors* f, int64_t n, const int32_t* uvl, const float* rnd,
+                          float* h, float* pdf, int32_t* bins, hipStream_t stream);
+
 /* ---- step 6: gradient of the query (not in the paper) -------------------- */
 
 /* Gradients of sum_i gout[i] * q[i] with respect to the stored values of U,

@@ -11,7 +11,7 @@ from ._lib import GlintError, NdfDesc  # noqa: F401
 from .api import (  # noqa: F401
     AlsResult, QueryTables, als_workspace, build_tensor, convert, cp_als, cumulative, cumulative_backward,
     cp_als_texel, desc_of, make_tables, mttkrp, mttkrp_texel, query, query_backward, query_grouped, query_trilinear,
-    range_bruteforce, texel_bins, texel_workspace,
+    range_bruteforce, sample, texel_bins, texel_workspace,
 )
 from .autograd import GlintQuery, glint_query_fn  # noqa: F401
 from .refine import refine  # noqa: F401

@@ -87,6 +87,7 @@ _SIGS = {
     "glint_query": (_I32, [_FAC, _I64, _P, _P, _P]),
     "glint_query_grouped": (_I32, [_FAC, _I64, _I32, _P, _P, _P, _P]),
     "glint_query_trilinear": (_I32, [_FAC, _I64, _P, _P, _P, _P]),
+    "glint_sample": (_I32, [_FAC, _I64, _P, _P, _P, _P, _P, _P]),
     "glint_query_backward": (_I32, [_FAC, _I64, _P, _P, _P, _P, _P, _P, _P, _P]),
     "glint_cumulative_backward": (_I32, [_I32, _I32, _P, _P, _P]),
     "glint_mse_grad": (_I32, [_I64, _P, _P, _P, _P, _P]),
@@ -297,6 +298,16 @@ def glint_query_trilinear(f: Factors, xyl, boxes, out, stream=None):
     _check("glint_query_trilinear", lib().glint_query_trilinear(
         ctypes.byref(f), nq, _ptr(xyl, torch.float32, "xyl"), _ptr(boxes, torch.int32, "boxes"),
         _ptr(out, torch.float32, "out"), _stream(stream)))
+
+
+def glint_sample(f: Factors, uvl, rnd, h, pdf, bins, stream=None):
+    n = uvl.shape[0]
+    if tuple(h.shape) != (n, 2) or tuple(bins.shape) != (n, 2) or pdf.shape[0] != n or rnd.shape[0] != n:
+        raise ValueError("shapes: uvl [n][3], rnd [n][log2(N)+2], h [n][2], pdf [n], bins [n][2]")
+    _check("glint_sample", lib().glint_sample(
+        ctypes.byref(f), n, _ptr(uvl, torch.int32, "uvl"), _ptr(rnd, torch.float32, "rnd"),
+        _ptr(h, torch.float32, "h"), _ptr(pdf, torch.float32, "pdf"), _ptr(bins, torch.int32, "bins"),
+        _stream(stream)))
 
 
 def glint_query_backward(f: Factors, q, gout, dU, dV, dL, dCS, dCT, stream=None):

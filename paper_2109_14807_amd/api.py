@@ -206,6 +206,21 @@ def query_trilinear(tables: QueryTables, xyl, boxes, out=None):
     return out
 
 
+def sample(tables: QueryTables, uvl, rnd):
+    """Hierarchical importance samples: (h [n][2], pdf [n], bins [n][2])."""
+    uvl = _dev(uvl, torch.int32)
+    rnd = _dev(rnd, torch.float32)
+    n = uvl.shape[0]
+    levels = int(tables.CS.shape[0] - 1).bit_length() - 1
+    if rnd.shape != (n, levels + 2):
+        raise ValueError(f"rnd must be [n][{levels + 2}]")
+    h = torch.empty((n, 2), dtype=torch.float32, device=_DEV)
+    pdf = torch.empty(n, dtype=torch.float32, device=_DEV)
+    bins = torch.empty((n, 2), dtype=torch.int32, device=_DEV)
+    L.glint_sample(tables.factors(), uvl, rnd, h, pdf, bins)
+    return h, pdf, bins
+
+
 def query_backward(tables: QueryTables, q, gout):
     """Gradients (dU, dV, dL, dCS, dCT) of sum gout * q w.r.t. the stored tables."""
     R = tables.R

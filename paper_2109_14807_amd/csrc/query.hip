@@ -507,6 +507,181 @@ __global__ __launch_bounds__(kQueryThreads) void k_query_trilinear(TriArgs a) {
   }
 }
 
+// Hierarchical importance sampling of the NDF image of a footprint (Sec.
+// 5.2): the image is split into four quads whose masses come from range
+// queries, one is drawn in proportion to its mass (negative masses count as
+// zero), and the split repeats inside it for log2(N) levels; the sample is
+// then placed uniformly inside the final bin.  One lane group per sample:
+// W = U V L once, the current bounds' summed-area rows carried in registers,
+// two new rows (the midpoints) and one four-way group reduction per level.
+// The choice is taken by the group's first lane and broadcast.  A sample
+// whose quads hold no positive mass fails: bin (-1, -1), pdf 0, h = (0, 0).
+struct SampleArgs {
+  const void* U;
+  const void* V;
+  const void* L;
+  const void* CS;
+  const void* CT;
+  Scales scale;
+  int nu, nv, nl, N, levels;
+  int64_t n;
+  const int32_t* uvl;
+  const float* rnd;     // [n][levels + 2]
+  float* h;             // [n][2]
+  float* pdf;           // [n]
+  int32_t* bins;        // [n][2]
+};
+
+template <typename FT, typename CT, int R, int RPL, bool GC>
+__global__ __launch_bounds__(kQueryThreads) void k_sample(SampleArgs a) {
+  constexpr int LPQ = R / RPL;
+  typedef typename LdsCum<CT>::type LT;
+  extern __shared__ __align__(16) float lds[];
+  float* Ls = lds;
+  LT* CSs = reinterpret_cast<LT*>(Ls + a.nl * R);
+  LT* CTs = CSs + (a.N + 1) * R;
+  const size_t cum_bytes = GC ? 0 : 2 * sizeof(LT) * (a.N + 1) * R;
+  int4* pts = reinterpret_cast<int4*>(
+      reinterpret_cast<unsigned char*>(lds) + glint_round_up(sizeof(float) * a.nl * R + cum_bytes, 16));
+  const CT* CSg = static_cast<const CT*>(a.CS);
+  const CT* CTg = static_cast<const CT*>(a.CT);
+  stage_table<FT>(Ls, static_cast<const FT*>(a.L), a.nl, R, &a.scale);
+  if constexpr (!GC) {
+    stage_cum<CT, LT>(CSs, CSg, (a.N + 1) * R);
+    stage_cum<CT, LT>(CTs, CTg, (a.N + 1) * R);
+  }
+  __syncthreads();
+
+  const FT* __restrict__ U = static_cast<const FT*>(a.U);
+  const FT* __restrict__ V = static_cast<const FT*>(a.V);
+  const int lane = threadIdx.x & 63;
+  const int g = lane / LPQ;
+  const int j = lane % LPQ;
+  const int r0 = j * RPL;
+  const int nr = a.levels + 2;
+  const float w = 2.0f / static_cast<float>(a.N);
+  int4* wpts = pts + (threadIdx.x >> 6) * 64;
+  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
+  for (int64_t base = wave * 64; base < a.n; base += nwaves * 64) {
+    {
+      const int64_t pi = base + lane;
+      const int64_t pc = pi < a.n ? pi : a.n - 1;
+      const int32_t* rec = a.uvl + pc * 3;
+      const int f0 = rec[0], f1 = rec[1], f2 = rec[2];
+      wpts[lane] = make_int4(glint_wrap(f0, a.nu) * R, glint_wrap(f1, a.nv) * R,
+                             glint_clampi(f2, 0, a.nl - 1) * R, 0);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    float hs = 0.0f, ht = 0.0f, pd = 0.0f;
+    int bs = -1, bt = -1;
+    for (int jj = 0; jj < LPQ; ++jj) {
+      const int64_t pi = base + g * LPQ + jj;
+      if (pi >= a.n) break;                 // group-uniform
+      const int4 pr = wpts[g * LPQ + jj];
+      float W[RPL];
+      {
+        float uu[RPL], vv[RPL], lr[RPL];
+        load_row<FT, RPL>(U + pr.x + r0, uu);
+        load_row<FT, RPL>(V + pr.y + r0, vv);
+        lds_row<RPL>(Ls + pr.z + r0, lr);
+#pragma unroll
+        for (int e = 0; e < RPL; ++e) W[e] = uu[e] * vv[e] * lr[e];
+      }
+      const float* rn = a.rnd + pi * nr;
+      int s0 = 0, s1 = a.N, t0 = 0, t1 = a.N;
+      float cs0[RPL], cs1[RPL], ct0[RPL], ct1[RPL];
+      cum_row<GC, CT, LT, RPL>(CSs, CSg, r0, cs0);
+      cum_row<GC, CT, LT, RPL>(CSs, CSg, a.N * R + r0, cs1);
+      cum_row<GC, CT, LT, RPL>(CTs, CTg, r0, ct0);
+      cum_row<GC, CT, LT, RPL>(CTs, CTg, a.N * R + r0, ct1);
+      float prob = 1.0f;
+      bool ok = true;
+      for (int k = 0; k < a.levels; ++k) {
+        const int sm = (s0 + s1) >> 1, tm = (t0 + t1) >> 1;
+        float csm[RPL], ctm[RPL];
+        cum_row<GC, CT, LT, RPL>(CSs, CSg, sm * R + r0, csm);
+        cum_row<GC, CT, LT, RPL>(CTs, CTg, tm * R + r0, ctm);
+        float q00 = 0.0f, q01 = 0.0f, q10 = 0.0f, q11 = 0.0f;
+#pragma unroll
+        for (int e = 0; e < RPL; ++e) {
+          const float sl = csm[e] - cs0[e], sh = cs1[e] - csm[e];
+          const float tl = ctm[e] - ct0[e], th = ct1[e] - ctm[e];
+          const float ws = W[e] * sl, wh = W[e] * sh;
+          q00 += ws * tl;
+          q01 += ws * th;
+          q10 += wh * tl;
+          q11 += wh * th;
+        }
+        q00 = glint_group_sum<LPQ>(q00);
+        q01 = glint_group_sum<LPQ>(q01);
+        q10 = glint_group_sum<LPQ>(q10);
+        q11 = glint_group_sum<LPQ>(q11);
+        const float m0 = fmaxf(q00, 0.0f), m1 = fmaxf(q01, 0.0f), m2 = fmaxf(q10, 0.0f), m3 = fmaxf(q11, 0.0f);
+        const float total = ((m0 + m1) + m2) + m3;
+        int pick = -1;
+        if (total > 0.0f) {
+          const float target = rn[k] * total;
+          float run = m0;
+          pick = 3;
+          if (target < run) pick = 0;
+          else if (target < (run += m1)) pick = 1;
+          else if (target < (run += m2)) pick = 2;
+          // never an empty quad (the target can meet the top of the range by rounding)
+          if (pick == 3 && !(m3 > 0.0f)) pick = m2 > 0.0f ? 2 : (m1 > 0.0f ? 1 : 0);
+        }
+        pick = __shfl(pick, g * LPQ);      // one decision per group
+        if (pick < 0) {
+          ok = false;
+          break;
+        }
+        const float mp = pick == 0 ? m0 : (pick == 1 ? m1 : (pick == 2 ? m2 : m3));
+        prob *= __shfl(mp / total, g * LPQ);
+        if (pick >= 2) {
+          s0 = sm;
+#pragma unroll
+          for (int e = 0; e < RPL; ++e) cs0[e] = csm[e];
+        } else {
+          s1 = sm;
+#pragma unroll
+          for (int e = 0; e < RPL; ++e) cs1[e] = csm[e];
+        }
+        if (pick & 1) {
+          t0 = tm;
+#pragma unroll
+          for (int e = 0; e < RPL; ++e) ct0[e] = ctm[e];
+        } else {
+          t1 = tm;
+#pragma unroll
+          for (int e = 0; e < RPL; ++e) ct1[e] = ctm[e];
+        }
+      }
+      if (j == jj) {
+        if (ok) {
+          bs = s0;
+          bt = t0;
+          hs = -1.0f + (static_cast<float>(s0) + rn[a.levels]) * w;
+          ht = -1.0f + (static_cast<float>(t0) + rn[a.levels + 1]) * w;
+          pd = prob / (w * w);
+        } else {
+          bs = bt = -1;
+          hs = ht = pd = 0.0f;
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int64_t qo = base + g * LPQ + j;
+    if (qo < a.n) {
+      a.h[2 * qo] = hs;
+      a.h[2 * qo + 1] = ht;
+      a.pdf[qo] = pd;
+      a.bins[2 * qo] = bs;
+      a.bins[2 * qo + 1] = bt;
+    }
+  }
+}
+
 // Backward.  Phase 1 (one lane per query, as in the forward) resolves the
 // record and its upstream gradient (0 for empty boxes and padding, so those
 // contribute exact zeros).  Phase 2: lane group g walks its LPQ consecutive
@@ -855,6 +1030,31 @@ glint_status launch_trilinear(const TriArgs& a, hipStream_t stream) {
 }
 
 template <typename FT, typename CT, int R>
+glint_status launch_sample(const SampleArgs& a, hipStream_t stream) {
+  constexpr int RPL = rpl_for<FT>() <= R ? rpl_for<FT>() : R;
+  const size_t slots = sizeof(int4) * (kQueryThreads / 64) * 64;
+  const bool gc = static_cast<int>(query_lds_bytes<CT, R>(a.nl, a.N, false, slots)) > g_max_lds;
+  const size_t lds = query_lds_bytes<CT, R>(a.nl, a.N, gc, slots);
+  if (static_cast<int>(lds) > g_max_lds)
+    return glint_fail(GLINT_E_UNSUPPORTED, "L needs %zu bytes of LDS (device max %d)", lds, g_max_lds);
+  const int64_t waves_needed = (a.n + 63) / 64;
+  constexpr int WPB = kQueryThreads / 64;
+  int64_t blocks = (waves_needed + WPB - 1) / WPB;
+  const int64_t cap = static_cast<int64_t>(g_cu_count) * 4;
+  if (blocks > cap) blocks = cap;
+  if (blocks < 1) blocks = 1;
+  glint_clear_launch_error();
+  if (gc)
+    hipLaunchKernelGGL((k_sample<FT, CT, R, RPL, true>), dim3(static_cast<unsigned>(blocks)), dim3(kQueryThreads),
+                       lds, stream, a);
+  else
+    hipLaunchKernelGGL((k_sample<FT, CT, R, RPL, false>), dim3(static_cast<unsigned>(blocks)), dim3(kQueryThreads),
+                       lds, stream, a);
+  GLINT_LAUNCHED("k_sample");
+  return GLINT_OK;
+}
+
+template <typename FT, typename CT, int R>
 glint_status launch_backward(const QueryArgs& a, const float* gout, float* dU, float* dV,
                              float* dL, float* dCS, float* dCT, hipStream_t stream) {
   constexpr int RPL = rpl_for<FT>() <= R ? rpl_for<FT>() : R;
@@ -973,6 +1173,28 @@ glint_status glint_query_trilinear(const glint_factors* f, int64_t nq, const flo
     using CT = decltype(ct);
     return by_rank<FT, CT>(f->R, [&](auto rr) -> glint_status {
       return launch_trilinear<FT, CT, decltype(rr)::value>(a, stream);
+    });
+  });
+}
+
+glint_status glint_sample(const glint_factors* f, int64_t n, const int32_t* uvl, const float* rnd, float* h,
+                          float* pdf, int32_t* bins, hipStream_t stream) {
+  glint_status st = check_factors(f);
+  if (st != GLINT_OK) return st;
+  GLINT_REQUIRE(n >= 0, "n must be >= 0");
+  if (n == 0) return GLINT_OK;
+  GLINT_REQUIRE(uvl && rnd && h && pdf && bins, "null pointer argument");
+  SampleArgs a;
+  a.U = f->U; a.V = f->V; a.L = f->L; a.CS = f->CS; a.CT = f->CT; a.scale = scales_of(f);
+  a.nu = f->nu; a.nv = f->nv; a.nl = f->nl; a.N = f->nbins;
+  a.levels = 0;
+  while ((2 << a.levels) <= f->nbins) ++a.levels;     // log2(nbins)
+  a.n = n; a.uvl = uvl; a.rnd = rnd; a.h = h; a.pdf = pdf; a.bins = bins;
+  return by_types(f->dtype, f->cum_dtype, [&](auto ft, auto ct) -> glint_status {
+    using FT = decltype(ft);
+    using CT = decltype(ct);
+    return by_rank<FT, CT>(f->R, [&](auto rr) -> glint_status {
+      return launch_sample<FT, CT, decltype(rr)::value>(a, stream);
     });
   });
 }
