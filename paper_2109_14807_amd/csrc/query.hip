@@ -477,15 +477,28 @@ __global__ __launch_bounds__(kQueryThreads) void k_query_trilinear(TriArgs a) {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     float res = 0.0f;
+    // the interpolated footprint product is reused while consecutive records
+    // share the centre and level (several boxes of one shading point)
+    int pu0 = -1, pv0 = -1, pl0 = -1;
+    float pwx = -1.0f, pwy = -1.0f, pwl = -1.0f;
+    float W[RPL];
     for (int jj = 0; jj < LPQ; ++jj) {
       const TriRows r = wrows[g * (LPQ + 1) + jj];
-      float ua[RPL], ub[RPL], va[RPL], vb[RPL], la[RPL], lb[RPL];
-      load_row<FT, RPL>(U + r.u0 + r0, ua);
-      load_row<FT, RPL>(U + r.u1 + r0, ub);
-      load_row<FT, RPL>(V + r.v0 + r0, va);
-      load_row<FT, RPL>(V + r.v1 + r0, vb);
-      lds_row<RPL>(Ls + r.l0 + r0, la);
-      lds_row<RPL>(Ls + r.l1 + r0, lb);
+      if (r.u0 != pu0 || r.v0 != pv0 || r.l0 != pl0 || r.wx != pwx || r.wy != pwy || r.wl != pwl) {
+        float ua[RPL], ub[RPL], va[RPL], vb[RPL], la[RPL], lb[RPL];
+        load_row<FT, RPL>(U + r.u0 + r0, ua);
+        load_row<FT, RPL>(U + r.u1 + r0, ub);
+        load_row<FT, RPL>(V + r.v0 + r0, va);
+        load_row<FT, RPL>(V + r.v1 + r0, vb);
+        lds_row<RPL>(Ls + r.l0 + r0, la);
+        lds_row<RPL>(Ls + r.l1 + r0, lb);
+#pragma unroll
+        for (int e = 0; e < RPL; ++e)
+          W[e] = (ua[e] + r.wx * (ub[e] - ua[e])) * (va[e] + r.wy * (vb[e] - va[e])) *
+                 (la[e] + r.wl * (lb[e] - la[e]));
+        pu0 = r.u0; pv0 = r.v0; pl0 = r.l0;
+        pwx = r.wx; pwy = r.wy; pwl = r.wl;
+      }
       float sh[RPL], sl[RPL], th[RPL], tl[RPL];
       cum_row<GC, CT, LT, RPL>(CSs, CSg, r.sh + r0, sh);
       cum_row<GC, CT, LT, RPL>(CSs, CSg, r.sl + r0, sl);
@@ -493,11 +506,7 @@ __global__ __launch_bounds__(kQueryThreads) void k_query_trilinear(TriArgs a) {
       cum_row<GC, CT, LT, RPL>(CTs, CTg, r.tl + r0, tl);
       float acc = 0.0f;
 #pragma unroll
-      for (int e = 0; e < RPL; ++e) {
-        const float w = (ua[e] + r.wx * (ub[e] - ua[e])) * (va[e] + r.wy * (vb[e] - va[e])) *
-                        (la[e] + r.wl * (lb[e] - la[e]));
-        acc += w * (sh[e] - sl[e]) * (th[e] - tl[e]);
-      }
+      for (int e = 0; e < RPL; ++e) acc += W[e] * (sh[e] - sl[e]) * (th[e] - tl[e]);
       acc = glint_group_sum<LPQ>(acc);
       res = (j == jj) ? acc : res;
     }

@@ -314,6 +314,7 @@ def test_trilinear_query_matches_oracle(dtype, cum_dtype, R, N):
     xyl[100:150, 2] = -np.inf
     xyl[150:200, 0] = 3e9
     xyl[200:250] = np.round(xyl[200:250])          # grid points
+    xyl[8000:16000] = np.repeat(xyl[8000:9000], 8, axis=0)   # 8 boxes per shading point
     boxes = _rand_queries(rng, n, nu, nv, nl, N, wild=True)[:, 3:7].copy()
     tabs = G.make_tables(*[torch.tensor(x, device="cuda") for x in F], dtype=dtype, cum_dtype=cum_dtype)
     got = G.query_trilinear(tabs, xyl, boxes).cpu().numpy()
