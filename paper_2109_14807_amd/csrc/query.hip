@@ -741,13 +741,16 @@ __global__ __launch_bounds__(kQueryThreads) void k_query_backward(QueryArgs a, c
   float aU[RPL], aV[RPL], aL[RPL];
 #pragma unroll
   for (int e = 0; e < RPL; ++e) aU[e] = aV[e] = aL[e] = 0.0f;
+  // The LDS gradient rows are swizzled: lane j's rank r0 + e sits at e*LPQ + j,
+  // so each atomic instruction of a lane group hits consecutive words (no bank
+  // conflicts); the rows are unswizzled when the block adds them to global memory.
   auto flush = [&]() {
     if (cu >= 0) {
 #pragma unroll
       for (int e = 0; e < RPL; ++e) {
         if (aU[e] != 0.0f) atomicAdd(&dU[cu + r0 + e], aU[e]);
         if (aV[e] != 0.0f) atomicAdd(&dV[cv + r0 + e], aV[e]);
-        if (aL[e] != 0.0f) atomicAdd(&gL[cl + r0 + e], aL[e]);
+        if (aL[e] != 0.0f) atomicAdd(&gL[cl + e * LPQ + j], aL[e]);
         aU[e] = aV[e] = aL[e] = 0.0f;
       }
     }
@@ -807,22 +810,189 @@ __global__ __launch_bounds__(kQueryThreads) void k_query_backward(QueryArgs a, c
         aV[e] += s * uu[e] * lr[e] * st;
         aL[e] += s * uv * st;
         const float wS = s * uv * lr[e] * dT;
-        atomicAdd(&gCS[r.sh + r0 + e], wS);
-        atomicAdd(&gCS[r.sl + r0 + e], -wS);
+        const int sw = e * LPQ + j;
+        atomicAdd(&gCS[r.sh + sw], wS);
+        atomicAdd(&gCS[r.sl + sw], -wS);
         const float wT = s * uv * lr[e] * dS;
-        atomicAdd(&gCT[r.th + r0 + e], wT);
-        atomicAdd(&gCT[r.tl + r0 + e], -wT);
+        atomicAdd(&gCT[r.th + sw], wT);
+        atomicAdd(&gCT[r.tl + sw], -wT);
       }
     }
     __builtin_amdgcn_wave_barrier();
   }
   flush();
   __syncthreads();
-  for (int i = threadIdx.x; i < nl * R; i += blockDim.x)
-    if (gL[i] != 0.0f) atomicAdd(&dL[i], gL[i]);
+  // swizzled position p of a row holds rank (p % LPQ) * RPL + p / LPQ
+  for (int i = threadIdx.x; i < nl * R; i += blockDim.x) {
+    const int row = i / R, p = i % R;
+    if (gL[i] != 0.0f) atomicAdd(&dL[row * R + (p % LPQ) * RPL + p / LPQ], gL[i]);
+  }
   for (int i = threadIdx.x; i < N1 * R; i += blockDim.x) {
-    if (gCS[i] != 0.0f) atomicAdd(&dCS[i], gCS[i]);
-    if (gCT[i] != 0.0f) atomicAdd(&dCT[i], gCT[i]);
+    const int row = i / R, p = i % R;
+    const int k = row * R + (p % LPQ) * RPL + p / LPQ;
+    if (gCS[i] != 0.0f) atomicAdd(&dCS[k], gCS[i]);
+    if (gCT[i] != 0.0f) atomicAdd(&dCT[k], gCT[i]);
+  }
+}
+
+// Query backward in the rank-owner layout, for N <= 64 (NT = ceil((N+1)/16)
+// row tiles): wavefront w of a block owns ranks [16 w, 16 w + 16) and every
+// wavefront walks the block's chunk of records four at a time, lane
+// j + 16 k holding rank 16 w + j of record k.  The summed-area-table
+// gradients dCS[row][r] = sum over records of ([row = s_hi] - [row = s_lo]) wS
+// (and dCT, and dL over the levels) are products of a one-hot record-to-row
+// matrix with the per-record rank vectors, so they accumulate on the matrix
+// cores (v_mfma_f32_16x16x4f32: A[i][k] from lane i + 16k, B[k][j] from lane
+// j + 16k) in registers for the whole chunk and reach global memory once per
+// block.  dU and dV are summed over the records of a step that share the
+// footprint and kept in registers while the footprint repeats.
+typedef float bwd_f32x4 __attribute__((ext_vector_type(4)));
+
+struct alignas(16) BwdRec {
+  int u, v, l, sh, sl, th, tl;
+  float g;
+};
+
+template <int NT>
+constexpr bool backward_mfma_tiles_ok() { return NT >= 1 && NT <= 5; }
+
+// waves of one record stream (one per 16-rank tile) and record streams per block
+template <int R>
+constexpr int bwd_streams() { return R / 16 >= 16 ? 1 : 16 / (R / 16); }
+
+template <typename FT, typename CT, int R, int NT>
+__global__ __launch_bounds__(1024) void k_query_backward_mfma(QueryArgs a, const float* __restrict__ gout,
+                                                                     float* __restrict__ dU,
+                                                                     float* __restrict__ dV,
+                                                                     float* __restrict__ dL,
+                                                                     float* __restrict__ dCS,
+                                                                     float* __restrict__ dCT, int64_t chunk) {
+  static_assert(backward_mfma_tiles_ok<NT>(), "row tiles");
+  extern __shared__ __align__(16) float lds[];
+  const int nl = a.nl, N1 = a.N + 1;
+  float* Ls = lds;                  // decoded L (no scale)
+  float* CSs = Ls + nl * R;
+  float* CTs = CSs + N1 * R;
+  float* sc = CTs + N1 * R;         // [R] folded scale
+  BwdRec* slots = reinterpret_cast<BwdRec*>(sc + R);
+  stage_table<FT>(Ls, static_cast<const FT*>(a.L), nl, R, nullptr);
+  stage_table<CT>(CSs, static_cast<const CT*>(a.CS), N1, R, nullptr);
+  stage_table<CT>(CTs, static_cast<const CT*>(a.CT), N1, R, nullptr);
+  for (int i = threadIdx.x; i < R; i += blockDim.x) sc[i] = folded_scale(a.scale, i);
+  __syncthreads();
+
+  const FT* __restrict__ U = static_cast<const FT*>(a.U);
+  const FT* __restrict__ V = static_cast<const FT*>(a.V);
+  constexpr int NW = R / 16;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int w = wid % NW, stream = wid / NW;           // rank tile and record stream of this wave
+  const int j = lane & 15, kq = lane >> 4;
+  const int r = 16 * w + j;
+  const float scr = sc[r];
+  BwdRec* wslots = slots + wid * 64;
+  bwd_f32x4 accS[NT], accT[NT], accL;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) accS[t] = accT[t] = bwd_f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  accL = bwd_f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  int cu = -1, cv = -1;          // footprint of the running dU, dV sums (lanes of record slot 0)
+  float ru = 0.0f, rv = 0.0f;
+  auto flush = [&]() {
+    if (kq == 0 && cu >= 0) {
+      if (ru != 0.0f) atomicAdd(&dU[cu * R + r], ru);
+      if (rv != 0.0f) atomicAdd(&dV[cv * R + r], rv);
+    }
+    cu = cv = -1;
+    ru = rv = 0.0f;
+  };
+  const int64_t t0 = (static_cast<int64_t>(blockIdx.x) * bwd_streams<R>() + stream) * chunk;
+  const int64_t t1 = t0 + chunk < a.nq ? t0 + chunk : a.nq;
+  for (int64_t base = t0; base < t1; base += 64) {
+    {
+      const int64_t qi = base + lane;
+      const bool in = qi < t1;
+      const int64_t qc = in ? qi : t1 - 1;
+      const int32_t* rec = a.q + qc * 7;
+      int f[7];
+#pragma unroll
+      for (int i = 0; i < 7; ++i) f[i] = rec[i];
+      const float gq = gout[qc];
+      BwdRec b;
+      b.u = glint_wrap(f[0], a.nu);
+      b.v = glint_wrap(f[1], a.nv);
+      b.l = glint_clampi(f[2], 0, nl - 1);
+      const int slo = glint_clampi(f[3], 0, a.N), shi = glint_clampi(f[4], 0, a.N);
+      const int tlo = glint_clampi(f[5], 0, a.N), thi = glint_clampi(f[6], 0, a.N);
+      b.sh = shi; b.sl = slo; b.th = thi; b.tl = tlo;
+      b.g = (in && slo < shi && tlo < thi) ? gq : 0.0f;
+      wslots[lane] = b;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    // the U and V values of the next step are loaded while this one is used
+    BwdRec bn = wslots[kq];
+    float un = dec<FT>(U[bn.u * R + r]), vn = dec<FT>(V[bn.v * R + r]);
+    for (int st = 0; st < 16; ++st) {
+      const BwdRec b = bn;
+      const float uu = un, vv = vn;
+      if (st < 15) {
+        bn = wslots[4 * (st + 1) + kq];
+        un = dec<FT>(U[bn.u * R + r]);
+        vn = dec<FT>(V[bn.v * R + r]);
+      }
+      const float ll = Ls[b.l * R + r];
+      const float dS = CSs[b.sh * R + r] - CSs[b.sl * R + r];
+      const float dT = CTs[b.th * R + r] - CTs[b.tl * R + r];
+      const float x = b.g * scr;
+      const float uvl = uu * vv * ll;
+      const float wS = x * uvl * dT, wT = x * uvl * dS;
+      const float st2 = dS * dT;
+      const float gu = x * vv * ll * st2, gv = x * uu * ll * st2, gl = x * uu * vv * st2;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int row = 16 * t + j;
+        const float as = (row == b.sh ? 1.0f : 0.0f) - (row == b.sl ? 1.0f : 0.0f);
+        const float at = (row == b.th ? 1.0f : 0.0f) - (row == b.tl ? 1.0f : 0.0f);
+        accS[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, wS, accS[t], 0, 0, 0);
+        accT[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(at, wT, accT[t], 0, 0, 0);
+      }
+      accL = __builtin_amdgcn_mfma_f32_16x16x4f32(j == b.l ? 1.0f : 0.0f, gl, accL, 0, 0, 0);
+      // dU, dV: one sum per step when its four records share the footprint
+      const int u0 = __shfl(b.u, j), v0 = __shfl(b.v, j);
+      if (__all(b.u == u0 && b.v == v0)) {
+        float su = gu + __shfl_xor(gu, 16), sv = gv + __shfl_xor(gv, 16);
+        su += __shfl_xor(su, 32);
+        sv += __shfl_xor(sv, 32);
+        if (u0 != cu || v0 != cv) {
+          flush();
+          cu = u0;
+          cv = v0;
+        }
+        ru += su;
+        rv += sv;
+      } else {
+        flush();
+        if (gu != 0.0f) atomicAdd(&dU[b.u * R + r], gu);
+        if (gv != 0.0f) atomicAdd(&dV[b.v * R + r], gv);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  flush();
+  // D[i][j] sits in lane j + 16 (i / 4), item i % 4
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = 16 * t + 4 * kq + q;
+      if (row < N1) {
+        if (accS[t][q] != 0.0f) atomicAdd(&dCS[row * R + r], accS[t][q]);
+        if (accT[t][q] != 0.0f) atomicAdd(&dCT[row * R + r], accT[t][q]);
+      }
+    }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int row = 4 * kq + q;
+    if (row < nl && accL[q] != 0.0f) atomicAdd(&dL[row * R + r], accL[q]);
   }
 }
 
@@ -1063,9 +1233,40 @@ glint_status launch_sample(const SampleArgs& a, hipStream_t stream) {
   return GLINT_OK;
 }
 
+template <typename FT, typename CT, int R, int NT>
+glint_status launch_backward_mfma(const QueryArgs& a, const float* gout, float* dU, float* dV, float* dL,
+                                  float* dCS, float* dCT, hipStream_t stream) {
+  constexpr int NW = R / 16, NS = bwd_streams<R>();
+  const size_t lds = sizeof(float) * (static_cast<size_t>(a.nl + 2 * (a.N + 1)) * R + R) +
+                     sizeof(BwdRec) * NW * NS * 64;
+  if (static_cast<int>(lds) > g_max_lds)
+    return glint_fail(GLINT_E_UNSUPPORTED, "backward needs %zu bytes of LDS (device max %d)", lds, g_max_lds);
+  // record streams of 64-record units, each a contiguous chunk
+  const int64_t units = (a.nq + 63) / 64;
+  int64_t streams = static_cast<int64_t>(g_cu_count) * 2 * NS;
+  if (streams > units) streams = units;
+  if (streams < 1) streams = 1;
+  const int64_t chunk = (units + streams - 1) / streams * 64;
+  streams = (a.nq + chunk - 1) / chunk;
+  const int64_t blocks = (streams + NS - 1) / NS;
+  glint_clear_launch_error();
+  hipLaunchKernelGGL((k_query_backward_mfma<FT, CT, R, NT>), dim3(static_cast<unsigned>(blocks)), dim3(NW * NS * 64),
+                     lds, stream, a, gout, dU, dV, dL, dCS, dCT, chunk);
+  GLINT_LAUNCHED("k_query_backward_mfma");
+  return GLINT_OK;
+}
+
 template <typename FT, typename CT, int R>
 glint_status launch_backward(const QueryArgs& a, const float* gout, float* dU, float* dV,
                              float* dL, float* dCS, float* dCT, hipStream_t stream) {
+  if (a.nl <= 16 && a.N <= 64) {
+    switch ((a.N + 1 + 15) / 16) {
+      case 1: return launch_backward_mfma<FT, CT, R, 1>(a, gout, dU, dV, dL, dCS, dCT, stream);
+      case 2: return launch_backward_mfma<FT, CT, R, 2>(a, gout, dU, dV, dL, dCS, dCT, stream);
+      case 3: return launch_backward_mfma<FT, CT, R, 3>(a, gout, dU, dV, dL, dCS, dCT, stream);
+      default: return launch_backward_mfma<FT, CT, R, 5>(a, gout, dU, dV, dL, dCS, dCT, stream);
+    }
+  }
   constexpr int RPL = rpl_for<FT>() <= R ? rpl_for<FT>() : R;
   const size_t lds = sizeof(float) * (2 * static_cast<size_t>(a.nl + 2 * (a.N + 1)) * R + R) +
                      sizeof(QueryRows) * (kQueryThreads / 64) * 64;
