@@ -240,8 +240,9 @@ def main():
     frac = torch.tensor([0.37, 0.61, 0.25], dtype=torch.float32, device=dev)
     xyl = (q[:, :3].float() + frac).contiguous()
     boxes = q[:, 3:7].contiguous()
-    tri_ms = timed(lambda: L.glint_query_trilinear(fac, xyl, boxes, out))
-    del xyl, boxes
+    out_tri = torch.empty_like(out)      # `out` keeps the step's query for the parity sample
+    tri_ms = timed(lambda: L.glint_query_trilinear(fac, xyl, boxes, out_tri))
+    del xyl, boxes, out_tri
     # hierarchical importance sampling: one sample per pixel footprint of the frame
     npix = nq // cfg.boxes_per_point
     s_uvl = q[::cfg.boxes_per_point, :3].contiguous()
