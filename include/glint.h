@@ -279,10 +279,12 @@ glint_status glint_sample(const glint_factors* f, int64_t n, const int32_t* uvl,
  * V, L, CS and CT (FP32, overwritten: the call clears them first).  f->dtype
  * and f->cum_dtype must be F32 or BF16.  dU [nu][R], dV [nv][R], dL [nl][R],
  * dCS, dCT [N+1][R].  Accumulation uses atomics, so the summation order (and
- * the last bits) vary between runs.  L, CS, CT and their gradient
- * accumulators are held in LDS: 8 (nl + 2 (N + 1)) R + 4 R bytes plus 16 KiB
- * of record slots must fit (e.g. rank 128 with N = 64 and 10 levels);
- * larger tables return GLINT_E_UNSUPPORTED. */
+ * the last bits) vary between runs.  L, CS and CT are staged in LDS as FP32:
+ * for N <= 64 (and nl <= 16) the summed-area-table and level gradients
+ * accumulate on the matrix cores, needing 4 (nl + 2 (N + 1)) R + 4 R bytes
+ * plus 32 KiB of record slots; for larger N their accumulators are held in
+ * LDS as well (8 (nl + 2 (N + 1)) R + 4 R bytes plus 16 KiB).  Tables beyond
+ * that return GLINT_E_UNSUPPORTED. */
 glint_status glint_query_backward(const glint_factors* f, int64_t nq, const int32_t* q,
                                   const float* gout, float* dU, float* dV, float* dL,
                                   float* dCS, float* dCT, hipStream_t stream);
