@@ -12,6 +12,8 @@ Modules
 ndf     per-texel bin masses of the intrinsic-roughness Gaussian (Sec. 3.1,
         Eq. geom), the brute-force NDF tensor over every texel position and
         footprint level (Sec. 4.1), and the brute-force range integral.
+cluster the paper's clustered layout (Sec. 4.2 practical choices): per
+        region-and-angular-block 3-way CP-ALS and the block-split range query.
 cp_als  plain CP decomposition by alternating least squares (Sec. 4.2,
         Eq. compress) and the texel-space MTTKRP identity used as a pin at
         sizes where the tensor cannot be formed.

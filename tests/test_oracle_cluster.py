@@ -1,0 +1,88 @@
+"""Pins of the clustered-layout oracle (Sec. 4.2 practical choices): the
+SplitMix64 generator against its published outputs, exact recovery of a
+tensor that is low-rank per region and block (with blank blocks), the
+block-split range query against explicit box sums of the reconstruction,
+and the accuracy gain over one global CP on the 64x64 workload."""
+import numpy as np
+
+import gen
+from oracle import cluster, cp_als, ndf, query
+
+
+def test_splitmix64_published_outputs():
+    # first outputs of SplitMix64 seeded with 0 (the reference implementation's test vector)
+    assert cluster.splitmix64_stream(0, 3) == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    u = cluster.uniform(0, np.arange(3))
+    assert np.allclose(u, [x / 2.0 ** 64 for x in (0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F)],
+                       rtol=0, atol=2.0 ** -53)
+
+
+def _blockwise_low_rank(rng, nu, nv, nl, N, t, cs, R, blank_every=3):
+    """A tensor that is exactly rank R in every (region, block), some blocks zero."""
+    T = np.zeros((nu, nv, nl, N, N))
+    ncu, ncv, nb, L, t = cluster.layout(nu, nv, nl, N, t, cs)
+    k = 0
+    for cu in range(ncu):
+        for cv in range(ncv):
+            for zs in range(nb):
+                for zt in range(nb):
+                    k += 1
+                    if k % blank_every == 0:
+                        continue
+                    X, Y, Z = rng.standard_normal((t, R)), rng.standard_normal((t, R)), rng.standard_normal((L, R))
+                    D = np.einsum("ar,br,fr->fab", X, Y, Z).reshape(cs, cs, nl, t, t)
+                    T[cu * cs:(cu + 1) * cs, cv * cs:(cv + 1) * cs, :, zs * t:(zs + 1) * t, zt * t:(zt + 1) * t] = D
+    return T
+
+
+def test_exact_recovery_per_region_and_block():
+    rng = np.random.default_rng(1)
+    nu, nv, nl, N, t, cs, R = 8, 8, 2, 8, 4, 4, 2
+    T = _blockwise_low_rank(rng, nu, nv, nl, N, t, cs, R)
+    X, Y, Z, blank, fails = cluster.clustered_cp(T, t, cs, R, iters=1000, seed=7)   # ALS swamps are slow
+    assert fails == 0
+    # blank exactly where the blocks are zero
+    for cu in range(2):
+        for cv in range(2):
+            for zs in range(2):
+                for zt in range(2):
+                    D = cluster.cluster_tensor(T, cu, cv, zs, zt, t, cs)
+                    assert blank[cu, cv, zs, zt] == (not np.any(D))
+    rec = cluster.reconstruct(X, Y, Z, nl, cs)
+    assert np.linalg.norm(rec - T) <= 1e-7 * np.linalg.norm(T)
+
+
+def test_block_split_query_equals_box_sums_of_the_reconstruction():
+    rng = np.random.default_rng(2)
+    nu, nv, nl, N, t, cs, R = 8, 4, 3, 16, 4, 4, 3
+    T = rng.random((nu, nv, nl, N, N))
+    X, Y, Z, blank, _ = cluster.clustered_cp(T, t, cs, R, iters=3, seed=3)
+    rec = cluster.reconstruct(X, Y, Z, nl, cs)
+    q = np.empty((500, 7), dtype=np.int64)
+    q[:, 0] = rng.integers(-8, 16, 500)
+    q[:, 1] = rng.integers(0, nv, 500)
+    q[:, 2] = rng.integers(-1, nl + 1, 500)
+    a = rng.integers(-2, N + 3, (500, 2))
+    b = rng.integers(0, N + 1, (500, 2))
+    q[:, 3], q[:, 4] = a.min(1), a.max(1)
+    q[:, 5], q[:, 6] = b.min(1), b.max(1)
+    got = cluster.clustered_range_query(X, Y, Z, q, nl, cs)
+    want = ndf.box_sum(rec, q)
+    assert np.max(np.abs(got - want)) <= 1e-12 * max(1.0, np.abs(want).max())
+
+
+def test_clustered_layout_is_far_more_accurate_than_one_global_cp():
+    """The 64x64 workload: rank 8 per region and block (3.4% of the tensor's
+    size) against brute-force range integrals, and the global rank-16 CP."""
+    cfg = gen.config("c1")
+    nxy = gen.normal_map(cfg)
+    T = ndf.ndf_bruteforce(nxy, cfg.nbins, cfg.sigma, cfg.nlevels)
+    q = gen.make_queries(cfg, nxy)
+    bf = ndf.box_sum(T, q)
+    X, Y, Z, blank, _ = cluster.clustered_cp(T, 16, 8, 8, iters=20, seed=11)
+    e_cl = np.linalg.norm(cluster.clustered_range_query(X, Y, Z, q, cfg.nlevels, 8) - bf) / np.linalg.norm(bf)
+    res = cp_als.cp_als(T, gen.als_init(cfg), iters=20)
+    F = res["factors"]
+    e_gl = np.linalg.norm(query.range_query(F[0], F[1], F[2], query.cumulative(F[3]), query.cumulative(F[4]), q)
+                          - bf) / np.linalg.norm(bf)
+    assert e_cl < 0.01 < 0.1 < e_gl
