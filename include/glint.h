@@ -206,6 +206,62 @@ glint_status glint_cp_als_texel(const glint_ndf_desc* desc, const float* nxy, in
                                 double* fit_hist, int32_t* info,
                                 void* workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* ---- clustered layout (Sec. 4.2, Eq. compress and its practical choices) --
+ * Each NDF image is cut into t x t angular blocks and footprints are grouped
+ * by the cs x cs texel region of their centre; the blocks of one region and
+ * one angular position form a 3-way tensor D[a][b][f] (a, b the bins inside
+ * the block, f = (du * cs + dv) * nlevels + l for the centre
+ * (cu * cs + du, cv * cs + dv)), fitted by its own rank-R CP.
+ * Tensor index = ((cu * ncv + cv) * nb + zs) * nb + zt with ncv = nv / cs,
+ * nb = nbins / t. */
+typedef struct {
+  int32_t t;    /* angular block side in bins (min(t, nbins) is used; must divide nbins; <= 16) */
+  int32_t cs;   /* region side in texels (divides nu and nv) */
+  int32_t R;    /* rank per region-and-block tensor: 4, 8, 16 or 32 */
+} glint_cluster_desc;
+
+/* CP-ALS of every region-and-block tensor of T (F64 or F32, the layout of
+ * glint_build_tensor), one workgroup per tensor, FP64 arithmetic.  Modes X
+ * (a), Y (b), Z (f) in that order, `iters` sweeps; normal equations with a
+ * ridge: A = M (G + mu I)^-1, mu = 1e-10 trace(G) / R, by Cholesky; a pivot
+ * <= 1e-13 times its diagonal entry keeps that mode's factor for the sweep
+ * (counted in info[0]).  Columns unit after each update; their weights end
+ * in Z.  Initial factors U[0,1) from SplitMix64 used as a counter-based
+ * generator: value = (mix(seed + (c + 1) * 0x9E3779B97F4A7C15) >> 11) 2^-53,
+ * c = ((tensor * 3 + mode) * max(t, L) + row) * R + r.  A tensor with
+ * sum |D| <= 1e-12 L is blank: zero factors, blank[tensor] = 1 (count in
+ * info[1]).  Outputs FP32: X, Y [ntensor][t][R], Z [ntensor][L][R] with
+ * L = cs * cs * nlevels; blank uint8 [ntensor]; info int32 [2].  The
+ * tensor's factors, Grams and partial products live in LDS for all sweeps:
+ * configurations that do not fit return GLINT_E_UNSUPPORTED (rank 16 fits
+ * with t = 16, cs = 8 and up to 8 levels from an F32 tensor). */
+glint_status glint_cp_als_clustered(const glint_ndf_desc* desc, const glint_cluster_desc* cd,
+                                    const void* T, glint_dtype T_dtype, int32_t iters,
+                                    uint64_t seed, float* X, float* Y, float* Z,
+                                    uint8_t* blank, int32_t* info, hipStream_t stream);
+
+/* C[b][j][r] = sum_{s<j} S[b][s][r] (FP64 accumulation, FP32 out) for
+ * nbatch stacked [n][R] tables; C is [nbatch][n+1][R]. */
+glint_status glint_make_cumulative_batched(int64_t nbatch, int32_t n, int32_t R, const float* S,
+                                           float* C, hipStream_t stream);
+
+/* Clustered query tables (FP32): summed-area tables of X and Y per tensor,
+ * CX, CY [ntensor][t+1][R], and Z [ntensor][L][R]; 16-byte aligned. */
+typedef struct {
+  int32_t t, cs, R;
+  int32_t nu, nv, nl, nbins;
+  const float* CX;
+  const float* CY;
+  const float* Z;
+} glint_clustered;
+
+/* Range query on the clustered tables: records as for glint_query (same
+ * wrap/clamp/empty rules); the box is split at block edges and the
+ * block-local queries sum_r Z[f][r] (CX[a1][r] - CX[a0][r]) (CY[b1][r] -
+ * CY[b0][r]) are added.  FP32 arithmetic. */
+glint_status glint_query_clustered(const glint_clustered* f, int64_t nq, const int32_t* q,
+                                   float* out, hipStream_t stream);
+
 /* ---- step 4: summed-area tables and storage types (Sec. 4.4) ------------ */
 
 /* C[j][r] = sum_{s<j} S[s][r] for j = 0..n, accumulated in FP64 and then

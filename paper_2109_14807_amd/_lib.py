@@ -55,6 +55,17 @@ class Factors(ctypes.Structure):
                 ("scale_CT", ctypes.c_void_p)]
 
 
+class ClusterDesc(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_int32), ("cs", ctypes.c_int32), ("R", ctypes.c_int32)]
+
+
+class Clustered(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_int32), ("cs", ctypes.c_int32), ("R", ctypes.c_int32),
+                ("nu", ctypes.c_int32), ("nv", ctypes.c_int32), ("nl", ctypes.c_int32),
+                ("nbins", ctypes.c_int32), ("CX", ctypes.c_void_p), ("CY", ctypes.c_void_p),
+                ("Z", ctypes.c_void_p)]
+
+
 _LIB = None
 
 _P = ctypes.c_void_p
@@ -65,6 +76,9 @@ _F64 = ctypes.c_double
 _SZ = ctypes.c_size_t
 _DESC = ctypes.POINTER(NdfDesc)
 _FAC = ctypes.POINTER(Factors)
+_CDESC = ctypes.POINTER(ClusterDesc)
+_CLU = ctypes.POINTER(Clustered)
+_U64 = ctypes.c_uint64
 
 _SIGS = {
     "glint_status_string": (ctypes.c_char_p, [_I32]),
@@ -92,6 +106,9 @@ _SIGS = {
     "glint_cumulative_backward": (_I32, [_I32, _I32, _P, _P, _P]),
     "glint_mse_grad": (_I32, [_I64, _P, _P, _P, _P, _P]),
     "glint_adam_step": (_I32, [_I64, _P, _P, _P, _P, _F32, _F32, _F32, _F32, _I32, _P]),
+    "glint_cp_als_clustered": (_I32, [_DESC, _CDESC, _P, _I32, _I32, _U64, _P, _P, _P, _P, _P, _P]),
+    "glint_make_cumulative_batched": (_I32, [_I64, _I32, _I32, _P, _P, _P]),
+    "glint_query_clustered": (_I32, [_CLU, _I64, _P, _P, _P]),
 }
 
 
@@ -335,3 +352,25 @@ def glint_adam_step(p, g, m, v, lr, b1, b2, eps, step, stream=None):
     _check("glint_adam_step", lib().glint_adam_step(
         p.numel(), _ptr(p, f32, "p"), _ptr(g, f32, "g"), _ptr(m, f32, "m"), _ptr(v, f32, "v"),
         float(lr), float(b1), float(b2), float(eps), int(step), _stream(stream)))
+
+
+def glint_cp_als_clustered(desc, cd: ClusterDesc, T, iters, seed, X, Y, Z, blank, info, stream=None):
+    f32 = torch.float32
+    _check("glint_cp_als_clustered", lib().glint_cp_als_clustered(
+        ctypes.byref(desc), ctypes.byref(cd), _ptr(T, None, "T"), _gdtype(T), int(iters),
+        int(seed) & ((1 << 64) - 1), _ptr(X, f32, "X"), _ptr(Y, f32, "Y"), _ptr(Z, f32, "Z"),
+        _ptr(blank, torch.uint8, "blank"), _ptr(info, torch.int32, "info"), _stream(stream)))
+
+
+def glint_make_cumulative_batched(S, C, stream=None):
+    nb, n, R = S.shape
+    if tuple(C.shape) != (nb, n + 1, R):
+        raise ValueError("C must have shape (nbatch, n+1, R)")
+    _check("glint_make_cumulative_batched", lib().glint_make_cumulative_batched(
+        nb, n, R, _ptr(S, torch.float32, "S"), _ptr(C, torch.float32, "C"), _stream(stream)))
+
+
+def glint_query_clustered(f: Clustered, q, out, stream=None):
+    _check("glint_query_clustered", lib().glint_query_clustered(
+        ctypes.byref(f), q.shape[0], _ptr(q, torch.int32, "q"), _ptr(out, torch.float32, "out"),
+        _stream(stream)))

@@ -236,3 +236,75 @@ def cumulative_backward(dC):
     dS = torch.empty((dC.shape[0] - 1, dC.shape[1]), dtype=torch.float32, device=_DEV)
     L.glint_cumulative_backward(dC.contiguous(), dS)
     return dS
+
+
+@dataclasses.dataclass
+class ClusteredTables:
+    """Per-(region, block) CP factors of the clustered layout (Sec. 4.2) and
+    their block-local summed-area tables, FP32 on the device.  X, Y
+    [ntensor][t][R], Z [ntensor][L][R] (weights absorbed), CX, CY
+    [ntensor][t+1][R]; tensor = ((cu * ncv + cv) * nb + zs) * nb + zt."""
+    desc: NdfDesc
+    t: int
+    cs: int
+    X: torch.Tensor
+    Y: torch.Tensor
+    Z: torch.Tensor
+    blank: torch.Tensor
+    info: torch.Tensor
+    CX: torch.Tensor = None
+    CY: torch.Tensor = None
+
+    @property
+    def R(self):
+        return self.X.shape[-1]
+
+    def shape(self):
+        d = self.desc
+        return d.nu // self.cs, d.nv // self.cs, d.nbins // self.t
+
+    def struct(self) -> L.Clustered:
+        d = self.desc
+        return L.Clustered(self.t, self.cs, self.R, d.nu, d.nv, d.nlevels, d.nbins,
+                           L._ptr(self.CX, torch.float32, "CX"), L._ptr(self.CY, torch.float32, "CY"),
+                           L._ptr(self.Z, torch.float32, "Z"))
+
+
+def cp_als_clustered(T: torch.Tensor, desc: NdfDesc, t: int, cs: int, R: int, iters: int,
+                     seed: int = 0) -> ClusteredTables:
+    """Clustered-layout CP of the built tensor T (F64 or F32) and its query
+    tables.  `t` is the angular block side (min(t, nbins) is used), `cs`
+    the region side in texels."""
+    t = min(int(t), desc.nbins)
+    ncu, ncv, nb = desc.nu // cs, desc.nv // cs, desc.nbins // t
+    ntensor = ncu * ncv * nb * nb
+    Lr = cs * cs * desc.nlevels
+    f32 = dict(dtype=torch.float32, device=_DEV)
+    X = torch.empty((ntensor, t, R), **f32)
+    Y = torch.empty((ntensor, t, R), **f32)
+    Z = torch.empty((ntensor, Lr, R), **f32)
+    blank = torch.empty(ntensor, dtype=torch.uint8, device=_DEV)
+    info = torch.empty(2, dtype=torch.int32, device=_DEV)
+    L.glint_cp_als_clustered(desc, L.ClusterDesc(t, int(cs), int(R)), T.contiguous(), iters, seed,
+                             X, Y, Z, blank, info)
+    tab = ClusteredTables(desc, t, int(cs), X, Y, Z, blank, info)
+    clustered_cumulative(tab)
+    return tab
+
+
+def clustered_cumulative(tab: ClusteredTables):
+    """(Re)build the block-local summed-area tables CX, CY of `tab`."""
+    n, t, R = tab.X.shape
+    if tab.CX is None:
+        tab.CX = torch.empty((n, t + 1, R), dtype=torch.float32, device=_DEV)
+        tab.CY = torch.empty((n, t + 1, R), dtype=torch.float32, device=_DEV)
+    L.glint_make_cumulative_batched(tab.X, tab.CX)
+    L.glint_make_cumulative_batched(tab.Y, tab.CY)
+    return tab
+
+
+def query_clustered(tab: ClusteredTables, q, out=None):
+    q = _dev(q, torch.int32)
+    out = torch.empty(q.shape[0], dtype=torch.float32, device=_DEV) if out is None else out
+    L.glint_query_clustered(tab.struct(), q, out)
+    return out
