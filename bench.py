@@ -36,34 +36,30 @@ FP64_MFMA_PEAK_TFLOPS = 78.6
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE on this workload,
 # scaled by the counters' reading for a plain 2 GiB copy (fetch x2.0, write x1.0);
-# see profiles/<kernel>_c2_hbm_traffic.md.  Valid only for the kernel source they
-# were taken with (sha1); otherwise traffic is reported as null.
+# see profiles/<kernel>_c2_hbm_traffic.md.  Valid only for the source file they
+# were taken with (sha1 of the whole file: a kernel's instantiation depends on
+# helpers and constants outside its own text); otherwise traffic is null.
 MEASURED_TRAFFIC = {
-    "k_mttkrp_y": ("paper_2109_14807_amd/csrc/cp_als.hip", "8f0b96faef3d3d8b25d17ae8ac059a47a899a204", 36579418647),
-    "k_mttkrp_z": ("paper_2109_14807_amd/csrc/cp_als.hip", "6c0880d3ad452058f93ed40f598a5a613a43b374", 34936220934),
-    "k_query": ("paper_2109_14807_amd/csrc/query.hip", "32ebcc8307719c734e263434761ea01a29ff291d", 534671702),
+    "k_mttkrp_y": ("paper_2109_14807_amd/csrc/cp_als.hip", "8f1fc0087c76e7f0be86b1f48cccf40f66e4460d", 36577501445),
+    "k_mttkrp_z": ("paper_2109_14807_amd/csrc/cp_als.hip", "8f1fc0087c76e7f0be86b1f48cccf40f66e4460d", 34933054870),
+    "k_query": ("paper_2109_14807_amd/csrc/query.hip", "329868931d8db1d0a22457ac570937bdc5d560ec", 535667416),
 }
 
 
-def kernel_source_sha(path, name):
-    """SHA-1 of a kernel's definition text: from the template line before
-    `void <name>(` to the first line that closes it at column 0."""
+def source_sha(path):
+    """SHA-1 of a source file's text."""
     import hashlib
-    with open(os.path.join(ROOT, path)) as f:
-        lines = f.read().split("\n")
-    at = next(i for i, l in enumerate(lines) if f"void {name}(" in l)
-    start = at - 1 if at > 0 and lines[at - 1].startswith("template") else at
-    end = next(i for i in range(at, len(lines)) if lines[i] == "}")
-    return hashlib.sha1("\n".join(lines[start:end + 1]).encode()).hexdigest()
+    with open(os.path.join(ROOT, path), "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()
 
 
 def measured_traffic(kernel):
     """HBM bytes per launch from the committed counter runs, or None once the
-    kernel's source has changed since they were taken."""
+    kernel's source file has changed since they were taken."""
     src, sha, nbytes = MEASURED_TRAFFIC[kernel]
     try:
-        cur = kernel_source_sha(src, kernel)
-    except (OSError, StopIteration):
+        cur = source_sha(src)
+    except OSError:
         return None
     return nbytes if cur == sha and nbytes > 0 else None
 
@@ -79,6 +75,8 @@ def parse():
                     help="events-timed launches of the MTTKRP and query kernels")
     ap.add_argument("--refine-steps", type=int, default=100,
                     help="Adam steps of the BF16 refinement report (0 to skip)")
+    ap.add_argument("--cluster-sweeps", type=int, default=20,
+                    help="ALS sweeps of the clustered layout's report (0 skips it)")
     ap.add_argument("--configs", default="",
                     help="comma-separated extra workloads (c1, c3, c4, c5) run end to end on their own "
                          "ALS factors after the step, reported under 'configs'")
@@ -345,6 +343,9 @@ def main():
     log(f"texel-space ALS: {tex_ms:.1f} ms vs dense {als_ms:.1f} ms; fit {res['als_texel']['fit']:.6f} "
         f"vs {fit_last:.6f}")
     del ws_tex
+    if args.cluster_sweeps > 0:
+        res["clustered"] = clustered_report(desc, T, q, q_bf, args.cluster_sweeps, timed)
+        log(f"clustered layout: {res['clustered']}")
     if args.refine_steps > 0:
         res["refinement"] = refine_report(cfg, nxy_h, desc, F, q, q_bf, args.refine_steps, timed)
         log(f"refinement report done: {res['refinement']}")
@@ -414,6 +415,42 @@ def refine_report(cfg, nxy_h, desc, F, q, q_bf, steps, timed):
         "query_ms_plain_f32": ms_plain, "query_ms_refined_bf16": ms_bf16,
         "speedup_bf16_over_f32": ms_plain / ms_bf16,
         "equal_or_lower_error": bool(e_bf16 <= e_plain),
+    }
+
+
+def clustered_report(desc, T, q, q_bf, sweeps, timed, t=16, cs=8, R=16):
+    """The clustered layout of the same tensor (Sec. 4.2 practical choices):
+    16 x 16 angular blocks, 8 x 8 texel regions, rank 16 per region and block,
+    FP64 ALS per block tensor; its batch query time and error against the
+    brute-force range integrals."""
+    import torch
+
+    import paper_2109_14807_amd as G
+    from paper_2109_14807_amd import _lib as L
+
+    G.cp_als_clustered(T, desc, t, cs, R, iters=1)          # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    e0.record(stream)
+    tab = G.cp_als_clustered(T, desc, t, cs, R, iters=sweeps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    als_ms = e0.elapsed_time(e1)
+    out = torch.empty(q.shape[0], dtype=torch.float32, device=q.device)
+    st = tab.struct()
+    query_ms = timed(lambda: L.glint_query_clustered(st, q, out))
+    ebf = float((torch.linalg.vector_norm(out.double() - q_bf) / torch.linalg.vector_norm(q_bf)).item())
+    info = tab.info.cpu().tolist()
+    ntensor = tab.X.shape[0]
+    return {
+        "what": f"per-(region, angular block) rank-{R} CP: {t}x{t} bin blocks, {cs}x{cs} texel regions, "
+                f"{sweeps} FP64 ALS sweeps per block tensor (blank blocks skipped), FP32 tables",
+        "block_tensors": ntensor, "blank": info[1], "solve_failures": info[0],
+        "als_ms_incl_tables": als_ms, "als_ms_per_sweep": als_ms / sweeps,
+        "query_ms": query_ms, "queries_per_s": q.shape[0] / (query_ms * 1e-3),
+        "error_vs_bruteforce": ebf,
+        "table_bytes": int(4 * (tab.CX.numel() + tab.CY.numel() + tab.Z.numel())),
     }
 
 
