@@ -6,24 +6,47 @@
 // range query (Sec. 4.4) splits a box at block edges and adds the
 // block-local queries.
 //
-// CP-ALS kernel: one 256-thread workgroup per (region, block) tensor runs
-// every sweep with its factors, Grams and the (a,b)-by-rank product
-// P = D x_f Z resident in LDS in FP64; D is streamed from the tensor T each
-// sweep (two passes: P for the X and Y updates, then D against the
-// Khatri-Rao product of X and Y for Z).
+// CP-ALS: a pre-pass flags the blank block tensors; then one 512-thread
+// workgroup per block tensor runs every sweep with its factors, Grams and
+// the (a,b)-by-rank product P = D x_f Z resident in LDS in FP64.  D is
+// streamed from the tensor T twice per sweep, and both streams are dense
+// contractions on the matrix cores (v_mfma_f64_16x16x4f64):
+//   pass A  P[ab][r] = sum_f D[ab][f] Z[f][r]          (for the X and Y updates)
+//   pass B  Z[f][r]  = sum_ab D[ab][f] X[a][r] Y[b][r]  (the Z update)
+// Pass A reads D straight from HBM (16 consecutive bins of one footprint per
+// lane group, double-buffered); pass B stages D through a padded LDS tile so
+// that each wave owns 16 footprints of the output.  The Grams are MFMA
+// products too, and the column norms come from their diagonals.
 #include <cstdint>
 
 #include "common.h"
 
 namespace {
 
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
 constexpr double kBlankRtol = 1e-12;    // blank block: sum |D| <= kBlankRtol * L
 constexpr double kPivotRtol = 1e-13;    // Cholesky breakdown
 constexpr double kRidgeRtol = 1e-10;    // normal equations use G + mu I, mu = kRidgeRtol * trace(G) / R
-constexpr int kClThreads = 256;
-// footprints per staged chunk of the Z pass (64 bytes per angular bin)
+constexpr int kClThreads = 512;
+constexpr int kClWaves = kClThreads / 64;
+constexpr int kBlankThreads = 256;
+constexpr int kFR = 16 * kClWaves;      // footprints per pass-B range: 16 per wave
+constexpr int kUK = 8;                  // pass-A MFMA steps (4 footprints each) per prefetched batch
+
+// pass-B stage: kFR footprints x AB bins of T, rows padded so that the 16
+// footprints x 4 bins an MFMA operand read touches fall in distinct banks
 template <typename TT>
-constexpr int stage_footprints() { return 64 / static_cast<int>(sizeof(TT)); }
+constexpr int stage_ab() { return sizeof(TT) == 4 ? 64 : 32; }
+template <typename TT>
+constexpr int stage_stride() { return stage_ab<TT>() + (sizeof(TT) == 4 ? 4 : 2); }   // 272 bytes
+constexpr int kGramPart = 2048;         // doubles of per-wave Gram partials (reuse the stage)
+
+// v_mfma_f64_16x16x4f64: A[i][k] from lane i + 16k, B[k][j] from lane j + 16k;
+// D[i][j] in lane j + 16 (i % 4), item i / 4.
+__device__ __forceinline__ f64x4 mfma64(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
 
 // SplitMix64 (Steele, Lea and Flood) as a counter-based generator: the
 // (counter+1)-th output of the generator seeded with `seed`, as U[0, 1).
@@ -48,12 +71,13 @@ struct ClusterArgs {
   int* info;
 };
 
-// Offsets of the LDS arrays (doubles) of the ALS kernel.
+// Offsets of the LDS arrays (in doubles) of the ALS kernel.  Z rows are
+// padded to R + 1 doubles (the per-row solves then spread over the banks).
 struct ClusterLds {
-  int x, y, z, p, gx, gy, gz, gm, lam, red, mtmp, stage, total_doubles;
+  int x, y, mt, z, p, gx, gy, gz, gm, lam, dg, dl, foff, stage, total_doubles;
 };
 
-__host__ __device__ inline ClusterLds cluster_lds(int t, int L, int R, int stage_elt_bytes) {
+__host__ __device__ inline ClusterLds cluster_lds(int t, int L, int R, int stage_doubles) {
   ClusterLds o;
   int at = 0;
   auto take = [&](int n) {
@@ -63,62 +87,100 @@ __host__ __device__ inline ClusterLds cluster_lds(int t, int L, int R, int stage
   };
   o.x = take(t * R);
   o.y = take(t * R);
-  o.z = take(L * R);
+  o.mt = take(t * R);
+  o.z = take(L * (R + 1));
   o.p = take(t * t * R);
   o.gx = take(R * R);
   o.gy = take(R * R);
   o.gz = take(R * R);
   o.gm = take(R * R);
   o.lam = take(R);
-  o.red = take(kClThreads);
-  o.mtmp = take(t * R);
-  o.stage = take((64 / stage_elt_bytes * t * t * stage_elt_bytes + 7) / 8);
+  o.dg = take(R);
+  o.dl = take(R);
+  o.foff = take(L);            // int64 footprint offsets
+  o.stage = take(stage_doubles > kGramPart ? stage_doubles : kGramPart);
   o.total_doubles = at;
   return o;
 }
 
 template <typename TT>
-struct TensorView {
-  const TT* T;
-  int64_t cell0;       // cell index of footprint f = 0
-  int nv, nl, cs, N;
-  __device__ int64_t ab_off(int a, int b, int zs, int zt, int t) const {
-    return static_cast<int64_t>(zs * t + a) * N + zt * t + b;
-  }
-  // element (a, b) of footprint f, at offset ab (from ab_off)
-  __device__ __forceinline__ double at(int64_t ab, int f) const {
-    const int du = f / (cs * nl), dv = (f / nl) % cs, l = f % nl;
-    const int64_t cell = cell0 + (static_cast<int64_t>(du) * nv + dv) * nl + l;
-    return static_cast<double>(T[cell * N * N + ab]);
-  }
+__host__ __device__ constexpr int stage_doubles() {
+  return (kFR * stage_stride<TT>() * static_cast<int>(sizeof(TT)) + 7) / 8;
+}
+
+// Position of one block tensor inside T.
+struct BlockPos {
+  int64_t base;   // element offset of footprint f = 0, bin (zs t, zt t)
+  int zs, zt;
 };
 
-// A = M (G + mu I)^-1 row by row for `rows` rows held in LDS (in place),
-// with Gm holding the Cholesky factor (lower, row-major, R x R).
-template <int R>
-__device__ void solve_rows(double* Mrows, int rows, const double* Lc) {
-  for (int row = threadIdx.x; row < rows; row += blockDim.x) {
-    double* m = Mrows + row * R;
-    double y[R];
+__device__ __forceinline__ BlockPos block_pos(const ClusterArgs& c, int tensor) {
+  BlockPos b;
+  b.zt = tensor % c.nb;
+  b.zs = (tensor / c.nb) % c.nb;
+  const int cv = (tensor / (c.nb * c.nb)) % c.ncv, cu = tensor / (c.nb * c.nb * c.ncv);
+  const int64_t cell0 = (static_cast<int64_t>(cu) * c.cs * c.nv + static_cast<int64_t>(cv) * c.cs) * c.nl;
+  b.base = cell0 * c.N * c.N + static_cast<int64_t>(b.zs) * c.t * c.N + static_cast<int64_t>(b.zt) * c.t;
+  return b;
+}
+
+// element offset of footprint f relative to footprint 0
+__device__ __forceinline__ int64_t footprint_offset(const ClusterArgs& c, int f) {
+  const int du = f / (c.cs * c.nl), dv = (f / c.nl) % c.cs, l = f % c.nl;
+  return ((static_cast<int64_t>(du) * c.nv + dv) * c.nl + l) * c.N * c.N;
+}
+
+// element offset of bin ab = a t + b inside the block
+__device__ __forceinline__ int64_t bin_offset(const ClusterArgs& c, int ab) {
+  return static_cast<int64_t>(ab / c.t) * c.N + ab % c.t;
+}
+
+// Blank flags: sum |D| <= kBlankRtol * L.  One 256-thread workgroup per
+// block tensor; each thread owns one bin and streams the footprints.
+template <typename TT>
+__global__ __launch_bounds__(kBlankThreads) void k_cluster_blank(ClusterArgs c) {
+  extern __shared__ __align__(16) double bl_lds[];
+  int64_t* foff = reinterpret_cast<int64_t*>(bl_lds);
+  __shared__ double red[kBlankThreads];
+  const int tensor = blockIdx.x;
+  const BlockPos bp = block_pos(c, tensor);
+  const int tt = c.t * c.t, L = c.L;
+  for (int f = threadIdx.x; f < L; f += blockDim.x) foff[f] = footprint_offset(c, f);
+  __syncthreads();
+  const TT* Tb = static_cast<const TT*>(c.T) + bp.base;
+  double s = 0.0;
+  const int ab = threadIdx.x;
+  if (ab < tt) {
+    const int64_t bo = bin_offset(c, ab);
+    for (int f0 = 0; f0 < L; f0 += 8) {
+      TT v[8];
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
-      double s = m[k];
-      for (int i = 0; i < k; ++i) s -= Lc[k * R + i] * y[i];
-      y[k] = s / Lc[k * R + k];
-    }
+      for (int u = 0; u < 8; ++u) v[u] = f0 + u < L ? Tb[foff[f0 + u] + bo] : TT(0);
 #pragma unroll
-    for (int k = R - 1; k >= 0; --k) {
-      double s = y[k];
-      for (int i = k + 1; i < R; ++i) s -= Lc[i * R + k] * m[i];
-      m[k] = s / Lc[k * R + k];
+      for (int u = 0; u < 8; ++u) s += fabs(static_cast<double>(v[u]));
     }
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kBlankThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const bool blank = !(red[0] > kBlankRtol * L);
+    c.blank[tensor] = blank ? 1 : 0;
+    if (blank) atomicAdd(&c.info[1], 1);
   }
 }
 
-// Gm = G1 o G2 + mu I factored in place (lower Cholesky); returns false on
-// breakdown (the same for every thread).
+// Gm = G1 o G2 + mu I, mu = kRidgeRtol * trace(G1 o G2) / R, factored in
+// place as L L^T (lower, row-major), right-looking: at step j the pivot is
+// the updated diagonal entry, column j is scaled by its square root and the
+// trailing lower triangle takes the rank-1 update, all entries in parallel.
+// A pivot <= kPivotRtol times the diagonal entry of the unfactored matrix
+// (kept in dg) is a breakdown: returns false (the same for every thread).
 template <int R>
-__device__ bool cholesky_hadamard(const double* G1, const double* G2, double* Gm, double* red) {
+__device__ bool cholesky_hadamard(const double* G1, const double* G2, double* Gm, double* dg, double* dl) {
   for (int i = threadIdx.x; i < R * R; i += blockDim.x) Gm[i] = G1[i] * G2[i];
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -128,67 +190,154 @@ __device__ bool cholesky_hadamard(const double* G1, const double* G2, double* Gm
     for (int k = 0; k < R; ++k) Gm[k * R + k] += mu;
   }
   __syncthreads();
-  // diagonal entries of G + mu I for the breakdown rule
-  if (threadIdx.x < R) red[threadIdx.x] = Gm[threadIdx.x * R + threadIdx.x];
+  if (threadIdx.x < R) dg[threadIdx.x] = Gm[threadIdx.x * R + threadIdx.x];
   __syncthreads();
-  bool ok = true;
   for (int j = 0; j < R; ++j) {
-    // pivot (every thread computes it from the same LDS values)
-    double d = Gm[j * R + j];
-    for (int k = 0; k < j; ++k) d -= Gm[j * R + k] * Gm[j * R + k];
-    if (!(d > kPivotRtol * red[j])) {
-      ok = false;
-      break;
-    }
+    const double d = Gm[j * R + j];
+    if (!(d > kPivotRtol * dg[j])) return false;
     const double ljj = sqrt(d);
+    if (threadIdx.x == 0) dl[j] = ljj;
+    for (int i = j + 1 + static_cast<int>(threadIdx.x); i < R; i += blockDim.x) Gm[i * R + j] /= ljj;
     __syncthreads();
-    if (threadIdx.x == 0) Gm[j * R + j] = ljj;
-    for (int i = j + 1 + static_cast<int>(threadIdx.x); i < R; i += blockDim.x) {
-      double s = Gm[i * R + j];
-      for (int k = 0; k < j; ++k) s -= Gm[i * R + k] * Gm[j * R + k];
-      Gm[i * R + j] = s / ljj;
+    for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) {
+      const int i = idx / R, k = idx % R;
+      if (k > j && k <= i) Gm[idx] -= Gm[i * R + j] * Gm[k * R + j];
     }
     __syncthreads();
   }
+  if (threadIdx.x < R) Gm[threadIdx.x * R + threadIdx.x] = dl[threadIdx.x];
   __syncthreads();
-  return ok;
+  return true;
 }
 
-// G = F^T F for F [rows][R] in LDS.
+// A = M (L L^T)^-1 for `rows` rows of stride ld held in LDS, in place: one
+// row per thread, forward substitution L y = m then back substitution
+// L^T x = y in registers.  The empty asm statements are compiler-only
+// barriers that keep each step's reads of the factor at that step (hoisted,
+// the R x R factor would occupy R*R registers).
+// Rank 32: R lanes share a row, lane j holding component j, the solved
+// component of each step broadcast from its lane (one register per lane
+// instead of R).
 template <int R>
-__device__ void gram_lds(const double* F, int rows, double* G) {
+__device__ void solve_rows_lanes(double* Mrows, int rows, int ld, const double* Lc) {
+  static_assert(64 % R == 0, "rank must divide the wavefront");
+  constexpr int RPW = 64 / R;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int j = lane % R, base = lane - j;
+  for (int row0 = wave * RPW; row0 < rows; row0 += nw * RPW) {
+    const int row = row0 + lane / R;
+    const bool ok = row < rows;
+    double s = ok ? Mrows[row * ld + j] : 0.0;
+    for (int k = 0; k < R; ++k) {
+      const double yk = __shfl(s / Lc[k * R + k], base + k);
+      if (j > k) s -= Lc[j * R + k] * yk;
+      else if (j == k) s = yk;
+    }
+    for (int k = R - 1; k >= 0; --k) {
+      const double xk = __shfl(s / Lc[k * R + k], base + k);
+      if (j < k) s -= Lc[k * R + j] * xk;
+      else if (j == k) s = xk;
+    }
+    if (ok) Mrows[row * ld + j] = s;
+  }
+}
+
+template <int R>
+__device__ void solve_rows(double* Mrows, int rows, int ld, const double* Lc) {
+  if constexpr (R > 16) {
+    solve_rows_lanes<R>(Mrows, rows, ld, Lc);
+    return;
+  }
+  for (int row = threadIdx.x; row < rows; row += blockDim.x) {
+    double* m = Mrows + row * ld;
+    double y[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) y[k] = m[k];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      asm volatile("" ::: "memory");
+      double s = y[k];
+#pragma unroll
+      for (int i = 0; i < k; ++i) s -= Lc[k * R + i] * y[i];
+      y[k] = s / Lc[k * R + k];
+    }
+#pragma unroll
+    for (int k = R - 1; k >= 0; --k) {
+      asm volatile("" ::: "memory");
+      double s = y[k];
+#pragma unroll
+      for (int i = k + 1; i < R; ++i) s -= Lc[i * R + k] * y[i];
+      y[k] = s / Lc[k * R + k];
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) m[k] = y[k];
+  }
+}
+
+// G = F^T F for F [rows][R] (row stride ld) in LDS on the matrix cores: the
+// R x R result in 16 x 16 tiles, the rows split over the waves, the waves'
+// partial tiles summed through `part` (kGramPart doubles).
+template <int R>
+__device__ void gram_mfma(const double* F, int rows, int ld, double* G, double* part) {
+  constexpr int RB = (R + 15) / 16, TILES = RB * RB, KG = kClWaves / TILES;
+  static_assert(KG * TILES * 256 <= kGramPart, "Gram partials exceed their scratch");
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int tile = wave % TILES, kg = wave / TILES;
+  if (kg < KG) {
+    const int ci = (tile / RB) * 16 + li, cj = (tile % RB) * 16 + li;
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    const int nsteps = (rows + 3) / 4;
+    for (int s = kg; s < nsteps; s += KG) {
+      const int row = s * 4 + lk;
+      const double a = (row < rows && ci < R) ? F[row * ld + ci] : 0.0;
+      const double b = (row < rows && cj < R) ? F[row * ld + cj] : 0.0;
+      acc = mfma64(a, b, acc);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) part[(kg * TILES + tile) * 256 + (lk + 4 * q) * 16 + li] = acc[q];
+  }
+  __syncthreads();
   for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) {
-    const int i = idx / R, j = idx % R;
+    const int r = idx / R, q = idx % R;
+    const int tl = (r / 16) * RB + q / 16;
     double s = 0.0;
-    for (int row = 0; row < rows; ++row) s += F[row * R + i] * F[row * R + j];
+    for (int g = 0; g < KG; ++g) s += part[(g * TILES + tl) * 256 + (r % 16) * 16 + q % 16];
     G[idx] = s;
   }
   __syncthreads();
 }
 
-// unit columns; lam[r] = column norm (zero columns stay zero)
+// Columns of F to unit length (zero columns stay zero), lam[r] = the norms,
+// and G (= F^T F on entry) to the Gram of the normalised F.
 template <int R>
-__device__ void normalize_cols(double* F, int rows, double* lam) {
-  if (threadIdx.x < R) {
-    double s = 0.0;
-    for (int row = 0; row < rows; ++row) s += F[row * R + threadIdx.x] * F[row * R + threadIdx.x];
-    lam[threadIdx.x] = sqrt(s);
-  }
+__device__ void normalize_by_gram(double* F, int rows, int ld, double* G, double* lam) {
+  if (threadIdx.x < R) lam[threadIdx.x] = sqrt(G[threadIdx.x * R + threadIdx.x]);
   __syncthreads();
   for (int idx = threadIdx.x; idx < rows * R; idx += blockDim.x) {
-    const double n = lam[idx % R];
-    if (n > 0.0) F[idx] /= n;
+    const int row = idx / R, r = idx % R;
+    const double n = lam[r];
+    if (n > 0.0) F[row * ld + r] /= n;
+  }
+  for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) {
+    const double nr = lam[idx / R], nq = lam[idx % R];
+    if (nr > 0.0 && nq > 0.0) G[idx] = G[idx] / nr / nq;
   }
   __syncthreads();
 }
 
 template <typename TT, int R>
 __global__ __launch_bounds__(kClThreads) void k_cluster_als(ClusterArgs c) {
+  constexpr int RB = (R + 15) / 16;
+  constexpr int ABC = stage_ab<TT>(), SS = stage_stride<TT>();
+  constexpr int PER = kFR * ABC / kClThreads;     // staged elements per thread per chunk
+  static_assert(kClThreads % ABC == 0, "stage rows must map to fixed lanes");
   extern __shared__ __align__(16) double cl_lds[];
-  const int t = c.t, L = c.L, tt = t * t;
-  const ClusterLds o = cluster_lds(t, L, R, sizeof(TT));
+  const int t = c.t, L = c.L, tt = t * t, ZS = R + 1;
+  const ClusterLds o = cluster_lds(t, L, R, stage_doubles<TT>());
   double* X = cl_lds + o.x;
   double* Y = cl_lds + o.y;
+  double* Mt = cl_lds + o.mt;
   double* Z = cl_lds + o.z;
   double* P = cl_lds + o.p;
   double* GX = cl_lds + o.gx;
@@ -196,49 +345,31 @@ __global__ __launch_bounds__(kClThreads) void k_cluster_als(ClusterArgs c) {
   double* GZ = cl_lds + o.gz;
   double* Gm = cl_lds + o.gm;
   double* lam = cl_lds + o.lam;
-  double* red = cl_lds + o.red;
-  double* Mt = cl_lds + o.mtmp;
+  double* dg = cl_lds + o.dg;
+  double* dl = cl_lds + o.dl;
+  int64_t* foff = reinterpret_cast<int64_t*>(cl_lds + o.foff);
   TT* stage = reinterpret_cast<TT*>(cl_lds + o.stage);
+  double* part = cl_lds + o.stage;
 
   const int tensor = blockIdx.x;
-  const int zt = tensor % c.nb, zs = (tensor / c.nb) % c.nb;
-  const int cv = (tensor / (c.nb * c.nb)) % c.ncv, cu = tensor / (c.nb * c.nb * c.ncv);
-  TensorView<TT> D;
-  D.T = static_cast<const TT*>(c.T);
-  D.cell0 = (static_cast<int64_t>(cu * c.cs) * c.nv + cv * c.cs) * c.nl;
-  D.nv = c.nv; D.nl = c.nl; D.cs = c.cs; D.N = c.N;
-  const int my_ab = threadIdx.x;
-  const bool ab_active = my_ab < tt;
-  const int64_t ab_off = ab_active ? D.ab_off(my_ab / t, my_ab % t, zs, zt, t) : 0;
-
-  // blank check: sum |D|
-  {
-    double s = 0.0;
-    if (ab_active)
-      for (int f = 0; f < L; ++f) s += fabs(D.at(ab_off, f));
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = kClThreads / 2; w > 0; w >>= 1) {
-      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-      __syncthreads();
+  float* outX = c.X + static_cast<int64_t>(tensor) * t * R;
+  float* outY = c.Y + static_cast<int64_t>(tensor) * t * R;
+  float* outZ = c.Z + static_cast<int64_t>(tensor) * L * R;
+  if (c.blank[tensor]) {
+    for (int i = threadIdx.x; i < t * R; i += blockDim.x) {
+      outX[i] = 0.0f;
+      outY[i] = 0.0f;
     }
-    const bool blank = !(red[0] > kBlankRtol * L);
-    __syncthreads();
-    if (blank) {
-      for (int i = threadIdx.x; i < t * R; i += blockDim.x) {
-        c.X[static_cast<int64_t>(tensor) * t * R + i] = 0.0f;
-        c.Y[static_cast<int64_t>(tensor) * t * R + i] = 0.0f;
-      }
-      for (int i = threadIdx.x; i < L * R; i += blockDim.x) c.Z[static_cast<int64_t>(tensor) * L * R + i] = 0.0f;
-      if (threadIdx.x == 0) {
-        c.blank[tensor] = 1;
-        atomicAdd(&c.info[1], 1);
-      }
-      return;
-    }
+    for (int i = threadIdx.x; i < L * R; i += blockDim.x) outZ[i] = 0.0f;
+    return;
   }
+  const BlockPos bp = block_pos(c, tensor);
+  const TT* Tb = static_cast<const TT*>(c.T) + bp.base;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
 
-  // initial factors (SplitMix64 counters) and Grams; lambda = 1
+  // footprint offsets, initial factors (SplitMix64 counters), lambda = 1
+  for (int f = threadIdx.x; f < L; f += blockDim.x) foff[f] = footprint_offset(c, f);
   const uint64_t rows_max = t > L ? t : L;
   for (int i = threadIdx.x; i < t * R; i += blockDim.x) {
     const uint64_t row = i / R, r = i % R;
@@ -247,31 +378,91 @@ __global__ __launch_bounds__(kClThreads) void k_cluster_als(ClusterArgs c) {
   }
   for (int i = threadIdx.x; i < L * R; i += blockDim.x) {
     const uint64_t row = i / R, r = i % R;
-    Z[i] = sm64_uniform(c.seed, ((static_cast<uint64_t>(tensor) * 3 + 2) * rows_max + row) * R + r);
+    Z[row * ZS + r] = sm64_uniform(c.seed, ((static_cast<uint64_t>(tensor) * 3 + 2) * rows_max + row) * R + r);
   }
   if (threadIdx.x < R) lam[threadIdx.x] = 1.0;
   __syncthreads();
-  gram_lds<R>(X, t, GX);
-  gram_lds<R>(Y, t, GY);
-  gram_lds<R>(Z, L, GZ);
+  gram_mfma<R>(X, t, R, GX, part);
+  gram_mfma<R>(Y, t, R, GY, part);
+  gram_mfma<R>(Z, L, ZS, GZ, part);
+
+  // pass A: this wave's bin blocks (16 bins each) are `wave` and `wave + 8`
+  const int nabb = (tt + 15) / 16;
+  int64_t aoff[2];
+  bool aok[2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int ab = (wave + kClWaves * b) * 16 + li;
+    aok[b] = ab < tt;
+    aoff[b] = aok[b] ? bin_offset(c, ab) : 0;
+  }
+  const bool own0 = wave < nabb, own1 = wave + kClWaves < nabb;
+  const int nsteps_a = (L + 3) / 4;
+  const int nbatch_a = (nsteps_a + kUK - 1) / kUK;
+  // pass B: the staged element e of this thread is bin (chunk start + sab),
+  // footprint (range start + sf0 + e * (kClThreads / ABC))
+  const int sab = threadIdx.x % ABC, sf0 = threadIdx.x / ABC;
+  const int nabc = (tt + ABC - 1) / ABC;
+  const int nchunk_b = ((L + kFR - 1) / kFR) * nabc;
   int fails = 0;
 
   for (int it = 0; it < c.iters; ++it) {
-    // pass A: P[ab][r] = sum_f D[ab][f] Z[f][r]
-    if (ab_active) {
-      double acc[R];
+    // ---- pass A: P[ab][r] = sum_f D[ab][f] Z[f][r] ----
+    {
+      f64x4 acc[2][RB];
 #pragma unroll
-      for (int r = 0; r < R; ++r) acc[r] = 0.0;
-      for (int f = 0; f < L; ++f) {
-        const double d = D.at(ab_off, f);
+      for (int b = 0; b < 2; ++b)
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] += d * Z[f * R + r];
+        for (int rb = 0; rb < RB; ++rb) acc[b][rb] = f64x4{0.0, 0.0, 0.0, 0.0};
+      TT cur[kUK][2], nxt[kUK][2];
+      auto load = [&](int batch, TT (&v)[kUK][2]) {
+#pragma unroll
+        for (int s = 0; s < kUK; ++s) {
+          const int f = (batch * kUK + s) * 4 + lk;
+          const bool fok = f < L;
+          const int64_t fo = fok ? foff[f] : 0;
+#pragma unroll
+          for (int b = 0; b < 2; ++b) v[s][b] = (fok && aok[b]) ? Tb[fo + aoff[b]] : TT(0);
+        }
+      };
+      if (own0) load(0, cur);
+      for (int bt = 0; bt < nbatch_a; ++bt) {
+        if (own0 && bt + 1 < nbatch_a) load(bt + 1, nxt);
+        if (own0) {
+#pragma unroll
+          for (int s = 0; s < kUK; ++s) {
+            const int f = (bt * kUK + s) * 4 + lk;
+            double bz[RB];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) bz[rb] = (f < L && rb * 16 + li < R) ? Z[f * ZS + rb * 16 + li] : 0.0;
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) acc[0][rb] = mfma64(static_cast<double>(cur[s][0]), bz[rb], acc[0][rb]);
+            if (own1) {
+#pragma unroll
+              for (int rb = 0; rb < RB; ++rb) acc[1][rb] = mfma64(static_cast<double>(cur[s][1]), bz[rb], acc[1][rb]);
+            }
+          }
+#pragma unroll
+          for (int s = 0; s < kUK; ++s) {
+            cur[s][0] = nxt[s][0];
+            cur[s][1] = nxt[s][1];
+          }
+        }
       }
 #pragma unroll
-      for (int r = 0; r < R; ++r) P[my_ab * R + r] = acc[r];
+      for (int b = 0; b < 2; ++b) {
+        if (b == 0 ? !own0 : !own1) continue;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int ab = (wave + kClWaves * b) * 16 + lk + 4 * q, r = rb * 16 + li;
+            if (ab < tt && r < R) P[ab * R + r] = acc[b][rb][q];
+          }
+      }
     }
     __syncthreads();
-    // mode X: M[a][r] = sum_b P[ab][r] Y[b][r]
+    // ---- mode X: M[a][r] = sum_b P[ab][r] Y[b][r] ----
     for (int idx = threadIdx.x; idx < t * R; idx += blockDim.x) {
       const int a = idx / R, r = idx % R;
       double s = 0.0;
@@ -279,17 +470,17 @@ __global__ __launch_bounds__(kClThreads) void k_cluster_als(ClusterArgs c) {
       Mt[idx] = s;
     }
     __syncthreads();
-    if (cholesky_hadamard<R>(GY, GZ, Gm, red)) {
-      solve_rows<R>(Mt, t, Gm);
+    if (cholesky_hadamard<R>(GY, GZ, Gm, dg, dl)) {
+      solve_rows<R>(Mt, t, R, Gm);
       __syncthreads();
       for (int i = threadIdx.x; i < t * R; i += blockDim.x) X[i] = Mt[i];
       __syncthreads();
-      normalize_cols<R>(X, t, lam);
-      gram_lds<R>(X, t, GX);
+      gram_mfma<R>(X, t, R, GX, part);
+      normalize_by_gram<R>(X, t, R, GX, lam);
     } else {
       ++fails;
     }
-    // mode Y: M[b][r] = sum_a P[ab][r] X[a][r]
+    // ---- mode Y: M[b][r] = sum_a P[ab][r] X[a][r] ----
     for (int idx = threadIdx.x; idx < t * R; idx += blockDim.x) {
       const int b = idx / R, r = idx % R;
       double s = 0.0;
@@ -297,56 +488,89 @@ __global__ __launch_bounds__(kClThreads) void k_cluster_als(ClusterArgs c) {
       Mt[idx] = s;
     }
     __syncthreads();
-    if (cholesky_hadamard<R>(GX, GZ, Gm, red)) {
-      solve_rows<R>(Mt, t, Gm);
+    if (cholesky_hadamard<R>(GX, GZ, Gm, dg, dl)) {
+      solve_rows<R>(Mt, t, R, Gm);
       __syncthreads();
       for (int i = threadIdx.x; i < t * R; i += blockDim.x) Y[i] = Mt[i];
       __syncthreads();
-      normalize_cols<R>(Y, t, lam);
-      gram_lds<R>(Y, t, GY);
+      gram_mfma<R>(Y, t, R, GY, part);
+      normalize_by_gram<R>(Y, t, R, GY, lam);
     } else {
       ++fails;
     }
-    // mode Z (factored first: Z is overwritten in place only when it succeeds)
-    if (cholesky_hadamard<R>(GX, GY, Gm, red)) {
+    // ---- mode Z (factored first: Z is overwritten in place only when it succeeds) ----
+    if (cholesky_hadamard<R>(GX, GY, Gm, dg, dl)) {
       for (int idx = threadIdx.x; idx < tt * R; idx += blockDim.x) {
         const int ab = idx / R, r = idx % R;
         P[idx] = X[(ab / t) * R + r] * Y[(ab % t) * R + r];      // Khatri-Rao of X and Y
       }
-      __syncthreads();
-      constexpr int FC = stage_footprints<TT>();
-      for (int f0 = 0; f0 < L; f0 += FC) {
-        const int nf = L - f0 < FC ? L - f0 : FC;
-        if (ab_active)
-          for (int i = 0; i < nf; ++i) stage[i * tt + my_ab] = static_cast<TT>(D.at(ab_off, f0 + i));
+      // pass B: Z[f][r] = sum_ab D[ab][f] P[ab][r], footprint ranges of kFR,
+      // bin chunks of ABC staged through LDS; wave w owns footprints 16w..16w+15
+      TT reg[PER];
+      auto sload = [&](int chunk) {
+        const int fr = (chunk / nabc) * kFR, a0 = (chunk % nabc) * ABC;
+        const int ab = a0 + sab;
+        const int64_t bo = ab < tt ? bin_offset(c, ab) : 0;
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+          const int f = fr + sf0 + e * (kClThreads / ABC);
+          reg[e] = (f < L && ab < tt) ? Tb[foff[f] + bo] : TT(0);
+        }
+      };
+      f64x4 accz[RB];
+      sload(0);
+      for (int ch = 0; ch < nchunk_b; ++ch) {
+        const int fr = (ch / nabc) * kFR, a0 = (ch % nabc) * ABC;
+#pragma unroll
+        for (int e = 0; e < PER; ++e) stage[(sf0 + e * (kClThreads / ABC)) * SS + sab] = reg[e];
         __syncthreads();
-        for (int idx = threadIdx.x; idx < nf * R; idx += blockDim.x) {
-          const int i = idx / R, r = idx % R;
-          double s = 0.0;
-          for (int ab = 0; ab < tt; ++ab) s += static_cast<double>(stage[i * tt + ab]) * P[ab * R + r];
-          Z[(f0 + i) * R + r] = s;
+        if (ch + 1 < nchunk_b) sload(ch + 1);
+        if (a0 == 0) {
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) accz[rb] = f64x4{0.0, 0.0, 0.0, 0.0};
+        }
+        const int f0 = fr + wave * 16;
+        if (f0 < L) {
+#pragma unroll 4
+          for (int s = 0; s < ABC / 4; ++s) {
+            const int ab = a0 + s * 4 + lk;
+            const double a = static_cast<double>(stage[(wave * 16 + li) * SS + s * 4 + lk]);
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+              const double b = (ab < tt && rb * 16 + li < R) ? P[ab * R + rb * 16 + li] : 0.0;
+              accz[rb] = mfma64(a, b, accz[rb]);
+            }
+          }
+          if (a0 + ABC >= tt) {
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const int f = f0 + lk + 4 * q, r = rb * 16 + li;
+                if (f < L && r < R) Z[f * ZS + r] = accz[rb][q];
+              }
+          }
         }
         __syncthreads();
       }
-      solve_rows<R>(Z, L, Gm);
+      solve_rows<R>(Z, L, ZS, Gm);
       __syncthreads();
-      normalize_cols<R>(Z, L, lam);
-      gram_lds<R>(Z, L, GZ);
+      gram_mfma<R>(Z, L, ZS, GZ, part);
+      normalize_by_gram<R>(Z, L, ZS, GZ, lam);
     } else {
       ++fails;
     }
   }
   // outputs: X, Y, Z * lambda (FP32)
   for (int i = threadIdx.x; i < t * R; i += blockDim.x) {
-    c.X[static_cast<int64_t>(tensor) * t * R + i] = static_cast<float>(X[i]);
-    c.Y[static_cast<int64_t>(tensor) * t * R + i] = static_cast<float>(Y[i]);
+    outX[i] = static_cast<float>(X[i]);
+    outY[i] = static_cast<float>(Y[i]);
   }
-  for (int i = threadIdx.x; i < L * R; i += blockDim.x)
-    c.Z[static_cast<int64_t>(tensor) * L * R + i] = static_cast<float>(Z[i] * lam[i % R]);
-  if (threadIdx.x == 0) {
-    c.blank[tensor] = 0;
-    if (fails) atomicAdd(&c.info[0], fails);
+  for (int i = threadIdx.x; i < L * R; i += blockDim.x) {
+    const int f = i / R, r = i % R;
+    outZ[i] = static_cast<float>(Z[f * ZS + r] * lam[r]);
   }
+  if (threadIdx.x == 0 && fails) atomicAdd(&c.info[0], fails);
 }
 
 __global__ void k_cluster_info_init(int* info) {
@@ -489,12 +713,14 @@ glint_status cluster_shape(const glint_ndf_desc* d, const glint_cluster_desc* cd
 }
 
 template <typename TT, int R>
-glint_status launch_cluster_als(const ClusterArgs& c, hipStream_t stream) {
-  const ClusterLds o = cluster_lds(c.t, c.L, R, sizeof(TT));
+glint_status launch_cluster_als(const ClusterArgs& c, int64_t ntensor, hipStream_t stream) {
+  const ClusterLds o = cluster_lds(c.t, c.L, R, stage_doubles<TT>());
   const size_t lds = sizeof(double) * o.total_doubles;
-  if (static_cast<int>(lds) > g_cl_lds)
+  if (static_cast<int64_t>(lds) > g_cl_lds)
     return glint_fail(GLINT_E_UNSUPPORTED, "clustered ALS needs %zu bytes of LDS (device max %d)", lds, g_cl_lds);
-  const int64_t ntensor = static_cast<int64_t>(c.ncv) * (c.nu / c.cs) * c.nb * c.nb;
+  const size_t blds = sizeof(int64_t) * c.L;
+  hipLaunchKernelGGL((k_cluster_blank<TT>), dim3(static_cast<unsigned>(ntensor)), dim3(kBlankThreads), blds, stream, c);
+  GLINT_LAUNCHED("k_cluster_blank");
   hipLaunchKernelGGL((k_cluster_als<TT, R>), dim3(static_cast<unsigned>(ntensor)), dim3(kClThreads), lds, stream, c);
   GLINT_LAUNCHED("k_cluster_als");
   return GLINT_OK;
@@ -522,11 +748,12 @@ glint_status glint_cp_als_clustered(const glint_ndf_desc* desc, const glint_clus
   hipLaunchKernelGGL(k_cluster_info_init, dim3(1), dim3(64), 0, stream, info);
   GLINT_LAUNCHED("k_cluster_info_init");
   const bool f64 = T_dtype == GLINT_F64;
+  const int64_t n = s.ntensor;
   switch (cd->R) {
-    case 4: return f64 ? launch_cluster_als<double, 4>(c, stream) : launch_cluster_als<float, 4>(c, stream);
-    case 8: return f64 ? launch_cluster_als<double, 8>(c, stream) : launch_cluster_als<float, 8>(c, stream);
-    case 16: return f64 ? launch_cluster_als<double, 16>(c, stream) : launch_cluster_als<float, 16>(c, stream);
-    default: return f64 ? launch_cluster_als<double, 32>(c, stream) : launch_cluster_als<float, 32>(c, stream);
+    case 4: return f64 ? launch_cluster_als<double, 4>(c, n, stream) : launch_cluster_als<float, 4>(c, n, stream);
+    case 8: return f64 ? launch_cluster_als<double, 8>(c, n, stream) : launch_cluster_als<float, 8>(c, n, stream);
+    case 16: return f64 ? launch_cluster_als<double, 16>(c, n, stream) : launch_cluster_als<float, 16>(c, n, stream);
+    default: return f64 ? launch_cluster_als<double, 32>(c, n, stream) : launch_cluster_als<float, 32>(c, n, stream);
   }
 }
 
