@@ -231,7 +231,8 @@ typedef struct {
  * c = ((tensor * 3 + mode) * max(t, L) + row) * R + r.  A tensor with
  * sum |D| <= 1e-12 L is blank: zero factors, blank[tensor] = 1 (count in
  * info[1]).  Outputs FP32: X, Y [ntensor][t][R], Z [ntensor][L][R] with
- * L = cs * cs * nlevels; blank uint8 [ntensor]; info int32 [2].  The
+ * L = cs * cs * nlevels; blank uint8 [ntensor]; info int32 [4] (info[2]
+ * is the work counter of the call's kernels, info[3] unused).  The
  * tensor's factors, Grams and partial products live in LDS for all sweeps:
  * configurations that do not fit return GLINT_E_UNSUPPORTED (rank 16 fits
  * with t = 16, cs = 8 and up to 8 levels from an F32 tensor). */

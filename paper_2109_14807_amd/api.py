@@ -284,7 +284,7 @@ def cp_als_clustered(T: torch.Tensor, desc: NdfDesc, t: int, cs: int, R: int, it
     Y = torch.empty((ntensor, t, R), **f32)
     Z = torch.empty((ntensor, Lr, R), **f32)
     blank = torch.empty(ntensor, dtype=torch.uint8, device=_DEV)
-    info = torch.empty(2, dtype=torch.int32, device=_DEV)
+    info = torch.empty(4, dtype=torch.int32, device=_DEV)
     L.glint_cp_als_clustered(desc, L.ClusterDesc(t, int(cs), int(R)), T.contiguous(), iters, seed,
                              X, Y, Z, blank, info)
     tab = ClusteredTables(desc, t, int(cs), X, Y, Z, blank, info)

@@ -32,7 +32,10 @@ constexpr int kClThreads = 512;
 constexpr int kClWaves = kClThreads / 64;
 constexpr int kBlankThreads = 256;
 constexpr int kFR = 16 * kClWaves;      // footprints per pass-B range: 16 per wave
-constexpr int kUK = 8;                  // pass-A MFMA steps (4 footprints each) per prefetched batch
+// pass-A MFMA steps (4 footprints each) per prefetched batch: one batch
+// in flight while the previous one runs on the matrix cores
+template <typename TT>
+constexpr int pass_a_batch() { return sizeof(TT) == 4 ? 16 : 8; }
 
 // pass-B stage: kFR footprints x AB bins of T, rows padded so that the 16
 // footprints x 4 bins an MFMA operand read touches fall in distinct banks
@@ -63,6 +66,7 @@ struct ClusterArgs {
   int nu, nv, nl, N;
   int t, cs, ncv, nb, L;
   int iters;
+  int ntensor;
   uint64_t seed;
   float* X;
   float* Y;
@@ -326,8 +330,9 @@ __device__ void normalize_by_gram(double* F, int rows, int ld, double* G, double
   __syncthreads();
 }
 
+// CP-ALS of one block tensor by the whole workgroup (every sweep).
 template <typename TT, int R>
-__global__ __launch_bounds__(kClThreads) void k_cluster_als(ClusterArgs c) {
+__device__ __forceinline__ void als_one(const ClusterArgs& c, int tensor) {
   constexpr int RB = (R + 15) / 16;
   constexpr int ABC = stage_ab<TT>(), SS = stage_stride<TT>();
   constexpr int PER = kFR * ABC / kClThreads;     // staged elements per thread per chunk
@@ -351,7 +356,6 @@ __global__ __launch_bounds__(kClThreads) void k_cluster_als(ClusterArgs c) {
   TT* stage = reinterpret_cast<TT*>(cl_lds + o.stage);
   double* part = cl_lds + o.stage;
 
-  const int tensor = blockIdx.x;
   float* outX = c.X + static_cast<int64_t>(tensor) * t * R;
   float* outY = c.Y + static_cast<int64_t>(tensor) * t * R;
   float* outZ = c.Z + static_cast<int64_t>(tensor) * L * R;
@@ -397,6 +401,7 @@ __global__ __launch_bounds__(kClThreads) void k_cluster_als(ClusterArgs c) {
     aoff[b] = aok[b] ? bin_offset(c, ab) : 0;
   }
   const bool own0 = wave < nabb, own1 = wave + kClWaves < nabb;
+  constexpr int kUK = pass_a_batch<TT>();
   const int nsteps_a = (L + 3) / 4;
   const int nbatch_a = (nsteps_a + kUK - 1) / kUK;
   // pass B: the staged element e of this thread is bin (chunk start + sab),
@@ -506,8 +511,7 @@ __global__ __launch_bounds__(kClThreads) void k_cluster_als(ClusterArgs c) {
       }
       // pass B: Z[f][r] = sum_ab D[ab][f] P[ab][r], footprint ranges of kFR,
       // bin chunks of ABC staged through LDS; wave w owns footprints 16w..16w+15
-      TT reg[PER];
-      auto sload = [&](int chunk) {
+      auto sload = [&](int chunk, TT (&reg)[PER]) {
         const int fr = (chunk / nabc) * kFR, a0 = (chunk % nabc) * ABC;
         const int ab = a0 + sab;
         const int64_t bo = ab < tt ? bin_offset(c, ab) : 0;
@@ -518,13 +522,14 @@ __global__ __launch_bounds__(kClThreads) void k_cluster_als(ClusterArgs c) {
         }
       };
       f64x4 accz[RB];
-      sload(0);
-      for (int ch = 0; ch < nchunk_b; ++ch) {
+      // one chunk: stage it, refill its registers with the chunk two ahead,
+      // then run this wave's 16 footprints through the matrix cores
+      auto chunk_step = [&](int ch, TT (&reg)[PER]) {
         const int fr = (ch / nabc) * kFR, a0 = (ch % nabc) * ABC;
 #pragma unroll
         for (int e = 0; e < PER; ++e) stage[(sf0 + e * (kClThreads / ABC)) * SS + sab] = reg[e];
         __syncthreads();
-        if (ch + 1 < nchunk_b) sload(ch + 1);
+        if (ch + 2 < nchunk_b) sload(ch + 2, reg);
         if (a0 == 0) {
 #pragma unroll
           for (int rb = 0; rb < RB; ++rb) accz[rb] = f64x4{0.0, 0.0, 0.0, 0.0};
@@ -552,6 +557,13 @@ __global__ __launch_bounds__(kClThreads) void k_cluster_als(ClusterArgs c) {
           }
         }
         __syncthreads();
+      };
+      TT ra[PER], rb2[PER];
+      sload(0, ra);
+      if (nchunk_b > 1) sload(1, rb2);
+      for (int ch = 0; ch < nchunk_b; ch += 2) {
+        chunk_step(ch, ra);
+        if (ch + 1 < nchunk_b) chunk_step(ch + 1, rb2);
       }
       solve_rows<R>(Z, L, ZS, Gm);
       __syncthreads();
@@ -573,8 +585,26 @@ __global__ __launch_bounds__(kClThreads) void k_cluster_als(ClusterArgs c) {
   if (threadIdx.x == 0 && fails) atomicAdd(&c.info[0], fails);
 }
 
+// Persistent workgroups (as many as fit on the chip at once) take block
+// tensors from a counter (info[2]) until all are done: blank blocks cost only
+// their zero outputs, and a fixed index-to-tensor mapping would let the
+// workgroup dispatcher's round-robin over XCDs and shader engines line up
+// with the angular positions of the non-blank blocks.
+template <typename TT, int R>
+__global__ __launch_bounds__(kClThreads) void k_cluster_als(ClusterArgs c) {
+  __shared__ int s_next;
+  for (;;) {
+    if (threadIdx.x == 0) s_next = atomicAdd(&c.info[2], 1);
+    __syncthreads();
+    const int tensor = s_next;
+    __syncthreads();
+    if (tensor >= c.ntensor) break;
+    als_one<TT, R>(c, tensor);
+  }
+}
+
 __global__ void k_cluster_info_init(int* info) {
-  if (threadIdx.x < 2) info[threadIdx.x] = 0;
+  if (threadIdx.x < 4) info[threadIdx.x] = 0;
 }
 
 // C[b][j][r] = sum_{s<j} S[b][s][r] (FP64 accumulation), FP32 out.
@@ -708,7 +738,7 @@ glint_status cluster_shape(const glint_ndf_desc* d, const glint_cluster_desc* cd
   s->nb = d->nbins / s->t;
   s->L = cd->cs * cd->cs * d->nlevels;
   s->ntensor = static_cast<int64_t>(s->ncu) * s->ncv * s->nb * s->nb;
-  GLINT_SUPPORT(s->ntensor < (int64_t{1} << 31), "too many region-and-block tensors");
+  GLINT_SUPPORT(s->ntensor < (int64_t{1} << 30), "too many region-and-block tensors");
   return GLINT_OK;
 }
 
@@ -716,12 +746,18 @@ template <typename TT, int R>
 glint_status launch_cluster_als(const ClusterArgs& c, int64_t ntensor, hipStream_t stream) {
   const ClusterLds o = cluster_lds(c.t, c.L, R, stage_doubles<TT>());
   const size_t lds = sizeof(double) * o.total_doubles;
-  if (static_cast<int64_t>(lds) > g_cl_lds)
+  if (static_cast<int64_t>(lds) + 16 > g_cl_lds)   // + the kernel's static work-counter slot
     return glint_fail(GLINT_E_UNSUPPORTED, "clustered ALS needs %zu bytes of LDS (device max %d)", lds, g_cl_lds);
   const size_t blds = sizeof(int64_t) * c.L;
   hipLaunchKernelGGL((k_cluster_blank<TT>), dim3(static_cast<unsigned>(ntensor)), dim3(kBlankThreads), blds, stream, c);
   GLINT_LAUNCHED("k_cluster_blank");
-  hipLaunchKernelGGL((k_cluster_als<TT, R>), dim3(static_cast<unsigned>(ntensor)), dim3(kClThreads), lds, stream, c);
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_cluster_als<TT, R>),
+                                                   kClThreads, lds) != hipSuccess || per_cu < 1)
+    return glint_fail(GLINT_E_HIP, "occupancy query for k_cluster_als failed");
+  int64_t grid = static_cast<int64_t>(g_cl_cus) * per_cu;
+  if (grid > ntensor) grid = ntensor;
+  hipLaunchKernelGGL((k_cluster_als<TT, R>), dim3(static_cast<unsigned>(grid)), dim3(kClThreads), lds, stream, c);
   GLINT_LAUNCHED("k_cluster_als");
   return GLINT_OK;
 }
@@ -743,7 +779,7 @@ glint_status glint_cp_als_clustered(const glint_ndf_desc* desc, const glint_clus
   ClusterArgs c;
   c.T = T; c.nu = desc->nu; c.nv = desc->nv; c.nl = desc->nlevels; c.N = desc->nbins;
   c.t = s.t; c.cs = cd->cs; c.ncv = s.ncv; c.nb = s.nb; c.L = s.L;
-  c.iters = iters; c.seed = seed; c.X = X; c.Y = Y; c.Z = Z; c.blank = blank; c.info = info;
+  c.iters = iters; c.ntensor = static_cast<int>(s.ntensor); c.seed = seed; c.X = X; c.Y = Y; c.Z = Z; c.blank = blank; c.info = info;
   glint_clear_launch_error();
   hipLaunchKernelGGL(k_cluster_info_init, dim3(1), dim3(64), 0, stream, info);
   GLINT_LAUNCHED("k_cluster_info_init");
