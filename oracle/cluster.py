@@ -17,14 +17,19 @@ What is computed:
     block-local range query of that block's CP (two summed-area look-ups
     per axis inside the block, Sec. 4.4), splitting the box at block edges.
 Readings:
-  * A block is blank when the sum of |D| is at most BLANK_RTOL * L (per
-    footprint mass below 1e-12); blank blocks store zero factors and
-    contribute exactly 0.
+  * Blank image blocks are thrown away before the fit (Sec. 4.2): the image
+    block of footprint f is blank when the sum of its |values| is at most
+    BLANK_TOL (1e-12; an NDF image has unit mass).  D is stacked from the
+    L' non-blank blocks only, in footprint order, and fitted as t x t x L';
+    the Z row of a blank footprint is zero, so it contributes exactly 0 to a
+    query.  A (region, block) tensor with no non-blank footprint is blank
+    and stores zero factors.
   * ALS initial factors: U[0, 1) from SplitMix64 used as a counter-based
     generator (the n-th output of the generator seeded with `seed`, n
     counted from 1): value(counter) = (mix(seed + (counter + 1) * gamma) >> 11)
     * 2^-53, with counter = ((tensor * 3 + mode) * max(t, L) + row) * R + r,
-    tensor = ((cu * ncv + cv) * nb + zs) * nb + zt.
+    tensor = ((cu * ncv + cv) * nb + zs) * nb + zt; the row of a Z entry is
+    the footprint index f of its (non-blank) block.
   * Normal equations with a small ridge: A = M (G + mu I)^-1, mu = 1e-10 x
     trace(G) / R (a region-and-block tensor is often of lower rank than R,
     and its Hadamard Gram then singular); Cholesky breakdown (pivot <= 1e-13 x
@@ -40,7 +45,7 @@ import scipy.linalg
 
 from .ndf import canonical_query
 
-BLANK_RTOL = 1e-12
+BLANK_TOL = 1e-12
 PIVOT_RTOL = 1e-13
 RIDGE_RTOL = 1e-10
 _GAMMA = 0x9E3779B97F4A7C15
@@ -85,16 +90,24 @@ def cluster_tensor(T: np.ndarray, cu: int, cv: int, zs: int, zt: int, t: int, cs
     return np.ascontiguousarray(sub.reshape(-1, t, t).transpose(1, 2, 0))
 
 
-def init_factors(seed: int, tensor: int, t: int, L: int, R: int):
+def init_factors(seed: int, tensor: int, t: int, L: int, R: int, zrows=None):
+    """Initial X [t][R], Y [t][R] and Z [len(zrows)][R] (zrows: the footprint
+    indices of the stacked blocks, default all L)."""
     rows_max = max(t, L)
+    zrows = np.arange(L) if zrows is None else np.asarray(zrows)
 
     def block(mode, rows):
-        i = np.arange(rows, dtype=np.uint64)[:, None]
+        i = np.asarray(rows, dtype=np.uint64)[:, None]
         r = np.arange(R, dtype=np.uint64)[None, :]
         c = ((np.uint64(tensor) * np.uint64(3) + np.uint64(mode)) * np.uint64(rows_max) + i) * np.uint64(R) + r
         return uniform(seed, c)
 
-    return block(0, t), block(1, t), block(2, L)
+    return block(0, np.arange(t)), block(1, np.arange(t)), block(2, zrows)
+
+
+def nonblank_footprints(D: np.ndarray) -> np.ndarray:
+    """Indices f of the non-blank image blocks D[:, :, f]."""
+    return np.nonzero(np.abs(D).sum(axis=(0, 1)) > BLANK_TOL)[0]
 
 
 def _solve(M, G):
@@ -149,28 +162,35 @@ def als3(D: np.ndarray, init, iters: int):
     return X, Y, Z * lam[None, :], fails
 
 
-def clustered_cp(T: np.ndarray, t: int, cs: int, R: int, iters: int, seed: int):
+def clustered_cp(T: np.ndarray, t: int, cs: int, R: int, iters: int, seed: int, counts: bool = False):
     """Factors of every (region, block): X, Y [ncu][ncv][nb][nb][t][R],
-    Z [ncu][ncv][nb][nb][L][R] (lambda absorbed), blank flags, failures."""
+    Z [ncu][ncv][nb][nb][L][R] (lambda absorbed; zero rows for blank image
+    blocks), blank flags, failures; with counts=True also L' per tensor."""
     nu, nv, nl, N = T.shape[:4]
     ncu, ncv, nb, L, t = layout(nu, nv, nl, N, t, cs)
     X = np.zeros((ncu, ncv, nb, nb, t, R))
     Y = np.zeros_like(X)
     Z = np.zeros((ncu, ncv, nb, nb, L, R))
     blank = np.zeros((ncu, ncv, nb, nb), dtype=bool)
+    nkept = np.zeros((ncu, ncv, nb, nb), dtype=np.int64)
     fails = 0
     for cu in range(ncu):
         for cv in range(ncv):
             for zs in range(nb):
                 for zt in range(nb):
                     D = cluster_tensor(T, cu, cv, zs, zt, t, cs)
-                    if np.abs(D).sum() <= BLANK_RTOL * L:
+                    keep = nonblank_footprints(D)
+                    nkept[cu, cv, zs, zt] = len(keep)
+                    if len(keep) == 0:
                         blank[cu, cv, zs, zt] = True
                         continue
                     tensor = ((cu * ncv + cv) * nb + zs) * nb + zt
-                    x, y, z, f = als3(D, init_factors(seed, tensor, t, L, R), iters)
-                    X[cu, cv, zs, zt], Y[cu, cv, zs, zt], Z[cu, cv, zs, zt] = x, y, z
+                    x, y, z, f = als3(D[:, :, keep], init_factors(seed, tensor, t, L, R, keep), iters)
+                    X[cu, cv, zs, zt], Y[cu, cv, zs, zt] = x, y
+                    Z[cu, cv, zs, zt][keep] = z
                     fails += f
+    if counts:
+        return X, Y, Z, blank, fails, nkept
     return X, Y, Z, blank, fails
 
 

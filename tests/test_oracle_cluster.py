@@ -17,8 +17,9 @@ def test_splitmix64_published_outputs():
                        rtol=0, atol=2.0 ** -53)
 
 
-def _blockwise_low_rank(rng, nu, nv, nl, N, t, cs, R, blank_every=3):
-    """A tensor that is exactly rank R in every (region, block), some blocks zero."""
+def _blockwise_low_rank(rng, nu, nv, nl, N, t, cs, R, blank_every=3, zero_rows=0):
+    """A tensor that is exactly rank R in every (region, block), some blocks
+    zero, and in the others `zero_rows` footprints' image blocks zero."""
     T = np.zeros((nu, nv, nl, N, N))
     ncu, ncv, nb, L, t = cluster.layout(nu, nv, nl, N, t, cs)
     k = 0
@@ -30,6 +31,8 @@ def _blockwise_low_rank(rng, nu, nv, nl, N, t, cs, R, blank_every=3):
                     if k % blank_every == 0:
                         continue
                     X, Y, Z = rng.standard_normal((t, R)), rng.standard_normal((t, R)), rng.standard_normal((L, R))
+                    if zero_rows:
+                        Z[rng.choice(L, zero_rows, replace=False)] = 0.0
                     D = np.einsum("ar,br,fr->fab", X, Y, Z).reshape(cs, cs, nl, t, t)
                     T[cu * cs:(cu + 1) * cs, cv * cs:(cv + 1) * cs, :, zs * t:(zs + 1) * t, zt * t:(zt + 1) * t] = D
     return T
@@ -48,6 +51,29 @@ def test_exact_recovery_per_region_and_block():
                 for zt in range(2):
                     D = cluster.cluster_tensor(T, cu, cv, zs, zt, t, cs)
                     assert blank[cu, cv, zs, zt] == (not np.any(D))
+    rec = cluster.reconstruct(X, Y, Z, nl, cs)
+    assert np.linalg.norm(rec - T) <= 1e-7 * np.linalg.norm(T)
+
+
+def test_blank_image_blocks_are_thrown_away():
+    """Sec. 4.2: only the non-blank image blocks of a cluster are stacked.
+    Exact recovery still holds, the stacked count L' is the number of
+    non-zero footprint blocks, and a blank footprint's Z row is exactly zero."""
+    rng = np.random.default_rng(5)
+    nu, nv, nl, N, t, cs, R = 8, 8, 2, 8, 4, 4, 2
+    T = _blockwise_low_rank(rng, nu, nv, nl, N, t, cs, R, zero_rows=11)
+    X, Y, Z, blank, fails, nkept = cluster.clustered_cp(T, t, cs, R, iters=1000, seed=7, counts=True)
+    assert fails == 0
+    for cu in range(2):
+        for cv in range(2):
+            for zs in range(2):
+                for zt in range(2):
+                    D = cluster.cluster_tensor(T, cu, cv, zs, zt, t, cs)
+                    nz = np.abs(D).sum(axis=(0, 1)) > 0
+                    assert nkept[cu, cv, zs, zt] == nz.sum() and blank[cu, cv, zs, zt] == (not nz.any())
+                    if nz.any():
+                        assert nz.sum() == 32 - 11
+                    assert not Z[cu, cv, zs, zt][~nz].any()
     rec = cluster.reconstruct(X, Y, Z, nl, cs)
     assert np.linalg.norm(rec - T) <= 1e-7 * np.linalg.norm(T)
 
