@@ -221,21 +221,26 @@ typedef struct {
 } glint_cluster_desc;
 
 /* CP-ALS of every region-and-block tensor of T (F64 or F32, the layout of
- * glint_build_tensor), one workgroup per tensor, FP64 arithmetic.  Modes X
- * (a), Y (b), Z (f) in that order, `iters` sweeps; normal equations with a
- * ridge: A = M (G + mu I)^-1, mu = 1e-10 trace(G) / R, by Cholesky; a pivot
- * <= 1e-13 times its diagonal entry keeps that mode's factor for the sweep
- * (counted in info[0]).  Columns unit after each update; their weights end
- * in Z.  Initial factors U[0,1) from SplitMix64 used as a counter-based
- * generator: value = (mix(seed + (c + 1) * 0x9E3779B97F4A7C15) >> 11) 2^-53,
- * c = ((tensor * 3 + mode) * max(t, L) + row) * R + r.  A tensor with
- * sum |D| <= 1e-12 L is blank: zero factors, blank[tensor] = 1 (count in
- * info[1]).  Outputs FP32: X, Y [ntensor][t][R], Z [ntensor][L][R] with
- * L = cs * cs * nlevels; blank uint8 [ntensor]; info int32 [4] (info[2]
- * is the work counter of the call's kernels, info[3] unused).  The
- * tensor's factors, Grams and partial products live in LDS for all sweeps:
- * configurations that do not fit return GLINT_E_UNSUPPORTED (rank 16 fits
- * with t = 16, cs = 8 and up to 8 levels from an F32 tensor). */
+ * glint_build_tensor), one workgroup per tensor, FP64 arithmetic.  Blank
+ * image blocks are thrown away first (Sec. 4.2): the block of footprint f
+ * is blank when the sum of its |values| is <= 1e-12, and only the L'
+ * non-blank blocks are stacked (in footprint order) and fitted; a blank
+ * footprint's Z row is zero.  A tensor with L' = 0 is blank: zero factors,
+ * blank[tensor] = 1, counted in info[1].  Modes X (a), Y (b), Z (f) in that
+ * order, `iters` sweeps; normal equations with a ridge: A = M (G + mu I)^-1,
+ * mu = 1e-10 trace(G) / R, by Cholesky; a pivot <= 1e-13 times its diagonal
+ * entry keeps that mode's factor for the sweep (counted in info[0]).
+ * Columns unit after each update; their weights end in Z.  Initial factors
+ * U[0,1) from SplitMix64 used as a counter-based generator: value =
+ * (mix(seed + (c + 1) * 0x9E3779B97F4A7C15) >> 11) 2^-53,
+ * c = ((tensor * 3 + mode) * max(t, L) + row) * R + r, where the row of a Z
+ * entry is its footprint f.  Outputs FP32: X, Y [ntensor][t][R],
+ * Z [ntensor][L][R] with L = cs * cs * nlevels; blank uint8 [ntensor];
+ * info int32 [4]: failures, blank tensors, the call's work counter, and the
+ * total L' over all tensors (the stacked blocks, for the compression
+ * ratio).  The tensor's factors, Grams and partial products live in LDS for
+ * all sweeps: configurations that do not fit return GLINT_E_UNSUPPORTED
+ * (rank 16 fits with t = 16, cs = 8 and up to 8 levels from an F32 tensor). */
 glint_status glint_cp_als_clustered(const glint_ndf_desc* desc, const glint_cluster_desc* cd,
                                     const void* T, glint_dtype T_dtype, int32_t iters,
                                     uint64_t seed, float* X, float* Y, float* Z,

@@ -6,10 +6,11 @@
 // range query (Sec. 4.4) splits a box at block edges and adds the
 // block-local queries.
 //
-// CP-ALS: a pre-pass flags the blank block tensors; then one 512-thread
-// workgroup per block tensor runs every sweep with its factors, Grams and
-// the (a,b)-by-rank product P = D x_f Z resident in LDS in FP64.  D is
-// streamed from the tensor T twice per sweep, and both streams are dense
+// CP-ALS: one 512-thread workgroup per block tensor throws away the blank
+// image blocks (Sec. 4.2: only the L' non-empty blocks of a cluster are
+// stacked), then runs every sweep with its factors, Grams and the
+// (a,b)-by-rank product P = D x_f Z resident in LDS in FP64.  D is streamed
+// from the tensor T twice per sweep, and both streams are dense
 // contractions on the matrix cores (v_mfma_f64_16x16x4f64):
 //   pass A  P[ab][r] = sum_f D[ab][f] Z[f][r]          (for the X and Y updates)
 //   pass B  Z[f][r]  = sum_ab D[ab][f] X[a][r] Y[b][r]  (the Z update)
@@ -25,12 +26,11 @@ namespace {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-constexpr double kBlankRtol = 1e-12;    // blank block: sum |D| <= kBlankRtol * L
+constexpr double kBlankTol = 1e-12;     // blank image block: sum of |values| <= kBlankTol
 constexpr double kPivotRtol = 1e-13;    // Cholesky breakdown
 constexpr double kRidgeRtol = 1e-10;    // normal equations use G + mu I, mu = kRidgeRtol * trace(G) / R
 constexpr int kClThreads = 512;
 constexpr int kClWaves = kClThreads / 64;
-constexpr int kBlankThreads = 256;
 constexpr int kFR = 16 * kClWaves;      // footprints per pass-B range: 16 per wave
 // pass-A MFMA steps (4 footprints each) per prefetched batch: one batch
 // in flight while the previous one runs on the matrix cores
@@ -78,7 +78,7 @@ struct ClusterArgs {
 // Offsets of the LDS arrays (in doubles) of the ALS kernel.  Z rows are
 // padded to R + 1 doubles (the per-row solves then spread over the banks).
 struct ClusterLds {
-  int x, y, mt, z, p, gx, gy, gz, gm, lam, dg, dl, foff, stage, total_doubles;
+  int x, y, mt, z, p, gx, gy, gz, gm, lam, dg, dl, foff, keep, rowof, stage, total_doubles;
 };
 
 __host__ __device__ inline ClusterLds cluster_lds(int t, int L, int R, int stage_doubles) {
@@ -101,7 +101,9 @@ __host__ __device__ inline ClusterLds cluster_lds(int t, int L, int R, int stage
   o.lam = take(R);
   o.dg = take(R);
   o.dl = take(R);
-  o.foff = take(L);            // int64 footprint offsets
+  o.foff = take(L);            // int64 footprint offsets of the stacked rows
+  o.keep = take((L + 1) / 2);  // int: footprint of stacked row j
+  o.rowof = take((L + 1) / 2); // int: stacked row of footprint f, or -1 (blank)
   o.stage = take(stage_doubles > kGramPart ? stage_doubles : kGramPart);
   o.total_doubles = at;
   return o;
@@ -139,44 +141,6 @@ __device__ __forceinline__ int64_t bin_offset(const ClusterArgs& c, int ab) {
   return static_cast<int64_t>(ab / c.t) * c.N + ab % c.t;
 }
 
-// Blank flags: sum |D| <= kBlankRtol * L.  One 256-thread workgroup per
-// block tensor; each thread owns one bin and streams the footprints.
-template <typename TT>
-__global__ __launch_bounds__(kBlankThreads) void k_cluster_blank(ClusterArgs c) {
-  extern __shared__ __align__(16) double bl_lds[];
-  int64_t* foff = reinterpret_cast<int64_t*>(bl_lds);
-  __shared__ double red[kBlankThreads];
-  const int tensor = blockIdx.x;
-  const BlockPos bp = block_pos(c, tensor);
-  const int tt = c.t * c.t, L = c.L;
-  for (int f = threadIdx.x; f < L; f += blockDim.x) foff[f] = footprint_offset(c, f);
-  __syncthreads();
-  const TT* Tb = static_cast<const TT*>(c.T) + bp.base;
-  double s = 0.0;
-  const int ab = threadIdx.x;
-  if (ab < tt) {
-    const int64_t bo = bin_offset(c, ab);
-    for (int f0 = 0; f0 < L; f0 += 8) {
-      TT v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = f0 + u < L ? Tb[foff[f0 + u] + bo] : TT(0);
-#pragma unroll
-      for (int u = 0; u < 8; ++u) s += fabs(static_cast<double>(v[u]));
-    }
-  }
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = kBlankThreads / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    const bool blank = !(red[0] > kBlankRtol * L);
-    c.blank[tensor] = blank ? 1 : 0;
-    if (blank) atomicAdd(&c.info[1], 1);
-  }
-}
-
 // Gm = G1 o G2 + mu I, mu = kRidgeRtol * trace(G1 o G2) / R, factored in
 // place as L L^T (lower, row-major), right-looking: at step j the pivot is
 // the updated diagonal entry, column j is scaled by its square root and the
@@ -198,7 +162,8 @@ __device__ bool cholesky_hadamard(const double* G1, const double* G2, double* Gm
   __syncthreads();
   for (int j = 0; j < R; ++j) {
     const double d = Gm[j * R + j];
-    if (!(d > kPivotRtol * dg[j])) return false;
+    // the same in every lane; made wave-uniform because it exits a loop with barriers
+    if (!__builtin_amdgcn_readfirstlane(d > kPivotRtol * dg[j] ? 1 : 0)) return false;
     const double ljj = sqrt(d);
     if (threadIdx.x == 0) dl[j] = ljj;
     for (int i = j + 1 + static_cast<int>(threadIdx.x); i < R; i += blockDim.x) Gm[i * R + j] /= ljj;
@@ -330,9 +295,11 @@ __device__ void normalize_by_gram(double* F, int rows, int ld, double* G, double
   __syncthreads();
 }
 
-// CP-ALS of one block tensor by the whole workgroup (every sweep).
+// CP-ALS of one block tensor by the whole workgroup (every sweep).  Not
+// inlined: its early exits then stay inside the call, and the persistent
+// loop around it is a plain scalar loop.
 template <typename TT, int R>
-__device__ __forceinline__ void als_one(const ClusterArgs& c, int tensor) {
+__device__ __noinline__ void als_one(const ClusterArgs& c, int tensor) {
   constexpr int RB = (R + 15) / 16;
   constexpr int ABC = stage_ab<TT>(), SS = stage_stride<TT>();
   constexpr int PER = kFR * ABC / kClThreads;     // staged elements per thread per chunk
@@ -356,39 +323,100 @@ __device__ __forceinline__ void als_one(const ClusterArgs& c, int tensor) {
   TT* stage = reinterpret_cast<TT*>(cl_lds + o.stage);
   double* part = cl_lds + o.stage;
 
+  int* keep = reinterpret_cast<int*>(cl_lds + o.keep);
+  int* rowof = reinterpret_cast<int*>(cl_lds + o.rowof);
+  __shared__ int wcnt[kClWaves];
+
   float* outX = c.X + static_cast<int64_t>(tensor) * t * R;
   float* outY = c.Y + static_cast<int64_t>(tensor) * t * R;
   float* outZ = c.Z + static_cast<int64_t>(tensor) * L * R;
-  if (c.blank[tensor]) {
-    for (int i = threadIdx.x; i < t * R; i += blockDim.x) {
-      outX[i] = 0.0f;
-      outY[i] = 0.0f;
-    }
-    for (int i = threadIdx.x; i < L * R; i += blockDim.x) outZ[i] = 0.0f;
-    return;
-  }
   const BlockPos bp = block_pos(c, tensor);
   const TT* Tb = static_cast<const TT*>(c.T) + bp.base;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
 
-  // footprint offsets, initial factors (SplitMix64 counters), lambda = 1
-  for (int f = threadIdx.x; f < L; f += blockDim.x) foff[f] = footprint_offset(c, f);
+  // blank image blocks are thrown away: rowof[f] = 1 if the block of
+  // footprint f has mass above kBlankTol (each wave sums four footprints at a
+  // time over its lanes), then the non-blank ones are stacked in order
+  {
+    int64_t boff[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ab = lane + 64 * q;
+      boff[q] = ab < tt ? bin_offset(c, ab) : -1;
+    }
+    for (int f0 = wave * 4; f0 < L; f0 += kClWaves * 4) {
+      TT v[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int f = f0 + u;
+        const int64_t fo = f < L ? footprint_offset(c, f) : 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[u][q] = (f < L && boff[q] >= 0) ? Tb[fo + boff[q]] : TT(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        double m = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) m += fabs(static_cast<double>(v[u][q]));
+        m = glint_wave_sum(m);
+        if (lane == 0 && f0 + u < L) rowof[f0 + u] = m > kBlankTol ? 1 : 0;
+      }
+    }
+    __syncthreads();
+  }
+  int Lc = 0;
+  for (int base = 0; base < L; base += kClThreads) {
+    const int f = base + static_cast<int>(threadIdx.x);
+    const bool nb = f < L && rowof[f] != 0;
+    const unsigned long long bal = __ballot(nb);
+    if (lane == 0) wcnt[wave] = __popcll(bal);
+    __syncthreads();
+    int off = Lc, tot = 0;
+    for (int w = 0; w < kClWaves; ++w) {
+      if (w < wave) off += wcnt[w];
+      tot += wcnt[w];
+    }
+    if (f < L) {
+      const int j = off + __popcll(bal & ((1ull << lane) - 1ull));
+      if (nb) keep[j] = f;
+      rowof[f] = nb ? j : -1;
+    }
+    Lc += __builtin_amdgcn_readfirstlane(tot);     // uniform: it decides branches around barriers
+    __syncthreads();
+  }
+  if (Lc == 0) {
+    for (int i = threadIdx.x; i < t * R; i += blockDim.x) {
+      outX[i] = 0.0f;
+      outY[i] = 0.0f;
+    }
+    for (int i = threadIdx.x; i < L * R; i += blockDim.x) outZ[i] = 0.0f;
+    if (threadIdx.x == 0) {
+      c.blank[tensor] = 1;
+      atomicAdd(&c.info[1], 1);
+    }
+    return;
+  }
+
+  // offsets of the stacked footprints, initial factors (SplitMix64 counters;
+  // a Z row is numbered by its footprint), lambda = 1
+  for (int j = threadIdx.x; j < Lc; j += blockDim.x) foff[j] = footprint_offset(c, keep[j]);
   const uint64_t rows_max = t > L ? t : L;
   for (int i = threadIdx.x; i < t * R; i += blockDim.x) {
     const uint64_t row = i / R, r = i % R;
     X[i] = sm64_uniform(c.seed, ((static_cast<uint64_t>(tensor) * 3 + 0) * rows_max + row) * R + r);
     Y[i] = sm64_uniform(c.seed, ((static_cast<uint64_t>(tensor) * 3 + 1) * rows_max + row) * R + r);
   }
-  for (int i = threadIdx.x; i < L * R; i += blockDim.x) {
-    const uint64_t row = i / R, r = i % R;
-    Z[row * ZS + r] = sm64_uniform(c.seed, ((static_cast<uint64_t>(tensor) * 3 + 2) * rows_max + row) * R + r);
+  for (int i = threadIdx.x; i < Lc * R; i += blockDim.x) {
+    const int j = i / R, r = i % R;
+    const uint64_t row = static_cast<uint64_t>(keep[j]);
+    Z[j * ZS + r] = sm64_uniform(c.seed, ((static_cast<uint64_t>(tensor) * 3 + 2) * rows_max + row) * R + r);
   }
   if (threadIdx.x < R) lam[threadIdx.x] = 1.0;
   __syncthreads();
   gram_mfma<R>(X, t, R, GX, part);
   gram_mfma<R>(Y, t, R, GY, part);
-  gram_mfma<R>(Z, L, ZS, GZ, part);
+  gram_mfma<R>(Z, Lc, ZS, GZ, part);
 
   // pass A: this wave's bin blocks (16 bins each) are `wave` and `wave + 8`
   const int nabb = (tt + 15) / 16;
@@ -402,13 +430,13 @@ __device__ __forceinline__ void als_one(const ClusterArgs& c, int tensor) {
   }
   const bool own0 = wave < nabb, own1 = wave + kClWaves < nabb;
   constexpr int kUK = pass_a_batch<TT>();
-  const int nsteps_a = (L + 3) / 4;
+  const int nsteps_a = (Lc + 3) / 4;
   const int nbatch_a = (nsteps_a + kUK - 1) / kUK;
   // pass B: the staged element e of this thread is bin (chunk start + sab),
   // footprint (range start + sf0 + e * (kClThreads / ABC))
   const int sab = threadIdx.x % ABC, sf0 = threadIdx.x / ABC;
   const int nabc = (tt + ABC - 1) / ABC;
-  const int nchunk_b = ((L + kFR - 1) / kFR) * nabc;
+  const int nchunk_b = ((Lc + kFR - 1) / kFR) * nabc;
   int fails = 0;
 
   for (int it = 0; it < c.iters; ++it) {
@@ -424,7 +452,7 @@ __device__ __forceinline__ void als_one(const ClusterArgs& c, int tensor) {
 #pragma unroll
         for (int s = 0; s < kUK; ++s) {
           const int f = (batch * kUK + s) * 4 + lk;
-          const bool fok = f < L;
+          const bool fok = f < Lc;
           const int64_t fo = fok ? foff[f] : 0;
 #pragma unroll
           for (int b = 0; b < 2; ++b) v[s][b] = (fok && aok[b]) ? Tb[fo + aoff[b]] : TT(0);
@@ -439,7 +467,7 @@ __device__ __forceinline__ void als_one(const ClusterArgs& c, int tensor) {
             const int f = (bt * kUK + s) * 4 + lk;
             double bz[RB];
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) bz[rb] = (f < L && rb * 16 + li < R) ? Z[f * ZS + rb * 16 + li] : 0.0;
+            for (int rb = 0; rb < RB; ++rb) bz[rb] = (f < Lc && rb * 16 + li < R) ? Z[f * ZS + rb * 16 + li] : 0.0;
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) acc[0][rb] = mfma64(static_cast<double>(cur[s][0]), bz[rb], acc[0][rb]);
             if (own1) {
@@ -518,7 +546,7 @@ __device__ __forceinline__ void als_one(const ClusterArgs& c, int tensor) {
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
           const int f = fr + sf0 + e * (kClThreads / ABC);
-          reg[e] = (f < L && ab < tt) ? Tb[foff[f] + bo] : TT(0);
+          reg[e] = (f < Lc && ab < tt) ? Tb[foff[f] + bo] : TT(0);
         }
       };
       f64x4 accz[RB];
@@ -535,7 +563,7 @@ __device__ __forceinline__ void als_one(const ClusterArgs& c, int tensor) {
           for (int rb = 0; rb < RB; ++rb) accz[rb] = f64x4{0.0, 0.0, 0.0, 0.0};
         }
         const int f0 = fr + wave * 16;
-        if (f0 < L) {
+        if (f0 < Lc) {
 #pragma unroll 4
           for (int s = 0; s < ABC / 4; ++s) {
             const int ab = a0 + s * 4 + lk;
@@ -552,7 +580,7 @@ __device__ __forceinline__ void als_one(const ClusterArgs& c, int tensor) {
 #pragma unroll
               for (int q = 0; q < 4; ++q) {
                 const int f = f0 + lk + 4 * q, r = rb * 16 + li;
-                if (f < L && r < R) Z[f * ZS + r] = accz[rb][q];
+                if (f < Lc && r < R) Z[f * ZS + r] = accz[rb][q];
               }
           }
         }
@@ -565,10 +593,10 @@ __device__ __forceinline__ void als_one(const ClusterArgs& c, int tensor) {
         chunk_step(ch, ra);
         if (ch + 1 < nchunk_b) chunk_step(ch + 1, rb2);
       }
-      solve_rows<R>(Z, L, ZS, Gm);
+      solve_rows<R>(Z, Lc, ZS, Gm);
       __syncthreads();
-      gram_mfma<R>(Z, L, ZS, GZ, part);
-      normalize_by_gram<R>(Z, L, ZS, GZ, lam);
+      gram_mfma<R>(Z, Lc, ZS, GZ, part);
+      normalize_by_gram<R>(Z, Lc, ZS, GZ, lam);
     } else {
       ++fails;
     }
@@ -579,8 +607,12 @@ __device__ __forceinline__ void als_one(const ClusterArgs& c, int tensor) {
     outY[i] = static_cast<float>(Y[i]);
   }
   for (int i = threadIdx.x; i < L * R; i += blockDim.x) {
-    const int f = i / R, r = i % R;
-    outZ[i] = static_cast<float>(Z[f * ZS + r] * lam[r]);
+    const int f = i / R, r = i % R, j = rowof[f];
+    outZ[i] = j >= 0 ? static_cast<float>(Z[j * ZS + r] * lam[r]) : 0.0f;
+  }
+  if (threadIdx.x == 0) {
+    c.blank[tensor] = 0;
+    atomicAdd(&c.info[3], Lc);
   }
   if (threadIdx.x == 0 && fails) atomicAdd(&c.info[0], fails);
 }
@@ -596,7 +628,10 @@ __global__ __launch_bounds__(kClThreads) void k_cluster_als(ClusterArgs c) {
   for (;;) {
     if (threadIdx.x == 0) s_next = atomicAdd(&c.info[2], 1);
     __syncthreads();
-    const int tensor = s_next;
+    // the same value in every lane: made wave-uniform so that the loop exit
+    // and everything below stay scalar branches (a per-lane exit would put
+    // the claiming lane under an exec mask on the next trip)
+    const int tensor = __builtin_amdgcn_readfirstlane(s_next);
     __syncthreads();
     if (tensor >= c.ntensor) break;
     als_one<TT, R>(c, tensor);
@@ -746,11 +781,8 @@ template <typename TT, int R>
 glint_status launch_cluster_als(const ClusterArgs& c, int64_t ntensor, hipStream_t stream) {
   const ClusterLds o = cluster_lds(c.t, c.L, R, stage_doubles<TT>());
   const size_t lds = sizeof(double) * o.total_doubles;
-  if (static_cast<int64_t>(lds) + 16 > g_cl_lds)   // + the kernel's static work-counter slot
+  if (static_cast<int64_t>(lds) + 64 > g_cl_lds)   // + the kernel's static slots
     return glint_fail(GLINT_E_UNSUPPORTED, "clustered ALS needs %zu bytes of LDS (device max %d)", lds, g_cl_lds);
-  const size_t blds = sizeof(int64_t) * c.L;
-  hipLaunchKernelGGL((k_cluster_blank<TT>), dim3(static_cast<unsigned>(ntensor)), dim3(kBlankThreads), blds, stream, c);
-  GLINT_LAUNCHED("k_cluster_blank");
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_cluster_als<TT, R>),
                                                    kClThreads, lds) != hipSuccess || per_cu < 1)

@@ -93,6 +93,7 @@ def test_cluster_als_factors_match_oracle_on_a_full_rank_tensor(R, dtype):
     assert not blank.any() and not blanko.any()
     info = tab.info.cpu().numpy()
     assert int(info[0]) == fails and int(info[1]) == 0
+    assert int(info[3]) == tab.Z.shape[0] * tab.Z.shape[1]               # no blank image block
     assert np.max(np.abs(X - Xo)) < 1e-5
     assert np.max(np.abs(Y - Yo)) < 1e-5
     assert np.max(np.abs(Z - Zo)) < 1e-5 * np.max(np.abs(Zo))
@@ -119,10 +120,11 @@ def test_cluster_als_reconstruction_matches_oracle_c1(R):
     for iters in (3, 10):
         tab = G.cp_als_clustered(_to_dev(T), d, 16, 8, R, iters=iters, seed=11)
         X, Y, Z, blank = _oracle_shaped(tab, cfg.nu, cfg.nv, cfg.nbins, 16, 8)
-        Xo, Yo, Zo, blanko, fails = cluster.clustered_cp(T, 16, 8, R, iters=iters, seed=11)
+        Xo, Yo, Zo, blanko, fails, nkept = cluster.clustered_cp(T, 16, 8, R, iters=iters, seed=11, counts=True)
         assert np.array_equal(blank, blanko)
         info = tab.info.cpu().numpy()
         assert int(info[1]) == int(blanko.sum()) and int(info[0]) == fails
+        assert int(info[3]) == int(nkept.sum()) < nkept.size * 320      # blank image blocks thrown away
         err = np.sqrt(np.sum((_block_recon(X, Y, Z) - _block_recon(Xo, Yo, Zo)) ** 2, axis=(-3, -2, -1)))
         bound = _fp32_output_bound(Xo, Yo, Zo)
         ok = ~blanko
@@ -130,8 +132,10 @@ def test_cluster_als_reconstruction_matches_oracle_c1(R):
 
 
 def test_cluster_blank_blocks_and_f32_tensor():
-    """A tensor that is zero in every third region-and-block tensor: exact
-    blank flags, zero factors there, and a rank-2 fit elsewhere (F32 T)."""
+    """A tensor that is zero in every third region-and-block tensor and, in
+    the others, in 7 of the 32 footprints' image blocks: exact blank flags
+    and stacked counts, zero factors and zero Z rows there, and a rank-2 fit
+    of the rest (F32 T)."""
     rng = np.random.default_rng(3)
     nu, nv, nl, N, t, cs, R = 8, 8, 2, 16, 8, 4, 4
     ncu, ncv, nb, Lr, t = cluster.layout(nu, nv, nl, N, t, cs)
@@ -145,6 +149,7 @@ def test_cluster_blank_blocks_and_f32_tensor():
                     if k % 3 == 0:
                         continue
                     A, B, C = rng.random((t, 2)), rng.random((t, 2)), rng.random((Lr, 2))
+                    C[rng.choice(Lr, 7, replace=False)] = 0.0
                     D = np.einsum("ar,br,fr->fab", A, B, C).reshape(cs, cs, nl, t, t)
                     T[cu * cs:(cu + 1) * cs, cv * cs:(cv + 1) * cs, :, zs * t:(zs + 1) * t,
                       zt * t:(zt + 1) * t] = D
@@ -152,10 +157,12 @@ def test_cluster_blank_blocks_and_f32_tensor():
     d = G.desc_of(nu, nv, nl, N, 0.02)
     tab = G.cp_als_clustered(_to_dev(T, torch.float32), d, t, cs, R, iters=30, seed=9)
     X, Y, Z, blank = _oracle_shaped(tab, nu, nv, N, t, cs)
-    Xo, Yo, Zo, blanko, fails = cluster.clustered_cp(T, t, cs, R, iters=30, seed=9)
+    Xo, Yo, Zo, blanko, fails, nkept = cluster.clustered_cp(T, t, cs, R, iters=30, seed=9, counts=True)
     assert np.array_equal(blank, blanko) and blank.sum() == k // 3
     assert int(tab.info[1]) == k // 3
+    assert int(tab.info[3]) == int(nkept.sum()) == (k - k // 3) * (Lr - 7)
     assert not X[blank].any() and not Y[blank].any() and not Z[blank].any()
+    assert np.array_equal(Z == 0, Zo == 0)       # the zero rows of the thrown-away blocks
     err = np.sqrt(np.sum((_block_recon(X, Y, Z) - _block_recon(Xo, Yo, Zo)) ** 2, axis=(-3, -2, -1)))
     assert np.all(err <= _fp32_output_bound(Xo, Yo, Zo) + 1e-300)
 
