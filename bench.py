@@ -32,7 +32,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix
-FP64_MFMA_PEAK_TFLOPS = 78.6
+FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE on this workload,
 # scaled by the counters' reading for a plain 2 GiB copy (fetch x2.0, write x1.0);
@@ -430,24 +430,44 @@ def clustered_report(desc, T, q, q_bf, sweeps, timed, t=16, cs=8, R=16):
 
     G.cp_als_clustered(T, desc, t, cs, R, iters=1)          # warm-up
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     stream = torch.cuda.current_stream()
-    e0.record(stream)
-    tab = G.cp_als_clustered(T, desc, t, cs, R, iters=sweeps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    als_ms = e0.elapsed_time(e1)
+
+    def run(iters):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        tab = G.cp_als_clustered(T, desc, t, cs, R, iters=iters)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return tab, e0.elapsed_time(e1)
+
+    _, one_ms = run(1)
+    tab, als_ms = run(sweeps)
+    sweep_ms = (als_ms - one_ms) / max(sweeps - 1, 1)
     out = torch.empty(q.shape[0], dtype=torch.float32, device=q.device)
     st = tab.struct()
     query_ms = timed(lambda: L.glint_query_clustered(st, q, out))
     ebf = float((torch.linalg.vector_norm(out.double() - q_bf) / torch.linalg.vector_norm(q_bf)).item())
     info = tab.info.cpu().tolist()
     ntensor = tab.X.shape[0]
+    stacked = info[3]                                 # non-blank image blocks over all block tensors
+    tt = t * t
+    flops = 2 * 2.0 * tt * stacked * R                # P = D Z and Z = D^T (X kr Y), per sweep
+    dbytes = 2 * 4.0 * tt * stacked                   # the two streams over the stacked blocks
+    tf = flops / (sweep_ms * 1e-3) / 1e12
+    gbs = dbytes / (sweep_ms * 1e-3) / 1e9
     return {
         "what": f"per-(region, angular block) rank-{R} CP: {t}x{t} bin blocks, {cs}x{cs} texel regions, "
                 f"{sweeps} FP64 ALS sweeps per block tensor (blank blocks skipped), FP32 tables",
         "block_tensors": ntensor, "blank": info[1], "solve_failures": info[0],
-        "als_ms_incl_tables": als_ms, "als_ms_per_sweep": als_ms / sweeps,
+        "als_ms_incl_tables": als_ms, "one_sweep_call_ms": one_ms, "als_ms_per_sweep": sweep_ms,
+        # R/2 flop per streamed byte (8 at rank 16) sits under the FP64 matrix balance
+        # (78.6 TFLOP/s / 8 TB/s = 9.8): HBM is the nearer bound
+        "roofline": {"kernel": f"k_cluster_als<float,{R}> (two FP64 MFMA streams over the stacked D per sweep)",
+                     "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                     "per_sweep": {"stream_bytes": dbytes, "flops": flops, "fp64_tflops": tf,
+                                   "fp64_frac": tf / FP64_MFMA_PEAK_TFLOPS}},
+        "stacked_blocks": info[3],
         "query_ms": query_ms, "queries_per_s": q.shape[0] / (query_ms * 1e-3),
         "error_vs_bruteforce": ebf,
         "table_bytes": int(4 * (tab.CX.numel() + tab.CY.numel() + tab.Z.numel())),

@@ -35,7 +35,7 @@ constexpr int kFR = 16 * kClWaves;      // footprints per pass-B range: 16 per w
 // pass-A MFMA steps (4 footprints each) per prefetched batch: one batch
 // in flight while the previous one runs on the matrix cores
 template <typename TT>
-constexpr int pass_a_batch() { return sizeof(TT) == 4 ? 16 : 8; }
+constexpr int pass_a_batch() { return sizeof(TT) == 4 ? 8 : 8; }
 
 // pass-B stage: kFR footprints x AB bins of T, rows padded so that the 16
 // footprints x 4 bins an MFMA operand read touches fall in distinct banks
