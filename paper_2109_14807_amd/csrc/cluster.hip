@@ -6,9 +6,10 @@
 // range query (Sec. 4.4) splits a box at block edges and adds the
 // block-local queries.
 //
-// CP-ALS: one 512-thread workgroup per block tensor throws away the blank
-// image blocks (Sec. 4.2: only the L' non-empty blocks of a cluster are
-// stacked), then runs every sweep with its factors, Grams and the
+// CP-ALS: a high-occupancy pre-pass flags the blank image blocks (Sec. 4.2:
+// only the L' non-empty blocks of a cluster are stacked); then one 512-thread
+// workgroup per block tensor stacks the rest and runs every sweep with its
+// factors, Grams and the
 // (a,b)-by-rank product P = D x_f Z resident in LDS in FP64.  D is streamed
 // from the tensor T twice per sweep, and both streams are dense
 // contractions on the matrix cores (v_mfma_f64_16x16x4f64):
@@ -67,6 +68,7 @@ struct ClusterArgs {
   int t, cs, ncv, nb, L;
   int iters;
   int ntensor;
+  int R;
   uint64_t seed;
   float* X;
   float* Y;
@@ -139,6 +141,46 @@ __device__ __forceinline__ int64_t footprint_offset(const ClusterArgs& c, int f)
 // element offset of bin ab = a t + b inside the block
 __device__ __forceinline__ int64_t bin_offset(const ClusterArgs& c, int ab) {
   return static_cast<int64_t>(ab / c.t) * c.N + ab % c.t;
+}
+
+// Blank image blocks (Sec. 4.2 throws complete blank ones away): one wave
+// per footprint at a time sums |D| over the block's bins; the non-blank flag
+// (1 or 0) goes to the first entry of the footprint's row of the Z output,
+// where the ALS kernel reads it before it writes the factors.
+constexpr int kMassThreads = 256;
+
+template <typename TT>
+__global__ __launch_bounds__(kMassThreads) void k_cluster_mass(ClusterArgs c) {
+  const int tensor = blockIdx.x;
+  const BlockPos bp = block_pos(c, tensor);
+  const TT* Tb = static_cast<const TT*>(c.T) + bp.base;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = kMassThreads / 64;
+  const int tt = c.t * c.t, L = c.L;
+  float* flags = c.Z + static_cast<int64_t>(tensor) * L * c.R;
+  int64_t boff[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int ab = lane + 64 * q;
+    boff[q] = ab < tt ? bin_offset(c, ab) : -1;
+  }
+  for (int f0 = wave * 4; f0 < L; f0 += nw * 4) {
+    TT v[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int f = f0 + u;
+      const int64_t fo = f < L ? footprint_offset(c, f) : 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[u][q] = (f < L && boff[q] >= 0) ? Tb[fo + boff[q]] : TT(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      double m = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) m += fabs(static_cast<double>(v[u][q]));
+      m = glint_wave_sum(m);
+      if (lane == 0 && f0 + u < L) flags[static_cast<int64_t>(f0 + u) * c.R] = m > kBlankTol ? 1.0f : 0.0f;
+    }
+  }
 }
 
 // Gm = G1 o G2 + mu I, mu = kRidgeRtol * trace(G1 o G2) / R, factored in
@@ -335,36 +377,10 @@ __device__ __noinline__ void als_one(const ClusterArgs& c, int tensor) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
 
-  // blank image blocks are thrown away: rowof[f] = 1 if the block of
-  // footprint f has mass above kBlankTol (each wave sums four footprints at a
-  // time over its lanes), then the non-blank ones are stacked in order
-  {
-    int64_t boff[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int ab = lane + 64 * q;
-      boff[q] = ab < tt ? bin_offset(c, ab) : -1;
-    }
-    for (int f0 = wave * 4; f0 < L; f0 += kClWaves * 4) {
-      TT v[4][4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int f = f0 + u;
-        const int64_t fo = f < L ? footprint_offset(c, f) : 0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) v[u][q] = (f < L && boff[q] >= 0) ? Tb[fo + boff[q]] : TT(0);
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        double m = 0.0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) m += fabs(static_cast<double>(v[u][q]));
-        m = glint_wave_sum(m);
-        if (lane == 0 && f0 + u < L) rowof[f0 + u] = m > kBlankTol ? 1 : 0;
-      }
-    }
-    __syncthreads();
-  }
+  // blank image blocks are thrown away: the flags k_cluster_mass left in the
+  // Z rows, then the non-blank footprints are stacked in order
+  for (int f = threadIdx.x; f < L; f += blockDim.x) rowof[f] = outZ[static_cast<int64_t>(f) * R] != 0.0f ? 1 : 0;
+  __syncthreads();
   int Lc = 0;
   for (int base = 0; base < L; base += kClThreads) {
     const int f = base + static_cast<int>(threadIdx.x);
@@ -783,6 +799,8 @@ glint_status launch_cluster_als(const ClusterArgs& c, int64_t ntensor, hipStream
   const size_t lds = sizeof(double) * o.total_doubles;
   if (static_cast<int64_t>(lds) + 64 > g_cl_lds)   // + the kernel's static slots
     return glint_fail(GLINT_E_UNSUPPORTED, "clustered ALS needs %zu bytes of LDS (device max %d)", lds, g_cl_lds);
+  hipLaunchKernelGGL((k_cluster_mass<TT>), dim3(static_cast<unsigned>(ntensor)), dim3(kMassThreads), 0, stream, c);
+  GLINT_LAUNCHED("k_cluster_mass");
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_cluster_als<TT, R>),
                                                    kClThreads, lds) != hipSuccess || per_cu < 1)
@@ -811,7 +829,7 @@ glint_status glint_cp_als_clustered(const glint_ndf_desc* desc, const glint_clus
   ClusterArgs c;
   c.T = T; c.nu = desc->nu; c.nv = desc->nv; c.nl = desc->nlevels; c.N = desc->nbins;
   c.t = s.t; c.cs = cd->cs; c.ncv = s.ncv; c.nb = s.nb; c.L = s.L;
-  c.iters = iters; c.ntensor = static_cast<int>(s.ntensor); c.seed = seed; c.X = X; c.Y = Y; c.Z = Z; c.blank = blank; c.info = info;
+  c.iters = iters; c.ntensor = static_cast<int>(s.ntensor); c.R = cd->R; c.seed = seed; c.X = X; c.Y = Y; c.Z = Z; c.blank = blank; c.info = info;
   glint_clear_launch_error();
   hipLaunchKernelGGL(k_cluster_info_init, dim3(1), dim3(64), 0, stream, info);
   GLINT_LAUNCHED("k_cluster_info_init");
