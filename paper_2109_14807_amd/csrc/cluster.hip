@@ -186,39 +186,56 @@ __global__ __launch_bounds__(kMassThreads) void k_cluster_mass(ClusterArgs c) {
 // Gm = G1 o G2 + mu I, mu = kRidgeRtol * trace(G1 o G2) / R, factored in
 // place as L L^T (lower, row-major), right-looking: at step j the pivot is
 // the updated diagonal entry, column j is scaled by its square root and the
-// trailing lower triangle takes the rank-1 update, all entries in parallel.
-// A pivot <= kPivotRtol times the diagonal entry of the unfactored matrix
-// (kept in dg) is a breakdown: returns false (the same for every thread).
+// trailing lower triangle takes the rank-1 update.  The factorisation runs
+// on wavefront 0 alone with wave-level LDS fences between the steps (a
+// block-wide barrier per step would stall all eight wavefronts); the other
+// wavefronts wait at one barrier.  A pivot <= kPivotRtol times the diagonal
+// entry of the unfactored matrix (kept in dg) is a breakdown: returns false
+// (the same for every thread).  flag: one LDS int.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int R>
-__device__ bool cholesky_hadamard(const double* G1, const double* G2, double* Gm, double* dg, double* dl) {
+__device__ bool cholesky_hadamard(const double* G1, const double* G2, double* Gm, double* dg, double* dl,
+                                  int* flag) {
   for (int i = threadIdx.x; i < R * R; i += blockDim.x) Gm[i] = G1[i] * G2[i];
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double tr = 0.0;
-    for (int k = 0; k < R; ++k) tr += Gm[k * R + k];
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    double tr = lane < R ? Gm[lane * R + lane] : 0.0;
+    tr = glint_wave_sum(tr);
     const double mu = kRidgeRtol * tr / R;
-    for (int k = 0; k < R; ++k) Gm[k * R + k] += mu;
-  }
-  __syncthreads();
-  if (threadIdx.x < R) dg[threadIdx.x] = Gm[threadIdx.x * R + threadIdx.x];
-  __syncthreads();
-  for (int j = 0; j < R; ++j) {
-    const double d = Gm[j * R + j];
-    // the same in every lane; made wave-uniform because it exits a loop with barriers
-    if (!__builtin_amdgcn_readfirstlane(d > kPivotRtol * dg[j] ? 1 : 0)) return false;
-    const double ljj = sqrt(d);
-    if (threadIdx.x == 0) dl[j] = ljj;
-    for (int i = j + 1 + static_cast<int>(threadIdx.x); i < R; i += blockDim.x) Gm[i * R + j] /= ljj;
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) {
-      const int i = idx / R, k = idx % R;
-      if (k > j && k <= i) Gm[idx] -= Gm[i * R + j] * Gm[k * R + j];
+    if (lane < R) {
+      const double d0 = Gm[lane * R + lane] + mu;
+      Gm[lane * R + lane] = d0;
+      dg[lane] = d0;
     }
-    __syncthreads();
+    wave_lds_sync();
+    int ok = 1;
+    for (int j = 0; j < R; ++j) {
+      const double d = Gm[j * R + j];
+      if (!(d > kPivotRtol * dg[j])) {
+        ok = 0;
+        break;
+      }
+      const double ljj = sqrt(d);
+      if (lane == 0) dl[j] = ljj;
+      for (int i = j + 1 + lane; i < R; i += 64) Gm[i * R + j] /= ljj;
+      wave_lds_sync();
+      for (int idx = lane; idx < R * R; idx += 64) {
+        const int i = idx / R, k = idx % R;
+        if (k > j && k <= i) Gm[idx] -= Gm[i * R + j] * Gm[k * R + j];
+      }
+      wave_lds_sync();
+    }
+    if (ok && lane < R) Gm[lane * R + lane] = dl[lane];
+    if (lane == 0) *flag = ok;
   }
-  if (threadIdx.x < R) Gm[threadIdx.x * R + threadIdx.x] = dl[threadIdx.x];
   __syncthreads();
-  return true;
+  return __builtin_amdgcn_readfirstlane(*flag) != 0;
 }
 
 // A = M (L L^T)^-1 for `rows` rows of stride ld held in LDS, in place: one
@@ -368,6 +385,7 @@ __device__ __noinline__ void als_one(const ClusterArgs& c, int tensor) {
   int* keep = reinterpret_cast<int*>(cl_lds + o.keep);
   int* rowof = reinterpret_cast<int*>(cl_lds + o.rowof);
   __shared__ int wcnt[kClWaves];
+  __shared__ int s_flag;
 
   float* outX = c.X + static_cast<int64_t>(tensor) * t * R;
   float* outY = c.Y + static_cast<int64_t>(tensor) * t * R;
@@ -519,7 +537,7 @@ __device__ __noinline__ void als_one(const ClusterArgs& c, int tensor) {
       Mt[idx] = s;
     }
     __syncthreads();
-    if (cholesky_hadamard<R>(GY, GZ, Gm, dg, dl)) {
+    if (cholesky_hadamard<R>(GY, GZ, Gm, dg, dl, &s_flag)) {
       solve_rows<R>(Mt, t, R, Gm);
       __syncthreads();
       for (int i = threadIdx.x; i < t * R; i += blockDim.x) X[i] = Mt[i];
@@ -537,7 +555,7 @@ __device__ __noinline__ void als_one(const ClusterArgs& c, int tensor) {
       Mt[idx] = s;
     }
     __syncthreads();
-    if (cholesky_hadamard<R>(GX, GZ, Gm, dg, dl)) {
+    if (cholesky_hadamard<R>(GX, GZ, Gm, dg, dl, &s_flag)) {
       solve_rows<R>(Mt, t, R, Gm);
       __syncthreads();
       for (int i = threadIdx.x; i < t * R; i += blockDim.x) Y[i] = Mt[i];
@@ -548,7 +566,7 @@ __device__ __noinline__ void als_one(const ClusterArgs& c, int tensor) {
       ++fails;
     }
     // ---- mode Z (factored first: Z is overwritten in place only when it succeeds) ----
-    if (cholesky_hadamard<R>(GX, GY, Gm, dg, dl)) {
+    if (cholesky_hadamard<R>(GX, GY, Gm, dg, dl, &s_flag)) {
       for (int idx = threadIdx.x; idx < tt * R; idx += blockDim.x) {
         const int ab = idx / R, r = idx % R;
         P[idx] = X[(ab / t) * R + r] * Y[(ab % t) * R + r];      // Khatri-Rao of X and Y
