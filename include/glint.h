@@ -335,6 +335,24 @@ glint_status glint_query_trilinear(const glint_factors* f, int64_t nq, const flo
 glint_status glint_sample(const glint_factors* f, int64_t n, const int32_t* uvl, const float* rnd,
                           float* h, float* pdf, int32_t* bins, hipStream_t stream);
 
+/* Environment-light prefiltering (Sec. 5.4, compact-eps support and the box
+ * side Q): for lookup i with footprint uvl[i] = (u, v, l), projected half
+ * vector h[i] = (h_s, h_t) in [-1, 1]^2 and the spherical-Gaussian light
+ * lobe sg[i] = (lambda, A) chosen for it, theta = arccos(clamp((ln eps -
+ * ln A) / lambda + 1, -1, 1)) (FP64) and the square of side
+ * w = min(2 theta / pi, 2) (N theta / pi bins) centred on h gives the bins
+ * lo = clamp(floor((h - w/2 + 1) N/2), 0, N-1),
+ * hi = clamp(floor((h + w/2 + 1) N/2), 0, N-1) + 1 per axis (at least one
+ * bin: a zero-width box is the point lookup of the bin holding h).  The
+ * records are written to q [n][7] (the glint_query layout, for reuse, e.g.
+ * by the backward), and out[i] = the box sum / its number of bins, the
+ * average bin mass.  A non-finite h component counts as 0; a lobe whose
+ * argument is not finite (lambda = 0, A <= 0) gives the point lookup.  eps
+ * (0.3 in the paper) must be finite and positive.  Other rules as
+ * glint_query. */
+glint_status glint_query_sg(const glint_factors* f, int64_t n, const int32_t* uvl, const float* h,
+                            const float* sg, float eps, int32_t* q, float* out, hipStream_t stream);
+
 /* ---- step 6: gradient of the query (not in the paper) -------------------- */
 
 /* Gradients of sum_i gout[i] * q[i] with respect to the stored values of U,

@@ -109,6 +109,7 @@ _SIGS = {
     "glint_cp_als_clustered": (_I32, [_DESC, _CDESC, _P, _I32, _I32, _U64, _P, _P, _P, _P, _P, _P]),
     "glint_make_cumulative_batched": (_I32, [_I64, _I32, _I32, _P, _P, _P]),
     "glint_query_clustered": (_I32, [_CLU, _I64, _P, _P, _P]),
+    "glint_query_sg": (_I32, [_FAC, _I64, _P, _P, _P, _F32, _P, _P, _P]),
 }
 
 
@@ -373,4 +374,14 @@ def glint_make_cumulative_batched(S, C, stream=None):
 def glint_query_clustered(f: Clustered, q, out, stream=None):
     _check("glint_query_clustered", lib().glint_query_clustered(
         ctypes.byref(f), q.shape[0], _ptr(q, torch.int32, "q"), _ptr(out, torch.float32, "out"),
+        _stream(stream)))
+
+
+def glint_query_sg(f: Factors, uvl, h, sg, eps, q, out, stream=None):
+    n = uvl.shape[0]
+    if tuple(h.shape) != (n, 2) or tuple(sg.shape) != (n, 2) or tuple(q.shape) != (n, 7) or out.shape[0] != n:
+        raise ValueError("shapes: uvl [n][3], h [n][2], sg [n][2] (lambda, A), q [n][7], out [n]")
+    _check("glint_query_sg", lib().glint_query_sg(
+        ctypes.byref(f), n, _ptr(uvl, torch.int32, "uvl"), _ptr(h, torch.float32, "h"),
+        _ptr(sg, torch.float32, "sg"), float(eps), _ptr(q, torch.int32, "q"), _ptr(out, torch.float32, "out"),
         _stream(stream)))

@@ -221,6 +221,19 @@ def sample(tables: QueryTables, uvl, rnd):
     return h, pdf, bins
 
 
+def query_sg(tables: QueryTables, uvl, h, sg, eps: float = 0.3):
+    """Environment-light prefiltered lookups (Sec. 5.4): the average bin mass
+    over each lookup's compact-eps box; returns (average [n], records [n][7])."""
+    uvl = _dev(uvl, torch.int32)
+    h = _dev(h, torch.float32)
+    sg = _dev(sg, torch.float32)
+    n = uvl.shape[0]
+    q = torch.empty((n, 7), dtype=torch.int32, device=_DEV)
+    out = torch.empty(n, dtype=torch.float32, device=_DEV)
+    L.glint_query_sg(tables.factors(), uvl, h, sg, eps, q, out)
+    return out, q
+
+
 def query_backward(tables: QueryTables, q, gout):
     """Gradients (dU, dV, dL, dCS, dCT) of sum gout * q w.r.t. the stored tables."""
     R = tables.R

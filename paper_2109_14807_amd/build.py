@@ -20,7 +20,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libglint.so")
 
-SOURCES = ["abi_common.cpp", "ndf.hip", "query.hip", "cp_als.hip", "refine.hip", "cluster.hip"]
+SOURCES = ["abi_common.cpp", "ndf.hip", "query.hip", "cp_als.hip", "refine.hip", "cluster.hip", "frontends.hip"]
 
 FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",

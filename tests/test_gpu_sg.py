@@ -1,0 +1,135 @@
+"""GPU parity: environment-light prefiltered lookups (Sec. 5.4) against the
+FP64 oracle - the compact-eps box records and the averaged range query."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+from oracle import query, sg
+
+pytestmark = pytest.mark.gpu
+
+import paper_2109_14807_amd as G  # noqa: E402
+
+TOL = 1e-5     # FP32 query vs FP64: |avg_gpu - avg_64| <= TOL * N_q / bins
+
+
+def _lookups(rng, n, nu, nv, nl):
+    uvl = np.stack([rng.integers(0, nu, n), rng.integers(0, nv, n), rng.integers(0, nl, n)], axis=1)
+    h = rng.uniform(-1.05, 1.05, (n, 2))
+    lam = np.exp(rng.uniform(np.log(1.0), np.log(3000.0), n))
+    amp = rng.uniform(0.05, 20.0, n)
+    return uvl.astype(np.int32), h.astype(np.float32), np.stack([lam, amp], 1).astype(np.float32)
+
+
+def _edge_ok(got, want, h, theta, N):
+    """Records may differ only where the FP64 continuous bin coordinate is
+    within rounding of an integer (the two sides' log/acos differ by an ulp)."""
+    w = np.minimum(2.0 * theta / math.pi, 2.0)
+    for col, (hh, sign) in ((3, (0, -1)), (4, (0, 1)), (5, (1, -1)), (6, (1, 1))):
+        x = (h[:, hh].astype(np.float64) + sign * 0.5 * w + 1.0) * (N / 2.0)
+        diff = got[:, col] != want[:, col]
+        near = np.abs(x - np.round(x)) < 1e-9
+        assert np.all(~diff | near), (col, int((diff & ~near).sum()))
+        assert np.all(np.abs(got[:, col] - want[:, col]) <= 1)
+
+
+@pytest.mark.parametrize("R,dtype", [(16, "f32"), (64, "bf16"), (256, "fp8")])
+def test_query_sg_matches_oracle(R, dtype):
+    rng = np.random.default_rng(500 + R)
+    nu, nv, nl, N = 24, 17, 5, 64
+    F = [rng.standard_normal((nu, R)) * 0.5, rng.standard_normal((nv, R)) * 0.5, rng.standard_normal((nl, R)),
+         np.abs(rng.standard_normal((N, R))) * 0.2, np.abs(rng.standard_normal((N, R))) * 0.2]
+    tabs = G.make_tables(*F, dtype=dtype, cum_dtype="f32" if dtype == "f32" else "bf16")
+    n = 20000
+    uvl, h, sgp = _lookups(rng, n, nu, nv, nl)
+    got, q = G.query_sg(tabs, torch.from_numpy(uvl), torch.from_numpy(h), torch.from_numpy(sgp))
+    got, q = got.cpu().numpy().astype(np.float64), q.cpu().numpy()
+    want_q = sg.sg_records(uvl, h.astype(np.float64), sgp[:, 0].astype(np.float64), sgp[:, 1].astype(np.float64), N)
+    theta = sg.support_angle(sgp[:, 0].astype(np.float64), sgp[:, 1].astype(np.float64))
+    _edge_ok(q, want_q, h, theta, N)
+    # the averages on the records the GPU formed, against the oracle on the stored tables
+    vals = [t.float().cpu().numpy().astype(np.float64) if t.dtype != torch.float8_e4m3fn else None
+            for t in (tabs.U, tabs.V, tabs.L, tabs.CS, tabs.CT)]
+    if dtype == "fp8":
+        from oracle import quant
+        scale = np.ones(R)
+        for i, (t, s) in enumerate(zip((tabs.U, tabs.V, tabs.L), tabs.scales[:3])):
+            vals[i] = quant.fp8_decode(t.view(torch.uint8).cpu().numpy())
+            scale = scale * s.cpu().numpy().astype(np.float64)
+    else:
+        scale = None
+    area = (q[:, 4] - q[:, 3]) * (q[:, 6] - q[:, 5])
+    want = query.range_query(*vals, q, scale=scale) / area
+    mag = query.range_query_magnitude(*vals, q, scale=scale) / area
+    err = np.abs(got - want)
+    assert np.all(err <= TOL * mag + 1e-30), float((err / np.maximum(mag, 1e-300)).max())
+    assert np.all(area >= 1)
+
+
+def test_query_sg_limits_and_invalid_lobes():
+    rng = np.random.default_rng(7)
+    nu, nv, nl, N, R = 4, 4, 2, 32, 16
+    F = [rng.random((nu, R)), rng.random((nv, R)), rng.random((nl, R)), rng.random((N, R)), rng.random((N, R))]
+    tabs = G.make_tables(*F)
+    T = np.einsum("ur,vr,lr,sr,tr->uvlst", *F)
+    uvl = np.array([[1, 2, 1]] * 6, dtype=np.int32)
+    h = np.array([[0.1, -0.2], [0.1, -0.2], [0.0, 0.0], [np.nan, 0.5], [0.3, np.inf], [-1.0, 0.99]], dtype=np.float32)
+    sgp = np.array([[50.0, 0.3],       # A = eps: point lookup
+                    [0.5, 1e6],        # support beyond pi: the whole image
+                    [0.0, 5.0],        # lambda = 0: point lookup
+                    [10.0, 2.0],       # NaN half vector counts as 0
+                    [10.0, -1.0],      # A <= 0: point lookup; infinite h counts as 0
+                    [100.0, 0.1]],     # below eps: point lookup
+                   dtype=np.float32)
+    got, q = G.query_sg(tabs, torch.from_numpy(uvl), torch.from_numpy(h), torch.from_numpy(sgp))
+    got, q = got.cpu().numpy(), q.cpu().numpy()
+    assert list(q[0, 3:]) == [17, 18, 12, 13]                      # bins holding (0.1, -0.2)
+    lo, hi = sg.box_bins(np.array([0.1, -0.2], dtype=np.float32).astype(np.float64), np.array([math.pi] * 2), N)
+    assert list(q[1, 3:]) == [lo[0], hi[0], lo[1], hi[1]] == [1, 32, 0, 29]   # the whole image, centred on h
+    assert list(q[2, 3:]) == [16, 17, 16, 17]
+    th = sg.support_angle(10.0, 2.0)
+    lo, hi = sg.box_bins(np.array([0.0, 0.5]), np.array([th, th]), N)
+    assert list(q[3, 3:]) == [lo[0], hi[0], lo[1], hi[1]]
+    assert list(q[4, 3:]) == [20, 21, 16, 17]
+    assert list(q[5, 3:]) == [0, 1, 31, 32]
+    for i in range(6):
+        u, v, l, slo, shi, tlo, thi = q[i]
+        want = T[u, v, l, slo:shi, tlo:thi].mean()
+        assert abs(got[i] - want) <= 1e-5 * T.max()
+    with pytest.raises(G.GlintError):
+        G.query_sg(tabs, torch.from_numpy(uvl), torch.from_numpy(h), torch.from_numpy(sgp), eps=0.0)
+    empty, qe = G.query_sg(tabs, torch.zeros((0, 3), dtype=torch.int32), torch.zeros((0, 2)), torch.zeros((0, 2)))
+    assert empty.numel() == 0 and qe.shape == (0, 7)
+
+
+def test_query_sg_full_size_c2_sampled():
+    """The 512x512 rank-64 FP32 table shape with one SG lookup per pixel of a
+    1920x1080 frame (lobes lambda logU[10, 1000], A U[1, 10]): 10^4 sampled
+    outputs against the oracle on the same records."""
+    cfg = gen.config("c2")
+    rng = np.random.default_rng(11)
+    R, N = cfg.rank, cfg.nbins
+    F = [rng.random((cfg.nu, R)) * 0.1, rng.random((cfg.nv, R)) * 0.1, rng.random((cfg.nlevels, R)),
+         rng.random((N, R)) * 0.05, rng.random((N, R)) * 0.05]
+    tabs = G.make_tables(*F)
+    n = 1920 * 1080
+    uvl = np.stack([rng.integers(0, cfg.nu, n), rng.integers(0, cfg.nv, n), rng.integers(0, cfg.nlevels, n)], 1)
+    h = rng.uniform(-0.6, 0.6, (n, 2)).astype(np.float32)
+    lam = np.exp(rng.uniform(np.log(10.0), np.log(1000.0), n))
+    sgp = np.stack([lam, rng.uniform(1.0, 10.0, n)], 1).astype(np.float32)
+    got, q = G.query_sg(tabs, torch.from_numpy(uvl.astype(np.int32)), torch.from_numpy(h), torch.from_numpy(sgp))
+    got, q = got.cpu().numpy().astype(np.float64), q.cpu().numpy()
+    idx = rng.choice(n, 10000, replace=False)
+    vals = [np.asarray(x, dtype=np.float32).astype(np.float64) for x in F[:3]] + \
+        [query.cumulative(x).astype(np.float32).astype(np.float64) for x in F[3:]]
+    qs = q[idx]
+    area = (qs[:, 4] - qs[:, 3]) * (qs[:, 6] - qs[:, 5])
+    want = query.range_query(*vals, qs) / area
+    mag = query.range_query_magnitude(*vals, qs) / area
+    assert np.all(np.abs(got[idx] - want) <= TOL * mag + 1e-30)
+    want_q = sg.sg_records(uvl[idx], h[idx].astype(np.float64), sgp[idx, 0].astype(np.float64),
+                           sgp[idx, 1].astype(np.float64), N)
+    _edge_ok(qs, want_q, h[idx], sg.support_angle(sgp[idx, 0].astype(np.float64), sgp[idx, 1].astype(np.float64)), N)
