@@ -23,6 +23,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -250,7 +251,16 @@ def main():
     s_pdf = torch.empty(npix, dtype=torch.float32, device=dev)
     s_bins = torch.empty((npix, 2), dtype=torch.int32, device=dev)
     sample_ms = timed(lambda: L.glint_sample(fac, s_uvl, s_rnd, s_h, s_pdf, s_bins))
-    del s_uvl, s_rnd, s_h, s_pdf, s_bins
+    # environment-light prefiltering: one SG lobe per pixel footprint (lambda logU[10, 1000],
+    # A U[1, 10]) around a half vector near the footprint's normals
+    gsg = torch.Generator(device=dev).manual_seed(6)
+    sg_h = (torch.rand((npix, 2), device=dev, generator=gsg) * 1.2 - 0.6).contiguous()
+    sg_p = torch.stack([torch.exp(math.log(10.0) + torch.rand(npix, device=dev, generator=gsg) * math.log(100.0)),
+                        1.0 + 9.0 * torch.rand(npix, device=dev, generator=gsg)], 1).contiguous()
+    sg_q = torch.empty((npix, 7), dtype=torch.int32, device=dev)
+    sg_out = torch.empty(npix, dtype=torch.float32, device=dev)
+    sg_ms = timed(lambda: L.glint_query_sg(fac, s_uvl, sg_h, sg_p, 0.3, sg_q, sg_out))
+    del s_uvl, s_rnd, s_h, s_pdf, s_bins, sg_h, sg_p, sg_q, sg_out
 
     ncells = cfg.nu * cfg.nv * nl
     t_elems = ncells * N * N
@@ -309,6 +319,11 @@ def main():
             "kernel": f"k_sample<float,float,64,4>: one hierarchical NDF importance sample ({levels} levels of "
                       "four-quad range queries) per pixel footprint of the frame",
             "samples": npix, "ms": sample_ms, "samples_per_s": npix / (sample_ms * 1e-3),
+        },
+        "sg_prefilter_kernel": {
+            "kernel": "glint_query_sg: k_sg_records + k_query<float,float,64,4> + k_box_average, one "
+                      "compact-eps SG box per pixel footprint of the frame, averaged",
+            "lookups": npix, "ms": sg_ms, "lookups_per_s": npix / (sg_ms * 1e-3),
         },
         "stages_ms": stage_ms,
         "events_ms_per_step": ev_total,
