@@ -24,6 +24,8 @@ query   summed-area (cumulative) tables (Sec. 4.4), point query (Sec. 4.3,
 sampling  hierarchical NDF importance sampling by range queries (Sec. 5.2).
 sg      environment-light prefiltering (Sec. 5.4): the compact-eps support of
         a spherical-Gaussian lobe as an angular box, averaged by range query.
+wang    constant-storage synthesis with Wang tiles (Sec. 5.5): hashed edge
+        colours, per-tile tensors with margins, sums over overlapped tiles.
 quant   BF16 and FP8 (OCP E4M3FN) rounding with per-column scales.
 adam    one Adam step (refinement of the factors; not in the paper).
 

@@ -22,6 +22,9 @@ Readings where the paper is silent:
   * Bin index of a value on an edge goes to the upper bin:
     i0 = clamp(floor((n + 1) * N / 2), 0, N - 1) evaluated in FP64.
   * Every bin is evaluated (no truncation window).
+  * A texel whose normal has a non-finite component is absent: it puts no
+    mass anywhere (the footprint weight stays 1/k^2).  Wang tiles use this
+    for the margin around a tile (Sec. 5.5).
 """
 from __future__ import annotations
 
@@ -67,11 +70,14 @@ def axis_norm(n, sigma):
 
 
 def axis_masses(n, nbins: int, sigma: float) -> np.ndarray:
-    """Normalised bin masses for every value of ``n``: shape n.shape + (nbins,)."""
+    """Normalised bin masses for every value of ``n``: shape n.shape + (nbins,).
+    A non-finite component marks an absent texel: all its masses are zero."""
     n = np.asarray(n, dtype=np.float64)[..., None]
+    ok = np.isfinite(n)
+    n = np.where(ok, n, 0.0)
     e = bin_edges(nbins)
     m = gauss_interval((e[:-1] - n) / sigma, (e[1:] - n) / sigma)
-    return m / axis_norm(n, sigma)
+    return np.where(ok, m / axis_norm(n, sigma), 0.0)
 
 
 def texel_masses(nxy: np.ndarray, nbins: int, sigma: float):
@@ -141,11 +147,12 @@ def range_bruteforce(nxy: np.ndarray, nbins: int, sigma: float, nlevels: int,
         xs = np.mod(u + footprint_offsets(k), nu)
         ys = np.mod(v + footprint_offsets(k), nv)
         n = nxy[np.ix_(xs, ys)]                       # [k][k][2]
-        nx = n[..., 0]
-        ny = n[..., 1]
+        present = np.isfinite(n[..., 0]) & np.isfinite(n[..., 1])     # absent texels contribute 0
+        nx = np.where(present, n[..., 0], 0.0)
+        ny = np.where(present, n[..., 1], 0.0)
         Ms = gauss_interval((e[slo] - nx) / sigma, (e[shi] - nx) / sigma) / axis_norm(nx, sigma)
         Mt = gauss_interval((e[tlo] - ny) / sigma, (e[thi] - ny) / sigma) / axis_norm(ny, sigma)
-        out[i] = float(np.sum(Ms * Mt)) / float(k * k)
+        out[i] = float(np.sum(np.where(present, Ms * Mt, 0.0))) / float(k * k)
     return out
 
 
