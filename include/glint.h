@@ -110,7 +110,11 @@ int32_t glint_window_radius(const glint_ndf_desc* desc);
  *   bins[(u*nv + v)*2 + a] = i0 = clamp(floor((n + 1) * N/2), 0, N-1), in FP64;
  *   mass[((u*nv + v)*2 + a)*(2K+1) + j] = normalised mass of bin i0 - K + j
  *     (0 where that bin is outside [0, N)).
- * nxy: [nu][nv][2] float32 projected normals.  bins: int32, mass: double. */
+ * nxy: [nu][nv][2] float32 projected normals.  bins: int32, mass: double.
+ * A non-finite component marks the axis of an absent texel: bin 0 and all
+ * masses 0, so the texel contributes nothing to the tensor, the range
+ * integrals or the texel-space ALS (Wang tiles pad a tile with absent texels,
+ * Sec. 5.5). */
 glint_status glint_texel_bins(const glint_ndf_desc* desc, const float* nxy,
                               int32_t* bins, double* mass, hipStream_t stream);
 
@@ -352,6 +356,39 @@ glint_status glint_sample(const glint_factors* f, int64_t n, const int32_t* uvl,
  * glint_query. */
 glint_status glint_query_sg(const glint_factors* f, int64_t n, const int32_t* uvl, const float* h,
                             const float* sg, float eps, int32_t* q, float* out, hipStream_t stream);
+
+/* Wang tiles (Sec. 5.5): constant-storage synthesis of an unbounded normal
+ * map.  The plane is a grid of S x S cells; cell (i, j) holds the plane
+ * texels x in [iS, (i+1)S), y in [jS, (j+1)S).  Vertex (i, j) colours the
+ * edge to its right (e = 0) and the edge below it (e = 1) with
+ * colour = [SplitMix64 U[0,1) >= 1/2] at counter
+ * ((((i mod 2^32) << 32) | (j mod 2^32)) << 1) | e (the generator of
+ * glint_cp_als_clustered, seeded with `seed`); cell (i, j)'s tile is
+ * edge_to_tile[8 top + 4 right + 2 bottom + left] with top = (i, j, 0),
+ * right = (i+1, j, 1), bottom = (i, j+1, 0), left = (i, j, 1).  Each tile's
+ * tables are a CP of the tensor of the tile padded with m absent texels
+ * (non-finite normals, see glint_texel_bins) on every side: P = S + 2m rows
+ * of U and V, padded index = tile index + m.  FP32 tables, stacked by tile:
+ * U, V [ntiles][P][R], L [ntiles][nl][R], CS, CT [ntiles][N+1][R]. */
+typedef struct {
+  int32_t ntiles, S, m, R, nl, nbins;
+  uint64_t seed;
+  uint8_t edge_to_tile[16];   /* host copy, values < ntiles */
+  const float* U;
+  const float* V;
+  const float* L;
+  const float* CS;
+  const float* CT;
+} glint_wang;
+
+/* Range queries on the synthesized plane: q [nq][7] = (x, y, l, s_lo, s_hi,
+ * t_lo, t_hi) with plane texel coordinates (any int32, no wrap); l and the
+ * bins clamp as for glint_query; out[i] = the sum, over the cells the level-l
+ * footprint centred on (x, y) overlaps, of that cell's tile query at centre
+ * (x - iS + m, y - jS + m).  Requires 2m >= 2^(nl-1) so every overlapped
+ * cell's centre lies in its tile's padded grid.  One thread per query, FP32. */
+glint_status glint_query_wang(const glint_wang* w, int64_t nq, const int32_t* q, float* out,
+                              hipStream_t stream);
 
 /* ---- step 6: gradient of the query (not in the paper) -------------------- */
 

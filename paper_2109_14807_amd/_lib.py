@@ -66,6 +66,14 @@ class Clustered(ctypes.Structure):
                 ("Z", ctypes.c_void_p)]
 
 
+class Wang(ctypes.Structure):
+    _fields_ = [("ntiles", ctypes.c_int32), ("S", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("R", ctypes.c_int32), ("nl", ctypes.c_int32), ("nbins", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("edge_to_tile", ctypes.c_uint8 * 16),
+                ("U", ctypes.c_void_p), ("V", ctypes.c_void_p), ("L", ctypes.c_void_p),
+                ("CS", ctypes.c_void_p), ("CT", ctypes.c_void_p)]
+
+
 _LIB = None
 
 _P = ctypes.c_void_p
@@ -110,6 +118,7 @@ _SIGS = {
     "glint_make_cumulative_batched": (_I32, [_I64, _I32, _I32, _P, _P, _P]),
     "glint_query_clustered": (_I32, [_CLU, _I64, _P, _P, _P]),
     "glint_query_sg": (_I32, [_FAC, _I64, _P, _P, _P, _F32, _P, _P, _P]),
+    "glint_query_wang": (_I32, [ctypes.POINTER(Wang), _I64, _P, _P, _P]),
 }
 
 
@@ -385,3 +394,8 @@ def glint_query_sg(f: Factors, uvl, h, sg, eps, q, out, stream=None):
         ctypes.byref(f), n, _ptr(uvl, torch.int32, "uvl"), _ptr(h, torch.float32, "h"),
         _ptr(sg, torch.float32, "sg"), float(eps), _ptr(q, torch.int32, "q"), _ptr(out, torch.float32, "out"),
         _stream(stream)))
+
+
+def glint_query_wang(w: Wang, q, out, stream=None):
+    _check("glint_query_wang", lib().glint_query_wang(
+        ctypes.byref(w), q.shape[0], _ptr(q, torch.int32, "q"), _ptr(out, torch.float32, "out"), _stream(stream)))

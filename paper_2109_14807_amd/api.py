@@ -6,6 +6,7 @@ kernels.
 """
 from __future__ import annotations
 
+import ctypes
 import dataclasses
 
 import numpy as np
@@ -320,4 +321,50 @@ def query_clustered(tab: ClusteredTables, q, out=None):
     q = _dev(q, torch.int32)
     out = torch.empty(q.shape[0], dtype=torch.float32, device=_DEV) if out is None else out
     L.glint_query_clustered(tab.struct(), q, out)
+    return out
+
+
+@dataclasses.dataclass
+class WangTables:
+    """Per-tile CP tables of a Wang-tile set (Sec. 5.5), FP32 on the device,
+    stacked by tile: U, V [ntiles][S+2m][R], L [ntiles][nl][R],
+    CS, CT [ntiles][N+1][R]."""
+    S: int
+    m: int
+    seed: int
+    edge_to_tile: tuple
+    U: torch.Tensor
+    V: torch.Tensor
+    L: torch.Tensor
+    CS: torch.Tensor
+    CT: torch.Tensor
+
+    def struct(self) -> L.Wang:
+        ntiles, _, R = self.U.shape
+        etl = (ctypes.c_uint8 * 16)(*[int(e) for e in self.edge_to_tile])
+        return L.Wang(ntiles, self.S, self.m, R, self.L.shape[1], self.CS.shape[1] - 1, int(self.seed) & ((1 << 64) - 1),
+                      etl, L._ptr(self.U, torch.float32, "U"), L._ptr(self.V, torch.float32, "V"),
+                      L._ptr(self.L, torch.float32, "L"), L._ptr(self.CS, torch.float32, "CS"),
+                      L._ptr(self.CT, torch.float32, "CT"))
+
+
+def wang_tables(tile_factors, S: int, m: int, seed: int, edge_to_tile) -> WangTables:
+    """Stack the CP factors (U, V, L, S, T) of every tile (each fitted on the
+    tile padded with m absent texels) into query tables."""
+    def stack(i):
+        return torch.stack([_dev(f[i], torch.float64).float() for f in tile_factors]).contiguous()
+    U, V, Lf, Sf, Tf = (stack(i) for i in range(5))
+    ntiles, N, R = Sf.shape
+    CS = torch.empty((ntiles, N + 1, R), dtype=torch.float32, device=_DEV)
+    CT = torch.empty((ntiles, N + 1, R), dtype=torch.float32, device=_DEV)
+    L.glint_make_cumulative_batched(Sf, CS)
+    L.glint_make_cumulative_batched(Tf, CT)
+    return WangTables(int(S), int(m), int(seed), tuple(int(e) for e in edge_to_tile), U, V, Lf, CS, CT)
+
+
+def query_wang(tab: WangTables, q, out=None):
+    """Range queries at plane coordinates on the Wang-tile synthesized map."""
+    q = _dev(q, torch.int32)
+    out = torch.empty(q.shape[0], dtype=torch.float32, device=_DEV) if out is None else out
+    L.glint_query_wang(tab.struct(), q, out)
     return out

@@ -52,16 +52,6 @@ __device__ __forceinline__ f64x4 mfma64(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// SplitMix64 (Steele, Lea and Flood) as a counter-based generator: the
-// (counter+1)-th output of the generator seeded with `seed`, as U[0, 1).
-__device__ __forceinline__ double sm64_uniform(uint64_t seed, uint64_t counter) {
-  uint64_t z = seed + (counter + 1) * 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  z ^= z >> 31;
-  return static_cast<double>(z >> 11) * (1.0 / 9007199254740992.0);
-}
-
 struct ClusterArgs {
   const void* T;
   int nu, nv, nl, N;
@@ -438,13 +428,13 @@ __device__ __noinline__ void als_one(const ClusterArgs& c, int tensor) {
   const uint64_t rows_max = t > L ? t : L;
   for (int i = threadIdx.x; i < t * R; i += blockDim.x) {
     const uint64_t row = i / R, r = i % R;
-    X[i] = sm64_uniform(c.seed, ((static_cast<uint64_t>(tensor) * 3 + 0) * rows_max + row) * R + r);
-    Y[i] = sm64_uniform(c.seed, ((static_cast<uint64_t>(tensor) * 3 + 1) * rows_max + row) * R + r);
+    X[i] = glint_sm64_uniform(c.seed, ((static_cast<uint64_t>(tensor) * 3 + 0) * rows_max + row) * R + r);
+    Y[i] = glint_sm64_uniform(c.seed, ((static_cast<uint64_t>(tensor) * 3 + 1) * rows_max + row) * R + r);
   }
   for (int i = threadIdx.x; i < Lc * R; i += blockDim.x) {
     const int j = i / R, r = i % R;
     const uint64_t row = static_cast<uint64_t>(keep[j]);
-    Z[j * ZS + r] = sm64_uniform(c.seed, ((static_cast<uint64_t>(tensor) * 3 + 2) * rows_max + row) * R + r);
+    Z[j * ZS + r] = glint_sm64_uniform(c.seed, ((static_cast<uint64_t>(tensor) * 3 + 2) * rows_max + row) * R + r);
   }
   if (threadIdx.x < R) lam[threadIdx.x] = 1.0;
   __syncthreads();

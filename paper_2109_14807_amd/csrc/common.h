@@ -146,6 +146,16 @@ __device__ __forceinline__ float glint_group_sum(float v) {
   return v;
 }
 
+// SplitMix64 (Steele, Lea and Flood) used as a counter-based generator: the
+// (counter+1)-th output of the generator seeded with `seed`, as U[0, 1).
+__device__ __forceinline__ double glint_sm64_uniform(uint64_t seed, uint64_t counter) {
+  uint64_t z = seed + (counter + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return static_cast<double>(z >> 11) * (1.0 / 9007199254740992.0);
+}
+
 __device__ __forceinline__ double glint_wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);

@@ -1,5 +1,11 @@
 // Query front-ends built on the range query.
 //
+// Wang tiles (Sec. 5.5): the plane is a grid of S x S cells whose tiles come
+// from hashed vertex edge colours and an edge-to-tile map, with no index map;
+// each tile's CP covers footprint centres reaching m texels past the tile,
+// with only the tile's texels contributing, so a footprint's range query is
+// the sum of its overlapped cells' tile queries at its local centre.
+//
 // Environment-light prefiltering (Sec. 5.4): a spherical-Gaussian light lobe
 // G(w) = A exp(lambda (cos w - 1)) exceeds eps exactly within its compact-eps
 // support angle theta = arccos((ln eps - ln A) / lambda + 1); the NDF is
@@ -61,9 +67,98 @@ __global__ __launch_bounds__(kSgThreads) void k_box_average(int64_t n, const int
   out[i] = out[i] / static_cast<float>(area);
 }
 
+// ---- Wang tiles ------------------------------------------------------------
+
+constexpr int kWangThreads = 256;
+
+struct WangArgs {
+  int ntiles, S, m, P, R, nl, N;
+  uint64_t seed;
+  uint8_t etl[16];
+  const float* U;
+  const float* V;
+  const float* L;
+  const float* CS;
+  const float* CT;
+  int64_t nq;
+  const int32_t* q;
+  float* out;
+};
+
+__device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b) {
+  return a >= 0 ? a / b : -((-a + b - 1) / b);
+}
+
+// colour of the edge to the right of vertex (i, j) (e = 0) or below it (e = 1)
+__device__ __forceinline__ int edge_colour(uint64_t seed, int64_t i, int64_t j, int e) {
+  const uint64_t c = ((((static_cast<uint64_t>(i) & 0xFFFFFFFFull) << 32) | (static_cast<uint64_t>(j) & 0xFFFFFFFFull))
+                      << 1) | static_cast<uint64_t>(e);
+  return glint_sm64_uniform(seed, c) >= 0.5 ? 1 : 0;
+}
+
+// one query per thread: the footprint's cells, each cell's tile, its CP query
+__global__ __launch_bounds__(kWangThreads) void k_query_wang(WangArgs a) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.nq) return;
+  const int32_t* r = a.q + 7 * i;
+  const int64_t x = r[0], y = r[1];
+  const int l = glint_clampi(r[2], 0, a.nl - 1);
+  const int slo = glint_clampi(r[3], 0, a.N), shi = glint_clampi(r[4], 0, a.N);
+  const int tlo = glint_clampi(r[5], 0, a.N), thi = glint_clampi(r[6], 0, a.N);
+  float acc = 0.0f;
+  if (slo < shi && tlo < thi) {
+    const int64_t k = int64_t{1} << l;
+    const int64_t x0 = x - k / 2, y0 = y - k / 2;
+    const int64_t ci0 = floor_div(x0, a.S), ci1 = floor_div(x0 + k - 1, a.S);
+    const int64_t cj0 = floor_div(y0, a.S), cj1 = floor_div(y0 + k - 1, a.S);
+    for (int64_t ci = ci0; ci <= ci1; ++ci) {
+      for (int64_t cj = cj0; cj <= cj1; ++cj) {
+        const int top = edge_colour(a.seed, ci, cj, 0), left = edge_colour(a.seed, ci, cj, 1);
+        const int right = edge_colour(a.seed, ci + 1, cj, 1), bottom = edge_colour(a.seed, ci, cj + 1, 0);
+        const int tile = a.etl[8 * top + 4 * right + 2 * bottom + left];
+        const int lu = static_cast<int>(x - ci * a.S + a.m), lv = static_cast<int>(y - cj * a.S + a.m);
+        const float* U = a.U + (static_cast<int64_t>(tile) * a.P + lu) * a.R;
+        const float* V = a.V + (static_cast<int64_t>(tile) * a.P + lv) * a.R;
+        const float* L = a.L + (static_cast<int64_t>(tile) * a.nl + l) * a.R;
+        const float* CS = a.CS + static_cast<int64_t>(tile) * (a.N + 1) * a.R;
+        const float* CT = a.CT + static_cast<int64_t>(tile) * (a.N + 1) * a.R;
+        for (int rr = 0; rr < a.R; ++rr)
+          acc += U[rr] * V[rr] * L[rr] * (CS[shi * a.R + rr] - CS[slo * a.R + rr]) *
+                 (CT[thi * a.R + rr] - CT[tlo * a.R + rr]);
+      }
+    }
+  }
+  a.out[i] = acc;
+}
+
 }  // namespace
 
 extern "C" {
+
+glint_status glint_query_wang(const glint_wang* w, int64_t nq, const int32_t* q, float* out, hipStream_t stream) {
+  GLINT_REQUIRE(w != nullptr, "tile set is NULL");
+  GLINT_REQUIRE(w->ntiles >= 1 && w->ntiles <= 256, "ntiles must be in [1, 256]");
+  GLINT_REQUIRE(w->S >= 1 && w->m >= 0 && w->R >= 1 && w->nl >= 1 && w->nl <= 24 && w->nbins >= 1,
+                "bad tile-set sizes");
+  GLINT_REQUIRE((int64_t{1} << (w->nl - 1)) <= 2 * static_cast<int64_t>(w->m),
+                "the margin m must be at least half the largest footprint (2m >= 2^(nl-1))");
+  for (int c = 0; c < 16; ++c)
+    GLINT_REQUIRE(w->edge_to_tile[c] < w->ntiles, "edge_to_tile[%d] = %d is not a tile", c, w->edge_to_tile[c]);
+  GLINT_REQUIRE(nq >= 0, "nq must be >= 0");
+  if (nq == 0) return GLINT_OK;
+  GLINT_REQUIRE(w->U && w->V && w->L && w->CS && w->CT && q && out, "null pointer argument");
+  WangArgs a;
+  a.ntiles = w->ntiles; a.S = w->S; a.m = w->m; a.P = w->S + 2 * w->m; a.R = w->R; a.nl = w->nl; a.N = w->nbins;
+  a.seed = w->seed;
+  for (int c = 0; c < 16; ++c) a.etl[c] = w->edge_to_tile[c];
+  a.U = w->U; a.V = w->V; a.L = w->L; a.CS = w->CS; a.CT = w->CT; a.nq = nq; a.q = q; a.out = out;
+  glint_clear_launch_error();
+  hipLaunchKernelGGL(k_query_wang, dim3(static_cast<unsigned>((nq + kWangThreads - 1) / kWangThreads)),
+                     dim3(kWangThreads), 0, stream, a);
+  GLINT_LAUNCHED("k_query_wang");
+  return GLINT_OK;
+}
+
 
 glint_status glint_query_sg(const glint_factors* f, int64_t n, const int32_t* uvl, const float* h,
                             const float* sg, float eps, int32_t* q, float* out, hipStream_t stream) {

@@ -28,14 +28,19 @@ __global__ __launch_bounds__(256) void k_texel_bins(const float* __restrict__ nx
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= n2) return;
   const double n = static_cast<double>(nxy[idx]);
+  const int P = 2 * K + 1;
+  double* out = mass + idx * P;
+  if (!isfinite(n)) {                // absent texel: no mass on this axis (so none at all)
+    bins[idx] = 0;
+    for (int j = 0; j < P; ++j) out[j] = 0.0;
+    return;
+  }
   const double halfN = 0.5 * static_cast<double>(N);
   int i0 = static_cast<int>(floor((n + 1.0) * halfN));
   i0 = glint_clampi(i0, 0, N - 1);
   bins[idx] = i0;
   const double w = 2.0 / static_cast<double>(N);
   const double zn = glint_gauss_interval((-1.0 - n) / sigma, (1.0 - n) / sigma);
-  const int P = 2 * K + 1;
-  double* out = mass + idx * P;
   for (int j = 0; j < P; ++j) {
     const int i = i0 - K + j;
     double m = 0.0;
