@@ -179,6 +179,91 @@ __device__ __forceinline__ void cum_row(const LT* lds_tab, const CT* __restrict_
   else lds_cum_row<LT, RPL>(lds_tab + off, out);
 }
 
+// Rank layout of the forward kernels: a lane's RPL ranks are RPL / CHR
+// chunks of CHR ranks (CHR = one 16-byte word of the LDS summed-area rows),
+// chunk c of lane j of a group of LPQ at ranks c * LPQ * CHR + j * CHR.  The
+// lanes of a group then read consecutive words of a row, so one LDS
+// instruction covers whole rows of several queries without bank conflicts
+// (with contiguous multi-word slices every query's words fell on the same
+// banks), and a group's global gathers are contiguous.  Every table uses the
+// same layout; the query sums over all ranks, so which lane holds which rank
+// does not matter.  Odd groups visit their chunks rotated by one (chunk c at
+// position c - 1): the two 8-lane groups that share an LDS cycle at rank 64
+// then read different halves of the bank space.  Sums over a lane's ranks
+// add the chunk partials in the chunks' own order, so a result does not
+// depend on the group that computed it.
+template <typename FT, typename CT, int RPL>
+constexpr int chunk_ranks() {
+  // BF16 factor tables keep one contiguous slice per lane (measured faster
+  // for them; the chunked layout wins for FP32 and FP8 factor tables)
+  if constexpr (sizeof(FT) == 2) return RPL;
+  constexpr int w = 16 / static_cast<int>(sizeof(typename LdsCum<CT>::type));
+  return RPL < w ? RPL : w;
+}
+
+template <typename T, int RPL, int CHR, int STRIDE>
+__device__ __forceinline__ void load_chunks(const T* __restrict__ p, int rot, float* out) {
+#pragma unroll
+  for (int c = 0; c < RPL / CHR; ++c) {
+    const int cc = (c + rot) & (RPL / CHR - 1);
+    load_cum_row<T, CHR>(p + cc * STRIDE, out + c * CHR);
+  }
+}
+
+template <int RPL, int CHR, int STRIDE>
+__device__ __forceinline__ void lds_chunks(const float* p, int rot, float* out) {
+#pragma unroll
+  for (int c = 0; c < RPL / CHR; ++c) {
+    const int cc = (c + rot) & (RPL / CHR - 1);
+    lds_row<CHR>(p + cc * STRIDE, out + c * CHR);
+  }
+}
+
+template <bool GC, typename CT, typename LT, int RPL, int CHR, int STRIDE>
+__device__ __forceinline__ void cum_chunks(const LT* lds_tab, const CT* __restrict__ glob_tab, int off, int rot,
+                                           float* out) {
+#pragma unroll
+  for (int c = 0; c < RPL / CHR; ++c) {
+    const int cc = (c + rot) & (RPL / CHR - 1);
+    cum_row<GC, CT, LT, CHR>(lds_tab, glob_tab, off + cc * STRIDE, out + c * CHR);
+  }
+}
+
+// sum over a lane's ranks of W (sh - sl)(th - tl): per-chunk partials in
+// element order, combined by a tree whose value does not depend on the
+// rotation (two chunks: one commutative add; four: pairs (0,1) and (2,3) of
+// the chunks' own order; more: un-rotated first)
+template <int RPL, int CHR>
+__device__ __forceinline__ float lane_terms(const float* W, const float* sh, const float* sl, const float* th,
+                                            const float* tl, int rot) {
+  constexpr int NCH = RPL / CHR;
+  float p[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    float t = 0.0f;
+#pragma unroll
+    for (int i = 0; i < CHR; ++i) {
+      const int e = c * CHR + i;
+      t += W[e] * (sh[e] - sl[e]) * (th[e] - tl[e]);
+    }
+    p[c] = t;
+  }
+  if constexpr (NCH == 1) {
+    return p[0];
+  } else if constexpr (NCH == 2) {
+    return p[0] + p[1];
+  } else if constexpr (NCH == 4) {
+    // rotated by one, positions hold chunks (1, 2, 3, 0)
+    const float b = rot ? p[3] : p[1], c = rot ? p[1] : p[2], d = rot ? p[2] : p[3];
+    return (p[0] + b) + (c + d);
+  } else {
+    float acc = 0.0f;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) acc += rot ? p[(c + NCH - 1) % NCH] : p[c];
+    return acc;
+  }
+}
+
 // GC: the summed-area tables are too large for LDS and are read from global
 // memory (L2-resident); L stays in LDS.
 template <typename FT, typename CT, int R, int RPL, bool GC>
@@ -207,7 +292,10 @@ __global__ __launch_bounds__(kQueryThreads) void k_query(QueryArgs a) {
   const int lane = threadIdx.x & 63;
   const int g = lane / LPQ;
   const int j = lane % LPQ;
-  const int r0 = j * RPL;
+  constexpr int CHR = chunk_ranks<FT, CT, RPL>();
+  constexpr int STR = LPQ * CHR;
+  const int r0 = j * CHR;
+  const int rot = RPL / CHR > 1 ? (g & 1) : 0;
   // record slots: query g*LPQ + jj sits at g*(LPQ+1) + jj, so the groups' slots
   // do not share LDS banks when read back
   constexpr int kSlots = 64 + 64 / LPQ;
@@ -254,21 +342,19 @@ __global__ __launch_bounds__(kQueryThreads) void k_query(QueryArgs a) {
       const QueryRows r = wrows[g * (LPQ + 1) + jj];
       if (r.u != pu || r.v != pv || r.l != pl) {
         float uu[RPL], vv[RPL], lr[RPL];
-        load_row<FT, RPL>(U + r.u + r0, uu);
-        load_row<FT, RPL>(V + r.v + r0, vv);
-        lds_row<RPL>(Ls + r.l + r0, lr);
+        load_chunks<FT, RPL, CHR, STR>(U + r.u + r0, rot, uu);
+        load_chunks<FT, RPL, CHR, STR>(V + r.v + r0, rot, vv);
+        lds_chunks<RPL, CHR, STR>(Ls + r.l + r0, rot, lr);
 #pragma unroll
         for (int e = 0; e < RPL; ++e) W[e] = uu[e] * vv[e] * lr[e];
         pu = r.u; pv = r.v; pl = r.l;
       }
       float sh[RPL], sl[RPL], th[RPL], tl[RPL];
-      cum_row<GC, CT, LT, RPL>(CSs, CSg, r.sh + r0, sh);
-      cum_row<GC, CT, LT, RPL>(CSs, CSg, r.sl + r0, sl);
-      cum_row<GC, CT, LT, RPL>(CTs, CTg, r.th + r0, th);
-      cum_row<GC, CT, LT, RPL>(CTs, CTg, r.tl + r0, tl);
-      float acc = 0.0f;
-#pragma unroll
-      for (int e = 0; e < RPL; ++e) acc += W[e] * (sh[e] - sl[e]) * (th[e] - tl[e]);
+      cum_chunks<GC, CT, LT, RPL, CHR, STR>(CSs, CSg, r.sh + r0, rot, sh);
+      cum_chunks<GC, CT, LT, RPL, CHR, STR>(CSs, CSg, r.sl + r0, rot, sl);
+      cum_chunks<GC, CT, LT, RPL, CHR, STR>(CTs, CTg, r.th + r0, rot, th);
+      cum_chunks<GC, CT, LT, RPL, CHR, STR>(CTs, CTg, r.tl + r0, rot, tl);
+      float acc = lane_terms<RPL, CHR>(W, sh, sl, th, tl, rot);
       acc = glint_group_sum<LPQ>(acc);
       res = (j == jj) ? acc : res;
     }
@@ -322,7 +408,10 @@ __global__ __launch_bounds__(kQueryThreads) void k_query_grouped(GroupedArgs a) 
   const int lane = threadIdx.x & 63;
   const int g = lane / LPQ;
   const int j = lane % LPQ;
-  const int r0 = j * RPL;
+  constexpr int CHR = chunk_ranks<FT, CT, RPL>();
+  constexpr int STR = LPQ * CHR;
+  const int r0 = j * CHR;
+  const int rot = RPL / CHR > 1 ? (g & 1) : 0;
   const int K = a.K;
   int4* wpts = pts + (threadIdx.x >> 6) * 64;
   const int64_t wave = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
@@ -345,9 +434,9 @@ __global__ __launch_bounds__(kQueryThreads) void k_query_grouped(GroupedArgs a) 
       float W[RPL];
       {
         float uu[RPL], vv[RPL], lr[RPL];
-        load_row<FT, RPL>(U + pr.x + r0, uu);
-        load_row<FT, RPL>(V + pr.y + r0, vv);
-        lds_row<RPL>(Ls + pr.z + r0, lr);
+        load_chunks<FT, RPL, CHR, STR>(U + pr.x + r0, rot, uu);
+        load_chunks<FT, RPL, CHR, STR>(V + pr.y + r0, rot, vv);
+        lds_chunks<RPL, CHR, STR>(Ls + pr.z + r0, rot, lr);
 #pragma unroll
         for (int e = 0; e < RPL; ++e) W[e] = uu[e] * vv[e] * lr[e];
       }
@@ -360,13 +449,11 @@ __global__ __launch_bounds__(kQueryThreads) void k_query_grouped(GroupedArgs a) 
         const int tlo = glint_clampi(box.z, 0, a.N), thi = glint_clampi(box.w, 0, a.N);
         const int shi = (slo < shi0 && tlo < thi) ? shi0 : slo;     // empty box: exact zeros
         float sh[RPL], sl[RPL], th[RPL], tl[RPL];
-        cum_row<GC, CT, LT, RPL>(CSs, CSg, shi * R + r0, sh);
-        cum_row<GC, CT, LT, RPL>(CSs, CSg, slo * R + r0, sl);
-        cum_row<GC, CT, LT, RPL>(CTs, CTg, thi * R + r0, th);
-        cum_row<GC, CT, LT, RPL>(CTs, CTg, tlo * R + r0, tl);
-        float acc = 0.0f;
-#pragma unroll
-        for (int e = 0; e < RPL; ++e) acc += W[e] * (sh[e] - sl[e]) * (th[e] - tl[e]);
+        cum_chunks<GC, CT, LT, RPL, CHR, STR>(CSs, CSg, shi * R + r0, rot, sh);
+        cum_chunks<GC, CT, LT, RPL, CHR, STR>(CSs, CSg, slo * R + r0, rot, sl);
+        cum_chunks<GC, CT, LT, RPL, CHR, STR>(CTs, CTg, thi * R + r0, rot, th);
+        cum_chunks<GC, CT, LT, RPL, CHR, STR>(CTs, CTg, tlo * R + r0, rot, tl);
+        float acc = lane_terms<RPL, CHR>(W, sh, sl, th, tl, rot);
         acc = glint_group_sum<LPQ>(acc);
         const int bj = b % LPQ;
         res = (j == bj) ? acc : res;
@@ -435,7 +522,10 @@ __global__ __launch_bounds__(kQueryThreads) void k_query_trilinear(TriArgs a) {
   const int lane = threadIdx.x & 63;
   const int g = lane / LPQ;
   const int j = lane % LPQ;
-  const int r0 = j * RPL;
+  constexpr int CHR = chunk_ranks<FT, CT, RPL>();
+  constexpr int STR = LPQ * CHR;
+  const int r0 = j * CHR;
+  const int rot = RPL / CHR > 1 ? (g & 1) : 0;
   constexpr int kSlots = 64 + 64 / LPQ;
   TriRows* wrows = rows + (threadIdx.x >> 6) * kSlots;
   const int my_slot = lane + lane / LPQ;
@@ -486,12 +576,12 @@ __global__ __launch_bounds__(kQueryThreads) void k_query_trilinear(TriArgs a) {
       const TriRows r = wrows[g * (LPQ + 1) + jj];
       if (r.u0 != pu0 || r.v0 != pv0 || r.l0 != pl0 || r.wx != pwx || r.wy != pwy || r.wl != pwl) {
         float ua[RPL], ub[RPL], va[RPL], vb[RPL], la[RPL], lb[RPL];
-        load_row<FT, RPL>(U + r.u0 + r0, ua);
-        load_row<FT, RPL>(U + r.u1 + r0, ub);
-        load_row<FT, RPL>(V + r.v0 + r0, va);
-        load_row<FT, RPL>(V + r.v1 + r0, vb);
-        lds_row<RPL>(Ls + r.l0 + r0, la);
-        lds_row<RPL>(Ls + r.l1 + r0, lb);
+        load_chunks<FT, RPL, CHR, STR>(U + r.u0 + r0, rot, ua);
+        load_chunks<FT, RPL, CHR, STR>(U + r.u1 + r0, rot, ub);
+        load_chunks<FT, RPL, CHR, STR>(V + r.v0 + r0, rot, va);
+        load_chunks<FT, RPL, CHR, STR>(V + r.v1 + r0, rot, vb);
+        lds_chunks<RPL, CHR, STR>(Ls + r.l0 + r0, rot, la);
+        lds_chunks<RPL, CHR, STR>(Ls + r.l1 + r0, rot, lb);
 #pragma unroll
         for (int e = 0; e < RPL; ++e)
           W[e] = (ua[e] + r.wx * (ub[e] - ua[e])) * (va[e] + r.wy * (vb[e] - va[e])) *
@@ -500,13 +590,11 @@ __global__ __launch_bounds__(kQueryThreads) void k_query_trilinear(TriArgs a) {
         pwx = r.wx; pwy = r.wy; pwl = r.wl;
       }
       float sh[RPL], sl[RPL], th[RPL], tl[RPL];
-      cum_row<GC, CT, LT, RPL>(CSs, CSg, r.sh + r0, sh);
-      cum_row<GC, CT, LT, RPL>(CSs, CSg, r.sl + r0, sl);
-      cum_row<GC, CT, LT, RPL>(CTs, CTg, r.th + r0, th);
-      cum_row<GC, CT, LT, RPL>(CTs, CTg, r.tl + r0, tl);
-      float acc = 0.0f;
-#pragma unroll
-      for (int e = 0; e < RPL; ++e) acc += W[e] * (sh[e] - sl[e]) * (th[e] - tl[e]);
+      cum_chunks<GC, CT, LT, RPL, CHR, STR>(CSs, CSg, r.sh + r0, rot, sh);
+      cum_chunks<GC, CT, LT, RPL, CHR, STR>(CSs, CSg, r.sl + r0, rot, sl);
+      cum_chunks<GC, CT, LT, RPL, CHR, STR>(CTs, CTg, r.th + r0, rot, th);
+      cum_chunks<GC, CT, LT, RPL, CHR, STR>(CTs, CTg, r.tl + r0, rot, tl);
+      float acc = lane_terms<RPL, CHR>(W, sh, sl, th, tl, rot);
       acc = glint_group_sum<LPQ>(acc);
       res = (j == jj) ? acc : res;
     }
@@ -566,7 +654,10 @@ __global__ __launch_bounds__(kQueryThreads) void k_sample(SampleArgs a) {
   const int lane = threadIdx.x & 63;
   const int g = lane / LPQ;
   const int j = lane % LPQ;
-  const int r0 = j * RPL;
+  constexpr int CHR = chunk_ranks<FT, CT, RPL>();
+  constexpr int STR = LPQ * CHR;
+  const int r0 = j * CHR;
+  const int rot = RPL / CHR > 1 ? (g & 1) : 0;
   const int nr = a.levels + 2;
   const float w = 2.0f / static_cast<float>(a.N);
   int4* wpts = pts + (threadIdx.x >> 6) * 64;
@@ -592,26 +683,26 @@ __global__ __launch_bounds__(kQueryThreads) void k_sample(SampleArgs a) {
       float W[RPL];
       {
         float uu[RPL], vv[RPL], lr[RPL];
-        load_row<FT, RPL>(U + pr.x + r0, uu);
-        load_row<FT, RPL>(V + pr.y + r0, vv);
-        lds_row<RPL>(Ls + pr.z + r0, lr);
+        load_chunks<FT, RPL, CHR, STR>(U + pr.x + r0, rot, uu);
+        load_chunks<FT, RPL, CHR, STR>(V + pr.y + r0, rot, vv);
+        lds_chunks<RPL, CHR, STR>(Ls + pr.z + r0, rot, lr);
 #pragma unroll
         for (int e = 0; e < RPL; ++e) W[e] = uu[e] * vv[e] * lr[e];
       }
       const float* rn = a.rnd + pi * nr;
       int s0 = 0, s1 = a.N, t0 = 0, t1 = a.N;
       float cs0[RPL], cs1[RPL], ct0[RPL], ct1[RPL];
-      cum_row<GC, CT, LT, RPL>(CSs, CSg, r0, cs0);
-      cum_row<GC, CT, LT, RPL>(CSs, CSg, a.N * R + r0, cs1);
-      cum_row<GC, CT, LT, RPL>(CTs, CTg, r0, ct0);
-      cum_row<GC, CT, LT, RPL>(CTs, CTg, a.N * R + r0, ct1);
+      cum_chunks<GC, CT, LT, RPL, CHR, STR>(CSs, CSg, r0, rot, cs0);
+      cum_chunks<GC, CT, LT, RPL, CHR, STR>(CSs, CSg, a.N * R + r0, rot, cs1);
+      cum_chunks<GC, CT, LT, RPL, CHR, STR>(CTs, CTg, r0, rot, ct0);
+      cum_chunks<GC, CT, LT, RPL, CHR, STR>(CTs, CTg, a.N * R + r0, rot, ct1);
       float prob = 1.0f;
       bool ok = true;
       for (int k = 0; k < a.levels; ++k) {
         const int sm = (s0 + s1) >> 1, tm = (t0 + t1) >> 1;
         float csm[RPL], ctm[RPL];
-        cum_row<GC, CT, LT, RPL>(CSs, CSg, sm * R + r0, csm);
-        cum_row<GC, CT, LT, RPL>(CTs, CTg, tm * R + r0, ctm);
+        cum_chunks<GC, CT, LT, RPL, CHR, STR>(CSs, CSg, sm * R + r0, rot, csm);
+        cum_chunks<GC, CT, LT, RPL, CHR, STR>(CTs, CTg, tm * R + r0, rot, ctm);
         float q00 = 0.0f, q01 = 0.0f, q10 = 0.0f, q11 = 0.0f;
 #pragma unroll
         for (int e = 0; e < RPL; ++e) {
