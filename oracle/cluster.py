@@ -37,6 +37,15 @@ Readings:
     columns are normalised to unit length after every update (zero columns
     stay zero); fixed sweep count.
   * cs must divide the map sides and t must divide N (t = N when N < t).
+  * Sampling on this layout (Sec. 5.2: start from a block chosen by the
+    blocks' averaged NDF values, then the four-quad descent inside it): the
+    block is drawn with probability proportional to its mass (the
+    block-local query over the whole block; negative masses count as zero;
+    block order zs-major), by the same running-sum rule as a quad, then
+    log2(t) quad levels inside it (t a power of two) and a uniform position
+    in the final bin.  Draws per sample: one for the block, log2(t) for the
+    levels, two for the position.  pdf = P(bin) / (2/N)^2; a footprint
+    without positive mass fails (bin (-1, -1), pdf 0, h = (0, 0)).
 """
 from __future__ import annotations
 
@@ -233,3 +242,78 @@ def clustered_range_query(X, Y, Z, q, nl: int, cs: int) -> np.ndarray:
                 acc += float(np.sum(Z[cu, cv, zs, zt, f] * (CX[a1] - CX[a0]) * (CY[b1] - CY[b0])))
         out[i] = acc
     return out
+
+
+def _pick(m, u):
+    """Index chosen by draw u from non-negative masses m (running-sum rule,
+    never an empty entry at the top of the range); None if all are empty."""
+    total = 0.0
+    for x in m:
+        total += x
+    if not total > 0.0:
+        return None, total
+    target = u * total
+    run = 0.0
+    pick = len(m) - 1
+    for i, x in enumerate(m):
+        run += x
+        if target < run:
+            pick = i
+            break
+    while m[pick] <= 0.0:
+        pick -= 1
+    return pick, total
+
+
+def clustered_sample(X, Y, Z, uvl, rnd, nl: int, cs: int):
+    """Hierarchical samples on the clustered layout for records uvl [n][3]
+    (wrapped/clamped like the query) with draws rnd [n][log2(t) + 3]."""
+    ncu, ncv, nb = X.shape[:3]
+    t = X.shape[4]
+    levels = int(round(np.log2(t)))
+    N = nb * t
+    uvl = np.asarray(uvl, dtype=np.int64)
+    rnd = np.asarray(rnd, dtype=np.float64)
+    n = uvl.shape[0]
+    h = np.zeros((n, 2))
+    pdf = np.zeros(n)
+    bins = np.full((n, 2), -1, dtype=np.int64)
+    w = 2.0 / N
+    for i in range(n):
+        u = int(np.mod(uvl[i, 0], ncu * cs))
+        v = int(np.mod(uvl[i, 1], ncv * cs))
+        l = int(np.clip(uvl[i, 2], 0, nl - 1))
+        cu, cv = u // cs, v // cs
+        f = ((u % cs) * cs + (v % cs)) * nl + l
+        CX = [np.concatenate([np.zeros((1, X.shape[-1])), np.cumsum(X[cu, cv, zs, zt], axis=0)])
+              for zs in range(nb) for zt in range(nb)]
+        CY = [np.concatenate([np.zeros((1, Y.shape[-1])), np.cumsum(Y[cu, cv, zs, zt], axis=0)])
+              for zs in range(nb) for zt in range(nb)]
+        zrow = [Z[cu, cv, b // nb, b % nb, f] for b in range(nb * nb)]
+        bm = [max(float(np.sum(zrow[b] * (CX[b][t] - CX[b][0]) * (CY[b][t] - CY[b][0]))), 0.0)
+              for b in range(nb * nb)]
+        b, total = _pick(bm, rnd[i, 0])
+        if b is None:
+            continue
+        prob = bm[b] / total
+        s0, s1, t0, t1 = 0, t, 0, t
+        failed = False
+        for k in range(levels):
+            sm, tm = (s0 + s1) // 2, (t0 + t1) // 2
+            dS = (CX[b][sm] - CX[b][s0], CX[b][s1] - CX[b][sm])
+            dT = (CY[b][tm] - CY[b][t0], CY[b][t1] - CY[b][tm])
+            m = [max(float(np.sum(zrow[b] * dS[a] * dT[c])), 0.0) for a in (0, 1) for c in (0, 1)]
+            q, qt = _pick(m, rnd[i, 1 + k])
+            if q is None:
+                failed = True
+                break
+            prob *= m[q] / qt
+            s0, s1 = (sm, s1) if q >= 2 else (s0, sm)
+            t0, t1 = (tm, t1) if q % 2 == 1 else (t0, tm)
+        if failed:
+            continue
+        bs, bt = (b // nb) * t + s0, (b % nb) * t + t0
+        bins[i] = (bs, bt)
+        h[i] = (-1.0 + (bs + rnd[i, 1 + levels]) * w, -1.0 + (bt + rnd[i, 2 + levels]) * w)
+        pdf[i] = prob / (w * w)
+    return h, pdf, bins

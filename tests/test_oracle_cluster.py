@@ -112,3 +112,38 @@ def test_clustered_layout_is_far_more_accurate_than_one_global_cp():
     e_gl = np.linalg.norm(query.range_query(F[0], F[1], F[2], query.cumulative(F[3]), query.cumulative(F[4]), q)
                           - bf) / np.linalg.norm(bf)
     assert e_cl < 0.01 < 0.1 < e_gl
+
+
+def test_clustered_sampling_pdf_is_the_normalised_mass_and_histogram_matches():
+    """Block choice by mass, then the quad descent inside the block: every
+    sample's pdf is its bin's mass over the footprint's total mass (per unit
+    area), and 2e5 samples bin like the reconstructed NDF image."""
+    rng = np.random.default_rng(21)
+    nu, nv, nl, N, t, cs, R = 8, 8, 2, 16, 8, 4, 3
+    T = rng.random((nu, nv, nl, N, N)) ** 4
+    X, Y, Z, blank, _ = cluster.clustered_cp(T, t, cs, R, iters=5, seed=2)
+    X, Y, Z = np.abs(X), np.abs(Y), np.abs(Z)            # a non-negative NDF approximation
+    rec = cluster.reconstruct(X, Y, Z, nl, cs)
+    u, v, l = 5, 2, 1
+    n = 200000
+    rnd = rng.random((n, 3 + 3))
+    uvl = np.tile([u, v, l], (n, 1))
+    h, pdf, bins = cluster.clustered_sample(X, Y, Z, uvl, rnd, nl, cs)
+    img = rec[u, v, l]
+    p = img / img.sum()
+    w = 2.0 / N
+    assert np.all(bins >= 0)
+    assert np.allclose(pdf, p[bins[:, 0], bins[:, 1]] / (w * w), rtol=1e-9)
+    hist = np.zeros((N, N))
+    np.add.at(hist, (bins[:, 0], bins[:, 1]), 1.0)
+    expect = p * n
+    ok = expect > 20
+    chi2 = float(np.sum((hist[ok] - expect[ok]) ** 2 / expect[ok]))
+    assert chi2 < ok.sum() + 6 * np.sqrt(2 * ok.sum())
+    # positions lie in their bins
+    assert np.all(np.floor((h + 1.0) / w).astype(int) == bins)
+    # a footprint with no mass fails
+    Z0 = Z.copy()
+    Z0[1, 0, :, :, (2 * cs + 1) * nl + 0] = 0.0
+    _, pdf0, b0 = cluster.clustered_sample(X, Y, Z0, [[6, 1, 0]], rnd[:1], nl, cs)
+    assert pdf0[0] == 0.0 and tuple(b0[0]) == (-1, -1)
