@@ -462,6 +462,16 @@ def clustered_report(desc, T, q, q_bf, sweeps, timed, t=16, cs=8, R=16):
     st = tab.struct()
     query_ms = timed(lambda: L.glint_query_clustered(st, q, out))
     ebf = float((torch.linalg.vector_norm(out.double() - q_bf) / torch.linalg.vector_norm(q_bf)).item())
+    # importance sampling on these tables (block by mass, then quads): one sample per pixel footprint
+    npix = q.shape[0] // 8
+    s_uvl = q[::8, :3].contiguous()
+    s_rnd = torch.rand((npix, (t.bit_length() - 1) + 3), device=q.device,
+                       generator=torch.Generator(device=q.device).manual_seed(8))
+    s_h = torch.empty((npix, 2), dtype=torch.float32, device=q.device)
+    s_pdf = torch.empty(npix, dtype=torch.float32, device=q.device)
+    s_bins = torch.empty((npix, 2), dtype=torch.int32, device=q.device)
+    sample_ms = timed(lambda: L.glint_sample_clustered(st, s_uvl, s_rnd, s_h, s_pdf, s_bins))
+    del s_uvl, s_rnd, s_h, s_pdf, s_bins
     info = tab.info.cpu().tolist()
     ntensor = tab.X.shape[0]
     stacked = info[3]                                 # non-blank image blocks over all block tensors
@@ -484,6 +494,7 @@ def clustered_report(desc, T, q, q_bf, sweeps, timed, t=16, cs=8, R=16):
                                    "fp64_frac": tf / FP64_MFMA_PEAK_TFLOPS}},
         "stacked_blocks": info[3],
         "query_ms": query_ms, "queries_per_s": q.shape[0] / (query_ms * 1e-3),
+        "sample_ms": sample_ms, "samples_per_s": npix / (sample_ms * 1e-3),
         "error_vs_bruteforce": ebf,
         "table_bytes": int(4 * (tab.CX.numel() + tab.CY.numel() + tab.Z.numel())),
     }

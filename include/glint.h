@@ -272,6 +272,23 @@ typedef struct {
 glint_status glint_query_clustered(const glint_clustered* f, int64_t nq, const int32_t* q,
                                    float* out, hipStream_t stream);
 
+/* Hierarchical importance sampling on the clustered tables (Sec. 5.2: start
+ * from an image block chosen by the blocks' masses, then descend by quads):
+ * for lookup i (uvl [n][3], wrapped/clamped as for queries) with draws
+ * rnd [n][log2(t) + 3] in [0, 1): the block by rnd[0] among the nb x nb
+ * blocks in zs-major order with probability proportional to its mass (the
+ * block-local query over the whole block, negative masses as zero; the
+ * draw picks the first block whose running mass exceeds rnd[0] times the
+ * total, never an empty one), then log2(t) levels of four quads, (s lo,
+ * t lo), (s lo, t hi), (s hi, t lo), (s hi, t hi), by rnd[1..log2 t] with
+ * the same rule, then h = (-1 + (s + rnd[log2 t + 1]) 2/N, -1 + (t +
+ * rnd[log2 t + 2]) 2/N) with (s, t) the global bin; pdf = the product of
+ * the choice probabilities / (2/N)^2.  No positive mass: bins (-1, -1),
+ * pdf 0, h 0.  t must be a power of two.  Outputs h float [n][2], pdf float
+ * [n], bins int32 [n][2].  One thread per lookup, FP32. */
+glint_status glint_sample_clustered(const glint_clustered* f, int64_t n, const int32_t* uvl, const float* rnd,
+                                    float* h, float* pdf, int32_t* bins, hipStream_t stream);
+
 /* ---- step 4: summed-area tables and storage types (Sec. 4.4) ------------ */
 
 /* C[j][r] = sum_{s<j} S[s][r] for j = 0..n, accumulated in FP64 and then

@@ -117,6 +117,7 @@ _SIGS = {
     "glint_cp_als_clustered": (_I32, [_DESC, _CDESC, _P, _I32, _I32, _U64, _P, _P, _P, _P, _P, _P]),
     "glint_make_cumulative_batched": (_I32, [_I64, _I32, _I32, _P, _P, _P]),
     "glint_query_clustered": (_I32, [_CLU, _I64, _P, _P, _P]),
+    "glint_sample_clustered": (_I32, [_CLU, _I64, _P, _P, _P, _P, _P, _P]),
     "glint_query_sg": (_I32, [_FAC, _I64, _P, _P, _P, _F32, _P, _P, _P]),
     "glint_query_wang": (_I32, [ctypes.POINTER(Wang), _I64, _P, _P, _P]),
 }
@@ -399,3 +400,13 @@ def glint_query_sg(f: Factors, uvl, h, sg, eps, q, out, stream=None):
 def glint_query_wang(w: Wang, q, out, stream=None):
     _check("glint_query_wang", lib().glint_query_wang(
         ctypes.byref(w), q.shape[0], _ptr(q, torch.int32, "q"), _ptr(out, torch.float32, "out"), _stream(stream)))
+
+
+def glint_sample_clustered(f: Clustered, uvl, rnd, h, pdf, bins, stream=None):
+    n = uvl.shape[0]
+    if tuple(h.shape) != (n, 2) or tuple(bins.shape) != (n, 2) or pdf.shape[0] != n or rnd.shape[0] != n:
+        raise ValueError("shapes: uvl [n][3], rnd [n][log2(t)+3], h [n][2], pdf [n], bins [n][2]")
+    _check("glint_sample_clustered", lib().glint_sample_clustered(
+        ctypes.byref(f), n, _ptr(uvl, torch.int32, "uvl"), _ptr(rnd, torch.float32, "rnd"),
+        _ptr(h, torch.float32, "h"), _ptr(pdf, torch.float32, "pdf"), _ptr(bins, torch.int32, "bins"),
+        _stream(stream)))

@@ -317,6 +317,22 @@ def clustered_cumulative(tab: ClusteredTables):
     return tab
 
 
+def sample_clustered(tab: ClusteredTables, uvl, rnd):
+    """Hierarchical importance samples on the clustered tables (block by mass,
+    then quads): (h [n][2], pdf [n], bins [n][2]); rnd [n][log2(t) + 3]."""
+    uvl = _dev(uvl, torch.int32)
+    rnd = _dev(rnd, torch.float32)
+    n = uvl.shape[0]
+    levels = int(tab.t).bit_length() - 1
+    if tuple(rnd.shape) != (n, levels + 3):
+        raise ValueError(f"rnd must be [n][{levels + 3}]")
+    h = torch.empty((n, 2), dtype=torch.float32, device=_DEV)
+    pdf = torch.empty(n, dtype=torch.float32, device=_DEV)
+    bins = torch.empty((n, 2), dtype=torch.int32, device=_DEV)
+    L.glint_sample_clustered(tab.struct(), uvl, rnd, h, pdf, bins)
+    return h, pdf, bins
+
+
 def query_clustered(tab: ClusteredTables, q, out=None):
     q = _dev(q, torch.int32)
     out = torch.empty(q.shape[0], dtype=torch.float32, device=_DEV) if out is None else out

@@ -765,6 +765,117 @@ __global__ __launch_bounds__(kClQueryThreads) void k_query_clustered(ClQueryArgs
   }
 }
 
+// ---------------------------------------------------------------------------
+// hierarchical importance sampling on the clustered tables (Sec. 5.2)
+// ---------------------------------------------------------------------------
+
+struct ClSampleArgs {
+  const float* CX;
+  const float* CY;
+  const float* Z;
+  int t, cs, nu, nv, nl, N, ncv, nb, L, levels;
+  int64_t n;
+  const int32_t* uvl;
+  const float* rnd;
+  float* h;
+  float* pdf;
+  int32_t* bins;
+};
+
+constexpr int kClSampleThreads = 256;
+
+// block-local range query of tensor `tensor` (footprint f) over [a0, a1) x [b0, b1)
+template <int R>
+__device__ __forceinline__ float cl_box(const ClSampleArgs& a, int64_t tensor, int f, int a0, int a1, int b0,
+                                        int b1) {
+  const float* z = a.Z + (tensor * a.L + f) * R;
+  const float* cx = a.CX + tensor * (a.t + 1) * R;
+  const float* cy = a.CY + tensor * (a.t + 1) * R;
+  float m = 0.0f;
+#pragma unroll
+  for (int r = 0; r < R; ++r) m += z[r] * (cx[a1 * R + r] - cx[a0 * R + r]) * (cy[b1 * R + r] - cy[b0 * R + r]);
+  return m;
+}
+
+// One sample per thread: the block by its mass (running-sum rule over the
+// blocks in zs-major order, negative masses as zero), then log2(t) levels of
+// four quads inside it, then a uniform position in the bin.
+template <int R>
+__global__ __launch_bounds__(kClSampleThreads) void k_sample_clustered(ClSampleArgs a) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const int u = glint_wrap(a.uvl[3 * i], a.nu), v = glint_wrap(a.uvl[3 * i + 1], a.nv);
+  const int l = glint_clampi(a.uvl[3 * i + 2], 0, a.nl - 1);
+  const int64_t tensor0 = (static_cast<int64_t>(u / a.cs) * a.ncv + v / a.cs) * a.nb * a.nb;
+  const int f = ((u % a.cs) * a.cs + v % a.cs) * a.nl + l;
+  const float* rn = a.rnd + i * (a.levels + 3);
+  const int nblk = a.nb * a.nb, t = a.t;
+  float total = 0.0f;
+  for (int b = 0; b < nblk; ++b) total += fmaxf(cl_box<R>(a, tensor0 + b, f, 0, t, 0, t), 0.0f);
+  a.h[2 * i] = 0.0f;
+  a.h[2 * i + 1] = 0.0f;
+  a.pdf[i] = 0.0f;
+  a.bins[2 * i] = -1;
+  a.bins[2 * i + 1] = -1;
+  if (!(total > 0.0f)) return;
+  const float target = rn[0] * total;
+  float run = 0.0f, pm = 0.0f, lastm = 0.0f;
+  int pick = -1, lastpos = 0;
+  for (int b = 0; b < nblk; ++b) {
+    const float m = fmaxf(cl_box<R>(a, tensor0 + b, f, 0, t, 0, t), 0.0f);
+    if (m > 0.0f) {
+      lastpos = b;
+      lastm = m;
+    }
+    run += m;
+    if (target < run) {
+      pick = b;
+      pm = m;
+      break;
+    }
+  }
+  if (pick < 0) {
+    pick = lastpos;
+    pm = lastm;
+  }
+  float prob = pm / total;
+  const int64_t tensor = tensor0 + pick;
+  int s0 = 0, s1 = t, t0 = 0, t1 = t;
+  for (int k = 0; k < a.levels; ++k) {
+    const int sm = (s0 + s1) >> 1, tm = (t0 + t1) >> 1;
+    float m[4];
+    m[0] = fmaxf(cl_box<R>(a, tensor, f, s0, sm, t0, tm), 0.0f);
+    m[1] = fmaxf(cl_box<R>(a, tensor, f, s0, sm, tm, t1), 0.0f);
+    m[2] = fmaxf(cl_box<R>(a, tensor, f, sm, s1, t0, tm), 0.0f);
+    m[3] = fmaxf(cl_box<R>(a, tensor, f, sm, s1, tm, t1), 0.0f);
+    const float qt = ((m[0] + m[1]) + m[2]) + m[3];
+    if (!(qt > 0.0f)) return;
+    const float tq = rn[1 + k] * qt;
+    int q = 3;
+    float rq = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      rq += m[j];
+      if (tq < rq) {
+        q = j;
+        break;
+      }
+    }
+    while (m[q] <= 0.0f) --q;
+    prob *= m[q] / qt;
+    if (q >= 2) s0 = sm; else s1 = sm;
+    if (q & 1) t0 = tm; else t1 = tm;
+  }
+  const int zs = pick / a.nb, zt = pick % a.nb;
+  const int bs = zs * t + s0, bt = zt * t + t0;
+  const float w = 2.0f / static_cast<float>(a.N);
+  a.bins[2 * i] = bs;
+  a.bins[2 * i + 1] = bt;
+  a.h[2 * i] = -1.0f + (static_cast<float>(bs) + rn[1 + a.levels]) * w;
+  a.h[2 * i + 1] = -1.0f + (static_cast<float>(bt) + rn[2 + a.levels]) * w;
+  a.pdf[i] = prob / (w * w);
+}
+
 int g_cl_cus = 0, g_cl_lds = 0;
 
 glint_status cl_device() {
@@ -897,6 +1008,41 @@ glint_status glint_query_clustered(const glint_clustered* f, int64_t nq, const i
     default: hipLaunchKernelGGL(k_query_clustered<32>, dim3(blocks), dim3(kClQueryThreads), 0, stream, a); break;
   }
   GLINT_LAUNCHED("k_query_clustered");
+  return GLINT_OK;
+}
+
+glint_status glint_sample_clustered(const glint_clustered* f, int64_t n, const int32_t* uvl, const float* rnd,
+                                    float* h, float* pdf, int32_t* bins, hipStream_t stream) {
+  GLINT_REQUIRE(f != nullptr, "tables are NULL");
+  glint_ndf_desc d;
+  d.nu = f->nu; d.nv = f->nv; d.nlevels = f->nl; d.nbins = f->nbins; d.sigma = 0.01;
+  glint_cluster_desc cd;
+  cd.t = f->t; cd.cs = f->cs; cd.R = f->R;
+  ClShape sh;
+  glint_status st = cluster_shape(&d, &cd, &sh);
+  if (st != GLINT_OK) return st;
+  GLINT_REQUIRE(f->t == sh.t, "block side must be min(t, nbins) = %d", sh.t);
+  GLINT_REQUIRE((sh.t & (sh.t - 1)) == 0, "block side %d must be a power of two", sh.t);
+  GLINT_REQUIRE(n >= 0, "n must be >= 0");
+  if (n == 0) return GLINT_OK;
+  GLINT_REQUIRE(f->CX && f->CY && f->Z && uvl && rnd && h && pdf && bins, "null pointer argument");
+  ClSampleArgs a;
+  a.CX = f->CX; a.CY = f->CY; a.Z = f->Z;
+  a.t = sh.t; a.cs = f->cs; a.nu = f->nu; a.nv = f->nv; a.nl = f->nl; a.N = f->nbins;
+  a.ncv = sh.ncv; a.nb = sh.nb; a.L = sh.L;
+  int levels = 0;
+  while ((1 << levels) < sh.t) ++levels;
+  a.levels = levels;
+  a.n = n; a.uvl = uvl; a.rnd = rnd; a.h = h; a.pdf = pdf; a.bins = bins;
+  const dim3 grid(static_cast<unsigned>((n + kClSampleThreads - 1) / kClSampleThreads));
+  glint_clear_launch_error();
+  switch (f->R) {
+    case 4: hipLaunchKernelGGL(k_sample_clustered<4>, grid, dim3(kClSampleThreads), 0, stream, a); break;
+    case 8: hipLaunchKernelGGL(k_sample_clustered<8>, grid, dim3(kClSampleThreads), 0, stream, a); break;
+    case 16: hipLaunchKernelGGL(k_sample_clustered<16>, grid, dim3(kClSampleThreads), 0, stream, a); break;
+    default: hipLaunchKernelGGL(k_sample_clustered<32>, grid, dim3(kClSampleThreads), 0, stream, a); break;
+  }
+  GLINT_LAUNCHED("k_sample_clustered");
   return GLINT_OK;
 }
 

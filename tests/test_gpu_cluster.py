@@ -219,3 +219,55 @@ def test_clustered_argument_errors():
     assert tab.t == 16 and int(tab.info[1]) == tab.X.shape[0] and bool(tab.blank.all())
     out = G.query_clustered(tab, torch.tensor([[0, 0, 0, 0, 16, 0, 16]], dtype=torch.int32))
     assert float(out[0]) == 0.0
+
+
+def test_clustered_sampling_matches_oracle_and_histogram():
+    """Sec. 5.2 on the clustered layout (block by mass, then quads): the same
+    draws give the oracle's bins (near-ties aside: at most 1% differ, each a
+    sample whose pdf is its bin's normalised mass), the same pdf and
+    position on identical bins, and 10^6 samples of one footprint bin like
+    the reconstructed NDF image."""
+    rng = np.random.default_rng(31)
+    nu, nv, nl, N, t, cs, R = 16, 8, 2, 32, 8, 4, 8
+    T = rng.random((nu, nv, nl, N, N)) ** 6
+    d = G.desc_of(nu, nv, nl, N, 0.02)
+    tab = G.cp_als_clustered(_to_dev(T), d, t, cs, R, iters=4, seed=3)
+    # non-negative factors (an NDF approximation), re-tabled
+    tab.X.abs_(); tab.Y.abs_(); tab.Z.abs_()
+    G.clustered_cumulative(tab)
+    X, Y, Z, _ = _oracle_shaped(tab, nu, nv, N, t, cs)
+    n = 20000
+    uvl = np.stack([rng.integers(-nu, 2 * nu, n), rng.integers(0, nv, n), rng.integers(-1, nl + 1, n)], 1)
+    rnd = rng.random((n, 6)).astype(np.float32)
+    h, pdf, bins = (x.cpu().numpy() for x in G.sample_clustered(tab, torch.from_numpy(uvl.astype(np.int32)),
+                                                                 torch.from_numpy(rnd)))
+    ho, pdfo, binso = cluster.clustered_sample(X, Y, Z, uvl, rnd.astype(np.float64), nl, cs)
+    same = np.all(bins == binso, axis=1)
+    assert same.mean() > 0.99, same.mean()
+    assert np.allclose(pdf[same], pdfo[same], rtol=1e-4)
+    assert np.allclose(h[same], ho[same], atol=1e-6)
+    rec = cluster.reconstruct(X, Y, Z, nl, cs)
+    w = 2.0 / N
+    for i in np.nonzero(~same)[0]:
+        u, v, l = int(uvl[i, 0]) % nu, int(uvl[i, 1]) % nv, int(np.clip(uvl[i, 2], 0, nl - 1))
+        img = rec[u, v, l]
+        assert bins[i, 0] >= 0 and abs(pdf[i] - img[bins[i, 0], bins[i, 1]] / img.sum() / (w * w)) <= 1e-3 * pdf[i]
+    # histogram of one footprint
+    m = 1_000_000
+    one = torch.tensor([[5, 3, 1]], dtype=torch.int32).repeat(m, 1)
+    r = torch.rand((m, 6), generator=torch.Generator().manual_seed(4))
+    _, pdf1, b1 = (x.cpu().numpy() for x in G.sample_clustered(tab, one, r))
+    img = rec[5, 3, 1]
+    p = img / img.sum()
+    hist = np.zeros((N, N))
+    np.add.at(hist, (b1[:, 0], b1[:, 1]), 1.0)
+    expect = p * m
+    ok = expect > 20
+    chi2 = float(np.sum((hist[ok] - expect[ok]) ** 2 / expect[ok]))
+    assert chi2 < ok.sum() + 6 * np.sqrt(2 * ok.sum()), (chi2, int(ok.sum()))
+    assert np.allclose(pdf1, p[b1[:, 0], b1[:, 1]] / (w * w), rtol=1e-3)
+    # no mass: failure
+    tab.Z.zero_()
+    _, pdf0, b0 = (x.cpu().numpy() for x in G.sample_clustered(tab, torch.tensor([[1, 1, 0]], dtype=torch.int32),
+                                                                 torch.rand((1, 6))))
+    assert pdf0[0] == 0.0 and tuple(b0[0]) == (-1, -1)
