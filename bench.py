@@ -308,7 +308,9 @@ def main():
             "kernel": "k_query<float,float,64,4>", "ms": query_ms, "queries_per_s": nq / (query_ms * 1e-3),
             "roofline": {"bound": "hbm", "achieved": q_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": q_gbs / HBM_PEAK_GBS, "traffic": measured_traffic("k_query"),
-                         "algorithmic_bytes_per_query": 32},
+                         "algorithmic_bytes_per_query": 32,
+                         "note": "HBM is the nominal bound; the counters in profiles/k_query_c2_lds_counters.md "
+                                 "show the on-chip gathers (LDS issue, 7R values per query) binding instead"},
         },
         "query_trilinear_kernel": {
             "kernel": "k_query_trilinear<float,float,64,4>: the batch at fractional centres and levels "
