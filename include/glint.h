@@ -356,6 +356,15 @@ glint_status glint_query_trilinear(const glint_factors* f, int64_t nq, const flo
 glint_status glint_sample(const glint_factors* f, int64_t n, const int32_t* uvl, const float* rnd,
                           float* h, float* pdf, int32_t* bins, hipStream_t stream);
 
+/* Counts the records the query's rules would change (for callers that want
+ * errors instead of wrapping and clamping): u or v outside the map, l
+ * outside [0, nl), a bin bound outside [0, N], or a reversed box (lo > hi;
+ * lo == hi is a valid empty box).  nbad: one device int64, overwritten
+ * (cleared by a small kernel, so the call can be captured in a graph).
+ * Only the table sizes of f are used. */
+glint_status glint_validate_queries(const glint_factors* f, int64_t nq, const int32_t* q, int64_t* nbad,
+                                    hipStream_t stream);
+
 /* Environment-light prefiltering (Sec. 5.4, compact-eps support and the box
  * side Q): for lookup i with footprint uvl[i] = (u, v, l), projected half
  * vector h[i] = (h_s, h_t) in [-1, 1]^2 and the spherical-Gaussian light

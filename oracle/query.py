@@ -167,3 +167,15 @@ def mse_loss(qv: np.ndarray, target: np.ndarray):
     target = np.asarray(target, dtype=np.float64)
     d = qv - target
     return float(np.mean(d * d)), 2.0 * d / d.shape[0]
+
+
+def count_invalid(q, nu: int, nv: int, nlevels: int, nbins: int) -> int:
+    """Records the query rules would change: u or v outside the map (they
+    wrap), l outside [0, nlevels) (it clamps), a bin bound outside [0, N]
+    (it clamps), or a reversed box (lo > hi; lo == hi is a valid empty box)."""
+    q = np.asarray(q, dtype=np.int64).reshape(-1, 7)
+    bad = (q[:, 0] < 0) | (q[:, 0] >= nu) | (q[:, 1] < 0) | (q[:, 1] >= nv)
+    bad |= (q[:, 2] < 0) | (q[:, 2] >= nlevels)
+    bad |= np.any((q[:, 3:7] < 0) | (q[:, 3:7] > nbins), axis=1)
+    bad |= (q[:, 3] > q[:, 4]) | (q[:, 5] > q[:, 6])
+    return int(bad.sum())

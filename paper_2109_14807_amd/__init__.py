@@ -12,7 +12,7 @@ from .api import (  # noqa: F401
     AlsResult, ClusteredTables, QueryTables, als_workspace, clustered_cumulative, cp_als_clustered,
     query_clustered, sample_clustered, build_tensor, convert, cp_als, cumulative, cumulative_backward,
     cp_als_texel, desc_of, make_tables, mttkrp, mttkrp_texel, query, query_backward, query_grouped, query_trilinear,
-    query_sg, query_wang, range_bruteforce, sample, texel_bins, texel_workspace, WangTables,
+    query_sg, query_wang, range_bruteforce, validate_queries, sample, texel_bins, texel_workspace, WangTables,
     wang_tables,
 )
 from .autograd import GlintQuery, glint_query_fn  # noqa: F401

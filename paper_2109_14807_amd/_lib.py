@@ -120,6 +120,7 @@ _SIGS = {
     "glint_sample_clustered": (_I32, [_CLU, _I64, _P, _P, _P, _P, _P, _P]),
     "glint_query_sg": (_I32, [_FAC, _I64, _P, _P, _P, _F32, _P, _P, _P]),
     "glint_query_wang": (_I32, [ctypes.POINTER(Wang), _I64, _P, _P, _P]),
+    "glint_validate_queries": (_I32, [_FAC, _I64, _P, _P, _P]),
 }
 
 
@@ -410,3 +411,8 @@ def glint_sample_clustered(f: Clustered, uvl, rnd, h, pdf, bins, stream=None):
         ctypes.byref(f), n, _ptr(uvl, torch.int32, "uvl"), _ptr(rnd, torch.float32, "rnd"),
         _ptr(h, torch.float32, "h"), _ptr(pdf, torch.float32, "pdf"), _ptr(bins, torch.int32, "bins"),
         _stream(stream)))
+
+
+def glint_validate_queries(f: Factors, q, nbad, stream=None):
+    _check("glint_validate_queries", lib().glint_validate_queries(
+        ctypes.byref(f), q.shape[0], _ptr(q, torch.int32, "q"), _ptr(nbad, torch.int64, "nbad"), _stream(stream)))

@@ -235,6 +235,14 @@ def query_sg(tables: QueryTables, uvl, h, sg, eps: float = 0.3):
     return out, q
 
 
+def validate_queries(tables: QueryTables, q) -> int:
+    """Number of records the query's wrap/clamp rules would change."""
+    q = _dev(q, torch.int32)
+    nbad = torch.empty(1, dtype=torch.int64, device=_DEV)
+    L.glint_validate_queries(tables.factors(), q, nbad)
+    return int(nbad.item())
+
+
 def query_backward(tables: QueryTables, q, gout):
     """Gradients (dU, dV, dL, dCS, dCT) of sum gout * q w.r.t. the stored tables."""
     R = tables.R

@@ -131,9 +131,58 @@ __global__ __launch_bounds__(kWangThreads) void k_query_wang(WangArgs a) {
   a.out[i] = acc;
 }
 
+// ---- record validation ---------------------------------------------------
+
+constexpr int kValThreads = 256;
+
+__global__ void k_zero_count(unsigned long long* n) {
+  if (threadIdx.x == 0) *n = 0ull;
+}
+
+// A record is invalid when the query's rules would change it: u or v outside
+// the map, l outside [0, nl), a bin bound outside [0, N], or lo > hi.
+__global__ __launch_bounds__(kValThreads) void k_validate(int64_t nq, const int32_t* __restrict__ q, int nu, int nv,
+                                                          int nl, int N, unsigned long long* __restrict__ nbad) {
+  unsigned long long count = 0;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i0 = static_cast<int64_t>(blockIdx.x) * blockDim.x; i0 < nq; i0 += stride) {
+    const int64_t i = i0 + threadIdx.x;
+    bool bad = false;
+    if (i < nq) {
+      const int32_t* r = q + 7 * i;
+      bad = r[0] < 0 || r[0] >= nu || r[1] < 0 || r[1] >= nv || r[2] < 0 || r[2] >= nl;
+#pragma unroll
+      for (int k = 3; k < 7; ++k) bad = bad || r[k] < 0 || r[k] > N;
+      bad = bad || r[3] > r[4] || r[5] > r[6];
+    }
+    count += static_cast<unsigned long long>(__popcll(__ballot(bad)));
+  }
+  if ((threadIdx.x & 63) == 0 && count) atomicAdd(nbad, count);
+}
+
 }  // namespace
 
 extern "C" {
+
+glint_status glint_validate_queries(const glint_factors* f, int64_t nq, const int32_t* q, int64_t* nbad,
+                                    hipStream_t stream) {
+  GLINT_REQUIRE(f != nullptr && nbad != nullptr, "null pointer argument");
+  GLINT_REQUIRE(f->nu >= 1 && f->nv >= 1 && f->nl >= 1 && f->nbins >= 1, "bad table sizes");
+  GLINT_REQUIRE(nq >= 0, "nq must be >= 0");
+  GLINT_REQUIRE(nq == 0 || q != nullptr, "null query pointer");
+  unsigned long long* n = reinterpret_cast<unsigned long long*>(nbad);
+  glint_clear_launch_error();
+  hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(64), 0, stream, n);
+  GLINT_LAUNCHED("k_zero_count");
+  if (nq == 0) return GLINT_OK;
+  int64_t blocks = (nq + kValThreads - 1) / kValThreads;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_validate, dim3(static_cast<unsigned>(blocks)), dim3(kValThreads), 0, stream, nq, q, f->nu,
+                     f->nv, f->nl, f->nbins, n);
+  GLINT_LAUNCHED("k_validate");
+  return GLINT_OK;
+}
+
 
 glint_status glint_query_wang(const glint_wang* w, int64_t nq, const int32_t* q, float* out, hipStream_t stream) {
   GLINT_REQUIRE(w != nullptr, "tile set is NULL");

@@ -323,3 +323,26 @@ def test_trilinear_query_matches_oracle(dtype, cum_dtype, R, N):
     c = np.clip(boxes, 0, N)
     empty = (c[:, 0] >= c[:, 1]) | (c[:, 2] >= c[:, 3])
     assert empty.any() and np.all(got[empty] == 0.0)
+
+
+@pytest.mark.parametrize("nq", [0, 1, 65, 200_003, 4_000_037])
+def test_validate_queries_counts_exactly(nq):
+    """The record check against the oracle's count (bit-exact): wild records
+    (wrapped, clamped, reversed) mixed with valid ones, sizes past the grid
+    stride of the launch, and a count buffer holding garbage beforehand."""
+    rng = np.random.default_rng(nq + 77)
+    nu, nv, nl, N = 37, 20, 6, 32
+    q = _rand_queries(rng, max(nq, 8), nu, nv, nl, N, wild=True)[:nq]
+    if nq > 8:
+        q[-5:] = [[0, 0, 0, N, N, 0, 0], [nu - 1, nv - 1, nl - 1, 0, N, 0, N], [nu, 0, 0, 0, 1, 0, 1],
+                  [0, 0, 0, 0, N + 1, 0, 1], [0, 0, 0, 3, 2, 0, 1]]
+    F = [np.ones((nu, 1)), np.ones((nv, 1)), np.ones((nl, 1)), np.ones((N, 1)), np.ones((N, 1))]
+    tabs = G.make_tables(*[torch.tensor(x, device="cuda") for x in F])
+    nbad = torch.full((2,), -12345, dtype=torch.int64, device="cuda")
+    G._lib.glint_validate_queries(tabs.factors(), torch.tensor(q, device="cuda").reshape(nq, 7), nbad[:1])
+    got = nbad.cpu().numpy()
+    assert got[0] == query.count_invalid(q, nu, nv, nl, N)
+    assert got[1] == -12345
+    assert G.validate_queries(tabs, q) == got[0]
+    if nq > 8:
+        assert got[0] > 0 and query.count_invalid(q[-5:-3], nu, nv, nl, N) == 0

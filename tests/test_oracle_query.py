@@ -283,3 +283,20 @@ def test_trilinear_boundary_rules():
     # the level weight is linear between two levels
     a, b, m = f([1.0, 2.0, 1.0]), f([1.0, 2.0, 2.0]), f([1.0, 2.0, 1.25])
     assert m == pytest.approx(0.75 * a + 0.25 * b, rel=1e-12)
+
+
+def test_count_invalid_records():
+    nu, nv, nl, N = 8, 6, 3, 16
+    good = [[0, 0, 0, 0, 16, 0, 16], [7, 5, 2, 3, 3, 4, 9], [1, 2, 1, 16, 16, 0, 0]]   # empty boxes are valid
+    bad = [[8, 0, 0, 0, 1, 0, 1], [-1, 0, 0, 0, 1, 0, 1], [0, 6, 0, 0, 1, 0, 1], [0, 0, 3, 0, 1, 0, 1],
+           [0, 0, -1, 0, 1, 0, 1], [0, 0, 0, -1, 1, 0, 1], [0, 0, 0, 0, 17, 0, 1], [0, 0, 0, 5, 4, 0, 1],
+           [0, 0, 0, 0, 1, 9, 2], [9, 9, 9, 99, -9, 99, -9]]
+    assert query.count_invalid(good, nu, nv, nl, N) == 0
+    assert query.count_invalid(bad, nu, nv, nl, N) == len(bad)
+    # a record the rules leave unchanged is exactly a valid one
+    rng = np.random.default_rng(5)
+    q = rng.integers(-3, 20, (2000, 7))
+    canon = np.stack([np.mod(q[:, 0], nu), np.mod(q[:, 1], nv), np.clip(q[:, 2], 0, nl - 1)], 1)
+    same = np.all(canon == q[:, :3], axis=1) & np.all((q[:, 3:] >= 0) & (q[:, 3:] <= N), axis=1) \
+        & (q[:, 3] <= q[:, 4]) & (q[:, 5] <= q[:, 6])
+    assert query.count_invalid(q, nu, nv, nl, N) == int((~same).sum())
