@@ -139,7 +139,7 @@ def test_fp8_decode_matches_the_format_on_every_code():
 
 
 CASES = [("f32", "f32", 16), ("f32", "f32", 32), ("f32", "f32", 64), ("f32", "f32", 128),
-         ("f32", "f32", 256), ("bf16", "bf16", 16), ("bf16", "bf16", 128), ("bf16", "f32", 64),
+         ("f32", "f32", 256), ("bf16", "bf16", 16), ("bf16", "bf16", 64), ("bf16", "bf16", 128), ("bf16", "f32", 64),
          ("fp8", "bf16", 256), ("fp8", "bf16", 32), ("fp8", "fp8", 64), ("f32", "bf16", 64)]
 
 
