@@ -41,9 +41,9 @@ FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix
 # were taken with (sha1 of the whole file: a kernel's instantiation depends on
 # helpers and constants outside its own text); otherwise traffic is null.
 MEASURED_TRAFFIC = {
-    "k_mttkrp_y": ("paper_2109_14807_amd/csrc/cp_als.hip", "8f1fc0087c76e7f0be86b1f48cccf40f66e4460d", 36584503008),
-    "k_mttkrp_z": ("paper_2109_14807_amd/csrc/cp_als.hip", "8f1fc0087c76e7f0be86b1f48cccf40f66e4460d", 34936716250),
-    "k_query": ("paper_2109_14807_amd/csrc/query.hip", "43e4dd028aab408cdaee0685074a186d78ca2a37", 534831171),
+    "k_mttkrp_y": ("paper_2109_14807_amd/csrc/cp_als.hip", "8f1fc0087c76e7f0be86b1f48cccf40f66e4460d", 36586907645),
+    "k_mttkrp_z": ("paper_2109_14807_amd/csrc/cp_als.hip", "8f1fc0087c76e7f0be86b1f48cccf40f66e4460d", 34935925110),
+    "k_query": ("paper_2109_14807_amd/csrc/query.hip", "d6f10014cb88e1951c8ba3dee2293774558184dd", 534756620),
 }
 
 
