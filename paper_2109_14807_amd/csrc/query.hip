@@ -269,6 +269,13 @@ __device__ __forceinline__ float lane_terms(const float* W, const float* sh, con
   }
 }
 
+// A resolved record of the flat query, 16 bytes: u | l << 26, v, and the
+// two tables' row pairs (hi | lo << 16): in LDS as byte offsets / 16, with
+// GC as row indices.
+struct alignas(16) PackedRows {
+  uint32_t ul, v, a, b;
+};
+
 // LDS layout of the flat query: L (FP32) at 0, CS at a 256-byte boundary,
 // CT half a bank width (128 bytes) past the next 256-byte boundary, then
 // the record slots.  With GC the summed-area tables stay in global memory.
@@ -313,7 +320,7 @@ __global__ __launch_bounds__(kQueryThreads) void k_query(QueryArgs a) {
   float* Ls = lds;
   LT* CSs = reinterpret_cast<LT*>(lds_b + lay.cs);
   LT* CTs = reinterpret_cast<LT*>(lds_b + lay.ct);
-  QueryRows* rows = reinterpret_cast<QueryRows*>(lds_b + lay.rows);
+  PackedRows* rows = reinterpret_cast<PackedRows*>(lds_b + lay.rows);
   const CT* CSg = static_cast<const CT*>(a.CS);
   const CT* CTg = static_cast<const CT*>(a.CT);
   stage_table<FT>(Ls, static_cast<const FT*>(a.L), a.nl, R, &a.scale);
@@ -333,7 +340,7 @@ __global__ __launch_bounds__(kQueryThreads) void k_query(QueryArgs a) {
   const int r0 = j * CHR;
   // record slots: query g*LPQ + jj sits at g*(LPQ+1) + jj, so the groups' slots
   // do not share LDS banks when read back
-  QueryRows* wrows = rows + (threadIdx.x >> 6) * kSlots;
+  PackedRows* wrows = rows + (threadIdx.x >> 6) * kSlots;
   const int my_slot = lane + lane / LPQ;
   // the lane's own columns of the LDS summed-area rows (record offsets are bytes from lds)
   const unsigned char* cum_lane = lds_b + r0 * sizeof(LT);
@@ -354,25 +361,25 @@ __global__ __launch_bounds__(kQueryThreads) void k_query(QueryArgs a) {
       const int slo = glint_clampi(f[3], 0, a.N), shi = glint_clampi(f[4], 0, a.N);
       const int tlo = glint_clampi(f[5], 0, a.N), thi = glint_clampi(f[6], 0, a.N);
       const bool empty = !(slo < shi && tlo < thi);
-      QueryRows r;
-      r.u = u * R;
-      r.v = v * R;
-      r.l = l * R;
-      const int s_hi = (empty ? slo : shi) * R, s_lo = slo * R, t_hi = thi * R, t_lo = tlo * R;
+      const int s_hi = empty ? slo : shi;
+      PackedRows r;
+      r.ul = static_cast<uint32_t>(u) | static_cast<uint32_t>(l) << 26;
+      r.v = static_cast<uint32_t>(v);
       if constexpr (GC) {
-        // element offsets into the global tables
-        r.sh = s_hi; r.sl = s_lo; r.th = t_hi; r.tl = t_lo;
+        // row indices into the global tables
+        r.a = static_cast<uint32_t>(s_hi) | static_cast<uint32_t>(slo) << 16;
+        r.b = static_cast<uint32_t>(thi) | static_cast<uint32_t>(tlo) << 16;
       } else {
-        // byte offsets from lds; the group that serves this query (lane / LPQ)
-        // takes CT first when odd
-        constexpr int E = static_cast<int>(sizeof(LT));
-        const int cs = static_cast<int>(lay.cs), ct = static_cast<int>(lay.ct);
+        // byte offsets from lds / 16; the group that serves this query
+        // (lane / LPQ) takes CT first when odd
+        constexpr uint32_t RB = static_cast<uint32_t>(sizeof(LT)) * R;   // bytes per row
+        const uint32_t cs = static_cast<uint32_t>(lay.cs), ct = static_cast<uint32_t>(lay.ct);
+        const uint32_t sp = ((cs + s_hi * RB) >> 4) | ((cs + slo * RB) >> 4) << 16;
+        const uint32_t tp = ((ct + thi * RB) >> 4) | ((ct + tlo * RB) >> 4) << 16;
         const bool odd = (lane / LPQ) & 1;
-        const int ah = cs + s_hi * E, al = cs + s_lo * E, bh = ct + t_hi * E, bl = ct + t_lo * E;
-        r.sh = odd ? bh : ah; r.sl = odd ? bl : al;
-        r.th = odd ? ah : bh; r.tl = odd ? al : bl;
+        r.a = odd ? tp : sp;
+        r.b = odd ? sp : tp;
       }
-      r.pad = 0;
       wrows[my_slot] = r;
     }
     __builtin_amdgcn_wave_barrier();
@@ -381,31 +388,35 @@ __global__ __launch_bounds__(kQueryThreads) void k_query(QueryArgs a) {
     // g*LPQ + j.  The footprint product W = U*V*L is reused while consecutive
     // queries share (u, v, l) (several angular boxes of one shading point).
     float res = 0.0f;
-    int pu = -1, pv = -1, pl = -1;
+    uint32_t pul = ~0u, pv = ~0u;
     float W[RPL];
 #pragma unroll 2
     for (int jj = 0; jj < LPQ; ++jj) {
-      const QueryRows r = wrows[g * (LPQ + 1) + jj];
-      if (r.u != pu || r.v != pv || r.l != pl) {
+      const PackedRows r = wrows[g * (LPQ + 1) + jj];
+      if (r.ul != pul || r.v != pv) {
         float uu[RPL], vv[RPL], lr[RPL];
-        load_chunks<FT, RPL, CHR, STR>(U + r.u + r0, 0, uu);
-        load_chunks<FT, RPL, CHR, STR>(V + r.v + r0, 0, vv);
-        lds_chunks<RPL, CHR, STR>(Ls + r.l + r0, 0, lr);
+        load_chunks<FT, RPL, CHR, STR>(U + static_cast<int64_t>(r.ul & 0x3ffffffu) * R + r0, 0, uu);
+        load_chunks<FT, RPL, CHR, STR>(V + static_cast<int64_t>(r.v) * R + r0, 0, vv);
+        lds_chunks<RPL, CHR, STR>(Ls + (r.ul >> 26) * R + r0, 0, lr);
 #pragma unroll
         for (int e = 0; e < RPL; ++e) W[e] = uu[e] * vv[e] * lr[e];
-        pu = r.u; pv = r.v; pl = r.l;
+        pul = r.ul; pv = r.v;
       }
       float sh[RPL], sl[RPL], th[RPL], tl[RPL];
       if constexpr (GC) {
-        cum_chunks<true, CT, LT, RPL, CHR, STR>(CSs, CSg, r.sh + r0, 0, sh);
-        cum_chunks<true, CT, LT, RPL, CHR, STR>(CSs, CSg, r.sl + r0, 0, sl);
-        cum_chunks<true, CT, LT, RPL, CHR, STR>(CTs, CTg, r.th + r0, 0, th);
-        cum_chunks<true, CT, LT, RPL, CHR, STR>(CTs, CTg, r.tl + r0, 0, tl);
+        cum_chunks<true, CT, LT, RPL, CHR, STR>(CSs, CSg, static_cast<int>(r.a & 0xffffu) * R + r0, 0, sh);
+        cum_chunks<true, CT, LT, RPL, CHR, STR>(CSs, CSg, static_cast<int>(r.a >> 16) * R + r0, 0, sl);
+        cum_chunks<true, CT, LT, RPL, CHR, STR>(CTs, CTg, static_cast<int>(r.b & 0xffffu) * R + r0, 0, th);
+        cum_chunks<true, CT, LT, RPL, CHR, STR>(CTs, CTg, static_cast<int>(r.b >> 16) * R + r0, 0, tl);
       } else {
-        cum_chunks<false, CT, LT, RPL, CHR, STR>(reinterpret_cast<const LT*>(cum_lane + r.sh), CSg, 0, 0, sh);
-        cum_chunks<false, CT, LT, RPL, CHR, STR>(reinterpret_cast<const LT*>(cum_lane + r.sl), CSg, 0, 0, sl);
-        cum_chunks<false, CT, LT, RPL, CHR, STR>(reinterpret_cast<const LT*>(cum_lane + r.th), CTg, 0, 0, th);
-        cum_chunks<false, CT, LT, RPL, CHR, STR>(reinterpret_cast<const LT*>(cum_lane + r.tl), CTg, 0, 0, tl);
+        const LT* ah = reinterpret_cast<const LT*>(cum_lane + ((r.a & 0xffffu) << 4));
+        const LT* al = reinterpret_cast<const LT*>(cum_lane + ((r.a >> 16) << 4));
+        const LT* bh = reinterpret_cast<const LT*>(cum_lane + ((r.b & 0xffffu) << 4));
+        const LT* bl = reinterpret_cast<const LT*>(cum_lane + ((r.b >> 16) << 4));
+        cum_chunks<false, CT, LT, RPL, CHR, STR>(ah, CSg, 0, 0, sh);
+        cum_chunks<false, CT, LT, RPL, CHR, STR>(al, CSg, 0, 0, sl);
+        cum_chunks<false, CT, LT, RPL, CHR, STR>(bh, CTg, 0, 0, th);
+        cum_chunks<false, CT, LT, RPL, CHR, STR>(bl, CTg, 0, 0, tl);
       }
       float acc = lane_terms<RPL, CHR>(W, sh, sl, th, tl, 0);
       acc = glint_group_sum<LPQ>(acc);
@@ -1300,7 +1311,10 @@ glint_status launch_query(const QueryArgs& a, hipStream_t stream) {
   typedef QueryPlan<FT, CT, R> P;
   typedef typename P::LT LT;
   constexpr int RPL = P::RPL;
-  const size_t slots = sizeof(QueryRows) * (kQueryThreads / 64) * (64 + 64 / (R / RPL));
+  // the packed records hold u in 26 bits and l in 6, LDS offsets / 16 in 16
+  if (a.nu > (1 << 26) || a.nl > 64)
+    return glint_fail(GLINT_E_UNSUPPORTED, "the flat query takes nu <= 2^26 and nl <= 64 (nu %d, nl %d)", a.nu, a.nl);
+  const size_t slots = sizeof(PackedRows) * (kQueryThreads / 64) * (64 + 64 / (R / RPL));
   const bool gc = query_lds(a.nl, a.N, R, sizeof(LT), false, slots).total > static_cast<size_t>(g_max_lds);
   const size_t lds = query_lds(a.nl, a.N, R, sizeof(LT), gc, slots).total;
   if (lds > static_cast<size_t>(g_max_lds))
