@@ -41,9 +41,9 @@ FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix
 # were taken with (sha1 of the whole file: a kernel's instantiation depends on
 # helpers and constants outside its own text); otherwise traffic is null.
 MEASURED_TRAFFIC = {
-    "k_mttkrp_y": ("paper_2109_14807_amd/csrc/cp_als.hip", "8f1fc0087c76e7f0be86b1f48cccf40f66e4460d", 36586907645),
-    "k_mttkrp_z": ("paper_2109_14807_amd/csrc/cp_als.hip", "8f1fc0087c76e7f0be86b1f48cccf40f66e4460d", 34935925110),
-    "k_query": ("paper_2109_14807_amd/csrc/query.hip", "d6f10014cb88e1951c8ba3dee2293774558184dd", 534756620),
+    "k_mttkrp_y": ("paper_2109_14807_amd/csrc/cp_als.hip", "8f1fc0087c76e7f0be86b1f48cccf40f66e4460d", 36579789723),
+    "k_mttkrp_z": ("paper_2109_14807_amd/csrc/cp_als.hip", "8f1fc0087c76e7f0be86b1f48cccf40f66e4460d", 34935632209),
+    "k_query": ("paper_2109_14807_amd/csrc/query.hip", "614826453c911d776e1a4a8e380695c6589614c0", 534688525),
 }
 
 
@@ -417,10 +417,20 @@ def refine_report(cfg, nxy_h, desc, F, q, q_bf, steps, timed):
     torch.cuda.synchronize()
     t_ref = time.perf_counter() - t0
     bf16 = G.make_tables(*refined, dtype="bf16", cum_dtype="bf16")
+    plain_bf16 = G.make_tables(*masters, dtype="bf16", cum_dtype="bf16")
     out = torch.empty(q.shape[0], dtype=torch.float32, device=dev)
-    f_plain, f_bf16 = plain.factors(), bf16.factors()
+    f_plain, f_bf16, f_pb = plain.factors(), bf16.factors(), plain_bf16.factors()
     ms_plain = timed(lambda: L.glint_query(f_plain, q, out))
     ms_bf16 = timed(lambda: L.glint_query(f_bf16, q, out))
+    ms_pb = timed(lambda: L.glint_query(f_pb, q, out))
+    ms_plain2 = timed(lambda: L.glint_query(f_plain, q, out))
+
+    def subnormal(tabs):
+        n = 0
+        for t in (tabs.U, tabs.V, tabs.L, tabs.CS, tabs.CT):
+            x = t.float().abs()
+            n += int(((x > 0) & (x < torch.finfo(torch.float32).tiny)).sum().item())
+        return n
     e_plain, e_bf16 = ebf(plain), ebf(bf16)
     ls = losses.cpu().numpy()
     return {
@@ -430,6 +440,8 @@ def refine_report(cfg, nxy_h, desc, F, q, q_bf, steps, timed):
         "error_vs_bruteforce_plain_f32": e_plain,
         "error_vs_bruteforce_refined_bf16": e_bf16,
         "query_ms_plain_f32": ms_plain, "query_ms_refined_bf16": ms_bf16,
+        "query_ms_plain_bf16": ms_pb, "query_ms_plain_f32_again": ms_plain2,
+        "subnormal_entries_refined_bf16": subnormal(bf16),
         "speedup_bf16_over_f32": ms_plain / ms_bf16,
         "equal_or_lower_error": bool(e_bf16 <= e_plain),
     }
