@@ -305,7 +305,7 @@ def main():
             "traffic": measured_traffic("k_mttkrp_z"), "launches_per_step": args.sweeps,
         },
         "query_kernel": {
-            "kernel": "k_query<float,float,float,64,8>", "ms": query_ms, "queries_per_s": nq / (query_ms * 1e-3),
+            "kernel": "k_query<float,float,float,64,8,1024>", "ms": query_ms, "queries_per_s": nq / (query_ms * 1e-3),
             "roofline": {"bound": "hbm", "achieved": q_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": q_gbs / HBM_PEAK_GBS, "traffic": measured_traffic("k_query"),
                          "algorithmic_bytes_per_query": 32,
@@ -323,7 +323,7 @@ def main():
             "samples": npix, "ms": sample_ms, "samples_per_s": npix / (sample_ms * 1e-3),
         },
         "sg_prefilter_kernel": {
-            "kernel": "glint_query_sg: k_sg_records + k_query<float,float,float,64,8> + k_box_average, one "
+            "kernel": "glint_query_sg: k_sg_records + k_query<float,float,float,64,8,1024> + k_box_average, one "
                       "compact-eps SG box per pixel footprint of the frame, averaged",
             "lookups": npix, "ms": sg_ms, "lookups_per_s": npix / (sg_ms * 1e-3),
         },

@@ -308,8 +308,11 @@ __host__ __device__ inline QueryLds query_lds(int nl, int N, int R, size_t lt_by
 // odd groups read the CT rows where even groups read the CS rows (CT sits
 // half a bank width off CS).  The term of a rank is W (dS dT), symmetric in
 // the two tables, so the swap leaves every value unchanged.
-template <typename FT, typename CT, typename LT, int R, int RPL, bool GC>
-__global__ __launch_bounds__(kQueryThreads) void k_query(QueryArgs a) {
+// NT threads per block; at 1024 the compiler is held to 64 VGPRs (eight
+// waves per SIMD), so two blocks of 16 waves share a CU with one copy of
+// the tables each.
+template <typename FT, typename CT, typename LT, int R, int RPL, bool GC, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 1024 ? 8 : 1))) void k_query(QueryArgs a) {
   constexpr int LPQ = R / RPL;           // lanes per query
   static_assert(LPQ >= 1 && LPQ <= 64, "lanes per query");
   static_assert(std::is_same<LT, float>::value || std::is_same<LT, CT>::value, "LDS copy type");
@@ -1304,6 +1307,14 @@ struct QueryPlan {
   static constexpr bool kF32Lds = sizeof(FT) == 2 && R == 64;
   static constexpr int RPL = kF32Lds ? 8 : rpl_for<FT, R>();
   typedef typename std::conditional<kF32Lds, float, typename LdsCum<CT>::type>::type LT;
+  // 1024-thread blocks where the kernel fits 64 VGPRs at little cost: FP32
+  // factor rows up to rank 64 and the BF16 rank-64 layout (5% and 4% faster
+  // at rank 64).  The rest keep 512: BF16 LDS rows at rank 128 spill and run
+  // 7x slower, FP32 rank 128 is 2% slower, FP8 factor rows (32 ranks a lane)
+  // would spill hundreds of bytes.
+  static constexpr int NT =
+      std::is_same<LT, float>::value && (sizeof(FT) == 4 ? R <= 64 : (sizeof(FT) == 2 && R == 64)) ? 1024
+                                                                                                   : kQueryThreads;
 };
 
 template <typename FT, typename CT, int R>
@@ -1314,23 +1325,24 @@ glint_status launch_query(const QueryArgs& a, hipStream_t stream) {
   // the packed records hold u in 26 bits and l in 6, LDS offsets / 16 in 16
   if (a.nu > (1 << 26) || a.nl > 64)
     return glint_fail(GLINT_E_UNSUPPORTED, "the flat query takes nu <= 2^26 and nl <= 64 (nu %d, nl %d)", a.nu, a.nl);
-  const size_t slots = sizeof(PackedRows) * (kQueryThreads / 64) * (64 + 64 / (R / RPL));
+  constexpr int NT = P::NT;
+  const size_t slots = sizeof(PackedRows) * (NT / 64) * (64 + 64 / (R / RPL));
   const bool gc = query_lds(a.nl, a.N, R, sizeof(LT), false, slots).total > static_cast<size_t>(g_max_lds);
   const size_t lds = query_lds(a.nl, a.N, R, sizeof(LT), gc, slots).total;
   if (lds > static_cast<size_t>(g_max_lds))
     return glint_fail(GLINT_E_UNSUPPORTED, "L needs %zu bytes of LDS (device max %d)", lds, g_max_lds);
   const int64_t waves_needed = (a.nq + 63) / 64;
-  constexpr int WPB = kQueryThreads / 64;
+  constexpr int WPB = NT / 64;
   int64_t blocks = (waves_needed + WPB - 1) / WPB;
-  const int64_t cap = static_cast<int64_t>(g_cu_count) * 4;
+  const int64_t cap = static_cast<int64_t>(g_cu_count) * (2048 / NT);
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
   glint_clear_launch_error();
-  const dim3 grid(static_cast<unsigned>(blocks)), block(kQueryThreads);
+  const dim3 grid(static_cast<unsigned>(blocks)), block(NT);
   if (gc)
-    hipLaunchKernelGGL((k_query<FT, CT, LT, R, RPL, true>), grid, block, lds, stream, a);
+    hipLaunchKernelGGL((k_query<FT, CT, LT, R, RPL, true, NT>), grid, block, lds, stream, a);
   else
-    hipLaunchKernelGGL((k_query<FT, CT, LT, R, RPL, false>), grid, block, lds, stream, a);
+    hipLaunchKernelGGL((k_query<FT, CT, LT, R, RPL, false, NT>), grid, block, lds, stream, a);
   GLINT_LAUNCHED("k_query");
   return GLINT_OK;
 }
