@@ -313,12 +313,12 @@ def main():
                                  "show the on-chip gathers (LDS issue, 7R values per query) binding instead"},
         },
         "query_trilinear_kernel": {
-            "kernel": "k_query_trilinear<float,float,64,4>: the batch at fractional centres and levels "
+            "kernel": "k_query_trilinear<float,float,64,8>: the batch at fractional centres and levels "
                       "(eight-footprint trilinear blend, two rows per factor)",
             "ms": tri_ms, "queries_per_s": nq / (tri_ms * 1e-3),
         },
         "sample_kernel": {
-            "kernel": f"k_sample<float,float,64,4>: one hierarchical NDF importance sample ({levels} levels of "
+            "kernel": f"k_sample<float,float,64,8>: one hierarchical NDF importance sample ({levels} levels of "
                       "four-quad range queries) per pixel footprint of the frame",
             "samples": npix, "ms": sample_ms, "samples_per_s": npix / (sample_ms * 1e-3),
         },

@@ -312,9 +312,12 @@ glint_status glint_convert(int64_t rows, int32_t R, const void* in, glint_dtype 
 
 /* out[i] for each record q[i] (int32 [nq][7], see the header comment), FP32
  * arithmetic on values decoded exactly from their storage types.
- * nq = 0 is a no-op.  Requires f->nbins in 4..256.  L is staged in LDS as
- * FP32 (nl * R * 4 bytes); CS and CT are staged there too (as BF16 when so
- * stored, else FP32) when they fit, and otherwise read from global memory. */
+ * nq = 0 is a no-op.  Requires f->nbins in 4..256, f->nu <= 2^26 and
+ * f->nl <= 64 (records are resolved into 16-byte packed rows; larger maps
+ * or level counts return GLINT_E_UNSUPPORTED before any launch).  L is
+ * staged in LDS as FP32 (nl * R * 4 bytes); CS and CT are staged there too
+ * (as FP32, or as BF16 when so stored beyond rank 64) when they fit, and
+ * otherwise read from global memory. */
 glint_status glint_query(const glint_factors* f, int64_t nq, const int32_t* q,
                          float* out, hipStream_t stream);
 

@@ -554,10 +554,13 @@ struct TriArgs {
   float* out;
 };
 
+// A resolved trilinear record, 32 bytes: u0 | l0 << 26, v0, the two tables'
+// row pairs (hi | lo << 16, row indices) and the three blend weights; the
+// upper corners u0 + 1, v0 + 1 (wrapped) and l0 + 1 (clamped) are derived
+// when the footprint changes.
 struct alignas(16) TriRows {
-  int u0, u1, v0, v1, l0, l1, sh, sl, th, tl;
-  float wx, wy, wl;
-  int pad[3];
+  uint32_t ul, v, s, t;
+  float wx, wy, wl, pad;
 };
 
 constexpr float kCoordLimit = 16777216.0f;
@@ -615,20 +618,14 @@ __global__ __launch_bounds__(kQueryThreads) void k_query_trilinear(TriArgs a) {
       const int tlo = glint_clampi(b2, 0, a.N), thi = glint_clampi(b3, 0, a.N);
       const bool empty = !(slo < shi && tlo < thi);
       TriRows r;
-      r.u0 = glint_wrap(ix, a.nu) * R;
-      r.u1 = glint_wrap(ix + 1, a.nu) * R;
-      r.v0 = glint_wrap(iy, a.nv) * R;
-      r.v1 = glint_wrap(iy + 1, a.nv) * R;
-      r.l0 = il * R;
-      r.l1 = min(il + 1, a.nl - 1) * R;
-      r.sh = (empty ? slo : shi) * R;
-      r.sl = slo * R;
-      r.th = thi * R;
-      r.tl = tlo * R;
+      r.ul = static_cast<uint32_t>(glint_wrap(ix, a.nu)) | static_cast<uint32_t>(il) << 26;
+      r.v = static_cast<uint32_t>(glint_wrap(iy, a.nv));
+      r.s = static_cast<uint32_t>(empty ? slo : shi) | static_cast<uint32_t>(slo) << 16;
+      r.t = static_cast<uint32_t>(thi) | static_cast<uint32_t>(tlo) << 16;
       r.wx = x - fx;
       r.wy = y - fy;
       r.wl = lam - fl;
-      r.pad[0] = r.pad[1] = r.pad[2] = 0;
+      r.pad = 0.0f;
       wrows[my_slot] = r;
     }
     __builtin_amdgcn_wave_barrier();
@@ -636,31 +633,35 @@ __global__ __launch_bounds__(kQueryThreads) void k_query_trilinear(TriArgs a) {
     float res = 0.0f;
     // the interpolated footprint product is reused while consecutive records
     // share the centre and level (several boxes of one shading point)
-    int pu0 = -1, pv0 = -1, pl0 = -1;
+    uint32_t pul = ~0u, pv = ~0u;
     float pwx = -1.0f, pwy = -1.0f, pwl = -1.0f;
     float W[RPL];
     for (int jj = 0; jj < LPQ; ++jj) {
       const TriRows r = wrows[g * (LPQ + 1) + jj];
-      if (r.u0 != pu0 || r.v0 != pv0 || r.l0 != pl0 || r.wx != pwx || r.wy != pwy || r.wl != pwl) {
+      if (r.ul != pul || r.v != pv || r.wx != pwx || r.wy != pwy || r.wl != pwl) {
+        const int u0 = static_cast<int>(r.ul & 0x3ffffffu), l0 = static_cast<int>(r.ul >> 26);
+        const int v0 = static_cast<int>(r.v);
+        const int u1 = u0 + 1 == a.nu ? 0 : u0 + 1, v1 = v0 + 1 == a.nv ? 0 : v0 + 1;
+        const int l1 = min(l0 + 1, a.nl - 1);
         float ua[RPL], ub[RPL], va[RPL], vb[RPL], la[RPL], lb[RPL];
-        load_chunks<FT, RPL, CHR, STR>(U + r.u0 + r0, rot, ua);
-        load_chunks<FT, RPL, CHR, STR>(U + r.u1 + r0, rot, ub);
-        load_chunks<FT, RPL, CHR, STR>(V + r.v0 + r0, rot, va);
-        load_chunks<FT, RPL, CHR, STR>(V + r.v1 + r0, rot, vb);
-        lds_chunks<RPL, CHR, STR>(Ls + r.l0 + r0, rot, la);
-        lds_chunks<RPL, CHR, STR>(Ls + r.l1 + r0, rot, lb);
+        load_chunks<FT, RPL, CHR, STR>(U + static_cast<int64_t>(u0) * R + r0, rot, ua);
+        load_chunks<FT, RPL, CHR, STR>(U + static_cast<int64_t>(u1) * R + r0, rot, ub);
+        load_chunks<FT, RPL, CHR, STR>(V + static_cast<int64_t>(v0) * R + r0, rot, va);
+        load_chunks<FT, RPL, CHR, STR>(V + static_cast<int64_t>(v1) * R + r0, rot, vb);
+        lds_chunks<RPL, CHR, STR>(Ls + l0 * R + r0, rot, la);
+        lds_chunks<RPL, CHR, STR>(Ls + l1 * R + r0, rot, lb);
 #pragma unroll
         for (int e = 0; e < RPL; ++e)
           W[e] = (ua[e] + r.wx * (ub[e] - ua[e])) * (va[e] + r.wy * (vb[e] - va[e])) *
                  (la[e] + r.wl * (lb[e] - la[e]));
-        pu0 = r.u0; pv0 = r.v0; pl0 = r.l0;
+        pul = r.ul; pv = r.v;
         pwx = r.wx; pwy = r.wy; pwl = r.wl;
       }
       float sh[RPL], sl[RPL], th[RPL], tl[RPL];
-      cum_chunks<GC, CT, LT, RPL, CHR, STR>(CSs, CSg, r.sh + r0, rot, sh);
-      cum_chunks<GC, CT, LT, RPL, CHR, STR>(CSs, CSg, r.sl + r0, rot, sl);
-      cum_chunks<GC, CT, LT, RPL, CHR, STR>(CTs, CTg, r.th + r0, rot, th);
-      cum_chunks<GC, CT, LT, RPL, CHR, STR>(CTs, CTg, r.tl + r0, rot, tl);
+      cum_chunks<GC, CT, LT, RPL, CHR, STR>(CSs, CSg, static_cast<int>(r.s & 0xffffu) * R + r0, rot, sh);
+      cum_chunks<GC, CT, LT, RPL, CHR, STR>(CSs, CSg, static_cast<int>(r.s >> 16) * R + r0, rot, sl);
+      cum_chunks<GC, CT, LT, RPL, CHR, STR>(CTs, CTg, static_cast<int>(r.t & 0xffffu) * R + r0, rot, th);
+      cum_chunks<GC, CT, LT, RPL, CHR, STR>(CTs, CTg, static_cast<int>(r.t >> 16) * R + r0, rot, tl);
       float acc = lane_terms<RPL, CHR>(W, sh, sl, th, tl, rot);
       acc = glint_group_sum<LPQ>(acc);
       res = (j == jj) ? acc : res;
@@ -1375,6 +1376,10 @@ glint_status launch_grouped(const GroupedArgs& a, hipStream_t stream) {
 template <typename FT, typename CT, int R>
 glint_status launch_trilinear(const TriArgs& a, hipStream_t stream) {
   constexpr int RPL = rpl_for<FT, R>();
+  // the packed records hold u in 26 bits and l in 6
+  if (a.nu > (1 << 26) || a.nl > 64)
+    return glint_fail(GLINT_E_UNSUPPORTED, "the trilinear query takes nu <= 2^26 and nl <= 64 (nu %d, nl %d)", a.nu,
+                      a.nl);
   const size_t slots = sizeof(TriRows) * (kQueryThreads / 64) * (64 + 64 / (R / RPL));
   const bool gc = static_cast<int>(query_lds_bytes<CT, R>(a.nl, a.N, false, slots)) > g_max_lds;
   const size_t lds = query_lds_bytes<CT, R>(a.nl, a.N, gc, slots);

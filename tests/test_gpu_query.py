@@ -346,3 +346,22 @@ def test_validate_queries_counts_exactly(nq):
     assert G.validate_queries(tabs, q) == got[0]
     if nq > 8:
         assert got[0] > 0 and query.count_invalid(q[-5:-3], nu, nv, nl, N) == 0
+
+
+def test_query_rejects_sizes_beyond_packed_records():
+    """Maps wider than 2^26 texels or more than 64 levels are refused on the
+    host before any launch (the output is left as it was)."""
+    rng = np.random.default_rng(3)
+    F = _rand_factors(rng, 8, 8, 3, 16, 16)
+    tabs = G.make_tables(*[torch.tensor(x, device="cuda") for x in F])
+    q = torch.tensor(_rand_queries(rng, 100, 8, 8, 3, 16), device="cuda")
+    out = torch.full((100,), 7.0, device="cuda")
+    for field, value in (("nu", (1 << 26) + 1), ("nl", 65)):
+        f = tabs.factors()
+        setattr(f, field, value)
+        with pytest.raises(G.GlintError):
+            G._lib.glint_query(f, q, out)
+    assert torch.all(out == 7.0)
+    f = tabs.factors()
+    G._lib.glint_query(f, q, out)
+    assert not torch.all(out == 7.0)
