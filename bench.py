@@ -41,9 +41,9 @@ FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix
 # were taken with (sha1 of the whole file: a kernel's instantiation depends on
 # helpers and constants outside its own text); otherwise traffic is null.
 MEASURED_TRAFFIC = {
-    "k_mttkrp_y": ("paper_2109_14807_amd/csrc/cp_als.hip", "8f1fc0087c76e7f0be86b1f48cccf40f66e4460d", 36582288592),
-    "k_mttkrp_z": ("paper_2109_14807_amd/csrc/cp_als.hip", "8f1fc0087c76e7f0be86b1f48cccf40f66e4460d", 34937733082),
-    "k_query": ("paper_2109_14807_amd/csrc/query.hip", "cac8c2daee6e540e32da574de72fc0789891bd49", 538665914),
+    "k_mttkrp_y": ("paper_2109_14807_amd/csrc/cp_als.hip", "8f1fc0087c76e7f0be86b1f48cccf40f66e4460d", 36580068392),
+    "k_mttkrp_z": ("paper_2109_14807_amd/csrc/cp_als.hip", "8f1fc0087c76e7f0be86b1f48cccf40f66e4460d", 34936702917),
+    "k_query": ("paper_2109_14807_amd/csrc/query.hip", "62bcaefe675668a679f218db5c4c145c6ceefd8e", 538682213),
 }
 
 
