@@ -810,8 +810,20 @@ __global__ __launch_bounds__(kClSampleThreads) void k_sample_clustered(ClSampleA
   const int f = ((u % a.cs) * a.cs + v % a.cs) * a.nl + l;
   const float* rn = a.rnd + i * (a.levels + 3);
   const int nblk = a.nb * a.nb, t = a.t;
+  // up to kCachedBlocks block masses stay in registers for the search
+  constexpr int kCachedBlocks = 16;
+  const bool cached = nblk <= kCachedBlocks;
+  float bm[kCachedBlocks];
   float total = 0.0f;
-  for (int b = 0; b < nblk; ++b) total += fmaxf(cl_box<R>(a, tensor0 + b, f, 0, t, 0, t), 0.0f);
+  if (cached) {
+#pragma unroll
+    for (int b = 0; b < kCachedBlocks; ++b) {
+      bm[b] = b < nblk ? fmaxf(cl_box<R>(a, tensor0 + b, f, 0, t, 0, t), 0.0f) : 0.0f;
+      total += bm[b];
+    }
+  } else {
+    for (int b = 0; b < nblk; ++b) total += fmaxf(cl_box<R>(a, tensor0 + b, f, 0, t, 0, t), 0.0f);
+  }
   a.h[2 * i] = 0.0f;
   a.h[2 * i + 1] = 0.0f;
   a.pdf[i] = 0.0f;
@@ -821,17 +833,35 @@ __global__ __launch_bounds__(kClSampleThreads) void k_sample_clustered(ClSampleA
   const float target = rn[0] * total;
   float run = 0.0f, pm = 0.0f, lastm = 0.0f;
   int pick = -1, lastpos = 0;
-  for (int b = 0; b < nblk; ++b) {
-    const float m = fmaxf(cl_box<R>(a, tensor0 + b, f, 0, t, 0, t), 0.0f);
-    if (m > 0.0f) {
-      lastpos = b;
-      lastm = m;
+  if (cached) {
+#pragma unroll
+    for (int b = 0; b < kCachedBlocks; ++b) {
+      if (b < nblk && pick < 0) {
+        const float m = bm[b];
+        if (m > 0.0f) {
+          lastpos = b;
+          lastm = m;
+        }
+        run += m;
+        if (target < run) {
+          pick = b;
+          pm = m;
+        }
+      }
     }
-    run += m;
-    if (target < run) {
-      pick = b;
-      pm = m;
-      break;
+  } else {
+    for (int b = 0; b < nblk; ++b) {
+      const float m = fmaxf(cl_box<R>(a, tensor0 + b, f, 0, t, 0, t), 0.0f);
+      if (m > 0.0f) {
+        lastpos = b;
+        lastm = m;
+      }
+      run += m;
+      if (target < run) {
+        pick = b;
+        pm = m;
+        break;
+      }
     }
   }
   if (pick < 0) {
