@@ -261,6 +261,20 @@ def main():
     sg_out = torch.empty(npix, dtype=torch.float32, device=dev)
     sg_ms = timed(lambda: L.glint_query_sg(fac, s_uvl, sg_h, sg_p, 0.3, sg_q, sg_out))
     del s_uvl, s_rnd, s_h, s_pdf, s_bins, sg_h, sg_p, sg_q, sg_out
+    # Wang-tile synthesis: 16 tiles of 64^2 texels (8-texel margins, 5 levels, rank 16,
+    # random FP32 tables: the query's cost does not depend on their values); the frame's
+    # records read as plane coordinates, levels taken mod 5
+    gw = np.random.default_rng(8)
+    wS, wm, wnl, wR = 64, 8, 5, 16
+    wF = [[torch.tensor(gw.random((n, wR)) * 0.1, device=dev) for n in (wS + 2 * wm, wS + 2 * wm, wnl, N, N)]
+          for _ in range(16)]
+    wtab = G.wang_tables(wF, wS, wm, 2024, gw.permutation(16))
+    wq = q.clone()
+    wq[:, 2] = torch.remainder(q[:, 2], wnl)
+    wout = torch.empty(nq, dtype=torch.float32, device=dev)
+    wstruct = wtab.struct()
+    wang_ms = timed(lambda: L.glint_query_wang(wstruct, wq, wout))
+    del wF, wtab, wq, wout
 
     ncells = cfg.nu * cfg.nv * nl
     t_elems = ncells * N * N
@@ -326,6 +340,12 @@ def main():
             "kernel": "glint_query_sg: k_sg_records + k_query<float,float,float,64,8,1024> + k_box_average, one "
                       "compact-eps SG box per pixel footprint of the frame, averaged",
             "lookups": npix, "ms": sg_ms, "lookups_per_s": npix / (sg_ms * 1e-3),
+        },
+        "wang_query_kernel": {
+            "kernel": "k_query_wang: range queries on the Wang-tile synthesized plane (16 tiles of 64^2 texels, "
+                      "8-texel margins, 5 levels, rank 16 FP32; per record the tile of every overlapped cell "
+                      "from the hashed edge colours, summed), the frame's records as plane coordinates",
+            "queries": nq, "ms": wang_ms, "queries_per_s": nq / (wang_ms * 1e-3),
         },
         "stages_ms": stage_ms,
         "events_ms_per_step": ev_total,
