@@ -415,7 +415,8 @@ typedef struct {
  * bins clamp as for glint_query; out[i] = the sum, over the cells the level-l
  * footprint centred on (x, y) overlaps, of that cell's tile query at centre
  * (x - iS + m, y - jS + m).  Requires 2m >= 2^(nl-1) so every overlapped
- * cell's centre lies in its tile's padded grid.  One thread per query, FP32. */
+ * cell's centre lies in its tile's padded grid, R a multiple of 4 and the
+ * tables 16-byte aligned.  One thread per query, FP32. */
 glint_status glint_query_wang(const glint_wang* w, int64_t nq, const int32_t* q, float* out,
                               hipStream_t stream);
 

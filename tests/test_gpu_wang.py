@@ -78,7 +78,7 @@ def test_query_wang_matches_oracle_on_the_same_tables():
 
 def test_query_wang_argument_errors():
     rng, etl, tiles, d = _setup()
-    F = [[np.ones((S + 2 * M, 1)), np.ones((S + 2 * M, 1)), np.ones((NL, 1)), np.ones((N, 1)), np.ones((N, 1))]] * 16
+    F = [[np.ones((S + 2 * M, 4)), np.ones((S + 2 * M, 4)), np.ones((NL, 4)), np.ones((N, 4)), np.ones((N, 4))]] * 16
     tab = G.wang_tables(F, S, M, SEED, etl)
     q = torch.zeros((1, 7), dtype=torch.int32)
     assert G.query_wang(tab, torch.zeros((0, 7), dtype=torch.int32)).numel() == 0
@@ -88,3 +88,6 @@ def test_query_wang_argument_errors():
     bad = G.wang_tables(F[:4], S, M, SEED, etl)        # edge_to_tile names tiles that do not exist
     with pytest.raises(G.GlintError):
         G.query_wang(bad, q)
+    F2 = [[np.ones((S + 2 * M, 2)), np.ones((S + 2 * M, 2)), np.ones((NL, 2)), np.ones((N, 2)), np.ones((N, 2))]] * 16
+    with pytest.raises(G.GlintError):                  # the rank must be a multiple of 4
+        G.query_wang(G.wang_tables(F2, S, M, SEED, etl), q)
