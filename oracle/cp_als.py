@@ -104,9 +104,26 @@ def cp_als(T: np.ndarray, init, iters: int, tol: float = 0.0, trace=None):
     is a list, every sweep's normalised factors and lambda are appended to it.
     """
     T = np.asarray(T, dtype=np.float64)
+    return _als(lambda A, n: mttkrp(T, A, n), float(np.sum(T * T)), init, iters, tol, trace)
+
+
+def cp_als_texel(ms: np.ndarray, mt: np.ndarray, nlevels: int, init, iters: int, normT2=None,
+                 tol: float = 0.0):
+    """The same ALS for the tensor of per-texel masses ms, mt ([nu][nv][N],
+    see ndf.texel_masses), with every MTTKRP taken by mttkrp_structured so the
+    tensor is never formed.  ||T||^2 is an input (it needs the tensor); when
+    it is None the fits are NaN and no tolerance stop is possible."""
+    ms = np.asarray(ms, dtype=np.float64)
+    mt = np.asarray(mt, dtype=np.float64)
+    if normT2 is None and tol > 0.0:
+        raise ValueError("a tolerance stop needs ||T||^2")
+    return _als(lambda A, n: mttkrp_structured(ms, mt, nlevels, A, n),
+                np.nan if normT2 is None else float(normT2), init, iters, tol, None)
+
+
+def _als(mttkrp_fn, normT2: float, init, iters: int, tol: float, trace):
     A = [np.array(a, dtype=np.float64, copy=True) for a in init]
     R = A[0].shape[1]
-    normT2 = float(np.sum(T * T))
     lam = np.ones(R)
     fits = []
     fallbacks = 0
@@ -114,7 +131,7 @@ def cp_als(T: np.ndarray, init, iters: int, tol: float = 0.0, trace=None):
     for it in range(iters):
         M = None
         for n in range(5):
-            M = mttkrp(T, A, n)
+            M = mttkrp_fn(A, n)
             G = gram_hadamard(A, n)
             X, fb = solve_gram(M, G)
             fallbacks += int(fb)
@@ -186,8 +203,10 @@ def mttkrp_structured(ms: np.ndarray, mt: np.ndarray, nlevels: int, A, n: int) -
             out += w * Hc
         elif n == 2:
             out[l] = np.einsum("xr,yr,xyr,xyr->r", Ub, Vb, gs, gt) / float(k * k)
-        elif n == 3:
-            out += np.einsum("xys,xyr,xr,yr->sr", ms, gt, Ub, Vb) * w
+        elif n == 3:   # sum_{x,y} ms[x,y,s] gt[x,y] Ub[x] Vb[y]: a product over texels, then a matmul
+            H = gt * Ub[:, None, :] * Vb[None, :, :]
+            out += (ms.reshape(-1, ms.shape[2]).T @ H.reshape(-1, R)) * w
         else:
-            out += np.einsum("xyt,xyr,xr,yr->tr", mt, gs, Ub, Vb) * w
+            H = gs * Ub[:, None, :] * Vb[None, :, :]
+            out += (mt.reshape(-1, mt.shape[2]).T @ H.reshape(-1, R)) * w
     return out

@@ -122,6 +122,29 @@ def range_query_magnitude(U, V, L, CS, CT, q, scale=None) -> np.ndarray:
     return out
 
 
+def range_query_term_magnitude(U, V, L, CS, CT, q, scale=None) -> np.ndarray:
+    """Sum of the magnitudes of the rank terms of Eq. rangeDecom:
+    M_q = sum_r |c_r U_r[u] V_r[v] L_r[l] (CS_r[s_hi] - CS_r[s_lo]) (CT_r[t_hi] - CT_r[t_lo])|.
+
+    An FP32 evaluation of the same stored values rounds each difference
+    relative to the difference itself (a correctly rounded subtraction), then
+    each product relative to the product, so every rank term is within a few
+    units in the last place of its own size and the rank sum is within a
+    rank-dependent multiple of M_q: M_q is the scale of a query's arithmetic
+    error.  (N_q above bounds it too, but loosely: for a narrow box the
+    summed-area values are much larger than their difference.)"""
+    U, V, L, CS, CT = (np.asarray(x, dtype=np.float64) for x in (U, V, L, CS, CT))
+    nu, nv, nl, N = U.shape[0], V.shape[0], L.shape[0], CS.shape[0] - 1
+    q = canonical_query(q, nu, nv, nl, N)
+    u, v, l, slo, shi, tlo, thi = q.T
+    P = U[u] * V[v] * L[l] * (CS[shi] - CS[slo]) * (CT[thi] - CT[tlo])
+    if scale is not None:
+        P = P * np.asarray(scale, dtype=np.float64)[None, :]
+    out = np.abs(P).sum(axis=1)
+    out[(slo >= shi) | (tlo >= thi)] = 0.0
+    return out
+
+
 def range_query_grad(U, V, L, CS, CT, q, g):
     """Gradients of sum_i g[i] * q[i] with respect to U, V, L, CS, CT (FP64)."""
     U, V, L, CS, CT = (np.asarray(x, dtype=np.float64) for x in (U, V, L, CS, CT))

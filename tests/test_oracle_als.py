@@ -139,3 +139,20 @@ def test_structured_mttkrp_equals_dense_on_c1():
         d = cp_als.mttkrp(T, A, n)
         s = cp_als.mttkrp_structured(ms, mt, cfg.nlevels, A, n)
         assert np.max(np.abs(d - s)) <= 1e-12 * np.max(np.abs(d)), n
+
+
+def test_texel_als_equals_dense_als_on_c1():
+    """The ALS driven by the structured MTTKRP follows the dense ALS on the
+    materialised 64x64 tensor sweep for sweep (factors and fits)."""
+    cfg = gen.config("c1")
+    nxy = gen.normal_map(cfg)
+    T = ndf.ndf_bruteforce(nxy, cfg.nbins, cfg.sigma, cfg.nlevels)
+    ms, mt = ndf.texel_masses(nxy, cfg.nbins, cfg.sigma)
+    init = gen.als_init(cfg)
+    dense = cp_als.cp_als(T, init, iters=2)
+    tex = cp_als.cp_als_texel(ms, mt, cfg.nlevels, init, iters=2, normT2=float(np.sum(T * T)))
+    for a, b in zip(tex["factors"], dense["factors"]):
+        assert np.max(np.abs(a - b)) <= 1e-10 * np.max(np.abs(b))
+    assert np.max(np.abs(tex["fits"] - dense["fits"])) < 1e-12
+    nofit = cp_als.cp_als_texel(ms, mt, cfg.nlevels, init, iters=1)
+    assert np.all(np.isnan(nofit["fits"]))

@@ -300,3 +300,49 @@ def test_count_invalid_records():
     same = np.all(canon == q[:, :3], axis=1) & np.all((q[:, 3:] >= 0) & (q[:, 3:] <= N), axis=1) \
         & (q[:, 3] <= q[:, 4]) & (q[:, 5] <= q[:, 6])
     assert query.count_invalid(q, nu, nv, nl, N) == int((~same).sum())
+
+
+def test_magnitudes_hand_computed():
+    """Both magnitudes on a two-rank case worked by hand.
+
+    U = [1, -2], V = [3, 1], L = [0.5, 2] (one row each), so U V L = [1.5, -4];
+    S = [[1, -1], [2, 3]] gives CS = [[0, 0], [1, -1], [3, 2]];
+    T = [[2, 1], [0, 3]] gives CT = [[0, 0], [2, 1], [2, 4]].
+    Box s [1, 2), t [0, 2): dS = [2, 3], dT = [2, 4]; terms 6 and -48, so
+    q = -42, M_q = 54, N_q = 1.5 (3 + 1)(2 + 0) + 4 (2 + 1)(4 + 0) = 60.
+    Box s [0, 1), t [1, 2): dS = [1, -1], dT = [0, 3]; terms 0 and 12, so
+    q = 12, M_q = 12, N_q = 1.5 (1 + 0)(2 + 2) + 4 (1 + 0)(4 + 1) = 26.
+    The third record is the first one out of range (u, v wrap, l, s_hi and
+    t_lo clamp); the fourth is empty.  With per-rank scales (2, 0.5) the
+    first box's terms become 12 and -24."""
+    U = np.array([[1.0, -2.0]])
+    V = np.array([[3.0, 1.0]])
+    L = np.array([[0.5, 2.0]])
+    CS = query.cumulative(np.array([[1.0, -1.0], [2.0, 3.0]]))
+    CT = query.cumulative(np.array([[2.0, 1.0], [0.0, 3.0]]))
+    assert np.array_equal(CS, [[0, 0], [1, -1], [3, 2]])
+    assert np.array_equal(CT, [[0, 0], [2, 1], [2, 4]])
+    q = np.array([[0, 0, 0, 1, 2, 0, 2],
+                  [0, 0, 0, 0, 1, 1, 2],
+                  [5, -3, 7, 1, 9, -1, 2],
+                  [0, 0, 0, 2, 2, 0, 2]])
+    assert np.array_equal(query.range_query(U, V, L, CS, CT, q), [-42.0, 12.0, -42.0, 0.0])
+    assert np.array_equal(query.range_query_term_magnitude(U, V, L, CS, CT, q), [54.0, 12.0, 54.0, 0.0])
+    assert np.array_equal(query.range_query_magnitude(U, V, L, CS, CT, q), [60.0, 26.0, 60.0, 0.0])
+    sc = np.array([2.0, 0.5])
+    assert np.array_equal(query.range_query(U, V, L, CS, CT, q[:1], scale=sc), [-12.0])
+    assert np.array_equal(query.range_query_term_magnitude(U, V, L, CS, CT, q[:1], scale=sc), [36.0])
+    assert np.array_equal(query.range_query_magnitude(U, V, L, CS, CT, q[:1], scale=sc), [48.0])
+
+
+def test_term_magnitude_between_value_and_condition_magnitude():
+    """|q| <= M_q <= N_q on random signed factors (the triangle inequality twice)."""
+    rng = np.random.default_rng(21)
+    U, V, L, S, Tf = _rand_factors(rng, (5, 4, 3, 6, 6), 3)
+    q = _rand_queries(rng, 200, 5, 4, 3, 6)
+    CS, CT = query.cumulative(S), query.cumulative(Tf)
+    val = np.abs(query.range_query(U, V, L, CS, CT, q))
+    m = query.range_query_term_magnitude(U, V, L, CS, CT, q)
+    n = query.range_query_magnitude(U, V, L, CS, CT, q)
+    assert np.all(val <= m * (1 + 1e-14)) and np.all(m <= n * (1 + 1e-14))
+    assert np.any(m < 0.5 * n)
