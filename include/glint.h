@@ -156,8 +156,11 @@ size_t glint_cp_als_workspace(const glint_ndf_desc* desc, int32_t R, glint_dtype
  * 1 - ||T - T^|| / ||T|| after each sweep (sweeps skipped after convergence
  * repeat the last value).  If tol > 0 the sweeps stop once the fit changes by
  * less than tol.  info (int32[4], may be NULL): sweeps run, mode updates whose
- * Gram was not positive definite (that factor then keeps its previous value),
- * and two reserved zeros.  R in {16, 32, 64, 128}; nbins >= 16. */
+ * Cholesky broke down (a pivot not above 1e-13 times its diagonal entry of
+ * G), and two reserved zeros.  Such an update takes A_n = M_n G+ instead,
+ * G+ the eigen pseudo-inverse of G with the eigenvalues not above 1e-12
+ * times the largest dropped (cyclic Jacobi on one workgroup, using the
+ * workspace's Cholesky buffers).  R in {16, 32, 64, 128}; nbins >= 16. */
 glint_status glint_cp_als(const glint_ndf_desc* desc, const void* T, glint_dtype T_dtype,
                           int32_t R, int32_t iters, double tol,
                           double* U, double* V, double* L, double* S, double* Tf,
@@ -177,8 +180,9 @@ glint_status glint_mttkrp(const glint_ndf_desc* desc, const void* T, glint_dtype
                           void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* Texel-space forms of the two calls above, for maps whose tensor T does not
- * fit in memory.  T (Sec. 4.1, Eq. geom with the box footprints of
- * Sec. 4.3) is the footprint average of per-texel outer products of the s-
+ * fit in memory.  T (Sec. 3.1, Eq. geom, over the footprint pyramid of
+ * Sec. 4.1 with the square footprints of glint_ndf_desc) is the footprint
+ * average of per-texel outer products of the s-
  * and t-bin masses, so each MTTKRP is evaluated from the per-texel bin
  * windows of glint_texel_bins and window sums of U and V over the footprint
  * pyramid; T is never formed.  The results equal those of glint_mttkrp /
@@ -415,7 +419,9 @@ typedef struct {
  * bins clamp as for glint_query; out[i] = the sum, over the cells the level-l
  * footprint centred on (x, y) overlaps, of that cell's tile query at centre
  * (x - iS + m, y - jS + m).  Requires 2m >= 2^(nl-1) so every overlapped
- * cell's centre lies in its tile's padded grid, R a multiple of 4 and the
+ * cell's centre lies in its tile's padded grid, 2^(nl-1) <= S (tiles at
+ * least as wide as the largest footprint, so a footprint overlaps at most
+ * 2 x 2 cells and a query's work is bounded), R a multiple of 4 and the
  * tables 16-byte aligned.  One thread per query, FP32. */
 glint_status glint_query_wang(const glint_wang* w, int64_t nq, const int32_t* q, float* out,
                               hipStream_t stream);

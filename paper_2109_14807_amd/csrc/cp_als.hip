@@ -450,7 +450,7 @@ __global__ __launch_bounds__(256) void k_reduce_z(const TT* __restrict__ Z, int 
 
 __global__ void k_gram(const double* __restrict__ A, int rows, int R, double* __restrict__ G,
                        const int* __restrict__ ctrl) {
-  if (ctrl[CTRL_DONE] || ctrl[CTRL_FAILNOW]) return;
+  if (ctrl[CTRL_DONE]) return;
   const int i = blockIdx.y * 16 + threadIdx.y;
   const int j = blockIdx.x * 16 + threadIdx.x;
   if (i >= R || j >= R) return;
@@ -567,6 +567,118 @@ __global__ __launch_bounds__(1024) void k_cholesky(const double* __restrict__ gr
     }
 }
 
+// Fallback of a failed Cholesky (reading R4): the pseudo-inverse of the
+// Hadamard Gram G of mode n through its eigendecomposition,
+//   G+ = Q diag(1/w_i for w_i > 1e-12 w_max, else 0) Q^T,
+// the eigenpairs by cyclic Jacobi rotations in one workgroup.  Each round
+// rotates R/2 disjoint index pairs at once (round-robin order: index 0 stays,
+// the others move one place per round, so R - 1 rounds meet every pair
+// once); a pair is rotated when |a_pq| > 1e-15 sqrt|a_pp a_qq| (the
+// symmetric 2x2 Schur rotation that zeroes a_pq); sweeps stop when one
+// rotates nothing, at most kJacobiSweeps.  Every 2x2 block (pair k rows,
+// pair m columns) of A = J^T A J is owned by one thread per round, and
+// Q = Q J.  A and Q live in the R x R Cholesky buffers (Lc, LcT), unused when
+// the factorisation failed; G+ is left in Lc for k_solve.  Runs only after a
+// failed factorisation (ctrl[CTRL_FAILNOW]).
+constexpr int kJacobiSweeps = 40;
+
+__device__ __forceinline__ int jacobi_player(int j, int round, int R) {
+  return j == 0 ? 0 : 1 + (j - 1 + round) % (R - 1);
+}
+
+template <int R>
+__global__ __launch_bounds__(1024) void k_eigh_pinv(const double* __restrict__ grams, int n, double* A,
+                                                    double* Q, const int* __restrict__ ctrl) {
+  if (ctrl[CTRL_DONE] || !ctrl[CTRL_FAILNOW]) return;
+  constexpr int H = R / 2;
+  constexpr int RR = R * R;
+  __shared__ double cs[H], sn[H], wv[R];
+  __shared__ int pp[H], qq[H], act[H];
+  __shared__ int rotated;
+  __shared__ double wmax_s;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int idx = tid; idx < RR; idx += nt) {
+    double v = 1.0;
+    for (int m = 0; m < 5; ++m)
+      if (m != n) v *= grams[static_cast<int64_t>(m) * RR + idx];
+    A[idx] = v;
+    Q[idx] = (idx / R == idx % R) ? 1.0 : 0.0;
+  }
+  __threadfence_block();
+  __syncthreads();
+  for (int sweep = 0; sweep < kJacobiSweeps; ++sweep) {
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int round = 0; round < R - 1; ++round) {
+      if (tid < H) {
+        const int p = jacobi_player(tid, round, R), q = jacobi_player(R - 1 - tid, round, R);
+        const double apq = A[p * R + q], app = A[p * R + p], aqq = A[q * R + q];
+        double c = 1.0, s = 0.0;
+        int a = 0;
+        if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-300) {
+          const double tau = (aqq - app) / (2.0 * apq);
+          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + t * t);
+          s = t * c;
+          a = 1;
+          rotated = 1;
+        }
+        cs[tid] = c;
+        sn[tid] = s;
+        pp[tid] = p;
+        qq[tid] = q;
+        act[tid] = a;
+      }
+      __syncthreads();
+      for (int b = tid; b < H * H; b += nt) {
+        const int k = b / H, m = b % H;
+        const int pk = pp[k], qk = qq[k], pm = pp[m], qm = qq[m];
+        const double ck = cs[k], sk = sn[k], cm = cs[m], sm = sn[m];
+        const double a00 = A[pk * R + pm], a01 = A[pk * R + qm], a10 = A[qk * R + pm], a11 = A[qk * R + qm];
+        const double r00 = ck * a00 - sk * a10, r01 = ck * a01 - sk * a11;
+        const double r10 = sk * a00 + ck * a10, r11 = sk * a01 + ck * a11;
+        double n01 = sm * r00 + cm * r01, n10 = cm * r10 - sm * r11;
+        if (k == m && act[k]) n01 = n10 = 0.0;
+        A[pk * R + pm] = cm * r00 - sm * r01;
+        A[pk * R + qm] = n01;
+        A[qk * R + pm] = n10;
+        A[qk * R + qm] = sm * r10 + cm * r11;
+      }
+      for (int b = tid; b < R * H; b += nt) {
+        const int i = b / H, m = b % H;
+        const int p = pp[m], q = qq[m];
+        const double c = cs[m], s = sn[m];
+        const double qp = Q[i * R + p], qv = Q[i * R + q];
+        Q[i * R + p] = c * qp - s * qv;
+        Q[i * R + q] = s * qp + c * qv;
+      }
+      __threadfence_block();
+      __syncthreads();
+    }
+    // every thread reads the flag before thread 0 may clear it for the next sweep
+    const int any = rotated;
+    __syncthreads();
+    if (!any) break;
+  }
+  for (int i = tid; i < R; i += nt) wv[i] = A[i * R + i];
+  __syncthreads();
+  if (tid == 0) {
+    double wm = wv[0];
+    for (int i = 1; i < R; ++i) wm = fmax(wm, wv[i]);
+    wmax_s = wm;
+  }
+  __syncthreads();
+  const double cut = 1e-12 * fmax(wmax_s, 0.0);
+  for (int i = tid; i < R; i += nt) wv[i] = wv[i] > cut ? 1.0 / wv[i] : 0.0;
+  __syncthreads();
+  for (int idx = tid; idx < RR; idx += nt) {
+    const int i = idx / R, j = idx % R;
+    double acc = 0.0;
+    for (int k = 0; k < R; ++k) acc += Q[i * R + k] * wv[k] * Q[j * R + k];
+    A[idx] = acc;
+  }
+}
+
 // One wave per row: x = m G^-1 with G = Lc Lc^T (forward then back
 // substitution).  For R <= 128 the factor is staged once per block in LDS
 // with row stride R + 1 (dynamic LDS of solve_lds_bytes(R)), so both the
@@ -581,11 +693,34 @@ template <int R>
 __global__ __launch_bounds__(1024) void k_solve(const double* __restrict__ M, int rows,
                                                const double* Lc, const double* LcT,
                                                double* __restrict__ A, const int* __restrict__ ctrl) {
-  if (ctrl[CTRL_DONE] || ctrl[CTRL_FAILNOW]) return;
+  if (ctrl[CTRL_DONE]) return;
   constexpr int E = (R + 63) / 64;
   constexpr bool kStage = R <= 128;
   constexpr int LD = kStage ? R + 1 : R;
   extern __shared__ __align__(16) double sL[];
+  if (ctrl[CTRL_FAILNOW]) {
+    // the factorisation failed: x = m G+ with the pseudo-inverse k_eigh_pinv left in Lc
+    const int lane = threadIdx.x & 63;
+    const int row = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (row >= rows) return;
+    double w[E];
+#pragma unroll
+    for (int t = 0; t < E; ++t) w[t] = 0.0;
+    for (int j = 0; j < R; ++j) {
+      const double mj = M[static_cast<int64_t>(row) * R + j];
+#pragma unroll
+      for (int t = 0; t < E; ++t) {
+        const int e = lane + 64 * t;
+        if (e < R) w[t] += mj * Lc[j * R + e];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+      const int e = lane + 64 * t;
+      if (e < R) A[static_cast<int64_t>(row) * R + e] = w[t];
+    }
+    return;
+  }
   const double* Lf;   // L[i][k] at Lf[i * LD + k]
   if constexpr (kStage) {
     for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) {
@@ -647,7 +782,7 @@ __global__ __launch_bounds__(1024) void k_solve(const double* __restrict__ M, in
 __global__ __launch_bounds__(1024) void k_normalize_gram(double* __restrict__ A, int rows, int R,
                                                          double* __restrict__ lam, double* __restrict__ G,
                                                          const int* __restrict__ ctrl) {
-  if (ctrl[CTRL_DONE] || ctrl[CTRL_FAILNOW]) return;
+  if (ctrl[CTRL_DONE]) return;
   __shared__ double sh[1024];
   __shared__ double lr[256];
   const int r = threadIdx.x % R;
@@ -865,6 +1000,8 @@ glint_status run_als(const glint_ndf_desc* d, const TT* T, int iters, double tol
     hipLaunchKernelGGL((k_cholesky<R>), dim3(1), dim3(cholesky_grid(R) * cholesky_grid(R)), 0, stream, grams, n, Lc,
                        LcT, ctrl);
     GLINT_LAUNCHED("k_cholesky");
+    hipLaunchKernelGGL((k_eigh_pinv<R>), dim3(1), dim3(1024), 0, stream, grams, n, Lc, LcT, ctrl);
+    GLINT_LAUNCHED("k_eigh_pinv");
     const int rws = rows[n];
     hipLaunchKernelGGL((k_solve<R>), dim3((rws + 15) / 16), dim3(1024), solve_lds_bytes<R>(), stream, Mb, rws, Lc,
                        LcT, F[n], ctrl);
@@ -1451,7 +1588,7 @@ __global__ void k_window_apply(const double* __restrict__ Hpref, int n, int R, i
 // output tiles, rows staged through LDS.
 __global__ __launch_bounds__(256) void k_gram_parts(const double* __restrict__ A, int rows, int R, int rchunk,
                                                     double* __restrict__ parts, const int* __restrict__ ctrl) {
-  if (ctrl[CTRL_DONE] || ctrl[CTRL_FAILNOW]) return;
+  if (ctrl[CTRL_DONE]) return;
   __shared__ double ai[32][17], aj[32][17];
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   const int i = blockIdx.y * 16 + ty, j = blockIdx.x * 16 + tx;
@@ -1739,11 +1876,10 @@ glint_status texel_mode(const TexelCtx& c, int mode, const double* L, const doub
   return GLINT_OK;
 }
 
-// G = sum of the row-chunk partial Grams (skipped, like the partials, when the
-// mode update was not applied)
+// G = sum of the row-chunk partial Grams
 __global__ void k_gram_reduce(const double* __restrict__ parts, int nsplit, int64_t n, double* __restrict__ G,
                               const int* __restrict__ ctrl) {
-  if (ctrl[CTRL_DONE] || ctrl[CTRL_FAILNOW]) return;
+  if (ctrl[CTRL_DONE]) return;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     double acc = 0.0;
@@ -1787,6 +1923,7 @@ glint_status run_texel_als(const glint_ndf_desc* d, const float* nxy, int iters,
   auto update = [&](int n) -> glint_status {
     hipLaunchKernelGGL((k_cholesky<R>), dim3(1), dim3(cholesky_grid(R) * cholesky_grid(R)), 0, stream, grams, n, Lc,
                        LcT, c.ctrl);
+    hipLaunchKernelGGL((k_eigh_pinv<R>), dim3(1), dim3(1024), 0, stream, grams, n, Lc, LcT, c.ctrl);
     hipLaunchKernelGGL((k_solve<R>), dim3((rows[n] + 15) / 16), dim3(1024), solve_lds_bytes<R>(), stream, c.M,
                        rows[n], Lc, LcT,
                        F[n], c.ctrl);

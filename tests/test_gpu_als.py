@@ -106,24 +106,27 @@ def test_tolerance_stops_early(c1_tensor):
     assert np.max(np.abs(fits[:info[0]] - ref["fits"])) < 1e-9
 
 
-def test_non_positive_definite_gram_is_reported():
-    """Duplicate initial columns make every Hadamard Gram singular: the GPU
-    reports the failed updates and keeps those factors (the oracle instead
-    takes the pseudo-inverse)."""
+def test_singular_gram_takes_the_pseudo_inverse_like_the_oracle():
+    """Duplicate initial columns make every Hadamard Gram singular: each update
+    fails the Cholesky pivot test and is solved by the eigen pseudo-inverse,
+    on the GPU (Jacobi in one workgroup) as in the oracle (LAPACK eigh).  The
+    two columns stay equal only up to rounding, which the sweeps amplify
+    (their difference grows from 1e-13 to 1e-11 over two sweeps), so the
+    factors are compared to 1e-9 after one and two sweeps (a Jacobi model of
+    the GPU's rule differs from the oracle by 1e-11 here)."""
     nxy = gen.flake_map(16, 16, 9, 0.25, 5)
     T = ndf.ndf_bruteforce(nxy, 16, 0.05, 2)
     rng = np.random.default_rng(4)
     init = [rng.random((d, 16)) for d in (16, 16, 2, 16, 16)]
     for a in init:
         a[:, 1] = a[:, 0]
-    F, fits, info = _run(T, (16, 16, 2, 16), init, 1)
-    assert info[1] > 0
-    assert all(np.all(np.isfinite(f)) for f in F)
-    # every Hadamard Gram holds two equal rows, so every update fails and the
-    # initial factors come back unchanged (unit column weights)
-    assert info[1] == 5
-    for a, b in zip(F, init):
-        assert np.array_equal(a, b)
+    for iters in (1, 2):
+        F, fits, info = _run(T, (16, 16, 2, 16), init, iters)
+        ref = cp_als.cp_als(T, init, iters=iters)
+        assert info[1] == ref["fallbacks"] == 5 * iters
+        for m in range(5):
+            assert _rel(F[m], ref["factors"][m]) < 1e-9, (iters, m, _rel(F[m], ref["factors"][m]))
+        assert np.max(np.abs(fits - ref["fits"])) < 1e-9
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
