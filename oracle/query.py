@@ -95,11 +95,14 @@ def trilinear_corners(xyl, nu, nv, nl):
 def range_query_trilinear(U, V, L, CS, CT, xyl, boxes, scale=None, magnitude=False) -> np.ndarray:
     """Trilinear blend over the 8 surrounding footprints of the range query of
     each box (boxes [n][4] = s_lo, s_hi, t_lo, t_hi); FP64.  With
-    ``magnitude`` the blend of the corners' condition magnitudes instead."""
+    ``magnitude`` the blend of the corners' rank-term magnitudes instead: an
+    evaluation that interpolates the factor rows first has its error scaled
+    by sum_r (sum_c w_c |U_c|)(sum_c w_c |V_c|)(sum_c w_c |L_c|) |dS dT|,
+    which is this blend."""
     nu, nv, nl = U.shape[0], V.shape[0], L.shape[0]
     corners, w = trilinear_corners(xyl, nu, nv, nl)
     boxes = np.asarray(boxes, dtype=np.int64)
-    fn = range_query_magnitude if magnitude else range_query
+    fn = range_query_term_magnitude if magnitude else range_query
     out = np.zeros(corners.shape[0])
     for c in range(8):
         rec = np.concatenate([corners[:, c, :], boxes], axis=1)

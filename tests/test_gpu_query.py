@@ -11,8 +11,10 @@ pytestmark = pytest.mark.gpu
 
 import paper_2109_14807_amd as G  # noqa: E402
 
-# FP32 query vs the FP64 oracle CP query on the same factors:
-# |q_gpu - q_64| <= TOL * N_q, N_q the condition magnitude of the evaluation.
+# FP32 query vs the FP64 oracle CP query on the same stored values:
+# |q_gpu - q_64| <= TOL * M_q, M_q = sum_r |c_r U V L dS dT| the sum of the rank
+# terms' magnitudes (each difference of stored summed-area values is rounded
+# relative to itself in FP32, so M_q is the scale of the arithmetic error).
 TOL = 1e-5
 
 
@@ -71,7 +73,7 @@ def _oracle(F, q, dtype, cum_dtype):
         if s is not None:
             scale = scale * s.astype(np.float64)
     return (query.range_query(*vals, q, scale=scale),
-            query.range_query_magnitude(*vals, q, scale=scale))
+            query.range_query_term_magnitude(*vals, q, scale=scale))
 
 
 def _check(got, want, mag, tol=TOL):
@@ -252,7 +254,7 @@ def test_query_c3_bf16_full_batch_sampled():
     idx[-1] = q.shape[0] - 1
     want, mag = _oracle(F, q[idx], "bf16", "bf16")
     _check(got[idx], want, mag)
-    print(f"c3 bf16: max |err| / N_q = {np.max(np.abs(got[idx] - want) / np.maximum(mag, 1e-300)):.2e}")
+    print(f"c3 bf16: max |err| / M_q = {np.max(np.abs(got[idx] - want) / np.maximum(mag, 1e-300)):.2e}")
 
 
 def test_grouped_c5_fp8_full_batch_sampled():
@@ -275,7 +277,7 @@ def test_grouped_c5_fp8_full_batch_sampled():
     flat = np.concatenate([uvl[p], boxes[p, k]], axis=1).astype(np.int32)
     want, mag = _oracle(F, flat, "fp8", "bf16")
     _check(got[idx], want, mag)
-    print(f"c5 fp8/bf16: max |err| / N_q = {np.max(np.abs(got[idx] - want) / np.maximum(mag, 1e-300)):.2e}")
+    print(f"c5 fp8/bf16: max |err| / M_q = {np.max(np.abs(got[idx] - want) / np.maximum(mag, 1e-300)):.2e}")
 
 
 def _oracle_trilinear(F, xyl, boxes, dtype, cum_dtype):

@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 
 import paper_2109_14807_amd as G  # noqa: E402
 
-TOL = 1e-5     # FP32 query vs FP64: |avg_gpu - avg_64| <= TOL * N_q / bins
+TOL = 1e-5     # FP32 query vs FP64: |avg_gpu - avg_64| <= TOL * M_q / bins, M_q the rank terms' magnitude sum
 
 
 def _lookups(rng, n, nu, nv, nl):
@@ -63,7 +63,7 @@ def test_query_sg_matches_oracle(R, dtype):
         scale = None
     area = (q[:, 4] - q[:, 3]) * (q[:, 6] - q[:, 5])
     want = query.range_query(*vals, q, scale=scale) / area
-    mag = query.range_query_magnitude(*vals, q, scale=scale) / area
+    mag = query.range_query_term_magnitude(*vals, q, scale=scale) / area
     err = np.abs(got - want)
     assert np.all(err <= TOL * mag + 1e-30), float((err / np.maximum(mag, 1e-300)).max())
     assert np.all(area >= 1)
@@ -128,7 +128,7 @@ def test_query_sg_full_size_c2_sampled():
     qs = q[idx]
     area = (qs[:, 4] - qs[:, 3]) * (qs[:, 6] - qs[:, 5])
     want = query.range_query(*vals, qs) / area
-    mag = query.range_query_magnitude(*vals, qs) / area
+    mag = query.range_query_term_magnitude(*vals, qs) / area
     assert np.all(np.abs(got[idx] - want) <= TOL * mag + 1e-30)
     want_q = sg.sg_records(uvl[idx], h[idx].astype(np.float64), sgp[idx, 0].astype(np.float64),
                            sgp[idx, 1].astype(np.float64), N)

@@ -60,14 +60,11 @@ def test_query_wang_matches_oracle_on_the_same_tables():
     q[: n // 10, 4] = q[: n // 10, 3]                       # empty boxes
     got = G.query_wang(tab, torch.from_numpy(q)).cpu().numpy().astype(np.float64)
     want = wang.wang_range_query(fac, q, S, M, SEED, etl)
-    absfac = [tuple(np.abs(x) for x in f) for f in fac]
-    # the magnitude of the FP32 evaluation: the same sum with |factors| and |differences|
+    # the scale of the FP32 evaluation's error: the magnitudes of every tile's rank terms, summed
     mag = np.zeros(n)
     for i, recs in enumerate(wang.local_records(q, S, M, NL, N, SEED, etl)):
         for t, r in recs:
-            U, V, Lf, CS, CT = absfac[t]
-            u, v, l, slo, shi, tlo, thi = r
-            mag[i] += float(np.sum(U[u] * V[v] * Lf[l] * (CS[shi] + CS[slo]) * (CT[thi] + CT[tlo])))
+            mag[i] += float(query.range_query_term_magnitude(*fac[t], np.asarray([r]))[0])
     assert np.all(np.abs(got - want) <= 1e-5 * mag + 1e-30), float(np.max(np.abs(got - want) / np.maximum(mag, 1e-300)))
     assert np.all(got[: n // 10] == 0.0)
     # and the result approximates the exact implicit NDF (CP error only)
@@ -83,6 +80,10 @@ def test_query_wang_argument_errors():
     q = torch.zeros((1, 7), dtype=torch.int32)
     assert G.query_wang(tab, torch.zeros((0, 7), dtype=torch.int32)).numel() == 0
     bad = G.wang_tables(F, S, 1, SEED, etl)            # margin below half the largest footprint
+    with pytest.raises(G.GlintError):
+        G.query_wang(bad, q)
+    Fs = [[np.ones((4 + 2 * M, 4)), np.ones((4 + 2 * M, 4)), np.ones((NL, 4)), np.ones((N, 4)), np.ones((N, 4))]] * 16
+    bad = G.wang_tables(Fs, 4, M, SEED, etl)           # tiles narrower than the largest footprint (8)
     with pytest.raises(G.GlintError):
         G.query_wang(bad, q)
     bad = G.wang_tables(F[:4], S, M, SEED, etl)        # edge_to_tile names tiles that do not exist
