@@ -376,7 +376,10 @@ def wang_tables(tile_factors, S: int, m: int, seed: int, edge_to_tile) -> WangTa
     """Stack the CP factors (U, V, L, S, T) of every tile (each fitted on the
     tile padded with m absent texels) into query tables."""
     def stack(i):
-        return torch.stack([_dev(f[i], torch.float64).float() for f in tile_factors]).contiguous()
+        f64 = torch.stack([_dev(f[i], torch.float64) for f in tile_factors]).contiguous()
+        out = torch.empty(f64.shape, dtype=torch.float32, device=_DEV)
+        L.glint_convert(f64.view(-1, f64.shape[-1]), out.view(-1, f64.shape[-1]))
+        return out
     U, V, Lf, Sf, Tf = (stack(i) for i in range(5))
     ntiles, N, R = Sf.shape
     CS = torch.empty((ntiles, N + 1, R), dtype=torch.float32, device=_DEV)

@@ -205,6 +205,8 @@ glint_status glint_query_wang(const glint_wang* w, int64_t nq, const int32_t* q,
   GLINT_REQUIRE(w->R % 4 == 0, "R %d must be a multiple of 4", w->R);
   GLINT_REQUIRE((int64_t{1} << (w->nl - 1)) <= 2 * static_cast<int64_t>(w->m),
                 "the margin m must be at least half the largest footprint (2m >= 2^(nl-1))");
+  GLINT_REQUIRE((int64_t{1} << (w->nl - 1)) <= static_cast<int64_t>(w->S),
+                "tiles must be at least as wide as the largest footprint (2^(nl-1) <= S)");
   for (int c = 0; c < 16; ++c)
     GLINT_REQUIRE(w->edge_to_tile[c] < w->ntiles, "edge_to_tile[%d] = %d is not a tile", c, w->edge_to_tile[c]);
   GLINT_REQUIRE(nq >= 0, "nq must be >= 0");
