@@ -134,6 +134,22 @@ glint_status glint_build_tensor(const glint_ndf_desc* desc, const float* nxy,
                                 void* workspace, size_t workspace_bytes,
                                 hipStream_t stream);
 
+/* glint_build_tensor for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc):
+ * the same kernels (the result equals glint_build_tensor's up to the order of
+ * the direct build's LDS-atomic sums), with the bin windows kept in a scratch array
+ * the library holds on each device it runs on (GLINT_NOALLOC_SCRATCH_BYTES,
+ * held until the process ends) instead of a caller workspace.  Maps whose
+ * glint_build_tensor_workspace exceeds that size return GLINT_E_UNSUPPORTED
+ * before any work is enqueued (512 x 512 at K = 3 needs 31.5 MiB).  Calls no
+ * allocating routine.  Every call on a device shares that device's scratch:
+ * calls that overlap on one device (two streams, two threads) race; calls
+ * in stream order are safe (every call overwrites what it reads). */
+#define GLINT_NOALLOC_SCRATCH_BYTES (48u << 20)
+glint_status glint_build_tensor_noalloc(const glint_ndf_desc* desc, const float* nxy,
+                                        void* T, glint_dtype T_dtype, int32_t direct_levels,
+                                        hipStream_t stream);
+
 /* Brute-force range integral for the refinement targets and the error
  * against the exact NDF: out[i] = (1/k^2) sum over footprint texels of
  * (mass of the texel's s-window inside [s_lo, s_hi)) * (same for t), FP64.

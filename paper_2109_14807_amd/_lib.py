@@ -18,6 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libglint.so")
 
 GLINT_F64, GLINT_F32, GLINT_BF16, GLINT_FP8E4M3 = 0, 1, 2, 3
+NOALLOC_SCRATCH_BYTES = 48 << 20     # GLINT_NOALLOC_SCRATCH_BYTES of glint.h
 
 TORCH_OF = {
     GLINT_F64: torch.float64,
@@ -96,6 +97,7 @@ _SIGS = {
     "glint_texel_bins": (_I32, [_DESC, _P, _P, _P, _P]),
     "glint_build_tensor_workspace": (_SZ, [_DESC]),
     "glint_build_tensor": (_I32, [_DESC, _P, _P, _I32, _I32, _P, _SZ, _P]),
+    "glint_build_tensor_noalloc": (_I32, [_DESC, _P, _P, _I32, _I32, _P]),
     "glint_range_bruteforce": (_I32, [_DESC, _P, _P, _I64, _P, _P, _P]),
     "glint_cp_als_workspace": (_SZ, [_DESC, _I32, _I32]),
     "glint_cp_als": (_I32, [_DESC, _P, _I32, _I32, _I32, _F64, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
@@ -210,6 +212,12 @@ def glint_build_tensor(desc, nxy, T, direct_levels, workspace, stream=None):
         ctypes.byref(desc), _ptr(nxy, torch.float32, "nxy"), _ptr(T, None, "T"), _gdtype(T),
         int(direct_levels), _ptr(workspace, torch.uint8, "workspace"), workspace.numel(),
         _stream(stream)))
+
+
+def glint_build_tensor_noalloc(desc, nxy, T, direct_levels, stream=None):
+    _check("glint_build_tensor_noalloc", lib().glint_build_tensor_noalloc(
+        ctypes.byref(desc), _ptr(nxy, torch.float32, "nxy"), _ptr(T, None, "T"), _gdtype(T),
+        int(direct_levels), _stream(stream)))
 
 
 def glint_range_bruteforce(desc, bins, mass, q, out, stream=None):

@@ -13,6 +13,8 @@
 //                     masses over the box.
 #include <math.h>
 
+#include <mutex>
+
 #include "common.h"
 
 namespace {
@@ -261,6 +263,36 @@ size_t bins_bytes(const glint_ndf_desc* d) {
   return glint_round_up(sizeof(int32_t) * 2 * static_cast<size_t>(d->nu) * d->nv, 256);
 }
 
+// Scratch of glint_build_tensor_noalloc: the per-texel bin windows and
+// masses that glint_build_tensor keeps in its workspace, in a file-scope
+// device array instead (each device holds its own copy while the library is
+// loaded).  Host code never passes `scratch` itself to a kernel: on the host
+// the name is a stand-in, not a device address.  The device address comes
+// from hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t kNoAllocScratchBytes = GLINT_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_addr[kMaxDevices] = {};
+
+glint_status scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return glint_fail(GLINT_E_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return glint_fail(GLINT_E_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (g_scratch_addr[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+      return glint_fail(GLINT_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return GLINT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -305,6 +337,19 @@ glint_status glint_build_tensor(const glint_ndf_desc* desc, const float* nxy, vo
   if (T_dtype == GLINT_F64)
     return build_levels<double>(desc, bins, mass, static_cast<double*>(T), direct_levels, stream);
   return build_levels<float>(desc, bins, mass, static_cast<float*>(T), direct_levels, stream);
+}
+
+glint_status glint_build_tensor_noalloc(const glint_ndf_desc* desc, const float* nxy, void* T,
+                                        glint_dtype T_dtype, int32_t direct_levels, hipStream_t stream) {
+  glint_status st = glint_check_desc(desc);
+  if (st != GLINT_OK) return st;
+  const size_t need = glint_build_tensor_workspace(desc);
+  if (need > kNoAllocScratchBytes)
+    return glint_fail(GLINT_E_UNSUPPORTED, "the map needs %zu bytes of scratch, the no-allocation build has %zu",
+                      need, kNoAllocScratchBytes);
+  void* ws = nullptr;
+  if ((st = scratch_address(&ws)) != GLINT_OK) return st;
+  return glint_build_tensor(desc, nxy, T, T_dtype, direct_levels, ws, kNoAllocScratchBytes, stream);
 }
 
 glint_status glint_range_bruteforce(const glint_ndf_desc* desc, const int32_t* bins,
