@@ -123,7 +123,9 @@ __device__ __forceinline__ void lds_row(const float* p, float* out) {
 }
 
 // Summed-area tables stay in LDS in BF16 when stored in BF16 (half the LDS
-// bytes per gathered row; decoding is exact), otherwise as FP32.
+// bytes per gathered row; decoding is exact) and when stored in FP8 (every
+// E4M3 value is exact in BF16: 3 fraction bits, exponents -9..8), otherwise
+// as FP32.
 template <typename CT>
 struct LdsCum {
   typedef float type;
@@ -132,11 +134,16 @@ template <>
 struct LdsCum<uint16_t> {
   typedef uint16_t type;
 };
+template <>
+struct LdsCum<uint8_t> {
+  typedef uint16_t type;
+};
 
 template <typename CT, typename LT>
 __device__ void stage_cum(LT* __restrict__ dst, const CT* __restrict__ src, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    if constexpr (std::is_same<LT, uint16_t>::value) dst[i] = src[i];
+    if constexpr (std::is_same<LT, uint16_t>::value && std::is_same<CT, uint16_t>::value) dst[i] = src[i];
+    else if constexpr (std::is_same<LT, uint16_t>::value) dst[i] = glint_f32_to_bf16(dec<CT>(src[i]));
     else dst[i] = dec<CT>(src[i]);
   }
 }
@@ -276,6 +283,31 @@ struct alignas(16) PackedRows {
   uint32_t ul, v, a, b;
 };
 
+// The four summed-area row slices of a resolved record (CS hi, CS lo, CT hi,
+// CT lo; for an odd group the two tables come swapped, see k_query).
+template <bool GC, typename CT, typename LT, int RPL, int CHR, int STR, int R>
+__device__ __forceinline__ void record_rows(const PackedRows& r, const unsigned char* cum_lane,
+                                            const LT* CSs, const LT* CTs, const CT* __restrict__ CSg,
+                                            const CT* __restrict__ CTg, int r0, float* sh, float* sl,
+                                            float* th, float* tl) {
+  if constexpr (GC) {
+    cum_chunks<true, CT, LT, RPL, CHR, STR>(CSs, CSg, static_cast<int>(r.a & 0xffffu) * R + r0, 0, sh);
+    cum_chunks<true, CT, LT, RPL, CHR, STR>(CSs, CSg, static_cast<int>(r.a >> 16) * R + r0, 0, sl);
+    cum_chunks<true, CT, LT, RPL, CHR, STR>(CTs, CTg, static_cast<int>(r.b & 0xffffu) * R + r0, 0, th);
+    cum_chunks<true, CT, LT, RPL, CHR, STR>(CTs, CTg, static_cast<int>(r.b >> 16) * R + r0, 0, tl);
+  } else {
+    const LT* ah = reinterpret_cast<const LT*>(cum_lane + ((r.a & 0xffffu) << 4));
+    const LT* al = reinterpret_cast<const LT*>(cum_lane + ((r.a >> 16) << 4));
+    const LT* bh = reinterpret_cast<const LT*>(cum_lane + ((r.b & 0xffffu) << 4));
+    const LT* bl = reinterpret_cast<const LT*>(cum_lane + ((r.b >> 16) << 4));
+    cum_chunks<false, CT, LT, RPL, CHR, STR>(ah, CSg, 0, 0, sh);
+    cum_chunks<false, CT, LT, RPL, CHR, STR>(al, CSg, 0, 0, sl);
+    cum_chunks<false, CT, LT, RPL, CHR, STR>(bh, CTg, 0, 0, th);
+    cum_chunks<false, CT, LT, RPL, CHR, STR>(bl, CTg, 0, 0, tl);
+  }
+}
+
+
 // LDS layout of the flat query: L (FP32) at 0, CS at a 256-byte boundary,
 // CT half a bank width (128 bytes) past the next 256-byte boundary, then
 // the record slots.  With GC the summed-area tables stay in global memory.
@@ -311,12 +343,32 @@ __host__ __device__ inline QueryLds query_lds(int nl, int N, int R, size_t lt_by
 // NT threads per block; at 1024 the compiler is held to 64 VGPRs (eight
 // waves per SIMD), so two blocks of 16 waves share a CU with one copy of
 // the tables each.
+// Plans that pipeline phase 2 of the flat query: 512 threads and up to 8
+// ranks a lane, except FP8 summed-area rows read from global memory (their
+// in-flight rows and decodes spill).
+constexpr bool query_pipelined(int NT, int RPL, bool GC, int cum_bytes) {
+  return NT == kQueryThreads && RPL <= 8 && !(GC && cum_bytes == 1);
+}
+// waves per SIMD the compiler plans registers for: eight for the 1024-thread
+// plans; four for pipelined plans with the summed-area tables in LDS (the LDS
+// allows no more); three when those tables are read from global memory (the
+// global rows in flight need more registers)
+constexpr int query_waves(int NT, int RPL, bool GC, int cum_bytes) {
+  return NT == 1024 ? 8 : (query_pipelined(NT, RPL, GC, cum_bytes) ? (GC ? 3 : 4) : 1);
+}
+
 template <typename FT, typename CT, typename LT, int R, int RPL, bool GC, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 1024 ? 8 : 1))) void k_query(QueryArgs a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(query_waves(NT, RPL, GC, sizeof(CT))))) void k_query(QueryArgs a) {
   constexpr int LPQ = R / RPL;           // lanes per query
   static_assert(LPQ >= 1 && LPQ <= 64, "lanes per query");
-  static_assert(std::is_same<LT, float>::value || std::is_same<LT, CT>::value, "LDS copy type");
+  static_assert(std::is_same<LT, float>::value || std::is_same<LT, CT>::value ||
+                    (std::is_same<LT, uint16_t>::value && std::is_same<CT, uint8_t>::value),
+                "LDS copy type");
   constexpr int kSlots = 64 + 64 / LPQ;
+  // the 512-thread plans with up to 8 ranks a lane have VGPRs to spare (their
+  // LDS allows four waves per SIMD): they pipeline phase 2 within 128 VGPRs;
+  // the 1024-thread plans are held to 64 VGPRs
+  constexpr bool kPipe = query_pipelined(NT, RPL, GC, sizeof(CT));
   extern __shared__ __align__(16) float lds[];
   unsigned char* lds_b = reinterpret_cast<unsigned char*>(lds);
   const QueryLds lay = query_lds(a.nl, a.N, R, sizeof(LT), GC, 0);
@@ -390,6 +442,59 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 1024 ?
     // phase 2: group g serves queries g*LPQ .. g*LPQ + LPQ - 1; lane j keeps query
     // g*LPQ + j.  The footprint product W = U*V*L is reused while consecutive
     // queries share (u, v, l) (several angular boxes of one shading point).
+    if constexpr (kPipe) {
+      // software pipeline: while query jj's rows are combined, the record of
+      // query jj + 1, its summed-area rows and (when its footprint differs)
+      // its U and V rows are already in flight
+      const PackedRows* grow = wrows + g * (LPQ + 1);
+      PackedRows r = grow[0];
+      float W[RPL], sh[RPL], sl[RPL], th[RPL], tl[RPL];
+      {
+        float uu[RPL], vv[RPL], lr[RPL];
+        load_chunks<FT, RPL, CHR, STR>(U + static_cast<int64_t>(r.ul & 0x3ffffffu) * R + r0, 0, uu);
+        load_chunks<FT, RPL, CHR, STR>(V + static_cast<int64_t>(r.v) * R + r0, 0, vv);
+        lds_chunks<RPL, CHR, STR>(Ls + (r.ul >> 26) * R + r0, 0, lr);
+#pragma unroll
+        for (int e = 0; e < RPL; ++e) W[e] = uu[e] * vv[e] * lr[e];
+      }
+      record_rows<GC, CT, LT, RPL, CHR, STR, R>(r, cum_lane, CSs, CTs, CSg, CTg, r0, sh, sl, th, tl);
+      float res = 0.0f;
+#pragma unroll 2
+      for (int jj = 0; jj < LPQ; ++jj) {
+        float shn[RPL], sln[RPL], thn[RPL], tln[RPL], uu[RPL], vv[RPL];
+        PackedRows rn = r;
+        bool nf = false;
+        if (jj + 1 < LPQ) {
+          rn = grow[jj + 1];
+          nf = rn.ul != r.ul || rn.v != r.v;
+          if (nf) {
+            load_chunks<FT, RPL, CHR, STR>(U + static_cast<int64_t>(rn.ul & 0x3ffffffu) * R + r0, 0, uu);
+            load_chunks<FT, RPL, CHR, STR>(V + static_cast<int64_t>(rn.v) * R + r0, 0, vv);
+          }
+          record_rows<GC, CT, LT, RPL, CHR, STR, R>(rn, cum_lane, CSs, CTs, CSg, CTg, r0, shn, sln, thn, tln);
+        }
+        float acc = lane_terms<RPL, CHR>(W, sh, sl, th, tl, 0);
+        acc = glint_group_sum<LPQ>(acc);
+        res = (j == jj) ? acc : res;
+        if (jj + 1 < LPQ) {
+          if (nf) {
+            float lr[RPL];
+            lds_chunks<RPL, CHR, STR>(Ls + (rn.ul >> 26) * R + r0, 0, lr);
+#pragma unroll
+            for (int e = 0; e < RPL; ++e) W[e] = uu[e] * vv[e] * lr[e];
+          }
+          r = rn;
+#pragma unroll
+          for (int e = 0; e < RPL; ++e) {
+            sh[e] = shn[e]; sl[e] = sln[e]; th[e] = thn[e]; tl[e] = tln[e];
+          }
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      const int64_t qo = base + g * LPQ + j;
+      if (qo < a.nq) a.out[qo] = res;
+      continue;
+    }
     float res = 0.0f;
     uint32_t pul = ~0u, pv = ~0u;
     float W[RPL];
@@ -406,21 +511,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 1024 ?
         pul = r.ul; pv = r.v;
       }
       float sh[RPL], sl[RPL], th[RPL], tl[RPL];
-      if constexpr (GC) {
-        cum_chunks<true, CT, LT, RPL, CHR, STR>(CSs, CSg, static_cast<int>(r.a & 0xffffu) * R + r0, 0, sh);
-        cum_chunks<true, CT, LT, RPL, CHR, STR>(CSs, CSg, static_cast<int>(r.a >> 16) * R + r0, 0, sl);
-        cum_chunks<true, CT, LT, RPL, CHR, STR>(CTs, CTg, static_cast<int>(r.b & 0xffffu) * R + r0, 0, th);
-        cum_chunks<true, CT, LT, RPL, CHR, STR>(CTs, CTg, static_cast<int>(r.b >> 16) * R + r0, 0, tl);
-      } else {
-        const LT* ah = reinterpret_cast<const LT*>(cum_lane + ((r.a & 0xffffu) << 4));
-        const LT* al = reinterpret_cast<const LT*>(cum_lane + ((r.a >> 16) << 4));
-        const LT* bh = reinterpret_cast<const LT*>(cum_lane + ((r.b & 0xffffu) << 4));
-        const LT* bl = reinterpret_cast<const LT*>(cum_lane + ((r.b >> 16) << 4));
-        cum_chunks<false, CT, LT, RPL, CHR, STR>(ah, CSg, 0, 0, sh);
-        cum_chunks<false, CT, LT, RPL, CHR, STR>(al, CSg, 0, 0, sl);
-        cum_chunks<false, CT, LT, RPL, CHR, STR>(bh, CTg, 0, 0, th);
-        cum_chunks<false, CT, LT, RPL, CHR, STR>(bl, CTg, 0, 0, tl);
-      }
+      record_rows<GC, CT, LT, RPL, CHR, STR, R>(r, cum_lane, CSs, CTs, CSg, CTg, r0, sh, sl, th, tl);
       float acc = lane_terms<RPL, CHR>(W, sh, sl, th, tl, 0);
       acc = glint_group_sum<LPQ>(acc);
       res = (j == jj) ? acc : res;
