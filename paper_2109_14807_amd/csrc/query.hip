@@ -343,32 +343,15 @@ __host__ __device__ inline QueryLds query_lds(int nl, int N, int R, size_t lt_by
 // NT threads per block; at 1024 the compiler is held to 64 VGPRs (eight
 // waves per SIMD), so two blocks of 16 waves share a CU with one copy of
 // the tables each.
-// Plans that pipeline phase 2 of the flat query: 512 threads and up to 8
-// ranks a lane, except FP8 summed-area rows read from global memory (their
-// in-flight rows and decodes spill).
-constexpr bool query_pipelined(int NT, int RPL, bool GC, int cum_bytes) {
-  return NT == kQueryThreads && RPL <= 8 && !(GC && cum_bytes == 1);
-}
-// waves per SIMD the compiler plans registers for: eight for the 1024-thread
-// plans; four for pipelined plans with the summed-area tables in LDS (the LDS
-// allows no more); three when those tables are read from global memory (the
-// global rows in flight need more registers)
-constexpr int query_waves(int NT, int RPL, bool GC, int cum_bytes) {
-  return NT == 1024 ? 8 : (query_pipelined(NT, RPL, GC, cum_bytes) ? (GC ? 3 : 4) : 1);
-}
 
 template <typename FT, typename CT, typename LT, int R, int RPL, bool GC, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(query_waves(NT, RPL, GC, sizeof(CT))))) void k_query(QueryArgs a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 1024 ? 8 : 1))) void k_query(QueryArgs a) {
   constexpr int LPQ = R / RPL;           // lanes per query
   static_assert(LPQ >= 1 && LPQ <= 64, "lanes per query");
   static_assert(std::is_same<LT, float>::value || std::is_same<LT, CT>::value ||
                     (std::is_same<LT, uint16_t>::value && std::is_same<CT, uint8_t>::value),
                 "LDS copy type");
   constexpr int kSlots = 64 + 64 / LPQ;
-  // the 512-thread plans with up to 8 ranks a lane have VGPRs to spare (their
-  // LDS allows four waves per SIMD): they pipeline phase 2 within 128 VGPRs;
-  // the 1024-thread plans are held to 64 VGPRs
-  constexpr bool kPipe = query_pipelined(NT, RPL, GC, sizeof(CT));
   extern __shared__ __align__(16) float lds[];
   unsigned char* lds_b = reinterpret_cast<unsigned char*>(lds);
   const QueryLds lay = query_lds(a.nl, a.N, R, sizeof(LT), GC, 0);
@@ -442,59 +425,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(query_waves(
     // phase 2: group g serves queries g*LPQ .. g*LPQ + LPQ - 1; lane j keeps query
     // g*LPQ + j.  The footprint product W = U*V*L is reused while consecutive
     // queries share (u, v, l) (several angular boxes of one shading point).
-    if constexpr (kPipe) {
-      // software pipeline: while query jj's rows are combined, the record of
-      // query jj + 1, its summed-area rows and (when its footprint differs)
-      // its U and V rows are already in flight
-      const PackedRows* grow = wrows + g * (LPQ + 1);
-      PackedRows r = grow[0];
-      float W[RPL], sh[RPL], sl[RPL], th[RPL], tl[RPL];
-      {
-        float uu[RPL], vv[RPL], lr[RPL];
-        load_chunks<FT, RPL, CHR, STR>(U + static_cast<int64_t>(r.ul & 0x3ffffffu) * R + r0, 0, uu);
-        load_chunks<FT, RPL, CHR, STR>(V + static_cast<int64_t>(r.v) * R + r0, 0, vv);
-        lds_chunks<RPL, CHR, STR>(Ls + (r.ul >> 26) * R + r0, 0, lr);
-#pragma unroll
-        for (int e = 0; e < RPL; ++e) W[e] = uu[e] * vv[e] * lr[e];
-      }
-      record_rows<GC, CT, LT, RPL, CHR, STR, R>(r, cum_lane, CSs, CTs, CSg, CTg, r0, sh, sl, th, tl);
-      float res = 0.0f;
-#pragma unroll 2
-      for (int jj = 0; jj < LPQ; ++jj) {
-        float shn[RPL], sln[RPL], thn[RPL], tln[RPL], uu[RPL], vv[RPL];
-        PackedRows rn = r;
-        bool nf = false;
-        if (jj + 1 < LPQ) {
-          rn = grow[jj + 1];
-          nf = rn.ul != r.ul || rn.v != r.v;
-          if (nf) {
-            load_chunks<FT, RPL, CHR, STR>(U + static_cast<int64_t>(rn.ul & 0x3ffffffu) * R + r0, 0, uu);
-            load_chunks<FT, RPL, CHR, STR>(V + static_cast<int64_t>(rn.v) * R + r0, 0, vv);
-          }
-          record_rows<GC, CT, LT, RPL, CHR, STR, R>(rn, cum_lane, CSs, CTs, CSg, CTg, r0, shn, sln, thn, tln);
-        }
-        float acc = lane_terms<RPL, CHR>(W, sh, sl, th, tl, 0);
-        acc = glint_group_sum<LPQ>(acc);
-        res = (j == jj) ? acc : res;
-        if (jj + 1 < LPQ) {
-          if (nf) {
-            float lr[RPL];
-            lds_chunks<RPL, CHR, STR>(Ls + (rn.ul >> 26) * R + r0, 0, lr);
-#pragma unroll
-            for (int e = 0; e < RPL; ++e) W[e] = uu[e] * vv[e] * lr[e];
-          }
-          r = rn;
-#pragma unroll
-          for (int e = 0; e < RPL; ++e) {
-            sh[e] = shn[e]; sl[e] = sln[e]; th[e] = thn[e]; tl[e] = tln[e];
-          }
-        }
-      }
-      __builtin_amdgcn_wave_barrier();
-      const int64_t qo = base + g * LPQ + j;
-      if (qo < a.nq) a.out[qo] = res;
-      continue;
-    }
     float res = 0.0f;
     uint32_t pul = ~0u, pv = ~0u;
     float W[RPL];
@@ -1394,10 +1324,16 @@ size_t query_lds_bytes(int nl, int N, bool global_cum, size_t slot_bytes) {
 // rows halve the gathered bytes and the summed-area rows need no decoding in
 // the loop (measured 10% faster than FP32 tables on pixel-coherent batches).
 // Larger ranks keep BF16 LDS copies, whose FP32 copies would cost occupancy.
+// FP32 tables from rank 128 up take 16 ranks (64 bytes) a lane: a wave then
+// serves eight queries per step, halving the per-query share of the record
+// read, the row-address arithmetic and the lane reduction, which bind there
+// once the LDS reads are conflict-free (rank 128: 26.3 -> 33.0 G queries/s
+// on the 2^24-record batch; rank 256 +11%; at ranks 16 and 64 the wider
+// slices lost 30% and 20%).
 template <typename FT, typename CT, int R>
 struct QueryPlan {
   static constexpr bool kF32Lds = sizeof(FT) == 2 && R == 64;
-  static constexpr int RPL = kF32Lds ? 8 : rpl_for<FT, R>();
+  static constexpr int RPL = kF32Lds ? 8 : ((sizeof(FT) == 4 && R >= 128) ? 16 : rpl_for<FT, R>());
   typedef typename std::conditional<kF32Lds, float, typename LdsCum<CT>::type>::type LT;
   // 1024-thread blocks where the kernel fits 64 VGPRs at little cost: FP32
   // factor rows up to rank 64 and the BF16 rank-64 layout (5% and 4% faster
