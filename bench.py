@@ -63,8 +63,8 @@ Q_BYTES = 32                   # algorithmic HBM bytes per flat query: 28-byte r
 MEASURED_TRAFFIC = {
     "k_mttkrp_y": ("paper_2109_14807_amd/csrc/cp_als.hip", "be75fb7ede7f7473b663578bb650f0887c45fe70", 36585863551),
     "k_mttkrp_z": ("paper_2109_14807_amd/csrc/cp_als.hip", "be75fb7ede7f7473b663578bb650f0887c45fe70", 34934655679),
-    "k_query_c4": ("paper_2109_14807_amd/csrc/query.hip", "", 0),
-    "k_query_r16": ("paper_2109_14807_amd/csrc/query.hip", "", 0),
+    "k_query_c4": ("paper_2109_14807_amd/csrc/query.hip", "cc2059d4f3c53ea9a0cb18747ead0a68d15bbe21", 601553894),
+    "k_query_r16": ("paper_2109_14807_amd/csrc/query.hip", "cc2059d4f3c53ea9a0cb18747ead0a68d15bbe21", 531095594),
 }
 
 LEGS = ("c3", "c5", "r16", "c2", "refine", "sweep", "cpu_baseline")
