@@ -270,25 +270,65 @@ glint_status glint_cp_als_clustered(const glint_ndf_desc* desc, const glint_clus
                                     uint64_t seed, float* X, float* Y, float* Z,
                                     uint8_t* blank, int32_t* info, hipStream_t stream);
 
+/* The clustered layout of a normal map whose tensor T is not stored (Sec. 4.2
+ * practical choices at the paper's scale: t = 16, 8 x 8 texel regions, rank
+ * 16 or 32, every level).  The angular blocks are taken one at a time: the
+ * tensor of one block, T restricted to bins [zs t, zs t + t) x [zt t, zt t +
+ * t) for every texel and level, is built in the workspace from the texel bin
+ * windows (as glint_build_tensor builds T: level 0 directly, each higher
+ * level the exact mean of four shifted blocks of the level below), in
+ * T_dtype (F32 or F64), and its region tensors are fitted there.  Factors,
+ * blank rule, ALS, initial factors and outputs X, Y, blank, info are those
+ * of glint_cp_als_clustered for the same tensor; Z is stored compactly:
+ * only the non-blank footprints' rows, at the rows zidx names.  Where the Z
+ * factors of a tensor do not fit the LDS (rank 32 with 320 or more
+ * footprints) they live in the workspace (one slot per running workgroup).
+ * Two calls in stream order:
+ *  - glint_cluster_map_index fills zidx int32 [ntensor][L] (the footprint's
+ *    row of Z or -1 for a blank image block; rows numbered tensor by tensor,
+ *    footprints in order) and zbase int64 [ntensor + 1] (the first row of
+ *    each tensor; zbase[ntensor] = the number of rows, which the caller
+ *    reads to size Z); info as for glint_cp_als_clustered (info[1] blank
+ *    tensors, info[3] rows).
+ *  - glint_cp_als_clustered_map fits every tensor and writes X, Y
+ *    [ntensor][t][R], Z [rows][R] (weights absorbed), blank [ntensor], info.
+ * Rows must stay below 2^31.  The workspace (glint_cluster_map_workspace
+ * bytes, 256-byte aligned; the block tensor takes nu nv nlevels t^2
+ * elements of T_dtype) is the same for both calls; the workspace size
+ * depends on the device's CU count. */
+size_t glint_cluster_map_workspace(const glint_ndf_desc* desc, const glint_cluster_desc* cd, glint_dtype T_dtype);
+glint_status glint_cluster_map_index(const glint_ndf_desc* desc, const glint_cluster_desc* cd, const float* nxy,
+                                     glint_dtype T_dtype, int32_t* zidx, int64_t* zbase, int32_t* info,
+                                     void* workspace, size_t workspace_bytes, hipStream_t stream);
+glint_status glint_cp_als_clustered_map(const glint_ndf_desc* desc, const glint_cluster_desc* cd, const float* nxy,
+                                        glint_dtype T_dtype, int32_t iters, uint64_t seed, const int32_t* zidx,
+                                        float* X, float* Y, float* Z, uint8_t* blank, int32_t* info,
+                                        void* workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* C[b][j][r] = sum_{s<j} S[b][s][r] (FP64 accumulation, FP32 out) for
  * nbatch stacked [n][R] tables; C is [nbatch][n+1][R]. */
 glint_status glint_make_cumulative_batched(int64_t nbatch, int32_t n, int32_t R, const float* S,
                                            float* C, hipStream_t stream);
 
 /* Clustered query tables (FP32): summed-area tables of X and Y per tensor,
- * CX, CY [ntensor][t+1][R], and Z [ntensor][L][R]; 16-byte aligned. */
+ * CX, CY [ntensor][t+1][R], and Z: dense [ntensor][L][R] (zidx NULL) or,
+ * in the compact layout, [rows][R] with zidx [ntensor][L] giving each
+ * footprint's row of Z, -1 for a blank image block (no terms); 16-byte
+ * aligned. */
 typedef struct {
   int32_t t, cs, R;
   int32_t nu, nv, nl, nbins;
   const float* CX;
   const float* CY;
   const float* Z;
+  const int32_t* zidx;
 } glint_clustered;
 
 /* Range query on the clustered tables: records as for glint_query (same
  * wrap/clamp/empty rules); the box is split at block edges and the
  * block-local queries sum_r Z[f][r] (CX[a1][r] - CX[a0][r]) (CY[b1][r] -
- * CY[b0][r]) are added.  FP32 arithmetic. */
+ * CY[b0][r]) are added (a blank image block of the compact layout adds
+ * nothing).  FP32 arithmetic. */
 glint_status glint_query_clustered(const glint_clustered* f, int64_t nq, const int32_t* q,
                                    float* out, hipStream_t stream);
 

@@ -10,6 +10,7 @@ from . import _lib  # noqa: F401
 from ._lib import GlintError, NdfDesc  # noqa: F401
 from .api import (  # noqa: F401
     AlsResult, ClusteredTables, QueryTables, als_workspace, clustered_cumulative, cp_als_clustered,
+    cp_als_clustered_map,
     query_clustered, sample_clustered, build_tensor, convert, cp_als, cumulative, cumulative_backward,
     cp_als_texel, desc_of, make_tables, mttkrp, mttkrp_texel, query, query_backward, query_grouped, query_trilinear,
     query_sg, query_wang, range_bruteforce, validate_queries, sample, texel_bins, texel_workspace, WangTables,

@@ -64,7 +64,7 @@ class Clustered(ctypes.Structure):
     _fields_ = [("t", ctypes.c_int32), ("cs", ctypes.c_int32), ("R", ctypes.c_int32),
                 ("nu", ctypes.c_int32), ("nv", ctypes.c_int32), ("nl", ctypes.c_int32),
                 ("nbins", ctypes.c_int32), ("CX", ctypes.c_void_p), ("CY", ctypes.c_void_p),
-                ("Z", ctypes.c_void_p)]
+                ("Z", ctypes.c_void_p), ("zidx", ctypes.c_void_p)]
 
 
 class Wang(ctypes.Structure):
@@ -117,6 +117,10 @@ _SIGS = {
     "glint_mse_grad": (_I32, [_I64, _P, _P, _P, _P, _P]),
     "glint_adam_step": (_I32, [_I64, _P, _P, _P, _P, _F32, _F32, _F32, _F32, _I32, _P]),
     "glint_cp_als_clustered": (_I32, [_DESC, _CDESC, _P, _I32, _I32, _U64, _P, _P, _P, _P, _P, _P]),
+    "glint_cluster_map_workspace": (_SZ, [_DESC, _CDESC, _I32]),
+    "glint_cluster_map_index": (_I32, [_DESC, _CDESC, _P, _I32, _P, _P, _P, _P, _SZ, _P]),
+    "glint_cp_als_clustered_map": (_I32, [_DESC, _CDESC, _P, _I32, _I32, _U64, _P, _P, _P, _P, _P, _P, _P,
+                                          _SZ, _P]),
     "glint_make_cumulative_batched": (_I32, [_I64, _I32, _I32, _P, _P, _P]),
     "glint_query_clustered": (_I32, [_CLU, _I64, _P, _P, _P]),
     "glint_sample_clustered": (_I32, [_CLU, _I64, _P, _P, _P, _P, _P, _P]),
@@ -173,9 +177,13 @@ def _ptr(t, dtype=None, name="tensor"):
 
 
 def _gdtype(t: torch.Tensor) -> int:
-    if t.dtype not in DTYPE_OF:
-        raise TypeError(f"unsupported storage dtype {t.dtype}")
-    return DTYPE_OF[t.dtype]
+    return _gdtype_of(t.dtype)
+
+
+def _gdtype_of(dtype: torch.dtype) -> int:
+    if dtype not in DTYPE_OF:
+        raise TypeError(f"unsupported storage dtype {dtype}")
+    return DTYPE_OF[dtype]
 
 
 # ----------------------------------------------------------------------------
@@ -380,6 +388,27 @@ def glint_cp_als_clustered(desc, cd: ClusterDesc, T, iters, seed, X, Y, Z, blank
         ctypes.byref(desc), ctypes.byref(cd), _ptr(T, None, "T"), _gdtype(T), int(iters),
         int(seed) & ((1 << 64) - 1), _ptr(X, f32, "X"), _ptr(Y, f32, "Y"), _ptr(Z, f32, "Z"),
         _ptr(blank, torch.uint8, "blank"), _ptr(info, torch.int32, "info"), _stream(stream)))
+
+
+def glint_cluster_map_workspace(desc, cd: ClusterDesc, dtype) -> int:
+    return int(lib().glint_cluster_map_workspace(ctypes.byref(desc), ctypes.byref(cd), _gdtype_of(dtype)))
+
+
+def glint_cluster_map_index(desc, cd: ClusterDesc, nxy, dtype, zidx, zbase, info, workspace, stream=None):
+    _check("glint_cluster_map_index", lib().glint_cluster_map_index(
+        ctypes.byref(desc), ctypes.byref(cd), _ptr(nxy, torch.float32, "nxy"), _gdtype_of(dtype),
+        _ptr(zidx, torch.int32, "zidx"), _ptr(zbase, torch.int64, "zbase"), _ptr(info, torch.int32, "info"),
+        _ptr(workspace, torch.uint8, "workspace"), workspace.numel(), _stream(stream)))
+
+
+def glint_cp_als_clustered_map(desc, cd: ClusterDesc, nxy, dtype, iters, seed, zidx, X, Y, Z, blank, info,
+                               workspace, stream=None):
+    f32 = torch.float32
+    _check("glint_cp_als_clustered_map", lib().glint_cp_als_clustered_map(
+        ctypes.byref(desc), ctypes.byref(cd), _ptr(nxy, f32, "nxy"), _gdtype_of(dtype), int(iters),
+        int(seed) & ((1 << 64) - 1), _ptr(zidx, torch.int32, "zidx"), _ptr(X, f32, "X"), _ptr(Y, f32, "Y"),
+        _ptr(Z, f32, "Z"), _ptr(blank, torch.uint8, "blank"), _ptr(info, torch.int32, "info"),
+        _ptr(workspace, torch.uint8, "workspace"), workspace.numel(), _stream(stream)))
 
 
 def glint_make_cumulative_batched(S, C, stream=None):

@@ -276,6 +276,8 @@ class ClusteredTables:
     info: torch.Tensor
     CX: torch.Tensor = None
     CY: torch.Tensor = None
+    zidx: torch.Tensor = None      # compact layout: [ntensor][L] row of Z or -1
+    zbase: torch.Tensor = None     # compact layout: first row of each tensor, then the row count
 
     @property
     def R(self):
@@ -289,7 +291,17 @@ class ClusteredTables:
         d = self.desc
         return L.Clustered(self.t, self.cs, self.R, d.nu, d.nv, d.nlevels, d.nbins,
                            L._ptr(self.CX, torch.float32, "CX"), L._ptr(self.CY, torch.float32, "CY"),
-                           L._ptr(self.Z, torch.float32, "Z"))
+                           L._ptr(self.Z, torch.float32, "Z"), L._ptr(self.zidx, torch.int32, "zidx"))
+
+    def dense_z(self) -> torch.Tensor:
+        """Z as [ntensor][L][R] with zero rows for blank image blocks."""
+        if self.zidx is None:
+            return self.Z
+        n, Lr = self.zidx.shape
+        out = torch.zeros((n * Lr, self.R), dtype=torch.float32, device=self.Z.device)
+        keep = self.zidx.reshape(-1) >= 0
+        out[keep] = self.Z[self.zidx.reshape(-1)[keep].long()]
+        return out.reshape(n, Lr, self.R)
 
 
 def cp_als_clustered(T: torch.Tensor, desc: NdfDesc, t: int, cs: int, R: int, iters: int,
@@ -310,6 +322,35 @@ def cp_als_clustered(T: torch.Tensor, desc: NdfDesc, t: int, cs: int, R: int, it
     L.glint_cp_als_clustered(desc, L.ClusterDesc(t, int(cs), int(R)), T.contiguous(), iters, seed,
                              X, Y, Z, blank, info)
     tab = ClusteredTables(desc, t, int(cs), X, Y, Z, blank, info)
+    clustered_cumulative(tab)
+    return tab
+
+
+def cp_als_clustered_map(nxy: torch.Tensor, desc: NdfDesc, t: int, cs: int, R: int, iters: int,
+                         seed: int = 0, dtype=torch.float32) -> ClusteredTables:
+    """Clustered-layout CP straight from the normal map (no stored T): each
+    angular block's tensor is built in `dtype` (F32 or F64) and fitted in
+    turn; Z is compact (`zidx` gives each footprint's row)."""
+    t = min(int(t), desc.nbins)
+    ncu, ncv, nb = desc.nu // cs, desc.nv // cs, desc.nbins // t
+    ntensor = ncu * ncv * nb * nb
+    Lr = cs * cs * desc.nlevels
+    cd = L.ClusterDesc(t, int(cs), int(R))
+    ws = torch.empty(L.glint_cluster_map_workspace(desc, cd, dtype), dtype=torch.uint8, device=_DEV)
+    nxy = nxy.to(_DEV, torch.float32).contiguous()
+    zidx = torch.empty((ntensor, Lr), dtype=torch.int32, device=_DEV)
+    zbase = torch.empty(ntensor + 1, dtype=torch.int64, device=_DEV)
+    info = torch.empty(4, dtype=torch.int32, device=_DEV)
+    L.glint_cluster_map_index(desc, cd, nxy, dtype, zidx, zbase, info, ws)
+    rows = int(zbase[-1].item())
+    f32 = dict(dtype=torch.float32, device=_DEV)
+    X = torch.empty((ntensor, t, R), **f32)
+    Y = torch.empty((ntensor, t, R), **f32)
+    Z = torch.empty((max(rows, 1), R), **f32)
+    blank = torch.empty(ntensor, dtype=torch.uint8, device=_DEV)
+    L.glint_cp_als_clustered_map(desc, cd, nxy, dtype, iters, seed, zidx, X, Y, Z, blank, info, ws)
+    del ws
+    tab = ClusteredTables(desc, t, int(cs), X, Y, Z, blank, info, zidx=zidx, zbase=zbase)
     clustered_cumulative(tab)
     return tab
 

@@ -65,6 +65,18 @@ struct ClusterArgs {
   float* Z;
   uint8_t* blank;
   int* info;
+  // tensor i of T is the layout's tensor i * tmul + tadd (T holding one
+  // angular block: tmul = nb^2 of the whole image, tadd = its zs nb + zt)
+  int64_t tmul, tadd;
+  // compact layout (null: dense Z [ntensor][L][R] with zero blank rows):
+  // zidx[tensor][f] is the footprint's row of Z or -1 (blank); the mass
+  // pass writes 0/1 flags there and counts[tensor] the non-blank footprints
+  int32_t* zidx;
+  int32_t* counts;
+  // Z factors in global memory (one slot of zws_stride doubles per
+  // workgroup) where the LDS cannot hold them
+  double* zws;
+  int64_t zws_stride;
 };
 
 // Offsets of the LDS arrays (in doubles) of the ALS kernel.  Z rows are
@@ -73,7 +85,7 @@ struct ClusterLds {
   int x, y, mt, z, p, gx, gy, gz, gm, lam, dg, dl, foff, keep, rowof, stage, total_doubles;
 };
 
-__host__ __device__ inline ClusterLds cluster_lds(int t, int L, int R, int stage_doubles) {
+__host__ __device__ inline ClusterLds cluster_lds(int t, int L, int R, int stage_doubles, bool z_global) {
   ClusterLds o;
   int at = 0;
   auto take = [&](int n) {
@@ -84,7 +96,7 @@ __host__ __device__ inline ClusterLds cluster_lds(int t, int L, int R, int stage
   o.x = take(t * R);
   o.y = take(t * R);
   o.mt = take(t * R);
-  o.z = take(L * (R + 1));
+  o.z = z_global ? -1 : take(L * (R + 1));
   o.p = take(t * t * R);
   o.gx = take(R * R);
   o.gy = take(R * R);
@@ -146,7 +158,9 @@ __global__ __launch_bounds__(kMassThreads) void k_cluster_mass(ClusterArgs c) {
   const TT* Tb = static_cast<const TT*>(c.T) + bp.base;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = kMassThreads / 64;
   const int tt = c.t * c.t, L = c.L;
-  float* flags = c.Z + static_cast<int64_t>(tensor) * L * c.R;
+  const int64_t tout = tensor * c.tmul + c.tadd;
+  float* flags = c.zidx ? nullptr : c.Z + tout * L * c.R;
+  int32_t* fidx = c.zidx ? c.zidx + tout * L : nullptr;
   int64_t boff[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -168,7 +182,14 @@ __global__ __launch_bounds__(kMassThreads) void k_cluster_mass(ClusterArgs c) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) m += fabs(static_cast<double>(v[u][q]));
       m = glint_wave_sum(m);
-      if (lane == 0 && f0 + u < L) flags[static_cast<int64_t>(f0 + u) * c.R] = m > kBlankTol ? 1.0f : 0.0f;
+      if (lane == 0 && f0 + u < L) {
+        if (fidx) {
+          fidx[f0 + u] = m > kBlankTol ? 1 : 0;
+          if (m > kBlankTol) atomicAdd(&c.counts[tout], 1);
+        } else {
+          flags[static_cast<int64_t>(f0 + u) * c.R] = m > kBlankTol ? 1.0f : 0.0f;
+        }
+      }
     }
   }
 }
@@ -347,7 +368,7 @@ __device__ void normalize_by_gram(double* F, int rows, int ld, double* G, double
 // CP-ALS of one block tensor by the whole workgroup (every sweep).  Not
 // inlined: its early exits then stay inside the call, and the persistent
 // loop around it is a plain scalar loop.
-template <typename TT, int R>
+template <typename TT, int R, bool ZG>
 __device__ __noinline__ void als_one(const ClusterArgs& c, int tensor) {
   constexpr int RB = (R + 15) / 16;
   constexpr int ABC = stage_ab<TT>(), SS = stage_stride<TT>();
@@ -355,11 +376,11 @@ __device__ __noinline__ void als_one(const ClusterArgs& c, int tensor) {
   static_assert(kClThreads % ABC == 0, "stage rows must map to fixed lanes");
   extern __shared__ __align__(16) double cl_lds[];
   const int t = c.t, L = c.L, tt = t * t, ZS = R + 1;
-  const ClusterLds o = cluster_lds(t, L, R, stage_doubles<TT>());
+  const ClusterLds o = cluster_lds(t, L, R, stage_doubles<TT>(), ZG);
   double* X = cl_lds + o.x;
   double* Y = cl_lds + o.y;
   double* Mt = cl_lds + o.mt;
-  double* Z = cl_lds + o.z;
+  double* Z = ZG ? c.zws + static_cast<int64_t>(blockIdx.x) * c.zws_stride : cl_lds + o.z;
   double* P = cl_lds + o.p;
   double* GX = cl_lds + o.gx;
   double* GY = cl_lds + o.gy;
@@ -377,17 +398,21 @@ __device__ __noinline__ void als_one(const ClusterArgs& c, int tensor) {
   __shared__ int wcnt[kClWaves];
   __shared__ int s_flag;
 
-  float* outX = c.X + static_cast<int64_t>(tensor) * t * R;
-  float* outY = c.Y + static_cast<int64_t>(tensor) * t * R;
-  float* outZ = c.Z + static_cast<int64_t>(tensor) * L * R;
+  const int64_t tout = tensor * c.tmul + c.tadd;
+  float* outX = c.X + tout * t * R;
+  float* outY = c.Y + tout * t * R;
+  float* outZ = c.zidx ? nullptr : c.Z + tout * L * R;      // dense layout
+  const int32_t* zrow = c.zidx ? c.zidx + tout * L : nullptr;  // compact layout
   const BlockPos bp = block_pos(c, tensor);
   const TT* Tb = static_cast<const TT*>(c.T) + bp.base;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
 
   // blank image blocks are thrown away: the flags k_cluster_mass left in the
-  // Z rows, then the non-blank footprints are stacked in order
-  for (int f = threadIdx.x; f < L; f += blockDim.x) rowof[f] = outZ[static_cast<int64_t>(f) * R] != 0.0f ? 1 : 0;
+  // Z rows (or the compact layout's row index), then the non-blank
+  // footprints are stacked in order
+  for (int f = threadIdx.x; f < L; f += blockDim.x)
+    rowof[f] = zrow ? (zrow[f] >= 0 ? 1 : 0) : (outZ[static_cast<int64_t>(f) * R] != 0.0f ? 1 : 0);
   __syncthreads();
   int Lc = 0;
   for (int base = 0; base < L; base += kClThreads) {
@@ -414,9 +439,10 @@ __device__ __noinline__ void als_one(const ClusterArgs& c, int tensor) {
       outX[i] = 0.0f;
       outY[i] = 0.0f;
     }
-    for (int i = threadIdx.x; i < L * R; i += blockDim.x) outZ[i] = 0.0f;
+    if (outZ)
+      for (int i = threadIdx.x; i < L * R; i += blockDim.x) outZ[i] = 0.0f;
     if (threadIdx.x == 0) {
-      c.blank[tensor] = 1;
+      c.blank[tout] = 1;
       atomicAdd(&c.info[1], 1);
     }
     return;
@@ -428,13 +454,13 @@ __device__ __noinline__ void als_one(const ClusterArgs& c, int tensor) {
   const uint64_t rows_max = t > L ? t : L;
   for (int i = threadIdx.x; i < t * R; i += blockDim.x) {
     const uint64_t row = i / R, r = i % R;
-    X[i] = glint_sm64_uniform(c.seed, ((static_cast<uint64_t>(tensor) * 3 + 0) * rows_max + row) * R + r);
-    Y[i] = glint_sm64_uniform(c.seed, ((static_cast<uint64_t>(tensor) * 3 + 1) * rows_max + row) * R + r);
+    X[i] = glint_sm64_uniform(c.seed, ((static_cast<uint64_t>(tout) * 3 + 0) * rows_max + row) * R + r);
+    Y[i] = glint_sm64_uniform(c.seed, ((static_cast<uint64_t>(tout) * 3 + 1) * rows_max + row) * R + r);
   }
   for (int i = threadIdx.x; i < Lc * R; i += blockDim.x) {
     const int j = i / R, r = i % R;
     const uint64_t row = static_cast<uint64_t>(keep[j]);
-    Z[j * ZS + r] = glint_sm64_uniform(c.seed, ((static_cast<uint64_t>(tensor) * 3 + 2) * rows_max + row) * R + r);
+    Z[j * ZS + r] = glint_sm64_uniform(c.seed, ((static_cast<uint64_t>(tout) * 3 + 2) * rows_max + row) * R + r);
   }
   if (threadIdx.x < R) lam[threadIdx.x] = 1.0;
   __syncthreads();
@@ -472,7 +498,10 @@ __device__ __noinline__ void als_one(const ClusterArgs& c, int tensor) {
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) acc[b][rb] = f64x4{0.0, 0.0, 0.0, 0.0};
       TT cur[kUK][2], nxt[kUK][2];
-      auto load = [&](int batch, TT (&v)[kUK][2]) {
+      // with Z in global memory its rows are fetched with the batch's D
+      constexpr int ZB = ZG ? kUK : 1;
+      double zc[ZB][RB], zn[ZB][RB];
+      auto load = [&](int batch, TT (&v)[kUK][2], double (&zv)[ZB][RB]) {
 #pragma unroll
         for (int s = 0; s < kUK; ++s) {
           const int f = (batch * kUK + s) * 4 + lk;
@@ -480,18 +509,25 @@ __device__ __noinline__ void als_one(const ClusterArgs& c, int tensor) {
           const int64_t fo = fok ? foff[f] : 0;
 #pragma unroll
           for (int b = 0; b < 2; ++b) v[s][b] = (fok && aok[b]) ? Tb[fo + aoff[b]] : TT(0);
+          if constexpr (ZG) {
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) zv[s][rb] = (fok && rb * 16 + li < R) ? Z[f * ZS + rb * 16 + li] : 0.0;
+          }
         }
       };
-      if (own0) load(0, cur);
+      if (own0) load(0, cur, zc);
       for (int bt = 0; bt < nbatch_a; ++bt) {
-        if (own0 && bt + 1 < nbatch_a) load(bt + 1, nxt);
+        if (own0 && bt + 1 < nbatch_a) load(bt + 1, nxt, zn);
         if (own0) {
 #pragma unroll
           for (int s = 0; s < kUK; ++s) {
             const int f = (bt * kUK + s) * 4 + lk;
             double bz[RB];
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) bz[rb] = (f < Lc && rb * 16 + li < R) ? Z[f * ZS + rb * 16 + li] : 0.0;
+            for (int rb = 0; rb < RB; ++rb) {
+              if constexpr (ZG) bz[rb] = zc[s][rb];
+              else bz[rb] = (f < Lc && rb * 16 + li < R) ? Z[f * ZS + rb * 16 + li] : 0.0;
+            }
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) acc[0][rb] = mfma64(static_cast<double>(cur[s][0]), bz[rb], acc[0][rb]);
             if (own1) {
@@ -503,6 +539,12 @@ __device__ __noinline__ void als_one(const ClusterArgs& c, int tensor) {
           for (int s = 0; s < kUK; ++s) {
             cur[s][0] = nxt[s][0];
             cur[s][1] = nxt[s][1];
+          }
+          if constexpr (ZG) {
+#pragma unroll
+            for (int s = 0; s < kUK; ++s)
+#pragma unroll
+              for (int rb = 0; rb < RB; ++rb) zc[s][rb] = zn[s][rb];
           }
         }
       }
@@ -630,12 +672,19 @@ __device__ __noinline__ void als_one(const ClusterArgs& c, int tensor) {
     outX[i] = static_cast<float>(X[i]);
     outY[i] = static_cast<float>(Y[i]);
   }
-  for (int i = threadIdx.x; i < L * R; i += blockDim.x) {
-    const int f = i / R, r = i % R, j = rowof[f];
-    outZ[i] = j >= 0 ? static_cast<float>(Z[j * ZS + r] * lam[r]) : 0.0f;
+  if (outZ) {
+    for (int i = threadIdx.x; i < L * R; i += blockDim.x) {
+      const int f = i / R, r = i % R, j = rowof[f];
+      outZ[i] = j >= 0 ? static_cast<float>(Z[j * ZS + r] * lam[r]) : 0.0f;
+    }
+  } else {
+    for (int i = threadIdx.x; i < Lc * R; i += blockDim.x) {
+      const int j = i / R, r = i % R;
+      c.Z[static_cast<int64_t>(zrow[keep[j]]) * R + r] = static_cast<float>(Z[j * ZS + r] * lam[r]);
+    }
   }
   if (threadIdx.x == 0) {
-    c.blank[tensor] = 0;
+    c.blank[tout] = 0;
     atomicAdd(&c.info[3], Lc);
   }
   if (threadIdx.x == 0 && fails) atomicAdd(&c.info[0], fails);
@@ -646,7 +695,7 @@ __device__ __noinline__ void als_one(const ClusterArgs& c, int tensor) {
 // their zero outputs, and a fixed index-to-tensor mapping would let the
 // workgroup dispatcher's round-robin over XCDs and shader engines line up
 // with the angular positions of the non-blank blocks.
-template <typename TT, int R>
+template <typename TT, int R, bool ZG>
 __global__ __launch_bounds__(kClThreads) void k_cluster_als(ClusterArgs c) {
   __shared__ int s_next;
   for (;;) {
@@ -658,12 +707,120 @@ __global__ __launch_bounds__(kClThreads) void k_cluster_als(ClusterArgs c) {
     const int tensor = __builtin_amdgcn_readfirstlane(s_next);
     __syncthreads();
     if (tensor >= c.ntensor) break;
-    als_one<TT, R>(c, tensor);
+    als_one<TT, R, ZG>(c, tensor);
   }
 }
 
 __global__ void k_cluster_info_init(int* info) {
   if (threadIdx.x < 4) info[threadIdx.x] = 0;
+}
+
+__global__ void k_cluster_claim_reset(int* info) {
+  if (threadIdx.x == 0) info[2] = 0;
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Exclusive prefix sum of the per-tensor counts into the compact rows'
+// bases: base[i] = sum_{j<i} counts[j], base[n] = the total.  Three steps
+// over chunks of kScanChunk counts: chunk sums, one workgroup scanning the
+// chunk sums in order (a running carry), and the scan inside each chunk.
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 4;
+constexpr int kScanChunk = kScanThreads * kScanPer;
+
+// exclusive scan of v over the workgroup (kScanThreads threads); *total = the sum
+__device__ int64_t block_exclusive_scan(int64_t v, int64_t* total) {
+  __shared__ int64_t wsum[kScanThreads / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int64_t inc = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int64_t o = __shfl_up(inc, d);
+    if (lane >= d) inc += o;
+  }
+  if (lane == 63) wsum[wave] = inc;
+  __syncthreads();
+  int64_t before = 0, all = 0;
+  for (int w = 0; w < kScanThreads / 64; ++w) {
+    if (w < wave) before += wsum[w];
+    all += wsum[w];
+  }
+  __syncthreads();
+  *total = all;
+  return before + inc - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_chunks(const int32_t* __restrict__ counts, int64_t n,
+                                                              int64_t* __restrict__ csum) {
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kScanChunk + threadIdx.x * kScanPer;
+  int64_t v = 0;
+#pragma unroll
+  for (int e = 0; e < kScanPer; ++e)
+    if (i0 + e < n) v += counts[i0 + e];
+  int64_t total;
+  block_exclusive_scan(v, &total);
+  if (threadIdx.x == 0) csum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(int64_t* __restrict__ csum, int64_t nchunk,
+                                                           int64_t* __restrict__ base, int64_t n, int* info) {
+  int64_t carry = 0;
+  for (int64_t c0 = 0; c0 < nchunk; c0 += kScanThreads) {
+    const int64_t c = c0 + threadIdx.x;
+    const int64_t v = c < nchunk ? csum[c] : 0;
+    int64_t total;
+    const int64_t ex = block_exclusive_scan(v, &total);
+    if (c < nchunk) csum[c] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) {
+    base[n] = carry;
+    info[3] = carry < 0x7fffffff ? static_cast<int>(carry) : 0x7fffffff;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int32_t* __restrict__ counts, int64_t n,
+                                                             const int64_t* __restrict__ csum,
+                                                             int64_t* __restrict__ base) {
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kScanChunk + threadIdx.x * kScanPer;
+  int64_t v = 0;
+#pragma unroll
+  for (int e = 0; e < kScanPer; ++e)
+    if (i0 + e < n) v += counts[i0 + e];
+  int64_t total;
+  int64_t run = csum[blockIdx.x] + block_exclusive_scan(v, &total);
+#pragma unroll
+  for (int e = 0; e < kScanPer; ++e)
+    if (i0 + e < n) {
+      base[i0 + e] = run;
+      run += counts[i0 + e];
+    }
+}
+
+// The compact rows: one wavefront per tensor turns the mass pass's 0/1
+// flags in zidx[tensor][f] into base[tensor] + (the footprint's place among
+// the tensor's non-blank footprints), or -1; a tensor without any counts
+// as blank (info[1]).
+__global__ __launch_bounds__(256) void k_cluster_rows(int32_t* __restrict__ zidx, const int64_t* __restrict__ base,
+                                                      int64_t ntensor, int L, int* info) {
+  const int lane = threadIdx.x & 63;
+  const int64_t tensor = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  if (tensor >= ntensor) return;
+  int32_t* z = zidx + tensor * L;
+  const int64_t b = base[tensor];
+  int run = 0;
+  for (int f0 = 0; f0 < L; f0 += 64) {
+    const int f = f0 + lane;
+    const bool nb = f < L && z[f] != 0;
+    const unsigned long long bal = __ballot(nb);
+    if (f < L) z[f] = nb ? static_cast<int32_t>(b + run + __popcll(bal & ((1ull << lane) - 1ull))) : -1;
+    run += __popcll(bal);
+  }
+  if (lane == 0 && run == 0) atomicAdd(&info[1], 1);
 }
 
 // C[b][j][r] = sum_{s<j} S[b][s][r] (FP64 accumulation), FP32 out.
@@ -690,7 +847,8 @@ __global__ void k_cumulative_batched(int64_t nbatch, int n, int R, const float* 
 struct ClQueryArgs {
   const float* CX;   // [ntensor][t+1][R]
   const float* CY;
-  const float* Z;    // [ntensor][L][R]
+  const float* Z;    // [ntensor][L][R], or [rows][R] with zidx
+  const int32_t* zidx;   // compact layout: [ntensor][L] row of Z or -1 (blank)
   int t, cs, nu, nv, nl, N, ncv, nb, L;
   int64_t nq;
   const int32_t* q;
@@ -747,9 +905,14 @@ __global__ __launch_bounds__(kClQueryThreads) void k_query_clustered(ClQueryArgs
           for (int zt = cr.tlo / t; zt <= (cr.thi - 1) / t; ++zt) {
             const int b0 = max(cr.tlo, zt * t) - zt * t, b1 = min(cr.thi, (zt + 1) * t) - zt * t;
             const int64_t tensor = cr.tensor0 + zs * a.nb + zt;
+            int64_t zr = tensor * a.L + cr.f;
+            if (a.zidx) {
+              zr = a.zidx[zr];
+              if (zr < 0) continue;     // blank image block: no terms
+            }
             const float* cx = a.CX + tensor * (t + 1) * R + r0;
             const float* cy = a.CY + tensor * (t + 1) * R + r0;
-            const float* z = a.Z + (tensor * a.L + cr.f) * R + r0;
+            const float* z = a.Z + zr * R + r0;
 #pragma unroll
             for (int e = 0; e < RPL; ++e)
               acc += z[e] * (cx[a1 * R + e] - cx[a0 * R + e]) * (cy[b1 * R + e] - cy[b0 * R + e]);
@@ -773,6 +936,7 @@ struct ClSampleArgs {
   const float* CX;
   const float* CY;
   const float* Z;
+  const int32_t* zidx;
   int t, cs, nu, nv, nl, N, ncv, nb, L, levels;
   int64_t n;
   const int32_t* uvl;
@@ -788,7 +952,12 @@ constexpr int kClSampleThreads = 256;
 template <int R>
 __device__ __forceinline__ float cl_box(const ClSampleArgs& a, int64_t tensor, int f, int a0, int a1, int b0,
                                         int b1) {
-  const float* z = a.Z + (tensor * a.L + f) * R;
+  int64_t zr = tensor * a.L + f;
+  if (a.zidx) {
+    zr = a.zidx[zr];
+    if (zr < 0) return 0.0f;
+  }
+  const float* z = a.Z + zr * R;
   const float* cx = a.CX + tensor * (a.t + 1) * R;
   const float* cy = a.CY + tensor * (a.t + 1) * R;
   float m = 0.0f;
@@ -943,22 +1112,125 @@ glint_status cluster_shape(const glint_ndf_desc* d, const glint_cluster_desc* cd
 }
 
 template <typename TT, int R>
-glint_status launch_cluster_als(const ClusterArgs& c, int64_t ntensor, hipStream_t stream) {
-  const ClusterLds o = cluster_lds(c.t, c.L, R, stage_doubles<TT>());
-  const size_t lds = sizeof(double) * o.total_doubles;
-  if (static_cast<int64_t>(lds) + 64 > g_cl_lds)   // + the kernel's static slots
+size_t cluster_als_lds(int t, int L, bool z_global) {
+  return sizeof(double) * static_cast<size_t>(cluster_lds(t, L, R, stage_doubles<TT>(), z_global).total_doubles);
+}
+
+// Z factor slots in global memory: as many as ALS workgroups can run at once
+// (the kernel's LDS use allows at most this many per CU when Z is global)
+constexpr int kZSlotsPerCu = 2;
+
+// The mass pass (when asked) and the persistent ALS kernel.  Z stays in LDS
+// when it fits; otherwise it goes to the zslots slots of c.zws, or the call
+// is refused when there are none.
+template <typename TT, int R>
+glint_status launch_cluster_als(const ClusterArgs& c0, int64_t ntensor, bool run_mass, int64_t zslots,
+                                hipStream_t stream) {
+  ClusterArgs c = c0;
+  const size_t lds_in = cluster_als_lds<TT, R>(c.t, c.L, false);
+  const bool zg = static_cast<int64_t>(lds_in) + 64 > g_cl_lds;   // + the kernel's static slots
+  const size_t lds = zg ? cluster_als_lds<TT, R>(c.t, c.L, true) : lds_in;
+  if (static_cast<int64_t>(lds) + 64 > g_cl_lds)
     return glint_fail(GLINT_E_UNSUPPORTED, "clustered ALS needs %zu bytes of LDS (device max %d)", lds, g_cl_lds);
-  hipLaunchKernelGGL((k_cluster_mass<TT>), dim3(static_cast<unsigned>(ntensor)), dim3(kMassThreads), 0, stream, c);
-  GLINT_LAUNCHED("k_cluster_mass");
+  if (zg && (c.zws == nullptr || zslots < 1))
+    return glint_fail(GLINT_E_UNSUPPORTED,
+                      "the Z factors of %d footprints at rank %d need %zu bytes of LDS (device max %d); "
+                      "glint_cp_als_clustered_map keeps them in its workspace instead", c.L, R, lds_in, g_cl_lds);
+  if (run_mass) {
+    hipLaunchKernelGGL((k_cluster_mass<TT>), dim3(static_cast<unsigned>(ntensor)), dim3(kMassThreads), 0, stream, c);
+    GLINT_LAUNCHED("k_cluster_mass");
+  }
+  const void* kfn = zg ? reinterpret_cast<const void*>(k_cluster_als<TT, R, true>)
+                       : reinterpret_cast<const void*>(k_cluster_als<TT, R, false>);
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_cluster_als<TT, R>),
-                                                   kClThreads, lds) != hipSuccess || per_cu < 1)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, kClThreads, lds) != hipSuccess || per_cu < 1)
     return glint_fail(GLINT_E_HIP, "occupancy query for k_cluster_als failed");
   int64_t grid = static_cast<int64_t>(g_cl_cus) * per_cu;
+  if (zg && grid > zslots) grid = zslots;
   if (grid > ntensor) grid = ntensor;
-  hipLaunchKernelGGL((k_cluster_als<TT, R>), dim3(static_cast<unsigned>(grid)), dim3(kClThreads), lds, stream, c);
+  hipLaunchKernelGGL(k_cluster_claim_reset, dim3(1), dim3(64), 0, stream, c.info);
+  GLINT_LAUNCHED("k_cluster_claim_reset");
+  if (zg)
+    hipLaunchKernelGGL((k_cluster_als<TT, R, true>), dim3(static_cast<unsigned>(grid)), dim3(kClThreads), lds,
+                       stream, c);
+  else
+    hipLaunchKernelGGL((k_cluster_als<TT, R, false>), dim3(static_cast<unsigned>(grid)), dim3(kClThreads), lds,
+                       stream, c);
   GLINT_LAUNCHED("k_cluster_als");
   return GLINT_OK;
+}
+
+template <typename TT>
+glint_status launch_cluster_als_r(const ClusterArgs& c, int64_t ntensor, bool run_mass, int64_t zslots,
+                                  hipStream_t stream) {
+  switch (c.R) {
+    case 4: return launch_cluster_als<TT, 4>(c, ntensor, run_mass, zslots, stream);
+    case 8: return launch_cluster_als<TT, 8>(c, ntensor, run_mass, zslots, stream);
+    case 16: return launch_cluster_als<TT, 16>(c, ntensor, run_mass, zslots, stream);
+    default: return launch_cluster_als<TT, 32>(c, ntensor, run_mass, zslots, stream);
+  }
+}
+
+// Workspace of the map-driven calls: the texel bin windows, one angular
+// block's tensor, the Z slots, the per-tensor counts and the scan's chunk sums.
+struct MapWs {
+  size_t bins, mass, sub, zws, counts, csum, total;
+  int64_t zslots, zstride, nchunk;
+};
+
+MapWs map_workspace(const glint_ndf_desc* d, const ClShape& s, int R, glint_dtype dt) {
+  MapWs w;
+  const int K = glint_window_k(d);
+  const size_t texels = static_cast<size_t>(d->nu) * d->nv;
+  size_t at = 0;
+  auto take = [&](size_t bytes) {
+    const size_t a = at;
+    at += glint_round_up(bytes, 256);
+    return a;
+  };
+  w.bins = take(sizeof(int32_t) * 2 * texels);
+  w.mass = take(sizeof(double) * 2 * texels * (2 * K + 1));
+  w.sub = take(glint_dtype_size(dt) * texels * d->nlevels * s.t * s.t);
+  w.zslots = static_cast<int64_t>(kZSlotsPerCu) * g_cl_cus;
+  w.zstride = static_cast<int64_t>(s.L) * (R + 1);
+  w.zws = take(sizeof(double) * static_cast<size_t>(w.zslots * w.zstride));
+  w.counts = take(sizeof(int32_t) * static_cast<size_t>(s.ntensor));
+  w.nchunk = (s.ntensor + kScanChunk - 1) / kScanChunk;
+  w.csum = take(sizeof(int64_t) * static_cast<size_t>(w.nchunk));
+  w.total = at;
+  return w;
+}
+
+// Arguments of the kernels for the tensor of angular block (zs, zt): T is
+// that block's tensor (nbins = t, one block), its tensors numbered
+// ((cu ncv + cv) nb + zs) nb + zt in the whole layout.
+ClusterArgs map_args(const glint_ndf_desc* d, const glint_cluster_desc* cd, const ClShape& s, const void* sub,
+                     int zs, int zt) {
+  ClusterArgs c = {};
+  c.T = sub; c.nu = d->nu; c.nv = d->nv; c.nl = d->nlevels; c.N = s.t;
+  c.t = s.t; c.cs = cd->cs; c.ncv = s.ncv; c.nb = 1; c.L = s.L; c.R = cd->R;
+  c.ntensor = static_cast<int>(s.ntensor / (static_cast<int64_t>(s.nb) * s.nb));
+  c.tmul = static_cast<int64_t>(s.nb) * s.nb;
+  c.tadd = static_cast<int64_t>(zs) * s.nb + zt;
+  return c;
+}
+
+glint_status map_prologue(const glint_ndf_desc* desc, const glint_cluster_desc* cd, const float* nxy,
+                          glint_dtype T_dtype, void* workspace, size_t workspace_bytes, ClShape* s, MapWs* w,
+                          hipStream_t stream) {
+  glint_status st = cluster_shape(desc, cd, s);
+  if (st != GLINT_OK) return st;
+  GLINT_SUPPORT(T_dtype == GLINT_F32 || T_dtype == GLINT_F64, "block tensors must be F32 or F64");
+  GLINT_REQUIRE(nxy && workspace, "null pointer argument");
+  GLINT_REQUIRE(glint_aligned(workspace, 256), "workspace must be 256-byte aligned");
+  GLINT_SUPPORT(s->t * s->t % 4 == 0, "block side %d: t^2 must be a multiple of 4", s->t);
+  if ((st = cl_device()) != GLINT_OK) return st;
+  *w = map_workspace(desc, *s, cd->R, T_dtype);
+  if (workspace_bytes < w->total)
+    return glint_fail(GLINT_E_WORKSPACE, "workspace %zu < %zu bytes", workspace_bytes, w->total);
+  unsigned char* ws = static_cast<unsigned char*>(workspace);
+  return glint_texel_bins(desc, nxy, reinterpret_cast<int32_t*>(ws + w->bins), reinterpret_cast<double*>(ws + w->mass),
+                          stream);
 }
 
 }  // namespace
@@ -979,17 +1251,103 @@ glint_status glint_cp_als_clustered(const glint_ndf_desc* desc, const glint_clus
   c.T = T; c.nu = desc->nu; c.nv = desc->nv; c.nl = desc->nlevels; c.N = desc->nbins;
   c.t = s.t; c.cs = cd->cs; c.ncv = s.ncv; c.nb = s.nb; c.L = s.L;
   c.iters = iters; c.ntensor = static_cast<int>(s.ntensor); c.R = cd->R; c.seed = seed; c.X = X; c.Y = Y; c.Z = Z; c.blank = blank; c.info = info;
+  c.tmul = 1; c.tadd = 0; c.zidx = nullptr; c.counts = nullptr; c.zws = nullptr; c.zws_stride = 0;
   glint_clear_launch_error();
   hipLaunchKernelGGL(k_cluster_info_init, dim3(1), dim3(64), 0, stream, info);
   GLINT_LAUNCHED("k_cluster_info_init");
-  const bool f64 = T_dtype == GLINT_F64;
-  const int64_t n = s.ntensor;
-  switch (cd->R) {
-    case 4: return f64 ? launch_cluster_als<double, 4>(c, n, stream) : launch_cluster_als<float, 4>(c, n, stream);
-    case 8: return f64 ? launch_cluster_als<double, 8>(c, n, stream) : launch_cluster_als<float, 8>(c, n, stream);
-    case 16: return f64 ? launch_cluster_als<double, 16>(c, n, stream) : launch_cluster_als<float, 16>(c, n, stream);
-    default: return f64 ? launch_cluster_als<double, 32>(c, n, stream) : launch_cluster_als<float, 32>(c, n, stream);
-  }
+  if (T_dtype == GLINT_F64) return launch_cluster_als_r<double>(c, s.ntensor, true, 0, stream);
+  return launch_cluster_als_r<float>(c, s.ntensor, true, 0, stream);
+}
+
+size_t glint_cluster_map_workspace(const glint_ndf_desc* desc, const glint_cluster_desc* cd, glint_dtype T_dtype) {
+  ClShape s;
+  if (cluster_shape(desc, cd, &s) != GLINT_OK || cl_device() != GLINT_OK) return 0;
+  if (T_dtype != GLINT_F32 && T_dtype != GLINT_F64) return 0;
+  return map_workspace(desc, s, cd->R, T_dtype).total;
+}
+
+glint_status glint_cluster_map_index(const glint_ndf_desc* desc, const glint_cluster_desc* cd, const float* nxy,
+                                     glint_dtype T_dtype, int32_t* zidx, int64_t* zbase, int32_t* info,
+                                     void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  ClShape s;
+  MapWs w;
+  GLINT_REQUIRE(zidx && zbase && info, "null pointer argument");
+  glint_status st = map_prologue(desc, cd, nxy, T_dtype, workspace, workspace_bytes, &s, &w, stream);
+  if (st != GLINT_OK) return st;
+  unsigned char* ws = static_cast<unsigned char*>(workspace);
+  const int32_t* bins = reinterpret_cast<const int32_t*>(ws + w.bins);
+  const double* mass = reinterpret_cast<const double*>(ws + w.mass);
+  int32_t* counts = reinterpret_cast<int32_t*>(ws + w.counts);
+  int64_t* csum = reinterpret_cast<int64_t*>(ws + w.csum);
+  glint_clear_launch_error();
+  hipLaunchKernelGGL(k_cluster_info_init, dim3(1), dim3(64), 0, stream, info);
+  GLINT_LAUNCHED("k_cluster_info_init");
+  hipLaunchKernelGGL(k_fill_i32, dim3(static_cast<unsigned>((s.ntensor + 255) / 256)), dim3(256), 0, stream, counts,
+                     s.ntensor, 0);
+  GLINT_LAUNCHED("k_fill_i32");
+  for (int zs = 0; zs < s.nb; ++zs)
+    for (int zt = 0; zt < s.nb; ++zt) {
+      if ((st = glint_build_window(desc, bins, mass, ws + w.sub, T_dtype, 1, zs * s.t, zt * s.t, s.t, stream)) !=
+          GLINT_OK)
+        return st;
+      ClusterArgs c = map_args(desc, cd, s, ws + w.sub, zs, zt);
+      c.zidx = zidx;
+      c.counts = counts;
+      c.info = info;
+      glint_clear_launch_error();
+      if (T_dtype == GLINT_F64)
+        hipLaunchKernelGGL((k_cluster_mass<double>), dim3(static_cast<unsigned>(c.ntensor)), dim3(kMassThreads), 0,
+                           stream, c);
+      else
+        hipLaunchKernelGGL((k_cluster_mass<float>), dim3(static_cast<unsigned>(c.ntensor)), dim3(kMassThreads), 0,
+                           stream, c);
+      GLINT_LAUNCHED("k_cluster_mass");
+    }
+  const unsigned nchunk = static_cast<unsigned>(w.nchunk);
+  glint_clear_launch_error();
+  hipLaunchKernelGGL(k_scan_chunks, dim3(nchunk), dim3(kScanThreads), 0, stream, counts, s.ntensor, csum);
+  GLINT_LAUNCHED("k_scan_chunks");
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, stream, csum, w.nchunk, zbase, s.ntensor, info);
+  GLINT_LAUNCHED("k_scan_top");
+  hipLaunchKernelGGL(k_scan_apply, dim3(nchunk), dim3(kScanThreads), 0, stream, counts, s.ntensor, csum, zbase);
+  GLINT_LAUNCHED("k_scan_apply");
+  hipLaunchKernelGGL(k_cluster_rows, dim3(static_cast<unsigned>((s.ntensor + 3) / 4)), dim3(256), 0, stream, zidx,
+                     zbase, s.ntensor, s.L, info);
+  GLINT_LAUNCHED("k_cluster_rows");
+  return GLINT_OK;
+}
+
+glint_status glint_cp_als_clustered_map(const glint_ndf_desc* desc, const glint_cluster_desc* cd, const float* nxy,
+                                        glint_dtype T_dtype, int32_t iters, uint64_t seed, const int32_t* zidx,
+                                        float* X, float* Y, float* Z, uint8_t* blank, int32_t* info,
+                                        void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  ClShape s;
+  MapWs w;
+  GLINT_REQUIRE(zidx && X && Y && Z && blank && info, "null pointer argument");
+  GLINT_REQUIRE(iters >= 1, "iters must be >= 1");
+  glint_status st = map_prologue(desc, cd, nxy, T_dtype, workspace, workspace_bytes, &s, &w, stream);
+  if (st != GLINT_OK) return st;
+  unsigned char* ws = static_cast<unsigned char*>(workspace);
+  const int32_t* bins = reinterpret_cast<const int32_t*>(ws + w.bins);
+  const double* mass = reinterpret_cast<const double*>(ws + w.mass);
+  glint_clear_launch_error();
+  hipLaunchKernelGGL(k_cluster_info_init, dim3(1), dim3(64), 0, stream, info);
+  GLINT_LAUNCHED("k_cluster_info_init");
+  for (int zs = 0; zs < s.nb; ++zs)
+    for (int zt = 0; zt < s.nb; ++zt) {
+      if ((st = glint_build_window(desc, bins, mass, ws + w.sub, T_dtype, 1, zs * s.t, zt * s.t, s.t, stream)) !=
+          GLINT_OK)
+        return st;
+      ClusterArgs c = map_args(desc, cd, s, ws + w.sub, zs, zt);
+      c.iters = iters; c.seed = seed; c.X = X; c.Y = Y; c.Z = Z; c.blank = blank; c.info = info;
+      c.zidx = const_cast<int32_t*>(zidx);     // read only by the ALS kernel
+      c.zws = reinterpret_cast<double*>(ws + w.zws);
+      c.zws_stride = w.zstride;
+      st = T_dtype == GLINT_F64 ? launch_cluster_als_r<double>(c, c.ntensor, false, w.zslots, stream)
+                                : launch_cluster_als_r<float>(c, c.ntensor, false, w.zslots, stream);
+      if (st != GLINT_OK) return st;
+    }
+  return GLINT_OK;
 }
 
 glint_status glint_make_cumulative_batched(int64_t nbatch, int32_t n, int32_t R, const float* S, float* C,
@@ -1023,7 +1381,7 @@ glint_status glint_query_clustered(const glint_clustered* f, int64_t nq, const i
                 "tables must be 16-byte aligned");
   if ((st = cl_device()) != GLINT_OK) return st;
   ClQueryArgs a;
-  a.CX = f->CX; a.CY = f->CY; a.Z = f->Z;
+  a.CX = f->CX; a.CY = f->CY; a.Z = f->Z; a.zidx = f->zidx;
   a.t = s.t; a.cs = f->cs; a.nu = f->nu; a.nv = f->nv; a.nl = f->nl; a.N = f->nbins;
   a.ncv = s.ncv; a.nb = s.nb; a.L = s.L; a.nq = nq; a.q = q; a.out = out;
   const int64_t waves = (nq + 63) / 64;
@@ -1057,7 +1415,7 @@ glint_status glint_sample_clustered(const glint_clustered* f, int64_t n, const i
   if (n == 0) return GLINT_OK;
   GLINT_REQUIRE(f->CX && f->CY && f->Z && uvl && rnd && h && pdf && bins, "null pointer argument");
   ClSampleArgs a;
-  a.CX = f->CX; a.CY = f->CY; a.Z = f->Z;
+  a.CX = f->CX; a.CY = f->CY; a.Z = f->Z; a.zidx = f->zidx;
   a.t = sh.t; a.cs = f->cs; a.nu = f->nu; a.nv = f->nv; a.nl = f->nl; a.N = f->nbins;
   a.ncv = sh.ncv; a.nb = sh.nb; a.L = sh.L;
   int levels = 0;

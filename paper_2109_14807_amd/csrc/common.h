@@ -65,6 +65,15 @@ glint_status glint_check_desc(const glint_ndf_desc* d);
 // Half-width of the per-texel bin window (see glint_window_radius).
 int32_t glint_window_k(const glint_ndf_desc* d);
 
+// The NDF tensor restricted to one window of bins: T[u][v][l][a][b] =
+// the full tensor's entry at bins (s_off + a, t_off + b), a, b < nout, built
+// from the texel bin windows of glint_texel_bins by the same kernels as
+// glint_build_tensor (direct levels, then exact level doubling).  Library
+// internal (the clustered layout builds its angular blocks this way).
+glint_status glint_build_window(const glint_ndf_desc* desc, const int32_t* bins, const double* mass, void* T,
+                                glint_dtype T_dtype, int32_t direct_levels, int32_t s_off, int32_t t_off,
+                                int32_t nout, hipStream_t stream);
+
 // ---------------------------------------------------------------------------
 // device-side value codecs (written from the storage formats' definitions)
 // ---------------------------------------------------------------------------

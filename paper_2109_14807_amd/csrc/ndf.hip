@@ -56,11 +56,14 @@ __global__ __launch_bounds__(256) void k_texel_bins(const float* __restrict__ nx
 }
 
 // Direct build of one level for a strip of CB cells (u, v0 .. v0+CB-1).
+// The output block of a cell is NO x NO bins, bins [s_off, s_off + NO) x
+// [t_off, t_off + NO) of the NDF image (the whole image: offsets 0, NO = N).
 // Dynamic LDS: [texels][2] bins | [texels][2][P] masses (OT) | block strip (OT).
 template <typename OT>
 __global__ __launch_bounds__(kBuildThreads) void k_build_direct(
     const int32_t* __restrict__ bins, const double* __restrict__ mass, int nu, int nv,
-    int nlevels, int N, int K, int level, int CB, int SR, OT* __restrict__ T) {
+    int nlevels, int K, int level, int CB, int SR, int s_off, int t_off, int NO,
+    OT* __restrict__ T) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int k = 1 << level;
   const int h = k >> 1;
@@ -96,10 +99,10 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_direct(
   const int items = k * k * P * P;
   for (int c = 0; c < ncell; ++c) {
     const int v = v0 + c;
-    OT* dst = T + ((static_cast<int64_t>(u) * nv + v) * nlevels + level) * N * N;
-    for (int s0 = 0; s0 < N; s0 += SR) {
-      const int rows = min(SR, N - s0);
-      for (int e = tid; e < rows * N; e += blockDim.x) blk[e] = OT(0);
+    OT* dst = T + ((static_cast<int64_t>(u) * nv + v) * nlevels + level) * NO * NO;
+    for (int s0 = 0; s0 < NO; s0 += SR) {
+      const int rows = min(SR, NO - s0);
+      for (int e = tid; e < rows * NO; e += blockDim.x) blk[e] = OT(0);
       __syncthreads();
       for (int it = tid; it < items; it += blockDim.x) {
         const int texi = it / (P * P);
@@ -107,16 +110,16 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_direct(
         const int a = rem / P, b = rem - (rem / P) * P;
         const int fi = texi / k, fj = texi - (texi / k) * k;   // footprint row, column
         const int sidx = fi * W + (c + fj);
-        const int s = sbin[2 * sidx] - K + a;
-        const int t = sbin[2 * sidx + 1] - K + b;
-        if (s >= s0 && s < s0 + rows && t >= 0 && t < N) {
+        const int s = sbin[2 * sidx] - K + a - s_off;
+        const int t = sbin[2 * sidx + 1] - K + b - t_off;
+        if (s >= s0 && s < s0 + rows && t >= 0 && t < NO) {
           const OT val = smass[sidx * 2 * P + a] * smass[sidx * 2 * P + P + b];
-          if (val != OT(0)) atomicAdd(&blk[(s - s0) * N + t], val);
+          if (val != OT(0)) atomicAdd(&blk[(s - s0) * NO + t], val);
         }
       }
       __syncthreads();
-      OT* d = dst + static_cast<int64_t>(s0) * N;
-      for (int e = tid; e < rows * N; e += blockDim.x) d[e] = blk[e] * inv_area;
+      OT* d = dst + static_cast<int64_t>(s0) * NO;
+      for (int e = tid; e < rows * NO; e += blockDim.x) d[e] = blk[e] * inv_area;
       __syncthreads();
     }
   }
@@ -159,6 +162,42 @@ __global__ __launch_bounds__(256) void k_level_double(OT* __restrict__ T, int nu
     }
     reinterpret_cast<V*>(O)[e] = o;
   }
+}
+
+// The same for blocks of NN <= 1024 elements (the angular blocks of the
+// clustered layout): one thread per 16 bytes of output over all cells, so a
+// workgroup covers several cells instead of leaving most of its lanes idle.
+template <typename OT>
+__global__ __launch_bounds__(256) void k_level_double_flat(OT* __restrict__ T, int nu, int nv,
+                                                           int nlevels, int NN, int level) {
+  constexpr int VEC = 16 / sizeof(OT);
+  using V = typename std::conditional<sizeof(OT) == 4, float4, double2>::type;
+  const int nvec = NN / VEC;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t cell = idx / nvec;
+  if (cell >= static_cast<int64_t>(nu) * nv) return;
+  const int e = static_cast<int>(idx - cell * nvec);
+  const int u = static_cast<int>(cell / nv), v = static_cast<int>(cell - static_cast<int64_t>(u) * nv);
+  const int k = 1 << level;
+  const int up = (k + 1) >> 1, dn = k >> 1;
+  const int ua = (u - up + nu) % nu, ub = (u + dn) % nu;
+  const int va = (v - up + nv) % nv, vb = (v + dn) % nv;
+  auto blk = [&](int x, int y, int l) {
+    return reinterpret_cast<const V*>(T + ((static_cast<int64_t>(x) * nv + y) * nlevels + l) * NN);
+  };
+  const V a = blk(ua, va, level)[e];
+  const V b = blk(ua, vb, level)[e];
+  const V c = blk(ub, va, level)[e];
+  const V d = blk(ub, vb, level)[e];
+  V o;
+  const OT q = OT(0.25);
+  o.x = ((a.x + b.x) + (c.x + d.x)) * q;
+  o.y = ((a.y + b.y) + (c.y + d.y)) * q;
+  if constexpr (VEC == 4) {
+    o.z = ((a.z + b.z) + (c.z + d.z)) * q;
+    o.w = ((a.w + b.w) + (c.w + d.w)) * q;
+  }
+  reinterpret_cast<V*>(T + (cell * nlevels + level + 1) * NN)[e] = o;
 }
 
 __global__ __launch_bounds__(256) void k_range_bruteforce(
@@ -211,7 +250,7 @@ struct BuildPlan {
 };
 
 template <typename OT>
-bool plan_direct(int level, int N, int K, int nv, BuildPlan* p) {
+bool plan_direct(int level, int NO, int K, int nv, BuildPlan* p) {
   const int k = 1 << level;
   const int P = 2 * K + 1;
   int CB = 16;
@@ -223,36 +262,44 @@ bool plan_direct(int level, int N, int K, int nv, BuildPlan* p) {
   }
   if (CB < 1) return false;
   if (CB > nv) CB = nv;
-  int SR = static_cast<int>(kBlockBudget / (sizeof(OT) * N));
-  if (SR > N) SR = N;
+  int SR = static_cast<int>(kBlockBudget / (sizeof(OT) * NO));
+  if (SR > NO) SR = NO;
   if (SR < 1) return false;
   const size_t ntex = static_cast<size_t>(k) * (CB + k - 1);
   p->CB = CB;
   p->SR = SR;
   p->lds = glint_round_up(sizeof(int32_t) * 2 * ntex, 16) +
-           glint_round_up(sizeof(OT) * 2 * P * ntex, 16) + sizeof(OT) * SR * N;
+           glint_round_up(sizeof(OT) * 2 * P * ntex, 16) + sizeof(OT) * SR * NO;
   return true;
 }
 
 template <typename OT>
 glint_status build_levels(const glint_ndf_desc* d, const int32_t* bins, const double* mass,
-                          OT* T, int direct_levels, hipStream_t stream) {
+                          OT* T, int direct_levels, int s_off, int t_off, int NO, hipStream_t stream) {
   const int K = glint_window_k(d);
+  const int NN = NO * NO;
   for (int l = 0; l < d->nlevels; ++l) {
     BuildPlan p;
     const bool direct = (l < direct_levels) || l == 0;
-    if (direct && plan_direct<OT>(l, d->nbins, K, d->nv, &p)) {
+    if (direct && plan_direct<OT>(l, NO, K, d->nv, &p)) {
       dim3 grid((d->nv + p.CB - 1) / p.CB, d->nu);
       glint_clear_launch_error();
       hipLaunchKernelGGL(k_build_direct<OT>, grid, dim3(kBuildThreads), p.lds, stream, bins,
-                         mass, d->nu, d->nv, d->nlevels, d->nbins, K, l, p.CB, p.SR, T);
+                         mass, d->nu, d->nv, d->nlevels, K, l, p.CB, p.SR, s_off, t_off, NO, T);
       GLINT_LAUNCHED("k_build_direct");
+    } else if (l == 0) {
+      return glint_fail(GLINT_E_UNSUPPORTED, "bin window too wide for the direct build");
+    } else if (NN <= 1024) {
+      const int64_t threads = static_cast<int64_t>(d->nu) * d->nv * (NN / (16 / static_cast<int>(sizeof(OT))));
+      glint_clear_launch_error();
+      hipLaunchKernelGGL(k_level_double_flat<OT>, dim3(static_cast<unsigned>((threads + 255) / 256)), dim3(256), 0,
+                         stream, T, d->nu, d->nv, d->nlevels, NN, l - 1);
+      GLINT_LAUNCHED("k_level_double_flat");
     } else {
-      if (l == 0) return glint_fail(GLINT_E_UNSUPPORTED, "bin window too wide for the direct build");
       dim3 grid(d->nv, d->nu);
       glint_clear_launch_error();
       hipLaunchKernelGGL(k_level_double<OT>, grid, dim3(256), 0, stream, T, d->nu, d->nv,
-                         d->nlevels, d->nbins, l - 1);
+                         d->nlevels, NO, l - 1);
       GLINT_LAUNCHED("k_level_double");
     }
   }
@@ -295,6 +342,22 @@ glint_status scratch_address(void** out) {
 
 }  // namespace
 
+glint_status glint_build_window(const glint_ndf_desc* desc, const int32_t* bins, const double* mass, void* T,
+                                glint_dtype T_dtype, int32_t direct_levels, int32_t s_off, int32_t t_off,
+                                int32_t nout, hipStream_t stream) {
+  GLINT_REQUIRE(nout >= 1 && s_off >= 0 && t_off >= 0 && s_off + nout <= desc->nbins && t_off + nout <= desc->nbins,
+                "bin window [%d, %d) x [%d, %d) outside the %d bins", s_off, s_off + nout, t_off, t_off + nout,
+                desc->nbins);
+  GLINT_REQUIRE(nout * nout % 4 == 0, "bin window of %d x %d bins: the level doubling moves 16-byte words", nout,
+                nout);
+  if (direct_levels <= 0) direct_levels = 4;
+  if (T_dtype == GLINT_F64)
+    return build_levels<double>(desc, bins, mass, static_cast<double*>(T), direct_levels, s_off, t_off, nout,
+                                stream);
+  GLINT_SUPPORT(T_dtype == GLINT_F32, "T dtype must be F64 or F32");
+  return build_levels<float>(desc, bins, mass, static_cast<float*>(T), direct_levels, s_off, t_off, nout, stream);
+}
+
 extern "C" {
 
 glint_status glint_texel_bins(const glint_ndf_desc* desc, const float* nxy, int32_t* bins,
@@ -335,8 +398,9 @@ glint_status glint_build_tensor(const glint_ndf_desc* desc, const float* nxy, vo
   st = glint_texel_bins(desc, nxy, bins, mass, stream);
   if (st != GLINT_OK) return st;
   if (T_dtype == GLINT_F64)
-    return build_levels<double>(desc, bins, mass, static_cast<double*>(T), direct_levels, stream);
-  return build_levels<float>(desc, bins, mass, static_cast<float*>(T), direct_levels, stream);
+    return build_levels<double>(desc, bins, mass, static_cast<double*>(T), direct_levels, 0, 0, desc->nbins,
+                                stream);
+  return build_levels<float>(desc, bins, mass, static_cast<float*>(T), direct_levels, 0, 0, desc->nbins, stream);
 }
 
 glint_status glint_build_tensor_noalloc(const glint_ndf_desc* desc, const float* nxy, void* T,
