@@ -197,25 +197,18 @@ __global__ __launch_bounds__(kMassThreads) void k_cluster_mass(ClusterArgs c) {
 // Gm = G1 o G2 + mu I, mu = kRidgeRtol * trace(G1 o G2) / R, factored in
 // place as L L^T (lower, row-major), right-looking: at step j the pivot is
 // the updated diagonal entry, column j is scaled by its square root and the
-// trailing lower triangle takes the rank-1 update.  The factorisation runs
-// on wavefront 0 alone with wave-level LDS fences between the steps (a
-// block-wide barrier per step would stall all eight wavefronts); the other
-// wavefronts wait at one barrier.  A pivot <= kPivotRtol times the diagonal
-// entry of the unfactored matrix (kept in dg) is a breakdown: returns false
-// (the same for every thread).  flag: one LDS int.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
+// trailing lower triangle takes the rank-1 update, spread over the whole
+// workgroup with a barrier after each of the two phases of a step (on one
+// wavefront the update is R^2/64 dependent LDS round trips per step).  A
+// pivot <= kPivotRtol times the diagonal entry of the unfactored matrix
+// (kept in dg) is a breakdown: returns false (the same for every thread).
 template <int R>
-__device__ bool cholesky_hadamard(const double* G1, const double* G2, double* Gm, double* dg, double* dl,
-                                  int* flag) {
-  for (int i = threadIdx.x; i < R * R; i += blockDim.x) Gm[i] = G1[i] * G2[i];
+__device__ bool cholesky_hadamard(const double* G1, const double* G2, double* Gm, double* dg, double* dl) {
+  const int tid = threadIdx.x;
+  for (int i = tid; i < R * R; i += blockDim.x) Gm[i] = G1[i] * G2[i];
   __syncthreads();
-  if (threadIdx.x < 64) {
-    const int lane = threadIdx.x;
+  if (tid < 64) {
+    const int lane = tid;
     double tr = lane < R ? Gm[lane * R + lane] : 0.0;
     tr = glint_wave_sum(tr);
     const double mu = kRidgeRtol * tr / R;
@@ -224,67 +217,101 @@ __device__ bool cholesky_hadamard(const double* G1, const double* G2, double* Gm
       Gm[lane * R + lane] = d0;
       dg[lane] = d0;
     }
-    wave_lds_sync();
-    int ok = 1;
-    for (int j = 0; j < R; ++j) {
-      const double d = Gm[j * R + j];
-      if (!(d > kPivotRtol * dg[j])) {
-        ok = 0;
-        break;
-      }
-      const double ljj = sqrt(d);
-      if (lane == 0) dl[j] = ljj;
-      for (int i = j + 1 + lane; i < R; i += 64) Gm[i * R + j] /= ljj;
-      wave_lds_sync();
-      for (int idx = lane; idx < R * R; idx += 64) {
-        const int i = idx / R, k = idx % R;
-        if (k > j && k <= i) Gm[idx] -= Gm[i * R + j] * Gm[k * R + j];
-      }
-      wave_lds_sync();
-    }
-    if (ok && lane < R) Gm[lane * R + lane] = dl[lane];
-    if (lane == 0) *flag = ok;
   }
   __syncthreads();
-  return __builtin_amdgcn_readfirstlane(*flag) != 0;
+  int ok = 1;
+  for (int j = 0; j < R; ++j) {
+    const double d = Gm[j * R + j];
+    // every thread reads the same values: the decision is uniform
+    if (!__builtin_amdgcn_readfirstlane(static_cast<int>(d > kPivotRtol * dg[j]))) {
+      ok = 0;
+      break;
+    }
+    const double ljj = sqrt(d);
+    if (tid == 0) dl[j] = ljj;
+    for (int i = j + 1 + tid; i < R; i += blockDim.x) Gm[i * R + j] /= ljj;
+    __syncthreads();
+    for (int idx = tid; idx < R * R; idx += blockDim.x) {
+      const int i = idx / R, k = idx % R;
+      if (k > j && k <= i) Gm[idx] -= Gm[i * R + j] * Gm[k * R + j];
+    }
+    __syncthreads();
+  }
+  if (ok && tid < R) Gm[tid * R + tid] = dl[tid];
+  __syncthreads();
+  return ok != 0;
 }
 
-// A = M (L L^T)^-1 for `rows` rows of stride ld held in LDS, in place: one
-// row per thread, forward substitution L y = m then back substitution
-// L^T x = y in registers.  The empty asm statements are compiler-only
-// barriers that keep each step's reads of the factor at that step (hoisted,
-// the R x R factor would occupy R*R registers).
-// Rank 32: R lanes share a row, lane j holding component j, the solved
-// component of each step broadcast from its lane (one register per lane
-// instead of R).
+// A = M (L L^T)^-1 for `rows` rows of stride ld, in place.
+// Up to rank 16: one row per thread, forward substitution L y = m then back
+// substitution L^T x = y in registers.  The empty asm statements are
+// compiler-only barriers that keep each step's reads of the factor at that
+// step (hoisted, the R x R factor would occupy R*R registers).
+// Rank 32: the rows would hold 32 FP64 registers each, and a solve spread
+// over lanes runs 2R dependent steps per row; instead G^-1 = L^-T L^-1 is
+// formed once (L^-1 by elimination over the workgroup, then the products)
+// in `work` (2 R^2 doubles of LDS) and every row is multiplied by
+// it on the matrix cores, 16 rows per wavefront at a time.  Both give M G^-1
+// to within the conditioning of G (which the ridge bounds).
 template <int R>
-__device__ void solve_rows_lanes(double* Mrows, int rows, int ld, const double* Lc) {
-  static_assert(64 % R == 0, "rank must divide the wavefront");
-  constexpr int RPW = 64 / R;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int j = lane % R, base = lane - j;
-  for (int row0 = wave * RPW; row0 < rows; row0 += nw * RPW) {
-    const int row = row0 + lane / R;
-    const bool ok = row < rows;
-    double s = ok ? Mrows[row * ld + j] : 0.0;
-    for (int k = 0; k < R; ++k) {
-      const double yk = __shfl(s / Lc[k * R + k], base + k);
-      if (j > k) s -= Lc[j * R + k] * yk;
-      else if (j == k) s = yk;
+__device__ void solve_rows_inverse(double* Mrows, int rows, int ld, const double* Lc, double* work) {
+  static_assert(R % 16 == 0, "rank must be a multiple of 16");
+  constexpr int RB = R / 16;
+  double* Li = work;          // L^-1, row-major, lower triangle
+  double* Gi = work + R * R;  // G^-1
+  const int tid = threadIdx.x;
+  // L^-1 row by row, right-looking: row k is final once divided by L[k][k];
+  // it is then eliminated from the rows below (each entry takes the terms
+  // of its column's substitution in the same order)
+  for (int idx = tid; idx < R * R; idx += blockDim.x) Li[idx] = (idx / R == idx % R) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int k = 0; k < R; ++k) {
+    if (tid <= k) Li[k * R + tid] /= Lc[k * R + k];
+    __syncthreads();
+    const int w = k + 1, n = (R - 1 - k) * w;
+    for (int idx = tid; idx < n; idx += blockDim.x) {
+      const int i = k + 1 + idx / w, j = idx % w;
+      Li[i * R + j] -= Lc[i * R + k] * Li[k * R + j];
     }
-    for (int k = R - 1; k >= 0; --k) {
-      const double xk = __shfl(s / Lc[k * R + k], base + k);
-      if (j < k) s -= Lc[k * R + j] * xk;
-      else if (j == k) s = xk;
-    }
-    if (ok) Mrows[row * ld + j] = s;
+    __syncthreads();
+  }
+  for (int idx = tid; idx < R * R; idx += blockDim.x) {
+    const int a = idx / R, b = idx % R;
+    const int i0 = a > b ? a : b;
+    double s = 0.0;
+    for (int i = i0; i < R; ++i) s += Li[i * R + a] * Li[i * R + b];
+    Gi[idx] = s;
+  }
+  __syncthreads();
+  const int lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int r0 = wave * 16; r0 < rows; r0 += nw * 16) {
+    const int row = r0 + li;
+    double a[R / 4];
+#pragma unroll
+    for (int s = 0; s < R / 4; ++s) a[s] = row < rows ? Mrows[row * ld + 4 * s + lk] : 0.0;
+    f64x4 acc[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) acc[rb] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < R / 4; ++s)
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) acc[rb] = mfma64(a[s], Gi[(4 * s + lk) * R + rb * 16 + li], acc[rb]);
+    // every read of these 16 rows is in registers: overwrite them
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = r0 + lk + 4 * q;
+        if (i < rows) Mrows[i * ld + rb * 16 + li] = acc[rb][q];
+      }
   }
 }
 
 template <int R>
-__device__ void solve_rows(double* Mrows, int rows, int ld, const double* Lc) {
+__device__ void solve_rows(double* Mrows, int rows, int ld, const double* Lc, double* work) {
   if constexpr (R > 16) {
-    solve_rows_lanes<R>(Mrows, rows, ld, Lc);
+    solve_rows_inverse<R>(Mrows, rows, ld, Lc, work);
     return;
   }
   for (int row = threadIdx.x; row < rows; row += blockDim.x) {
@@ -396,7 +423,6 @@ __device__ __noinline__ void als_one(const ClusterArgs& c, int tensor) {
   int* keep = reinterpret_cast<int*>(cl_lds + o.keep);
   int* rowof = reinterpret_cast<int*>(cl_lds + o.rowof);
   __shared__ int wcnt[kClWaves];
-  __shared__ int s_flag;
 
   const int64_t tout = tensor * c.tmul + c.tadd;
   float* outX = c.X + tout * t * R;
@@ -569,8 +595,8 @@ __device__ __noinline__ void als_one(const ClusterArgs& c, int tensor) {
       Mt[idx] = s;
     }
     __syncthreads();
-    if (cholesky_hadamard<R>(GY, GZ, Gm, dg, dl, &s_flag)) {
-      solve_rows<R>(Mt, t, R, Gm);
+    if (cholesky_hadamard<R>(GY, GZ, Gm, dg, dl)) {
+      solve_rows<R>(Mt, t, R, Gm, part);
       __syncthreads();
       for (int i = threadIdx.x; i < t * R; i += blockDim.x) X[i] = Mt[i];
       __syncthreads();
@@ -587,8 +613,8 @@ __device__ __noinline__ void als_one(const ClusterArgs& c, int tensor) {
       Mt[idx] = s;
     }
     __syncthreads();
-    if (cholesky_hadamard<R>(GX, GZ, Gm, dg, dl, &s_flag)) {
-      solve_rows<R>(Mt, t, R, Gm);
+    if (cholesky_hadamard<R>(GX, GZ, Gm, dg, dl)) {
+      solve_rows<R>(Mt, t, R, Gm, part);
       __syncthreads();
       for (int i = threadIdx.x; i < t * R; i += blockDim.x) Y[i] = Mt[i];
       __syncthreads();
@@ -598,7 +624,7 @@ __device__ __noinline__ void als_one(const ClusterArgs& c, int tensor) {
       ++fails;
     }
     // ---- mode Z (factored first: Z is overwritten in place only when it succeeds) ----
-    if (cholesky_hadamard<R>(GX, GY, Gm, dg, dl, &s_flag)) {
+    if (cholesky_hadamard<R>(GX, GY, Gm, dg, dl)) {
       for (int idx = threadIdx.x; idx < tt * R; idx += blockDim.x) {
         const int ab = idx / R, r = idx % R;
         P[idx] = X[(ab / t) * R + r] * Y[(ab % t) * R + r];      // Khatri-Rao of X and Y
@@ -659,7 +685,7 @@ __device__ __noinline__ void als_one(const ClusterArgs& c, int tensor) {
         chunk_step(ch, ra);
         if (ch + 1 < nchunk_b) chunk_step(ch + 1, rb2);
       }
-      solve_rows<R>(Z, Lc, ZS, Gm);
+      solve_rows<R>(Z, Lc, ZS, Gm, part);
       __syncthreads();
       gram_mfma<R>(Z, Lc, ZS, GZ, part);
       normalize_by_gram<R>(Z, Lc, ZS, GZ, lam);
