@@ -67,7 +67,7 @@ MEASURED_TRAFFIC = {
     "k_query_r16": ("paper_2109_14807_amd/csrc/query.hip", "cc2059d4f3c53ea9a0cb18747ead0a68d15bbe21", 531095594),
 }
 
-LEGS = ("c3", "c5", "r16", "c2", "refine", "sweep", "cpu_baseline")
+LEGS = ("c3", "c5", "r16", "c2", "clustered", "refine", "sweep", "cpu_baseline")
 
 
 def source_sha(path):
@@ -98,6 +98,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="same as leaving cpu_baseline out of --legs")
     ap.add_argument("--reps", type=int, default=10, help="event-timed launches per kernel figure")
     ap.add_argument("--refine-steps", type=int, default=200)
+    ap.add_argument("--cluster-sweeps", type=int, default=20, help="ALS sweeps per region tensor (clustered leg)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 2 GiB device copy (read 2 GiB, write 2 GiB), the reference "
                          "for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE")
@@ -441,6 +442,89 @@ def leg_r16(args, dev, keep):
     return rep
 
 
+def leg_clustered(args, dev, keep):
+    """The paper's own layout at its own scale (Sec. 4.2 practical choices):
+    the 2048^2 flake map of the headline in 16 x 16 angular blocks and 8 x 8
+    texel regions, rank 32 per region tensor, built block by block from the
+    map (no stored T), compact Z; its range query on the headline batch."""
+    import numpy as np
+    import torch
+    import gen
+    import paper_2109_14807_amd as G
+    from paper_2109_14807_amd import _lib as L
+
+    cfg = gen.config("c4")
+    nxy_h = gen.normal_map(cfg)
+    desc = G.desc_of(cfg.nu, cfg.nv, cfg.nlevels, cfg.nbins, cfg.sigma)
+    nxy = torch.tensor(nxy_h, device=dev)
+    t, cs, R = 16, 8, 32
+    ncu, ncv, nb = cfg.nu // cs, cfg.nv // cs, cfg.nbins // t
+    ntensor, Lr = ncu * ncv * nb * nb, cs * cs * cfg.nlevels
+    cd = L.ClusterDesc(t, cs, R)
+    ws = torch.empty(L.glint_cluster_map_workspace(desc, cd, torch.float32), dtype=torch.uint8, device=dev)
+    zidx = torch.empty((ntensor, Lr), dtype=torch.int32, device=dev)
+    zbase = torch.empty(ntensor + 1, dtype=torch.int64, device=dev)
+    info = torch.empty(4, dtype=torch.int32, device=dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    L.glint_cluster_map_index(desc, cd, nxy, torch.float32, zidx, zbase, info, ws)
+    ev[1].record()
+    rows = int(zbase[-1].item())
+    f32 = dict(dtype=torch.float32, device=dev)
+    X, Y = torch.empty((ntensor, t, R), **f32), torch.empty((ntensor, t, R), **f32)
+    Z = torch.empty((max(rows, 1), R), **f32)
+    blank = torch.empty(ntensor, dtype=torch.uint8, device=dev)
+    ev[2].record()
+    L.glint_cp_als_clustered_map(desc, cd, nxy, torch.float32, args.cluster_sweeps, 5, zidx, X, Y, Z, blank, info, ws)
+    ev[3].record()
+    torch.cuda.synchronize()
+    index_ms, als_ms = ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3])
+    inf = info.cpu().tolist()
+    del ws
+    tab = G.ClusteredTables(desc, t, cs, X, Y, Z, blank, info, zidx=zidx, zbase=zbase)
+    G.clustered_cumulative(tab)
+    log(f"clustered: index {index_ms:.0f} ms, ALS {als_ms:.0f} ms, {rows} of {ntensor * Lr} image blocks stacked")
+    q_h = gen.make_queries(cfg, nxy_h)
+    q = torch.tensor(q_h, device=dev)
+    nq = q.shape[0]
+    out = torch.empty(nq, dtype=torch.float32, device=dev)
+    ms = timed(lambda: L.glint_query_clustered(tab.struct(), q, out), args.reps)
+    idx = torch.tensor(sample_idx(nq, 1 << 18, 12), device=dev)
+    ebf, _ = error_vs_bruteforce(desc, nxy, q[idx], out[idx], levels=cfg.nlevels)
+    nonblank_tensors = ntensor - inf[1]
+    full = cfg.nu * cfg.nv * cfg.nlevels * cfg.nbins ** 2
+    stored = nonblank_tensors * 2 * t * R + rows * R
+    # parity sample: every record's region (its nb^2 tensors, FP32 factors
+    # and the Z rows of its footprint) goes to the oracle as a one-region,
+    # one-footprint layout
+    pidx = sample_idx(nq, 2000, 8)
+    recs = q_h[pidx].astype(np.int64)
+    u = np.mod(recs[:, 0], cfg.nu)
+    v = np.mod(recs[:, 1], cfg.nv)
+    l = np.clip(recs[:, 2], 0, cfg.nlevels - 1)
+    t0 = ((u // cs) * ncv + v // cs) * nb * nb
+    tens = torch.tensor(t0[:, None] + np.arange(nb * nb)[None, :], device=dev)
+    f = torch.tensor(((u % cs) * cs + v % cs) * cfg.nlevels + l, device=dev)
+    rowsel = zidx[tens, f[:, None]]
+    Zs = torch.where(rowsel[..., None] >= 0, Z[rowsel.clamp(min=0).long()], torch.zeros((), **f32))
+    keep["parity"].append({"leg": "clustered (2048^2, t 16, 8x8 regions, rank 32, compact Z)", "kind": "clustered",
+                           "X": X[tens].cpu().numpy(), "Y": Y[tens].cpu().numpy(), "Z": Zs.cpu().numpy(),
+                           "records": recs, "got": out[torch.tensor(pidx, device=dev)].cpu().numpy(),
+                           "nb": nb, "t": t})
+    rep = {"workload": "2048x2048 flake map (80000 sites, alpha 0.2) of the headline, clustered layout: 16x16 "
+                       "angular blocks, 8x8 texel regions, 10 levels, rank 32 per region tensor, "
+                       f"{args.cluster_sweeps} FP64 ALS sweeps, FP32 block tensors built from the map one angular "
+                       "block at a time (no stored T), compact Z; queries: the headline's 2^24 records",
+           "index_ms": index_ms, "als_ms": als_ms, "als_ms_per_sweep": als_ms / args.cluster_sweeps,
+           "region_tensors": ntensor, "blank_tensors": inf[1], "solve_failures": inf[0],
+           "stacked_image_blocks": rows, "image_blocks": ntensor * Lr,
+           "compression": {"stored_floats": stored, "tensor_floats": full, "ratio": stored / full,
+                           "what": "X, Y of the non-blank tensors and the stacked Z rows, over the entries of T"},
+           **flat_rate(nq, ms), "error_vs_bruteforce": ebf["all"], "error_vs_bruteforce_per_level": ebf["per_level"]}
+    log(f"clustered: query {rep['queries_per_s'] / 1e9:.2f} G q/s, E_bf {ebf['all']:.4f}")
+    return rep
+
+
 def leg_refine(args, dev, keep):
     """Adam refinement of the headline factors against brute-force range
     integrals of the headline batch; held-out error on a separate batch of the
@@ -762,6 +846,44 @@ def clustered_report(desc, T, q, nxy, reps, t=16, cs=8, R=16, sweeps=20):
 # the only part of the benchmark that runs the oracle
 # ---------------------------------------------------------------------------
 
+def clustered_parity(p):
+    """Each sampled record against the oracle's block-split query
+    (oracle.cluster.clustered_range_query) over its region's downloaded FP32
+    factors, laid out as one region of one texel and one level.  The oracle
+    forms the blocks' cumulative sums of X and Y in FP64, the GPU reads them
+    rounded to FP32, each off by up to 2^-24 of the block's absolute sum: the
+    error scale M_q is the same query over |X|, |Y|, |Z| with the box widened
+    to the whole blocks it touches."""
+    import numpy as np
+    from oracle import cluster
+    got = p["got"].astype(np.float64)
+    want = np.empty(got.size)
+    mag = np.empty(got.size)
+    nb, t = p["nb"], p["t"]
+    N = nb * t
+    for i, r in enumerate(p["records"]):
+        X = p["X"][i].astype(np.float64).reshape(1, 1, nb, nb, t, -1)
+        Y = p["Y"][i].astype(np.float64).reshape(1, 1, nb, nb, t, -1)
+        Z = p["Z"][i].astype(np.float64).reshape(1, 1, nb, nb, 1, -1)
+        q1 = np.array([[0, 0, 0, r[3], r[4], r[5], r[6]]], dtype=np.int64)
+        want[i] = cluster.clustered_range_query(X, Y, Z, q1, 1, 1)[0]
+        slo, shi, tlo, thi = (min(max(int(x), 0), N) for x in r[3:7])
+        if slo < shi and tlo < thi:
+            w = np.array([[0, 0, 0, slo // t * t, ((shi - 1) // t + 1) * t, tlo // t * t, ((thi - 1) // t + 1) * t]])
+            mag[i] = cluster.clustered_range_query(np.abs(X), np.abs(Y), np.abs(Z), w, 1, 1)[0]
+        else:
+            mag[i] = 0.0
+    err = np.abs(got - want)
+    normal = mag >= 1e-30
+    ent = {"leg": p["leg"], "n": int(got.size),
+           "max_err_over_Mq": float(np.max(err[normal] / mag[normal])) if normal.any() else 0.0,
+           "records_with_Mq_below_1e-30": int((~normal).sum()),
+           "max_abs_err_there": float(np.max(err[~normal])) if (~normal).any() else 0.0,
+           "tolerance": "|q_gpu - q_64| <= 1e-5 M_q + 1e-30 (M_q over whole blocks)"}
+    ent["pass"] = bool(np.all(err <= 1e-5 * mag + 1e-30))
+    return ent
+
+
 def leg_cpu_baseline(args, keep):
     """The oracle as it stands, timed on the host: its range query on a
     sample of the headline batch on one core (the baseline), and its
@@ -819,6 +941,10 @@ def leg_cpu_baseline(args, keep):
     # parity samples
     par = []
     for p in keep["parity"]:
+        if p.get("kind") == "clustered":
+            par.append(clustered_parity(p))
+            log(f"parity {p['leg']}: max |err|/M_q {par[-1]['max_err_over_Mq']:.2e}")
+            continue
         v, s = p["tables"]
         want = query.range_query(*v, p["records"], scale=s)
         mag = query.range_query_term_magnitude(*v, p["records"], scale=s)
@@ -876,7 +1002,8 @@ def main():
         "dtype": "f32", "data": "synthetic", "config": head["workload"],
         "roofline": head["roofline"], "error_vs_bruteforce": head["error_vs_bruteforce"],
     }
-    fns = {"c3": leg_c3, "c5": leg_c5, "r16": leg_r16, "c2": leg_c2, "refine": leg_refine, "sweep": leg_sweep}
+    fns = {"c3": leg_c3, "c5": leg_c5, "r16": leg_r16, "c2": leg_c2, "clustered": leg_clustered,
+           "refine": leg_refine, "sweep": leg_sweep}
     res["legs"] = {}
     for name in legs:
         if name == "cpu_baseline":
