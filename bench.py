@@ -676,13 +676,19 @@ def leg_c2(args, dev, keep):
     init = [torch.tensor(a, device=dev) for a in gen.als_init(cfg)]
     rep = {"workload": "512x512 flake map (5000 sites, alpha 0.15), sigma 0.005, 64x64 bins, 8 levels, rank 64, "
                        "1920x1080x8 frame queries"}
-    # build: T FP32 (34.4 GB), HBM write-bound
+    # build: T FP32 (34.4 GB); the default plan builds levels 0-2 directly
+    # (writes only) and doubles the rest (each doubled level reads the level
+    # below once at least): algorithmic bytes = T + the doubled levels' sources
     T = torch.empty((cfg.nu, cfg.nv, nl, N, N), dtype=torch.float32, device=dev)
     ws_b = torch.empty(L.glint_build_tensor_workspace(desc), dtype=torch.uint8, device=dev)
     b_ms = timed(lambda: L.glint_build_tensor(desc, nxy, T, 0, ws_b), 3)
     tb = T.numel() * 4
-    rep["build"] = {"ms": b_ms, "tensor_bytes": tb, "hbm_gbs": tb / (b_ms * 1e-3) / 1e9,
-                    "hbm_frac": tb / (b_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    direct = min(3, nl)
+    alg = tb + tb // nl * (nl - direct)
+    rep["build"] = {"ms": b_ms, "tensor_bytes": tb, "written_gbs": tb / (b_ms * 1e-3) / 1e9,
+                    "written_frac": tb / (b_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "direct_levels": direct, "algorithmic_bytes": alg,
+                    "hbm_gbs": alg / (b_ms * 1e-3) / 1e9, "hbm_frac": alg / (b_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     del ws_b
     # dense ALS on the matrix cores
     ws = torch.empty(L.glint_cp_als_workspace(desc, R, L.GLINT_F32), dtype=torch.uint8, device=dev)

@@ -127,7 +127,9 @@ size_t glint_build_tensor_workspace(const glint_ndf_desc* desc);
  * l < direct_levels are built directly from their footprint texels (the
  * texels' bin windows staged in LDS); each higher level is the exact mean of
  * four shifted blocks of the level below (a 2k box is two k boxes per axis).
- * direct_levels <= 0 selects the default (4); values above nlevels mean
+ * direct_levels <= 0 selects the default (3: above it the direct build's
+ * LDS accumulation of k^2 overlapping texel windows costs more than a
+ * doubling pass, measured on the 512^2 map); values above nlevels mean
  * "every level directly".  T must be 16-byte aligned. */
 glint_status glint_build_tensor(const glint_ndf_desc* desc, const float* nxy,
                                 void* T, glint_dtype T_dtype, int32_t direct_levels,
