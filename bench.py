@@ -65,6 +65,7 @@ MEASURED_TRAFFIC = {
     "k_mttkrp_z": ("paper_2109_14807_amd/csrc/cp_als.hip", "be75fb7ede7f7473b663578bb650f0887c45fe70", 34934655679),
     "k_query_c4": ("paper_2109_14807_amd/csrc/query.hip", "cc2059d4f3c53ea9a0cb18747ead0a68d15bbe21", 601553894),
     "k_query_r16": ("paper_2109_14807_amd/csrc/query.hip", "cc2059d4f3c53ea9a0cb18747ead0a68d15bbe21", 531095594),
+    "k_query_clustered": ("paper_2109_14807_amd/csrc/cluster.hip", "923c835b12482c077b9e2cb4af21fcfc8122dfb1", 9297634240),
 }
 
 LEGS = ("c3", "c5", "r16", "c2", "clustered", "refine", "sweep", "cpu_baseline")
@@ -521,6 +522,12 @@ def leg_clustered(args, dev, keep):
            "compression": {"stored_floats": stored, "tensor_floats": full, "ratio": stored / full,
                            "what": "X, Y of the non-blank tensors and the stacked Z rows, over the entries of T"},
            **flat_rate(nq, ms), "error_vs_bruteforce": ebf["all"], "error_vs_bruteforce_per_level": ebf["per_level"]}
+    # the tables (31 GB) stay in HBM: the gathers are HBM traffic too
+    tr = measured_traffic("k_query_clustered")
+    rep["traffic"] = tr
+    if tr:
+        rep["traffic_gbs"] = tr / (ms * 1e-3) / 1e9
+        rep["traffic_frac"] = rep["traffic_gbs"] / HBM_PEAK_GBS
     log(f"clustered: query {rep['queries_per_s'] / 1e9:.2f} G q/s, E_bf {ebf['all']:.4f}")
     return rep
 
