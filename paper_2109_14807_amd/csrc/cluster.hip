@@ -194,6 +194,71 @@ __global__ __launch_bounds__(kMassThreads) void k_cluster_mass(ClusterArgs c) {
   }
 }
 
+// lane k's value of x in every lane (k uniform)
+__device__ __forceinline__ double lane_bcast(double x, int k) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b & 0xffffffffll), k);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), k);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// Rank 32: Gm = (G1 o G2 + mu I)^-1 directly, by Gauss-Jordan elimination
+// without pivoting (the matrix is symmetric positive definite) on wavefront
+// 0 alone, lane j holding column j in registers: at step k the pivot column
+// reaches every lane by readlane, so no step waits on LDS or a barrier
+// (Cholesky, the inverse of its factor and their product took three passes
+// of 2R workgroup barriers each; passing the column through LDS instead
+// measured 8x slower).  The pivot of step k is the diagonal entry
+// of the Schur complement, the quantity the Cholesky rule tests: a pivot <=
+// kPivotRtol times the diagonal entry of the unfactored matrix is a
+// breakdown (returns false, the same for every thread).
+template <int R>
+__device__ bool hadamard_inverse(const double* G1, const double* G2, double* Gm, int* flag) {
+  static_assert(R <= 64, "one column per lane");
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const int j = lane < R ? lane : R - 1;     // lanes past R mirror the last column, never stored
+    double a[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) a[i] = G1[i * R + j] * G2[i * R + j];
+    double d = 0.0;     // this column's diagonal entry
+#pragma unroll
+    for (int i = 0; i < R; ++i) d = (i == j) ? a[i] : d;
+    const double tr = glint_wave_sum(lane < R ? d : 0.0);
+    const double mu = kRidgeRtol * tr / R;
+    d += mu;
+#pragma unroll
+    for (int i = 0; i < R; ++i) a[i] = (i == j) ? d : a[i];
+    int ok = 1;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const double p = lane_bcast(a[k], k);      // pivot A[k][k]
+      const double dk = lane_bcast(d, k);        // its entry before elimination
+      if (!(p > kPivotRtol * dk)) {
+        ok = 0;
+        break;
+      }
+      const double inv = 1.0 / p;
+      const bool is_k = j == k;
+      const double tk = a[k] * inv;             // new row k entry of this column
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        if (i == k) continue;
+        const double c = lane_bcast(a[i], k);    // A[i][k] before this step
+        a[i] = is_k ? -c * inv : fma(-c, tk, a[i]);
+      }
+      a[k] = is_k ? inv : tk;
+    }
+    if (ok && lane < R) {
+#pragma unroll
+      for (int i = 0; i < R; ++i) Gm[i * R + lane] = a[i];
+    }
+    if (lane == 0) *flag = ok;
+  }
+  __syncthreads();
+  return __builtin_amdgcn_readfirstlane(*flag) != 0;
+}
+
 // Gm = G1 o G2 + mu I, mu = kRidgeRtol * trace(G1 o G2) / R, factored in
 // place as L L^T (lower, row-major), right-looking: at step j the pivot is
 // the updated diagonal entry, column j is scaled by its square root and the
@@ -202,8 +267,14 @@ __global__ __launch_bounds__(kMassThreads) void k_cluster_mass(ClusterArgs c) {
 // wavefront the update is R^2/64 dependent LDS round trips per step).  A
 // pivot <= kPivotRtol times the diagonal entry of the unfactored matrix
 // (kept in dg) is a breakdown: returns false (the same for every thread).
+// Rank 32 takes hadamard_inverse and leaves G^-1 in Gm instead.
 template <int R>
 __device__ bool cholesky_hadamard(const double* G1, const double* G2, double* Gm, double* dg, double* dl) {
+  if constexpr (R > 16) {
+    // rank 32 keeps G^-1 itself in Gm (solve_rows applies it)
+    __shared__ int s_ok;
+    return hadamard_inverse<R>(G1, G2, Gm, &s_ok);
+  }
   const int tid = threadIdx.x;
   for (int i = tid; i < R * R; i += blockDim.x) Gm[i] = G1[i] * G2[i];
   __syncthreads();
@@ -242,47 +313,22 @@ __device__ bool cholesky_hadamard(const double* G1, const double* G2, double* Gm
   return ok != 0;
 }
 
-// A = M (L L^T)^-1 for `rows` rows of stride ld, in place.
-// Up to rank 16: one row per thread, forward substitution L y = m then back
-// substitution L^T x = y in registers.  The empty asm statements are
-// compiler-only barriers that keep each step's reads of the factor at that
-// step (hoisted, the R x R factor would occupy R*R registers).
-// Rank 32: the rows would hold 32 FP64 registers each, and a solve spread
-// over lanes runs 2R dependent steps per row; instead G^-1 = L^-T L^-1 is
-// formed once (L^-1 by elimination over the workgroup, then the products)
-// in `work` (2 R^2 doubles of LDS) and every row is multiplied by
-// it on the matrix cores, 16 rows per wavefront at a time.  Both give M G^-1
-// to within the conditioning of G (which the ridge bounds).
+// A = M G^-1 for `rows` rows of stride ld, in place.
+// Up to rank 16 (Lc = the Cholesky factor L of G): one row per thread,
+// forward substitution L y = m then back substitution L^T x = y in
+// registers.  The empty asm statements are compiler-only barriers that keep
+// each step's reads of the factor at that step (hoisted, the R x R factor
+// would occupy R*R registers).
+// Rank 32 (Lc = G^-1 itself, from hadamard_inverse): the rows would hold 32
+// FP64 registers each, and a substitution spread over lanes runs 2R
+// dependent steps per row; instead every row is multiplied by G^-1 on the
+// matrix cores, 16 rows per wavefront at a time.  Both give M G^-1 to
+// within the conditioning of G (which the ridge bounds).
 template <int R>
-__device__ void solve_rows_inverse(double* Mrows, int rows, int ld, const double* Lc, double* work) {
+__device__ void apply_inverse(double* Mrows, int rows, int ld, const double* Gi) {
   static_assert(R % 16 == 0, "rank must be a multiple of 16");
   constexpr int RB = R / 16;
-  double* Li = work;          // L^-1, row-major, lower triangle
-  double* Gi = work + R * R;  // G^-1
   const int tid = threadIdx.x;
-  // L^-1 row by row, right-looking: row k is final once divided by L[k][k];
-  // it is then eliminated from the rows below (each entry takes the terms
-  // of its column's substitution in the same order)
-  for (int idx = tid; idx < R * R; idx += blockDim.x) Li[idx] = (idx / R == idx % R) ? 1.0 : 0.0;
-  __syncthreads();
-  for (int k = 0; k < R; ++k) {
-    if (tid <= k) Li[k * R + tid] /= Lc[k * R + k];
-    __syncthreads();
-    const int w = k + 1, n = (R - 1 - k) * w;
-    for (int idx = tid; idx < n; idx += blockDim.x) {
-      const int i = k + 1 + idx / w, j = idx % w;
-      Li[i * R + j] -= Lc[i * R + k] * Li[k * R + j];
-    }
-    __syncthreads();
-  }
-  for (int idx = tid; idx < R * R; idx += blockDim.x) {
-    const int a = idx / R, b = idx % R;
-    const int i0 = a > b ? a : b;
-    double s = 0.0;
-    for (int i = i0; i < R; ++i) s += Li[i * R + a] * Li[i * R + b];
-    Gi[idx] = s;
-  }
-  __syncthreads();
   const int lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   for (int r0 = wave * 16; r0 < rows; r0 += nw * 16) {
@@ -309,9 +355,9 @@ __device__ void solve_rows_inverse(double* Mrows, int rows, int ld, const double
 }
 
 template <int R>
-__device__ void solve_rows(double* Mrows, int rows, int ld, const double* Lc, double* work) {
+__device__ void solve_rows(double* Mrows, int rows, int ld, const double* Lc) {
   if constexpr (R > 16) {
-    solve_rows_inverse<R>(Mrows, rows, ld, Lc, work);
+    apply_inverse<R>(Mrows, rows, ld, Lc);
     return;
   }
   for (int row = threadIdx.x; row < rows; row += blockDim.x) {
@@ -596,7 +642,7 @@ __device__ __noinline__ void als_one(const ClusterArgs& c, int tensor) {
     }
     __syncthreads();
     if (cholesky_hadamard<R>(GY, GZ, Gm, dg, dl)) {
-      solve_rows<R>(Mt, t, R, Gm, part);
+      solve_rows<R>(Mt, t, R, Gm);
       __syncthreads();
       for (int i = threadIdx.x; i < t * R; i += blockDim.x) X[i] = Mt[i];
       __syncthreads();
@@ -614,7 +660,7 @@ __device__ __noinline__ void als_one(const ClusterArgs& c, int tensor) {
     }
     __syncthreads();
     if (cholesky_hadamard<R>(GX, GZ, Gm, dg, dl)) {
-      solve_rows<R>(Mt, t, R, Gm, part);
+      solve_rows<R>(Mt, t, R, Gm);
       __syncthreads();
       for (int i = threadIdx.x; i < t * R; i += blockDim.x) Y[i] = Mt[i];
       __syncthreads();
@@ -685,7 +731,7 @@ __device__ __noinline__ void als_one(const ClusterArgs& c, int tensor) {
         chunk_step(ch, ra);
         if (ch + 1 < nchunk_b) chunk_step(ch + 1, rb2);
       }
-      solve_rows<R>(Z, Lc, ZS, Gm, part);
+      solve_rows<R>(Z, Lc, ZS, Gm);
       __syncthreads();
       gram_mfma<R>(Z, Lc, ZS, GZ, part);
       normalize_by_gram<R>(Z, Lc, ZS, GZ, lam);
