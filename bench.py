@@ -63,9 +63,10 @@ Q_BYTES = 32                   # algorithmic HBM bytes per flat query: 28-byte r
 MEASURED_TRAFFIC = {
     "k_mttkrp_y": ("paper_2109_14807_amd/csrc/cp_als.hip", "be75fb7ede7f7473b663578bb650f0887c45fe70", 36585863551),
     "k_mttkrp_z": ("paper_2109_14807_amd/csrc/cp_als.hip", "be75fb7ede7f7473b663578bb650f0887c45fe70", 34934655679),
-    "k_query_c4": ("paper_2109_14807_amd/csrc/query.hip", "cc2059d4f3c53ea9a0cb18747ead0a68d15bbe21", 601553894),
-    "k_query_r16": ("paper_2109_14807_amd/csrc/query.hip", "cc2059d4f3c53ea9a0cb18747ead0a68d15bbe21", 531095594),
-    "k_query_clustered": ("paper_2109_14807_amd/csrc/cluster.hip", "923c835b12482c077b9e2cb4af21fcfc8122dfb1", 9297634240),
+    "k_query_c4": ("paper_2109_14807_amd/csrc/query.hip", "76dbf1750c2c2696a73239a9effc44027635b717", 601548672),
+    "k_query_r16": ("paper_2109_14807_amd/csrc/query.hip", "76dbf1750c2c2696a73239a9effc44027635b717", 531102848),
+    "k_query_clustered": ("paper_2109_14807_amd/csrc/cluster.hip", "fc2449c87f6a75f2ef4cb443fe819c7d93fa9885", 9295752320),
+    "k_query_c3": ("paper_2109_14807_amd/csrc/query.hip", "76dbf1750c2c2696a73239a9effc44027635b717", 2076726400),
 }
 
 LEGS = ("c3", "c5", "r16", "c2", "clustered", "refine", "sweep", "cpu_baseline")
@@ -363,6 +364,7 @@ def leg_c3(args, dev, keep):
     rep = {"workload": "2048x2048 flake map (80000 sites, alpha 0.2), rank 128, BF16 factor and summed-area "
                        "tables, 6.4e7 queries (8 boxes per random footprint)",
            "queries": nq, "tables": tables_report(tabs), "als": als, **flat_rate(nq, ms),
+           "traffic": measured_traffic("k_query_c3"),
            "error_vs_bruteforce": ebf["all"], "error_vs_bruteforce_f32_tables": ebf32}
     log(f"c3: {rep['queries_per_s'] / 1e9:.2f} G q/s, E_bf {ebf['all']:.4f}")
     return rep
