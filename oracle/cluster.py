@@ -52,7 +52,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg
 
-from .ndf import canonical_query
+from .ndf import canonical_query, footprint_offsets, texel_masses
 
 BLANK_TOL = 1e-12
 PIVOT_RTOL = 1e-13
@@ -97,6 +97,34 @@ def cluster_tensor(T: np.ndarray, cu: int, cv: int, zs: int, zt: int, t: int, cs
     sub = T[cu * cs:(cu + 1) * cs, cv * cs:(cv + 1) * cs, :, zs * t:(zs + 1) * t, zt * t:(zt + 1) * t]
     # sub[du][dv][l][a][b] -> D[a][b][(du*cs + dv)*nl + l]
     return np.ascontiguousarray(sub.reshape(-1, t, t).transpose(1, 2, 0))
+
+
+def region_block_tensor(nxy: np.ndarray, nbins: int, sigma: float, nlevels: int, t: int, cs: int,
+                        cu: int, cv: int, zs: int, zt: int) -> np.ndarray:
+    """D[a][b][f] of region (cu, cv) and angular block (zs, zt) straight from
+    the normal map, for maps whose tensor is too large to form: footprint f =
+    (du cs + dv) nl + l, centred at (cu cs + du, cv cs + dv), is the mean over
+    its k x k texels (toroidal, the offsets of ndf_bruteforce) of
+    m_s[zs t + a] m_t[zt t + b] (Sec. 3.1 Eq. geom restricted to the block's
+    bins): the same entries cluster_tensor takes from the full tensor.  The
+    sum over a footprint's texels is one product of its texels' s-masses and
+    t-masses."""
+    ms, mt = texel_masses(nxy, nbins, sigma)
+    nu, nv = ms.shape[:2]
+    ms = ms[:, :, zs * t:(zs + 1) * t]
+    mt = mt[:, :, zt * t:(zt + 1) * t]
+    D = np.zeros((t, t, cs * cs * nlevels))
+    for du in range(cs):
+        for dv in range(cs):
+            u, v = cu * cs + du, cv * cs + dv
+            for l in range(nlevels):
+                k = 1 << l
+                xs = (u + footprint_offsets(k)) % nu
+                ys = (v + footprint_offsets(k)) % nv
+                a = ms[xs][:, ys].reshape(-1, t)
+                b = mt[xs][:, ys].reshape(-1, t)
+                D[:, :, (du * cs + dv) * nlevels + l] = (a.T @ b) / float(k * k)
+    return D
 
 
 def init_factors(seed: int, tensor: int, t: int, L: int, R: int, zrows=None):

@@ -159,3 +159,42 @@ def test_map_path_argument_errors():
         G.cp_als_clustered_map(x, d, 16, 8, 12, iters=1)       # rank not supported
     with pytest.raises(G.GlintError):
         G.cp_als_clustered_map(x, d, 16, 8, 8, iters=1, dtype=torch.bfloat16)  # block tensors F32 or F64
+
+
+def test_map_path_rank32_nine_levels_sampled_tensors():
+    """At the paper's region size and rank on a map whose tensor is not
+    formed: 256 x 256 flakes, N = 64 (16 angular blocks), 9 levels (footprints
+    up to 256 texels: 576 footprints a region, so the Z factors live in the
+    workspace), rank 32, FP64 block tensors, 3 sweeps.  Six region tensors
+    (the three with the most non-blank image blocks, three others) against
+    the oracle built from the map for that tensor alone: the non-blank
+    footprints exactly, and the reconstruction within 1e-4 of the block's
+    norm plus the FP32 storage bound (the rank-32 rule above)."""
+    nu, nl, N, t, cs, R, seed = 256, 9, 64, 16, 8, 32, 17
+    nxy = gen.flake_map(nu, nu, 1500, 0.2, 33)
+    d = G.desc_of(nu, nu, nl, N, 0.005)
+    print("cluster map 256^2 rank 32", flush=True)
+    tab = G.cp_als_clustered_map(torch.from_numpy(nxy), d, t, cs, R, iters=3, seed=seed, dtype=torch.float64)
+    ncu, ncv, nb, Lr, t = cluster.layout(nu, nu, nl, N, t, cs)
+    zidx = tab.zidx.cpu().numpy()
+    counts = (zidx >= 0).sum(axis=1)
+    order = np.argsort(-counts, kind="stable")
+    rng = np.random.default_rng(3)
+    nonblank = np.flatnonzero(counts > 0)
+    picks = list(order[:3]) + list(rng.choice(nonblank, 3, replace=False))
+    X = tab.X.cpu().numpy().astype(np.float64)
+    Y = tab.Y.cpu().numpy().astype(np.float64)
+    Zc = tab.Z.cpu().numpy().astype(np.float64)
+    for tensor in picks:
+        tensor = int(tensor)
+        zt, zs = tensor % nb, (tensor // nb) % nb
+        cv, cu = (tensor // (nb * nb)) % ncv, tensor // (nb * nb * ncv)
+        D = cluster.region_block_tensor(nxy, N, 0.005, nl, t, cs, cu, cv, zs, zt)
+        keep = cluster.nonblank_footprints(D)
+        assert np.array_equal(np.flatnonzero(zidx[tensor] >= 0), keep), tensor
+        xo, yo, zo, _ = cluster.als3(D[:, :, keep], cluster.init_factors(seed, tensor, t, Lr, R, keep), 3)
+        z = Zc[zidx[tensor][keep]]
+        rec = np.einsum("ar,br,fr->abf", X[tensor], Y[tensor], z)
+        reco = np.einsum("ar,br,fr->abf", xo, yo, zo)
+        bound = _fp32_output_bound(xo[None], yo[None], zo[None])[0] + 1e-4 * np.linalg.norm(D)
+        assert np.linalg.norm(rec - reco) <= bound, (tensor, float(np.linalg.norm(rec - reco) / bound))

@@ -147,3 +147,21 @@ def test_clustered_sampling_pdf_is_the_normalised_mass_and_histogram_matches():
     Z0[1, 0, :, :, (2 * cs + 1) * nl + 0] = 0.0
     _, pdf0, b0 = cluster.clustered_sample(X, Y, Z0, [[6, 1, 0]], rnd[:1], nl, cs)
     assert pdf0[0] == 0.0 and tuple(b0[0]) == (-1, -1)
+
+
+def test_region_block_tensor_equals_the_block_of_the_brute_force_tensor():
+    """The region-and-block tensor built from the map (for maps whose T is
+    too large) takes exactly the entries of the brute-force T: a 24 x 16 flake
+    map, 5 levels (footprints up to 16 texels, wrapping), N = 32 in blocks of
+    16 or 8, regions of 4 or 8 texels, every region and block."""
+    nxy = gen.flake_map(24, 16, 12, 0.25, 8)
+    T = ndf.ndf_bruteforce(nxy, 32, 0.02, 5)
+    for t, cs in ((16, 8), (8, 4)):
+        ncu, ncv, nb, L, t = cluster.layout(24, 16, 5, 32, t, cs)
+        for cu in range(ncu):
+            for cv in range(ncv):
+                for zs in range(nb):
+                    for zt in range(nb):
+                        want = cluster.cluster_tensor(T, cu, cv, zs, zt, t, cs)
+                        got = cluster.region_block_tensor(nxy, 32, 0.02, 5, t, cs, cu, cv, zs, zt)
+                        assert np.max(np.abs(got - want)) <= 1e-14 * max(np.max(np.abs(want)), 1e-300)
