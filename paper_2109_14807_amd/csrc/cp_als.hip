@@ -1354,7 +1354,11 @@ __global__ __launch_bounds__(256) void k_texel_contract(const double* __restrict
 }
 
 // Wt[x][y][r] = sum_l L[l][r] / k^2 Ub[l][x][r] Vb[l][y][r], XT rows x per
-// thread, y split over gridDim.y, the next y's window sums loaded ahead.
+// thread, y split over gridDim.y.  Up to 8 levels the next y's window sums
+// are loaded ahead; at 12 levels the loads-ahead would take the kernel past
+// 256 VGPRs, one wavefront a SIMD, and without them it runs two (measured at
+// 4096^2 texels, rank 256: 14.8 -> 11.4 ms; 2048^2, rank 128, 10 levels:
+// 1.72 -> 1.36 ms)
 template <int R, int XT, int NL>
 __global__ __launch_bounds__(256) void k_texel_w(const double* __restrict__ Ub, const double* __restrict__ Vb,
                                                  const double* __restrict__ L, int nu, int nv, int nl,
@@ -1382,16 +1386,24 @@ __global__ __launch_bounds__(256) void k_texel_w(const double* __restrict__ Ub, 
   double* wp[XT];
 #pragma unroll
   for (int xt = 0; xt < XT; ++xt) wp[xt] = Wt + static_cast<int64_t>(min(x0 + xt, nu - 1)) * nv * R + r;
+  constexpr bool kAhead = NL <= 8;
   double vn[NL];
+  if constexpr (kAhead) {
 #pragma unroll
-  for (int l = 0; l < NL; ++l) vn[l] = vp[l * lstride + static_cast<int64_t>(y0) * R];
+    for (int l = 0; l < NL; ++l) vn[l] = vp[l * lstride + static_cast<int64_t>(y0) * R];
+  }
   for (int y = y0; y < y1; ++y) {
     double v[NL];
+    if constexpr (kAhead) {
 #pragma unroll
-    for (int l = 0; l < NL; ++l) v[l] = vn[l];
-    const int yn = y + 1 < y1 ? y + 1 : y;
+      for (int l = 0; l < NL; ++l) v[l] = vn[l];
+      const int yn = y + 1 < y1 ? y + 1 : y;
 #pragma unroll
-    for (int l = 0; l < NL; ++l) vn[l] = vp[l * lstride + static_cast<int64_t>(yn) * R];
+      for (int l = 0; l < NL; ++l) vn[l] = vp[l * lstride + static_cast<int64_t>(yn) * R];
+    } else {
+#pragma unroll
+      for (int l = 0; l < NL; ++l) v[l] = vp[l * lstride + static_cast<int64_t>(y) * R];
+    }
     double w[XT];
 #pragma unroll
     for (int xt = 0; xt < XT; ++xt) w[xt] = 0.0;
