@@ -61,12 +61,16 @@ Q_BYTES = 32                   # algorithmic HBM bytes per flat query: 28-byte r
 # taken with (sha1 of the whole file: a kernel's instantiation depends on
 # helpers and constants outside its own text); otherwise traffic is null.
 MEASURED_TRAFFIC = {
-    "k_mttkrp_y": ("paper_2109_14807_amd/csrc/cp_als.hip", "be75fb7ede7f7473b663578bb650f0887c45fe70", 36585863551),
-    "k_mttkrp_z": ("paper_2109_14807_amd/csrc/cp_als.hip", "be75fb7ede7f7473b663578bb650f0887c45fe70", 34934655679),
-    "k_query_c4": ("paper_2109_14807_amd/csrc/query.hip", "76dbf1750c2c2696a73239a9effc44027635b717", 601548672),
-    "k_query_r16": ("paper_2109_14807_amd/csrc/query.hip", "76dbf1750c2c2696a73239a9effc44027635b717", 531102848),
+    "k_mttkrp_y": ("paper_2109_14807_amd/csrc/cp_als.hip", "fc21e4c6223d0b00e6b413af67d951920b9cea9a", 36577139135),
+    "k_mttkrp_z": ("paper_2109_14807_amd/csrc/cp_als.hip", "fc21e4c6223d0b00e6b413af67d951920b9cea9a", 34934241770),
+    "k_query_c4": ("paper_2109_14807_amd/csrc/query.hip", "2632f4ad84388cd28c87a4ddec8d23ea7e3af0b3", 600555589),
+    "k_query_r16": ("paper_2109_14807_amd/csrc/query.hip", "2632f4ad84388cd28c87a4ddec8d23ea7e3af0b3", 531093976),
     "k_query_clustered": ("paper_2109_14807_amd/csrc/cluster.hip", "fc2449c87f6a75f2ef4cb443fe819c7d93fa9885", 9295752320),
-    "k_query_c3": ("paper_2109_14807_amd/csrc/query.hip", "76dbf1750c2c2696a73239a9effc44027635b717", 2076726400),
+    "k_query_c3": ("paper_2109_14807_amd/csrc/query.hip", "2632f4ad84388cd28c87a4ddec8d23ea7e3af0b3", 2076701861),
+    "k_query_grouped_c5_bf16": ("paper_2109_14807_amd/csrc/query.hip", "2632f4ad84388cd28c87a4ddec8d23ea7e3af0b3",
+                                966120969),
+    "k_query_grouped_c5_fp8": ("paper_2109_14807_amd/csrc/query.hip", "2632f4ad84388cd28c87a4ddec8d23ea7e3af0b3",
+                               964983115),
 }
 
 LEGS = ("c3", "c5", "r16", "c2", "clustered", "refine", "sweep", "cpu_baseline")
@@ -408,7 +412,8 @@ def leg_c5(args, dev, keep):
         gbs = (20.0 + 12.0 / K) * nq / (ms * 1e-3) / 1e9
         name = "fp8_factors_bf16_sat" if cum == "bf16" else "all_fp8"
         rep[name] = {"tables": tables_report(tabs), "ms": ms, "boxes_per_s": nq / (ms * 1e-3), "hbm_gbs": gbs,
-                     "hbm_frac": gbs / HBM_PEAK_GBS, "error_vs_bruteforce": e}
+                     "hbm_frac": gbs / HBM_PEAK_GBS, "error_vs_bruteforce": e,
+                     "traffic": measured_traffic("k_query_grouped_c5_" + cum)}
         keep["parity"].append({"leg": f"c5 (FP8 factors, {cum.upper()} summed-area tables, grouped)",
                                "tables": stored_tables(tabs), "master": stored_tables(master), "records": rec_p,
                                "got": o[prec].cpu().numpy()})

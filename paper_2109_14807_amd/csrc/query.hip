@@ -1345,6 +1345,117 @@ glint_status device_limits() {
 // from rank 64 up (half the lanes per query, so the group reduction and the
 // per-record bookkeeping are shared by twice as many queries per instruction;
 // measured 1.0-1.5x faster there), 16 bytes below; never more than R.
+// Rank 16 over FP32 tables small enough for LDS (U and V up to kRepRows
+// rows): every 64-byte table row (L with the folded scales, CS, CT, U, V) is
+// stored four times side by side, one copy in each quarter of the LDS banks,
+// and the lane groups at positions 0..3 of a 16-lane LDS pass read copies
+// 0..3, so the seven random rows of the four queries in a pass never share a
+// bank (rows of one table otherwise start on one of four bank positions and
+// collide about two ways) and the U and V gathers leave the texture
+// address path.  Same arithmetic in the same order as k_query at rank 16.
+constexpr int kRepRows = 128;
+
+__host__ __device__ inline size_t rep16_lds_bytes(int nl, int N, int nu, int nv) {
+  return sizeof(float) * 64 * (static_cast<size_t>(nl) + 2 * (static_cast<size_t>(N) + 1) + nu + nv) +
+         sizeof(PackedRows) * 16 * (64 + 16);
+}
+
+__device__ void stage_rep16(float* __restrict__ dst, const float* __restrict__ src, int rows, const Scales* sc) {
+  const int n = rows * 16;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    float x = src[i];
+    if (sc) x *= folded_scale(*sc, i % 16);
+    float* d = dst + (i / 16) * 64 + i % 16;
+    d[0] = x;
+    d[16] = x;
+    d[32] = x;
+    d[48] = x;
+  }
+}
+
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_query_rep16(QueryArgs a) {
+  constexpr int R = 16, RPL = 4, LPQ = 4, RW = 64, kSlots = 64 + 16;
+  extern __shared__ __align__(16) float lds[];
+  unsigned char* lds_b = reinterpret_cast<unsigned char*>(lds);
+  float* Ls = lds;
+  float* CSs = Ls + a.nl * RW;
+  float* CTs = CSs + (a.N + 1) * RW;
+  float* Us = CTs + (a.N + 1) * RW;
+  float* Vs = Us + a.nu * RW;
+  PackedRows* rows = reinterpret_cast<PackedRows*>(Vs + a.nv * RW);
+  stage_rep16(Ls, static_cast<const float*>(a.L), a.nl, &a.scale);
+  stage_rep16(CSs, static_cast<const float*>(a.CS), a.N + 1, nullptr);
+  stage_rep16(CTs, static_cast<const float*>(a.CT), a.N + 1, nullptr);
+  stage_rep16(Us, static_cast<const float*>(a.U), a.nu, nullptr);
+  stage_rep16(Vs, static_cast<const float*>(a.V), a.nv, nullptr);
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63;
+  const int g = lane / LPQ;
+  const int j = lane % LPQ;
+  const int r0 = j * RPL + (g & 3) * R;   // the lane's columns in its group's copy
+  PackedRows* wrows = rows + (threadIdx.x >> 6) * kSlots;
+  const int my_slot = lane + lane / LPQ;
+  const unsigned char* cum_lane = lds_b + r0 * sizeof(float);
+  const uint32_t cs = static_cast<uint32_t>(reinterpret_cast<unsigned char*>(CSs) - lds_b);
+  const uint32_t ct = static_cast<uint32_t>(reinterpret_cast<unsigned char*>(CTs) - lds_b);
+  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
+  for (int64_t base = wave * 64; base < a.nq; base += nwaves * 64) {
+    {
+      const int64_t qi = base + lane;
+      const int64_t qc = qi < a.nq ? qi : a.nq - 1;
+      const int32_t* rec = a.q + qc * 7;
+      int f[7];
+#pragma unroll
+      for (int i = 0; i < 7; ++i) f[i] = rec[i];
+      const int u = glint_wrap(f[0], a.nu);
+      const int v = glint_wrap(f[1], a.nv);
+      const int l = glint_clampi(f[2], 0, a.nl - 1);
+      const int slo = glint_clampi(f[3], 0, a.N), shi = glint_clampi(f[4], 0, a.N);
+      const int tlo = glint_clampi(f[5], 0, a.N), thi = glint_clampi(f[6], 0, a.N);
+      const bool empty = !(slo < shi && tlo < thi);
+      const int s_hi = empty ? slo : shi;
+      constexpr uint32_t RB = sizeof(float) * RW;
+      PackedRows r;
+      r.ul = static_cast<uint32_t>(u) | static_cast<uint32_t>(l) << 26;
+      r.v = static_cast<uint32_t>(v);
+      r.a = ((cs + s_hi * RB) >> 4) | ((cs + slo * RB) >> 4) << 16;
+      r.b = ((ct + thi * RB) >> 4) | ((ct + tlo * RB) >> 4) << 16;
+      wrows[my_slot] = r;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    float res = 0.0f;
+    uint32_t pul = ~0u, pv = ~0u;
+    float W[RPL];
+#pragma unroll 2
+    for (int jj = 0; jj < LPQ; ++jj) {
+      const PackedRows r = wrows[g * (LPQ + 1) + jj];
+      if (r.ul != pul || r.v != pv) {
+        float uu[RPL], vv[RPL], lr[RPL];
+        lds_row<RPL>(Us + (r.ul & 0x3ffffffu) * RW + r0, uu);
+        lds_row<RPL>(Vs + r.v * RW + r0, vv);
+        lds_row<RPL>(Ls + (r.ul >> 26) * RW + r0, lr);
+#pragma unroll
+        for (int e = 0; e < RPL; ++e) W[e] = uu[e] * vv[e] * lr[e];
+        pul = r.ul; pv = r.v;
+      }
+      float sh[RPL], sl[RPL], th[RPL], tl[RPL];
+      lds_row<RPL>(reinterpret_cast<const float*>(cum_lane + ((r.a & 0xffffu) << 4)), sh);
+      lds_row<RPL>(reinterpret_cast<const float*>(cum_lane + ((r.a >> 16) << 4)), sl);
+      lds_row<RPL>(reinterpret_cast<const float*>(cum_lane + ((r.b & 0xffffu) << 4)), th);
+      lds_row<RPL>(reinterpret_cast<const float*>(cum_lane + ((r.b >> 16) << 4)), tl);
+      float acc = lane_terms<RPL, RPL>(W, sh, sl, th, tl, 0);
+      acc = glint_group_sum<LPQ>(acc);
+      res = (j == jj) ? acc : res;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int64_t qo = base + g * LPQ + j;
+    if (qo < a.nq) a.out[qo] = res;
+  }
+}
+
 template <typename FT, int R>
 constexpr int rpl_for() {
   return (R >= 64 ? 32 : 16) / static_cast<int>(sizeof(FT)) <= R ? (R >= 64 ? 32 : 16) / static_cast<int>(sizeof(FT))
@@ -1404,6 +1515,21 @@ glint_status launch_query(const QueryArgs& a, hipStream_t stream) {
   if (a.nu > (1 << 26) || a.nl > 64)
     return glint_fail(GLINT_E_UNSUPPORTED, "the flat query takes nu <= 2^26 and nl <= 64 (nu %d, nl %d)", a.nu, a.nl);
   constexpr int NT = P::NT;
+  if constexpr (R == 16 && std::is_same<FT, float>::value && std::is_same<CT, float>::value) {
+    const size_t rep = rep16_lds_bytes(a.nl, a.N, a.nu, a.nv);
+    if (a.nu <= kRepRows && a.nv <= kRepRows && rep <= static_cast<size_t>(g_max_lds) &&
+        16 * (static_cast<size_t>(a.nl) + 2 * (static_cast<size_t>(a.N) + 1)) < 65536) {
+      const int64_t waves_needed = (a.nq + 63) / 64;
+      int64_t blocks = (waves_needed + 15) / 16;
+      const int64_t cap = static_cast<int64_t>(g_cu_count) * 2;
+      if (blocks > cap) blocks = cap;
+      if (blocks < 1) blocks = 1;
+      glint_clear_launch_error();
+      hipLaunchKernelGGL(k_query_rep16, dim3(static_cast<unsigned>(blocks)), dim3(1024), rep, stream, a);
+      GLINT_LAUNCHED("k_query_rep16");
+      return GLINT_OK;
+    }
+  }
   const size_t slots = sizeof(PackedRows) * (NT / 64) * (64 + 64 / (R / RPL));
   const bool gc = query_lds(a.nl, a.N, R, sizeof(LT), false, slots).total > static_cast<size_t>(g_max_lds);
   const size_t lds = query_lds(a.nl, a.N, R, sizeof(LT), gc, slots).total;

@@ -204,6 +204,23 @@ def test_query_sizes(nq):
         _check(got[:nq], want, mag)
 
 
+@pytest.mark.parametrize("nu,nv,N", [(128, 128, 32), (129, 40, 32), (40, 129, 32), (64, 64, 256), (1, 1, 4)])
+def test_rank16_replicated_lds_tables_and_fallback(nu, nv, N):
+    """Rank 16 over FP32 tables keeps U and V (up to 128 rows) and the other
+    tables in LDS, four copies a row; larger maps or tables take the general
+    kernel.  Both sides of each limit against the oracle, wrapped and clamped
+    records included."""
+    print(f"rank-16 query nu={nu} nv={nv} N={N}", flush=True)
+    rng = np.random.default_rng(nu * 1000 + nv + N)
+    nl, R = 5, 16
+    F = _rand_factors(rng, nu, nv, nl, N, R)
+    q = _rand_queries(rng, 30011, nu, nv, nl, N, wild=True)
+    tabs = G.make_tables(*[torch.tensor(x, device="cuda") for x in F])
+    got = G.query(tabs, q).cpu().numpy()
+    want, mag = _oracle(F, q, "f32", "f32")
+    _check(got, want, mag)
+
+
 def test_grouped_equals_flat():
     rng = np.random.default_rng(9)
     nu, nv, nl, N, R = 64, 64, 12, 128, 64
