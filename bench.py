@@ -63,14 +63,14 @@ Q_BYTES = 32                   # algorithmic HBM bytes per flat query: 28-byte r
 MEASURED_TRAFFIC = {
     "k_mttkrp_y": ("paper_2109_14807_amd/csrc/cp_als.hip", "fc21e4c6223d0b00e6b413af67d951920b9cea9a", 36577139135),
     "k_mttkrp_z": ("paper_2109_14807_amd/csrc/cp_als.hip", "fc21e4c6223d0b00e6b413af67d951920b9cea9a", 34934241770),
-    "k_query_c4": ("paper_2109_14807_amd/csrc/query.hip", "2632f4ad84388cd28c87a4ddec8d23ea7e3af0b3", 600555589),
-    "k_query_r16": ("paper_2109_14807_amd/csrc/query.hip", "2632f4ad84388cd28c87a4ddec8d23ea7e3af0b3", 531093976),
+    "k_query_c4": ("paper_2109_14807_amd/csrc/query.hip", "8a7a75a2ad759f50156271a15ebf7d6f529c805e", 601509696),
+    "k_query_r16": ("paper_2109_14807_amd/csrc/query.hip", "8a7a75a2ad759f50156271a15ebf7d6f529c805e", 531011584),
     "k_query_clustered": ("paper_2109_14807_amd/csrc/cluster.hip", "fc2449c87f6a75f2ef4cb443fe819c7d93fa9885", 9295752320),
-    "k_query_c3": ("paper_2109_14807_amd/csrc/query.hip", "2632f4ad84388cd28c87a4ddec8d23ea7e3af0b3", 2076701861),
-    "k_query_grouped_c5_bf16": ("paper_2109_14807_amd/csrc/query.hip", "2632f4ad84388cd28c87a4ddec8d23ea7e3af0b3",
-                                966120969),
-    "k_query_grouped_c5_fp8": ("paper_2109_14807_amd/csrc/query.hip", "2632f4ad84388cd28c87a4ddec8d23ea7e3af0b3",
-                               964983115),
+    "k_query_c3": ("paper_2109_14807_amd/csrc/query.hip", "8a7a75a2ad759f50156271a15ebf7d6f529c805e", 2076635648),
+    "k_query_grouped_c5_bf16": ("paper_2109_14807_amd/csrc/query.hip", "8a7a75a2ad759f50156271a15ebf7d6f529c805e",
+                                966139392),
+    "k_query_grouped_c5_fp8": ("paper_2109_14807_amd/csrc/query.hip", "8a7a75a2ad759f50156271a15ebf7d6f529c805e",
+                               965117760),
 }
 
 LEGS = ("c3", "c5", "r16", "c2", "clustered", "refine", "sweep", "cpu_baseline")
