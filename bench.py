@@ -536,6 +536,26 @@ def leg_clustered(args, dev, keep):
         rep["traffic_gbs"] = tr / (ms * 1e-3) / 1e9
         rep["traffic_frac"] = rep["traffic_gbs"] / HBM_PEAK_GBS
     log(f"clustered: query {rep['queries_per_s'] / 1e9:.2f} G q/s, E_bf {ebf['all']:.4f}")
+    # the same tables stored in BF16 (CX, CY and Z rounded to nearest even)
+    bt = G.clustered_bf16(tab)
+    outb = torch.empty(nq, dtype=torch.float32, device=dev)
+    msb = timed(lambda: L.glint_query_clustered(bt.struct(), q, outb), args.reps)
+    ebfb, _ = error_vs_bruteforce(desc, nxy, q[idx], outb[idx], levels=cfg.nlevels)
+    d32 = float(torch.linalg.vector_norm((outb - out).double()) / torch.linalg.vector_norm(out.double()))
+    bsel = bt.Z[rowsel.clamp(min=0).long()]
+    Zb = torch.where(rowsel[..., None] >= 0, bsel, torch.zeros((), dtype=torch.bfloat16, device=dev))
+    keep["parity"].append({"leg": "clustered BF16 tables (2048^2, t 16, 8x8 regions, rank 32, compact Z)",
+                           "kind": "clustered_tables", "CX": bt.CX[tens].float().cpu().numpy(),
+                           "CY": bt.CY[tens].float().cpu().numpy(), "Z": Zb.float().cpu().numpy(),
+                           "records": recs, "got": outb[torch.tensor(pidx, device=dev)].cpu().numpy(),
+                           "nb": nb, "t": t})
+    rep["bf16_tables"] = {"what": "CX, CY and Z stored in BF16 (each FP32 value rounded to nearest even), "
+                                  "FP32 arithmetic on the decoded values",
+                          "table_bytes": int(sum(x.numel() * 2 for x in (bt.CX, bt.CY, bt.Z))),
+                          "fp32_table_bytes": int(sum(x.numel() * 4 for x in (tab.CX, tab.CY, tab.Z))),
+                          **flat_rate(nq, msb), "speedup_over_fp32_tables": ms / msb,
+                          "error_vs_bruteforce": ebfb["all"], "rel_l2_vs_fp32_tables": d32}
+    log(f"clustered BF16: query {rep['bf16_tables']['queries_per_s'] / 1e9:.2f} G q/s, E_bf {ebfb['all']:.4f}")
     return rep
 
 
@@ -866,6 +886,43 @@ def clustered_report(desc, T, q, nxy, reps, t=16, cs=8, R=16, sweeps=20):
 # the only part of the benchmark that runs the oracle
 # ---------------------------------------------------------------------------
 
+def clustered_tables_parity(p):
+    """Each sampled record against the oracle's block-split query on the
+    stored tables (oracle.cluster.clustered_range_query_tables) of its
+    region, as one region of one texel and one level; M_q = the sum of the
+    query's |rank terms| on those tables (the scale of its FP32 rounding)."""
+    import numpy as np
+    from oracle import cluster
+    got = p["got"].astype(np.float64)
+    want = np.empty(got.size)
+    mag = np.zeros(got.size)
+    nb, t = p["nb"], p["t"]
+    N = nb * t
+    for i, r in enumerate(p["records"]):
+        CX = p["CX"][i].astype(np.float64).reshape(1, 1, nb, nb, t + 1, -1)
+        CY = p["CY"][i].astype(np.float64).reshape(1, 1, nb, nb, t + 1, -1)
+        Z = p["Z"][i].astype(np.float64).reshape(1, 1, nb, nb, 1, -1)
+        q1 = np.array([[0, 0, 0, r[3], r[4], r[5], r[6]]], dtype=np.int64)
+        want[i] = cluster.clustered_range_query_tables(CX, CY, Z, q1, 1, 1)[0]
+        slo, shi, tlo, thi = (min(max(int(x), 0), N) for x in r[3:7])
+        if slo < shi and tlo < thi:
+            for zs in range(slo // t, (shi - 1) // t + 1):
+                a0, a1 = max(slo, zs * t) - zs * t, min(shi, (zs + 1) * t) - zs * t
+                for zt in range(tlo // t, (thi - 1) // t + 1):
+                    b0, b1 = max(tlo, zt * t) - zt * t, min(thi, (zt + 1) * t) - zt * t
+                    cx, cy = CX[0, 0, zs, zt], CY[0, 0, zs, zt]
+                    mag[i] += float(np.sum(np.abs(Z[0, 0, zs, zt, 0] * (cx[a1] - cx[a0]) * (cy[b1] - cy[b0]))))
+    err = np.abs(got - want)
+    normal = mag >= 1e-30
+    ent = {"leg": p["leg"], "n": int(got.size),
+           "max_err_over_Mq": float(np.max(err[normal] / mag[normal])) if normal.any() else 0.0,
+           "records_with_Mq_below_1e-30": int((~normal).sum()),
+           "max_abs_err_there": float(np.max(err[~normal])) if (~normal).any() else 0.0,
+           "tolerance": "|q_gpu - q_64| <= 1e-5 M_q + 1e-30"}
+    ent["pass"] = bool(np.all(err <= 1e-5 * mag + 1e-30))
+    return ent
+
+
 def clustered_parity(p):
     """Each sampled record against the oracle's block-split query
     (oracle.cluster.clustered_range_query) over its region's downloaded FP32
@@ -961,8 +1018,8 @@ def leg_cpu_baseline(args, keep):
     # parity samples
     par = []
     for p in keep["parity"]:
-        if p.get("kind") == "clustered":
-            par.append(clustered_parity(p))
+        if p.get("kind") in ("clustered", "clustered_tables"):
+            par.append(clustered_parity(p) if p["kind"] == "clustered" else clustered_tables_parity(p))
             log(f"parity {p['leg']}: max |err|/M_q {par[-1]['max_err_over_Mq']:.2e}")
             continue
         v, s = p["tables"]

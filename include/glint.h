@@ -312,25 +312,30 @@ glint_status glint_cp_als_clustered_map(const glint_ndf_desc* desc, const glint_
 glint_status glint_make_cumulative_batched(int64_t nbatch, int32_t n, int32_t R, const float* S,
                                            float* C, hipStream_t stream);
 
-/* Clustered query tables (FP32): summed-area tables of X and Y per tensor,
+/* Clustered query tables: summed-area tables of X and Y per tensor,
  * CX, CY [ntensor][t+1][R], and Z: dense [ntensor][L][R] (zidx NULL) or,
  * in the compact layout, [rows][R] with zidx [ntensor][L] giving each
  * footprint's row of Z, -1 for a blank image block (no terms); 16-byte
- * aligned. */
+ * aligned.  dtype is the element type of CX, CY and Z: GLINT_F32, or
+ * GLINT_BF16 (Sec. 4.4 storage: each FP32 table value rounded to nearest
+ * even, as glint_convert does; half the gathered bytes), read by
+ * glint_query_clustered only; any other value is GLINT_E_INVALID. */
 typedef struct {
   int32_t t, cs, R;
   int32_t nu, nv, nl, nbins;
-  const float* CX;
-  const float* CY;
-  const float* Z;
+  const void* CX;
+  const void* CY;
+  const void* Z;
   const int32_t* zidx;
+  int32_t dtype;
 } glint_clustered;
 
 /* Range query on the clustered tables: records as for glint_query (same
  * wrap/clamp/empty rules); the box is split at block edges and the
  * block-local queries sum_r Z[f][r] (CX[a1][r] - CX[a0][r]) (CY[b1][r] -
  * CY[b0][r]) are added (a blank image block of the compact layout adds
- * nothing).  FP32 arithmetic. */
+ * nothing).  FP32 arithmetic on the stored values (BF16 tables decoded
+ * exactly to FP32). */
 glint_status glint_query_clustered(const glint_clustered* f, int64_t nq, const int32_t* q,
                                    float* out, hipStream_t stream);
 
@@ -347,7 +352,8 @@ glint_status glint_query_clustered(const glint_clustered* f, int64_t nq, const i
  * rnd[log2 t + 2]) 2/N) with (s, t) the global bin; pdf = the product of
  * the choice probabilities / (2/N)^2.  No positive mass: bins (-1, -1),
  * pdf 0, h 0.  t must be a power of two.  Outputs h float [n][2], pdf float
- * [n], bins int32 [n][2].  One thread per lookup, FP32. */
+ * [n], bins int32 [n][2].  One thread per lookup, FP32; FP32 tables only
+ * (dtype GLINT_F32, else GLINT_E_UNSUPPORTED). */
 glint_status glint_sample_clustered(const glint_clustered* f, int64_t n, const int32_t* uvl, const float* rnd,
                                     float* h, float* pdf, int32_t* bins, hipStream_t stream);
 

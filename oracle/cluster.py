@@ -247,11 +247,28 @@ def reconstruct(X, Y, Z, nl: int, cs: int) -> np.ndarray:
     return out
 
 
+def block_cumulative(X) -> np.ndarray:
+    """Block-local summed-area tables: C[..., j, r] = sum_{a<j} X[..., a, r]
+    for j = 0..t (Sec. 4.4 within each angular block), FP64."""
+    X = np.asarray(X, dtype=np.float64)
+    z = np.zeros(X.shape[:-2] + (1, X.shape[-1]))
+    return np.concatenate([z, np.cumsum(X, axis=-2)], axis=-2)
+
+
 def clustered_range_query(X, Y, Z, q, nl: int, cs: int) -> np.ndarray:
     """Box sums by splitting each box at block edges and adding the
     block-local range queries (cumulative sums of X and Y inside a block)."""
-    ncu, ncv, nb = X.shape[:3]
-    t = X.shape[4]
+    return clustered_range_query_tables(block_cumulative(X), block_cumulative(Y), Z, q, nl, cs)
+
+
+def clustered_range_query_tables(CX, CY, Z, q, nl: int, cs: int) -> np.ndarray:
+    """The block-split range query on given block-local summed-area tables
+    CX, CY [ncu][ncv][nb][nb][t+1][R] (e.g. stored values rounded to a
+    storage type, Sec. 4.4): over the blocks the box overlaps, the term
+    sum_r Z[f][r] (CX[a1][r] - CX[a0][r]) (CY[b1][r] - CY[b0][r]) with the
+    box clipped to the block, in FP64."""
+    ncu, ncv, nb = CX.shape[:3]
+    t = CX.shape[4] - 1
     nu, nv, N = ncu * cs, ncv * cs, nb * t
     q = canonical_query(q, nu, nv, nl, N)
     out = np.zeros(q.shape[0])
@@ -265,9 +282,9 @@ def clustered_range_query(X, Y, Z, q, nl: int, cs: int) -> np.ndarray:
             a0, a1 = max(slo, zs * t) - zs * t, min(shi, (zs + 1) * t) - zs * t
             for zt in range(tlo // t, (thi - 1) // t + 1):
                 b0, b1 = max(tlo, zt * t) - zt * t, min(thi, (zt + 1) * t) - zt * t
-                CX = np.concatenate([np.zeros((1, X.shape[-1])), np.cumsum(X[cu, cv, zs, zt], axis=0)])
-                CY = np.concatenate([np.zeros((1, Y.shape[-1])), np.cumsum(Y[cu, cv, zs, zt], axis=0)])
-                acc += float(np.sum(Z[cu, cv, zs, zt, f] * (CX[a1] - CX[a0]) * (CY[b1] - CY[b0])))
+                cx, cy = CX[cu, cv, zs, zt], CY[cu, cv, zs, zt]
+                acc += float(np.sum(np.asarray(Z[cu, cv, zs, zt, f], dtype=np.float64)
+                                    * (cx[a1] - cx[a0]) * (cy[b1] - cy[b0])))
         out[i] = acc
     return out
 

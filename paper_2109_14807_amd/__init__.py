@@ -9,7 +9,7 @@ gfx950 under csrc/); this package only binds it.  Build it in-tree with
 from . import _lib  # noqa: F401
 from ._lib import GlintError, NdfDesc  # noqa: F401
 from .api import (  # noqa: F401
-    AlsResult, ClusteredTables, QueryTables, als_workspace, clustered_cumulative, cp_als_clustered,
+    AlsResult, ClusteredTables, QueryTables, als_workspace, clustered_bf16, clustered_cumulative, cp_als_clustered,
     cp_als_clustered_map,
     query_clustered, sample_clustered, build_tensor, convert, cp_als, cumulative, cumulative_backward,
     cp_als_texel, desc_of, make_tables, mttkrp, mttkrp_texel, query, query_backward, query_grouped, query_trilinear,

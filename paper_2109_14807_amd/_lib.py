@@ -64,7 +64,7 @@ class Clustered(ctypes.Structure):
     _fields_ = [("t", ctypes.c_int32), ("cs", ctypes.c_int32), ("R", ctypes.c_int32),
                 ("nu", ctypes.c_int32), ("nv", ctypes.c_int32), ("nl", ctypes.c_int32),
                 ("nbins", ctypes.c_int32), ("CX", ctypes.c_void_p), ("CY", ctypes.c_void_p),
-                ("Z", ctypes.c_void_p), ("zidx", ctypes.c_void_p)]
+                ("Z", ctypes.c_void_p), ("zidx", ctypes.c_void_p), ("dtype", ctypes.c_int32)]
 
 
 class Wang(ctypes.Structure):

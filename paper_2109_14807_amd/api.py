@@ -278,6 +278,7 @@ class ClusteredTables:
     CY: torch.Tensor = None
     zidx: torch.Tensor = None      # compact layout: [ntensor][L] row of Z or -1
     zbase: torch.Tensor = None     # compact layout: first row of each tensor, then the row count
+    dtype: str = "f32"             # element type of CX, CY and Z as the query reads them
 
     @property
     def R(self):
@@ -289,9 +290,11 @@ class ClusteredTables:
 
     def struct(self) -> L.Clustered:
         d = self.desc
+        et = _STORE[self.dtype]
         return L.Clustered(self.t, self.cs, self.R, d.nu, d.nv, d.nlevels, d.nbins,
-                           L._ptr(self.CX, torch.float32, "CX"), L._ptr(self.CY, torch.float32, "CY"),
-                           L._ptr(self.Z, torch.float32, "Z"), L._ptr(self.zidx, torch.int32, "zidx"))
+                           L._ptr(self.CX, et, "CX"), L._ptr(self.CY, et, "CY"),
+                           L._ptr(self.Z, et, "Z"), L._ptr(self.zidx, torch.int32, "zidx"),
+                           L._gdtype_of(et))
 
     def dense_z(self) -> torch.Tensor:
         """Z as [ntensor][L][R] with zero rows for blank image blocks."""
@@ -364,6 +367,22 @@ def clustered_cumulative(tab: ClusteredTables):
     L.glint_make_cumulative_batched(tab.X, tab.CX)
     L.glint_make_cumulative_batched(tab.Y, tab.CY)
     return tab
+
+
+def clustered_bf16(tab: ClusteredTables) -> ClusteredTables:
+    """The query tables of `tab` stored in BF16 (Sec. 4.4 storage): CX, CY
+    and Z, each FP32 value rounded to nearest even by the library
+    (glint_convert); X, Y, blank, zidx shared with `tab`.  Read by
+    query_clustered; sampling takes the FP32 tables."""
+    if tab.dtype != "f32":
+        raise ValueError("clustered_bf16 converts FP32 tables")
+
+    def bf(x):
+        out = torch.empty(x.shape, dtype=torch.bfloat16, device=_DEV)
+        L.glint_convert(x.reshape(-1, x.shape[-1]), out.view(-1, x.shape[-1]))
+        return out
+
+    return dataclasses.replace(tab, CX=bf(tab.CX), CY=bf(tab.CY), Z=bf(tab.Z), dtype="bf16")
 
 
 def sample_clustered(tab: ClusteredTables, uvl, rnd):

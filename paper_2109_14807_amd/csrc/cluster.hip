@@ -917,9 +917,9 @@ __global__ void k_cumulative_batched(int64_t nbatch, int n, int R, const float* 
 // ---------------------------------------------------------------------------
 
 struct ClQueryArgs {
-  const float* CX;   // [ntensor][t+1][R]
-  const float* CY;
-  const float* Z;    // [ntensor][L][R], or [rows][R] with zidx
+  const void* CX;    // [ntensor][t+1][R], FP32 or BF16
+  const void* CY;
+  const void* Z;     // [ntensor][L][R], or [rows][R] with zidx
   const int32_t* zidx;   // compact layout: [ntensor][L] row of Z or -1 (blank)
   int t, cs, nu, nv, nl, N, ncv, nb, L;
   int64_t nq;
@@ -952,14 +952,56 @@ __device__ __forceinline__ int64_t cl_row(const ClQueryArgs& a, int64_t tensor, 
   return a.zidx ? static_cast<int64_t>(a.zidx[zr]) : zr;
 }
 
-// lane group of LPQ = R / 4 lanes per query, 4 ranks (16 bytes) per lane.
+// A lane's RPL consecutive values of a table row: FP32 kept as loaded, BF16
+// kept as the loaded words (one 16-byte load for eight ranks, 8 bytes for
+// four; rows aligned to that) and decoded exactly to FP32 where used.
+template <typename ET, int RPL>
+struct ClRow {
+  float v[RPL];
+  __device__ __forceinline__ void load(const float* p) {
+#pragma unroll
+    for (int e = 0; e < RPL; ++e) v[e] = p[e];
+  }
+  __device__ __forceinline__ float operator[](int e) const { return v[e]; }
+};
+
+template <int RPL>
+struct ClRow<uint16_t, RPL> {
+  static_assert(RPL == 4 || RPL == 8, "BF16 rows: 4 or 8 ranks a lane");
+  uint32_t w[RPL / 2];
+  __device__ __forceinline__ void load(const uint16_t* p) {
+    if constexpr (RPL == 8) {
+      const uint4 x = *reinterpret_cast<const uint4*>(p);
+      w[0] = x.x; w[1] = x.y; w[2] = x.z; w[3] = x.w;
+    } else {
+      const uint2 x = *reinterpret_cast<const uint2*>(p);
+      w[0] = x.x; w[1] = x.y;
+    }
+  }
+  __device__ __forceinline__ float operator[](int e) const {
+    return (e & 1) ? __uint_as_float(w[e >> 1] & 0xffff0000u) : __uint_as_float(w[e >> 1] << 16);
+  }
+};
+
+// Ranks a lane of the clustered query: 16 bytes of a row (FP32: 4, BF16: 8,
+// BF16 rank 4: 4).
+template <typename ET, int R>
+constexpr int cl_rpl() {
+  return sizeof(ET) == 2 && R >= 8 ? 8 : 4;
+}
+
+// lane group of LPQ = R / RPL lanes per query, RPL ranks per lane.
 // Phase 1: lane i resolves record base + i (and its first blocks' Z rows);
 // phase 2: group g serves records g*LPQ .. g*LPQ + LPQ - 1, loading the rows
 // of the first kClPre blocks of a box together before any arithmetic.  The
 // blocks' terms are added in zs-major order, ranks in order within a block.
-template <int R>
+template <typename ET, int R>
 __global__ __launch_bounds__(kClQueryThreads) void k_query_clustered(ClQueryArgs a) {
-  constexpr int RPL = R < 4 ? R : 4;
+  constexpr int RPL = cl_rpl<ET, R>();
+  static_assert(R % RPL == 0, "rank a multiple of the ranks a lane");
+  const ET* __restrict__ CXg = static_cast<const ET*>(a.CX);
+  const ET* __restrict__ CYg = static_cast<const ET*>(a.CY);
+  const ET* __restrict__ Zg = static_cast<const ET*>(a.Z);
   constexpr int LPQ = R / RPL;
   __shared__ ClRec recs[kClQueryThreads / 64][64];
   const int lane = threadIdx.x & 63;
@@ -1005,7 +1047,7 @@ __global__ __launch_bounds__(kClQueryThreads) void k_query_clustered(ClQueryArgs
         const int zs0 = cr.slo / t, zt0 = cr.tlo / t;
         const int nzt = (cr.thi - 1) / t - zt0 + 1;
         // the first kClPre blocks: every row loaded before the arithmetic
-        float zz[kClPre][RPL], xh[kClPre][RPL], xl[kClPre][RPL], yh[kClPre][RPL], yl[kClPre][RPL];
+        ClRow<ET, RPL> zz[kClPre], xh[kClPre], xl[kClPre], yh[kClPre], yl[kClPre];
 #pragma unroll
         for (int b = 0; b < kClPre; ++b) {
           if (b < cr.nblk && cr.rows[b] >= 0) {
@@ -1013,17 +1055,13 @@ __global__ __launch_bounds__(kClQueryThreads) void k_query_clustered(ClQueryArgs
             const int a0 = max(cr.slo, zs * t) - zs * t, a1 = min(cr.shi, (zs + 1) * t) - zs * t;
             const int b0 = max(cr.tlo, zt * t) - zt * t, b1 = min(cr.thi, (zt + 1) * t) - zt * t;
             const int64_t tensor = cr.tensor0 + zs * a.nb + zt;
-            const float* cx = a.CX + tensor * (t + 1) * R + r0;
-            const float* cy = a.CY + tensor * (t + 1) * R + r0;
-            const float* z = a.Z + cr.rows[b] * R + r0;
-#pragma unroll
-            for (int e = 0; e < RPL; ++e) {
-              zz[b][e] = z[e];
-              xh[b][e] = cx[a1 * R + e];
-              xl[b][e] = cx[a0 * R + e];
-              yh[b][e] = cy[b1 * R + e];
-              yl[b][e] = cy[b0 * R + e];
-            }
+            const ET* cx = CXg + tensor * (t + 1) * R + r0;
+            const ET* cy = CYg + tensor * (t + 1) * R + r0;
+            zz[b].load(Zg + cr.rows[b] * R + r0);
+            xh[b].load(cx + a1 * R);
+            xl[b].load(cx + a0 * R);
+            yh[b].load(cy + b1 * R);
+            yl[b].load(cy + b0 * R);
           }
         }
 #pragma unroll
@@ -1041,12 +1079,16 @@ __global__ __launch_bounds__(kClQueryThreads) void k_query_clustered(ClQueryArgs
           if (zr < 0) continue;     // blank image block: no terms
           const int a0 = max(cr.slo, zs * t) - zs * t, a1 = min(cr.shi, (zs + 1) * t) - zs * t;
           const int b0 = max(cr.tlo, zt * t) - zt * t, b1 = min(cr.thi, (zt + 1) * t) - zt * t;
-          const float* cx = a.CX + tensor * (t + 1) * R + r0;
-          const float* cy = a.CY + tensor * (t + 1) * R + r0;
-          const float* z = a.Z + zr * R + r0;
+          const ET* cx = CXg + tensor * (t + 1) * R + r0;
+          const ET* cy = CYg + tensor * (t + 1) * R + r0;
+          ClRow<ET, RPL> z, xh, xl, yh, yl;
+          z.load(Zg + zr * R + r0);
+          xh.load(cx + a1 * R);
+          xl.load(cx + a0 * R);
+          yh.load(cy + b1 * R);
+          yl.load(cy + b0 * R);
 #pragma unroll
-          for (int e = 0; e < RPL; ++e)
-            acc += z[e] * (cx[a1 * R + e] - cx[a0 * R + e]) * (cy[b1 * R + e] - cy[b0 * R + e]);
+          for (int e = 0; e < RPL; ++e) acc += z[e] * (xh[e] - xl[e]) * (yh[e] - yl[e]);
         }
       }
       acc = glint_group_sum<LPQ>(acc);
@@ -1509,6 +1551,8 @@ glint_status glint_query_clustered(const glint_clustered* f, int64_t nq, const i
   GLINT_REQUIRE(f->CX && f->CY && f->Z && q && out, "null pointer argument");
   GLINT_REQUIRE(glint_aligned(f->CX, 16) && glint_aligned(f->CY, 16) && glint_aligned(f->Z, 16),
                 "tables must be 16-byte aligned");
+  GLINT_REQUIRE(f->dtype == GLINT_F32 || f->dtype == GLINT_BF16, "clustered tables must be F32 or BF16 (dtype %d)",
+                f->dtype);
   if ((st = cl_device()) != GLINT_OK) return st;
   ClQueryArgs a;
   a.CX = f->CX; a.CY = f->CY; a.Z = f->Z; a.zidx = f->zidx;
@@ -1519,11 +1563,20 @@ glint_status glint_query_clustered(const glint_clustered* f, int64_t nq, const i
   const int64_t cap = static_cast<int64_t>(g_cl_cus) * 8;
   if (blocks > cap) blocks = cap;
   glint_clear_launch_error();
-  switch (f->R) {
-    case 4: hipLaunchKernelGGL(k_query_clustered<4>, dim3(blocks), dim3(kClQueryThreads), 0, stream, a); break;
-    case 8: hipLaunchKernelGGL(k_query_clustered<8>, dim3(blocks), dim3(kClQueryThreads), 0, stream, a); break;
-    case 16: hipLaunchKernelGGL(k_query_clustered<16>, dim3(blocks), dim3(kClQueryThreads), 0, stream, a); break;
-    default: hipLaunchKernelGGL(k_query_clustered<32>, dim3(blocks), dim3(kClQueryThreads), 0, stream, a); break;
+  if (f->dtype == GLINT_BF16) {
+    switch (f->R) {
+      case 4: hipLaunchKernelGGL((k_query_clustered<uint16_t, 4>), dim3(blocks), dim3(kClQueryThreads), 0, stream, a); break;
+      case 8: hipLaunchKernelGGL((k_query_clustered<uint16_t, 8>), dim3(blocks), dim3(kClQueryThreads), 0, stream, a); break;
+      case 16: hipLaunchKernelGGL((k_query_clustered<uint16_t, 16>), dim3(blocks), dim3(kClQueryThreads), 0, stream, a); break;
+      default: hipLaunchKernelGGL((k_query_clustered<uint16_t, 32>), dim3(blocks), dim3(kClQueryThreads), 0, stream, a); break;
+    }
+  } else {
+    switch (f->R) {
+      case 4: hipLaunchKernelGGL((k_query_clustered<float, 4>), dim3(blocks), dim3(kClQueryThreads), 0, stream, a); break;
+      case 8: hipLaunchKernelGGL((k_query_clustered<float, 8>), dim3(blocks), dim3(kClQueryThreads), 0, stream, a); break;
+      case 16: hipLaunchKernelGGL((k_query_clustered<float, 16>), dim3(blocks), dim3(kClQueryThreads), 0, stream, a); break;
+      default: hipLaunchKernelGGL((k_query_clustered<float, 32>), dim3(blocks), dim3(kClQueryThreads), 0, stream, a); break;
+    }
   }
   GLINT_LAUNCHED("k_query_clustered");
   return GLINT_OK;
@@ -1544,8 +1597,11 @@ glint_status glint_sample_clustered(const glint_clustered* f, int64_t n, const i
   GLINT_REQUIRE(n >= 0, "n must be >= 0");
   if (n == 0) return GLINT_OK;
   GLINT_REQUIRE(f->CX && f->CY && f->Z && uvl && rnd && h && pdf && bins, "null pointer argument");
+  if (f->dtype != GLINT_F32)
+    return glint_fail(GLINT_E_UNSUPPORTED, "clustered sampling takes FP32 tables (dtype %d)", f->dtype);
   ClSampleArgs a;
-  a.CX = f->CX; a.CY = f->CY; a.Z = f->Z; a.zidx = f->zidx;
+  a.CX = static_cast<const float*>(f->CX); a.CY = static_cast<const float*>(f->CY);
+  a.Z = static_cast<const float*>(f->Z); a.zidx = f->zidx;
   a.t = sh.t; a.cs = f->cs; a.nu = f->nu; a.nv = f->nv; a.nl = f->nl; a.N = f->nbins;
   a.ncv = sh.ncv; a.nb = sh.nb; a.L = sh.L;
   int levels = 0;

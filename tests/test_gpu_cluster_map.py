@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import gen
-from oracle import cluster, ndf
+from oracle import cluster, ndf, quant
 
 pytestmark = pytest.mark.gpu
 
@@ -133,6 +133,63 @@ def test_map_path_compact_query_matches_oracle_r32():
     want = cluster.clustered_range_query(X, Y, Z, q, cfg.nlevels, 8)
     mag = _magnitude(X, Y, Z, q, cfg.nlevels, 8)
     assert np.all(np.abs(got - want) <= 1e-5 * mag + 1e-30)
+
+
+def _table_magnitude(CX, CY, Z, q, nl, cs):
+    """Sum of the |rank terms| of a block-split query on given tables: the
+    scale of its FP32 rounding."""
+    ncu, ncv, nb = CX.shape[:3]
+    t = CX.shape[4] - 1
+    qc = ndf.canonical_query(q, ncu * cs, ncv * cs, nl, nb * t)
+    out = np.zeros(len(q))
+    for i, (u, v, l, slo, shi, tlo, thi) in enumerate(qc):
+        if slo >= shi or tlo >= thi:
+            continue
+        f = ((u % cs) * cs + v % cs) * nl + l
+        for zs in range(slo // t, (shi - 1) // t + 1):
+            a0, a1 = max(slo, zs * t) - zs * t, min(shi, (zs + 1) * t) - zs * t
+            for zt in range(tlo // t, (thi - 1) // t + 1):
+                b0, b1 = max(tlo, zt * t) - zt * t, min(thi, (zt + 1) * t) - zt * t
+                k = (u // cs, v // cs, zs, zt)
+                out[i] += float(np.sum(np.abs(Z[k][f] * (CX[k][a1] - CX[k][a0]) * (CY[k][b1] - CY[k][b0]))))
+    return out
+
+
+def test_map_path_bf16_tables_match_oracle_r32():
+    """BF16 query tables of the compact rank-32 layout (Sec. 4.4 storage):
+    the library's CX, CY and Z bit-equal to the oracle's rounding of its own
+    summed-area tables of the fitted X, Y (FP64 sums, then FP32, then BF16)
+    and of Z; the query on them against the oracle's block-split query on
+    the same stored values within 1e-5 of the rank terms' magnitude; the
+    query error against the FP32 tables within the BF16 storage bound;
+    sampling refuses BF16 tables."""
+    cfg, nxy, d = _c1()
+    cs, t = 8, 16
+    tab = G.cp_als_clustered_map(torch.from_numpy(nxy), d, t, cs, 32, iters=2, seed=3)
+    bt = G.clustered_bf16(tab)
+    assert bt.dtype == "bf16" and bt.CX.dtype == torch.bfloat16 and bt.Z.shape == tab.Z.shape
+    X, Y, Z, _ = _shaped(tab, cfg.nu, cfg.nv, cfg.nbins, t, cs)
+    CXb = quant.bf16_round(cluster.block_cumulative(X)).astype(np.float64)
+    CYb = quant.bf16_round(cluster.block_cumulative(Y)).astype(np.float64)
+    Zb = quant.bf16_round(Z).astype(np.float64)
+    assert np.array_equal(bt.CX.float().cpu().numpy().reshape(CXb.shape), CXb)
+    assert np.array_equal(bt.CY.float().cpu().numpy().reshape(CYb.shape), CYb)
+    assert np.array_equal(bt.Z.float().cpu().numpy(), quant.bf16_round(tab.Z.cpu().numpy()))
+    rng = np.random.default_rng(9)
+    q = _random_queries(rng, 4000, cfg.nu, cfg.nv, cfg.nlevels, cfg.nbins)
+    qd = torch.from_numpy(q.astype(np.int32))
+    got = G.query_clustered(bt, qd).cpu().numpy().astype(np.float64)
+    want = cluster.clustered_range_query_tables(CXb, CYb, Zb, q, cfg.nlevels, cs)
+    mag = _table_magnitude(CXb, CYb, Zb, q, cfg.nlevels, cs)
+    assert np.all(np.abs(got - want) <= 1e-5 * mag + 1e-30)
+    # BF16 storage against the FP32 tables: three rounded factors of a term
+    f32 = G.query_clustered(tab, qd).cpu().numpy().astype(np.float64)
+    m32 = _magnitude(X, Y, Z, q, cfg.nlevels, cs)
+    assert np.all(np.abs(got - f32) <= 4 * 2.0 ** -8 * m32 + 1e-30)
+    uvl = torch.zeros((4, 3), dtype=torch.int32)
+    rnd = torch.zeros((4, 7), dtype=torch.float32)
+    with pytest.raises(G.GlintError):
+        G.sample_clustered(bt, uvl, rnd)
 
 
 def test_map_index_many_tensors_and_scan_chunks():

@@ -2,11 +2,13 @@
 SplitMix64 generator against its published outputs, exact recovery of a
 tensor that is low-rank per region and block (with blank blocks), the
 block-split range query against explicit box sums of the reconstruction,
-and the accuracy gain over one global CP on the 64x64 workload."""
+the query on stored (BF16-rounded) summed-area tables against the query of
+the per-bin values those tables sum, and the accuracy gain over one global
+CP on the 64x64 workload."""
 import numpy as np
 
 import gen
-from oracle import cluster, cp_als, ndf, query
+from oracle import cluster, cp_als, ndf, quant, query
 
 
 def test_splitmix64_published_outputs():
@@ -95,6 +97,39 @@ def test_block_split_query_equals_box_sums_of_the_reconstruction():
     got = cluster.clustered_range_query(X, Y, Z, q, nl, cs)
     want = ndf.box_sum(rec, q)
     assert np.max(np.abs(got - want)) <= 1e-12 * max(1.0, np.abs(want).max())
+
+
+def test_query_on_rounded_tables_is_the_query_of_their_bin_differences():
+    """Summed-area tables rounded to BF16 (Sec. 4.4 storage) are exactly the
+    summed-area tables of their own first differences (BF16 values differ
+    and add exactly in FP64), so the query on the stored tables equals the
+    plain block-split query of those per-bin values, and both equal the box
+    sums of that reconstruction; the FP32-level rounding moves the result
+    away from the unrounded query."""
+    rng = np.random.default_rng(4)
+    nu, nv, nl, N, t, cs, R = 8, 4, 3, 16, 4, 4, 3
+    T = rng.random((nu, nv, nl, N, N))
+    X, Y, Z, _, _ = cluster.clustered_cp(T, t, cs, R, iters=2, seed=5)
+    CXb = quant.bf16_round(cluster.block_cumulative(X)).astype(np.float64)
+    CYb = quant.bf16_round(cluster.block_cumulative(Y)).astype(np.float64)
+    Zb = quant.bf16_round(Z).astype(np.float64)
+    assert np.all(CXb[..., 0, :] == 0.0)
+    Xd, Yd = np.diff(CXb, axis=-2), np.diff(CYb, axis=-2)
+    assert np.array_equal(cluster.block_cumulative(Xd), CXb)
+    q = np.empty((400, 7), dtype=np.int64)
+    q[:, 0] = rng.integers(-8, 16, 400)
+    q[:, 1] = rng.integers(0, nv, 400)
+    q[:, 2] = rng.integers(0, nl, 400)
+    a = rng.integers(0, N + 1, (400, 2))
+    b = rng.integers(0, N + 1, (400, 2))
+    q[:, 3], q[:, 4] = a.min(1), a.max(1)
+    q[:, 5], q[:, 6] = b.min(1), b.max(1)
+    got = cluster.clustered_range_query_tables(CXb, CYb, Zb, q, nl, cs)
+    assert np.array_equal(got, cluster.clustered_range_query(Xd, Yd, Zb, q, nl, cs))
+    want = ndf.box_sum(cluster.reconstruct(Xd, Yd, Zb, nl, cs), q)
+    assert np.max(np.abs(got - want)) <= 1e-12 * max(1.0, np.abs(want).max())
+    plain = cluster.clustered_range_query(X, Y, Z, q, nl, cs)
+    assert np.max(np.abs(got - plain)) > 1e-6 * np.abs(plain).max()
 
 
 def test_clustered_layout_is_far_more_accurate_than_one_global_cp():
