@@ -65,7 +65,9 @@ MEASURED_TRAFFIC = {
     "k_mttkrp_z": ("paper_2109_14807_amd/csrc/cp_als.hip", "fc21e4c6223d0b00e6b413af67d951920b9cea9a", 34934241770),
     "k_query_c4": ("paper_2109_14807_amd/csrc/query.hip", "8a7a75a2ad759f50156271a15ebf7d6f529c805e", 601509696),
     "k_query_r16": ("paper_2109_14807_amd/csrc/query.hip", "8a7a75a2ad759f50156271a15ebf7d6f529c805e", 531011584),
-    "k_query_clustered": ("paper_2109_14807_amd/csrc/cluster.hip", "fc2449c87f6a75f2ef4cb443fe819c7d93fa9885", 9295752320),
+    "k_query_clustered": ("paper_2109_14807_amd/csrc/cluster.hip", "1c5724aef40734c52bbd83704fecd3945011d498", 9298941888),
+    "k_query_clustered_bf16": ("paper_2109_14807_amd/csrc/cluster.hip", "1c5724aef40734c52bbd83704fecd3945011d498",
+                               8388655040),
     "k_query_c3": ("paper_2109_14807_amd/csrc/query.hip", "8a7a75a2ad759f50156271a15ebf7d6f529c805e", 2076635648),
     "k_query_grouped_c5_bf16": ("paper_2109_14807_amd/csrc/query.hip", "8a7a75a2ad759f50156271a15ebf7d6f529c805e",
                                 966139392),
@@ -555,6 +557,11 @@ def leg_clustered(args, dev, keep):
                           "fp32_table_bytes": int(sum(x.numel() * 4 for x in (tab.CX, tab.CY, tab.Z))),
                           **flat_rate(nq, msb), "speedup_over_fp32_tables": ms / msb,
                           "error_vs_bruteforce": ebfb["all"], "rel_l2_vs_fp32_tables": d32}
+    trb = measured_traffic("k_query_clustered_bf16")
+    rep["bf16_tables"]["traffic"] = trb
+    if trb:
+        rep["bf16_tables"]["traffic_gbs"] = trb / (msb * 1e-3) / 1e9
+        rep["bf16_tables"]["traffic_frac"] = rep["bf16_tables"]["traffic_gbs"] / HBM_PEAK_GBS
     log(f"clustered BF16: query {rep['bf16_tables']['queries_per_s'] / 1e9:.2f} G q/s, E_bf {ebfb['all']:.4f}")
     return rep
 
