@@ -155,8 +155,11 @@ def _table_magnitude(CX, CY, Z, q, nl, cs):
     return out
 
 
-def test_map_path_bf16_tables_match_oracle_r32():
-    """BF16 query tables of the compact rank-32 layout (Sec. 4.4 storage):
+@pytest.mark.parametrize("R", [4, 8, 16, 32])
+def test_map_path_bf16_tables_match_oracle(R):
+    """BF16 query tables of the compact layout (Sec. 4.4 storage; rank 4
+    reads four ranks a lane from 8-byte loads, ranks 8 to 32 eight from
+    16-byte loads, one to four lanes a query):
     the library's CX, CY and Z bit-equal to the oracle's rounding of its own
     summed-area tables of the fitted X, Y (FP64 sums, then FP32, then BF16)
     and of Z; the query on them against the oracle's block-split query on
@@ -165,7 +168,7 @@ def test_map_path_bf16_tables_match_oracle_r32():
     sampling refuses BF16 tables."""
     cfg, nxy, d = _c1()
     cs, t = 8, 16
-    tab = G.cp_als_clustered_map(torch.from_numpy(nxy), d, t, cs, 32, iters=2, seed=3)
+    tab = G.cp_als_clustered_map(torch.from_numpy(nxy), d, t, cs, R, iters=2, seed=3)
     bt = G.clustered_bf16(tab)
     assert bt.dtype == "bf16" and bt.CX.dtype == torch.bfloat16 and bt.Z.shape == tab.Z.shape
     X, Y, Z, _ = _shaped(tab, cfg.nu, cfg.nv, cfg.nbins, t, cs)
