@@ -63,16 +63,16 @@ Q_BYTES = 32                   # algorithmic HBM bytes per flat query: 28-byte r
 MEASURED_TRAFFIC = {
     "k_mttkrp_y": ("paper_2109_14807_amd/csrc/cp_als.hip", "fc21e4c6223d0b00e6b413af67d951920b9cea9a", 36577139135),
     "k_mttkrp_z": ("paper_2109_14807_amd/csrc/cp_als.hip", "fc21e4c6223d0b00e6b413af67d951920b9cea9a", 34934241770),
-    "k_query_c4": ("paper_2109_14807_amd/csrc/query.hip", "8a7a75a2ad759f50156271a15ebf7d6f529c805e", 601509696),
-    "k_query_r16": ("paper_2109_14807_amd/csrc/query.hip", "8a7a75a2ad759f50156271a15ebf7d6f529c805e", 531011584),
+    "k_query_c4": ("paper_2109_14807_amd/csrc/query.hip", "a1e2724f94e86b56b0967e488a072eeaab4adb8a", 554306304),
+    "k_query_r16": ("paper_2109_14807_amd/csrc/query.hip", "a1e2724f94e86b56b0967e488a072eeaab4adb8a", 532277504),
     "k_query_clustered": ("paper_2109_14807_amd/csrc/cluster.hip", "1c5724aef40734c52bbd83704fecd3945011d498", 9298941888),
     "k_query_clustered_bf16": ("paper_2109_14807_amd/csrc/cluster.hip", "1c5724aef40734c52bbd83704fecd3945011d498",
                                8388655040),
-    "k_query_c3": ("paper_2109_14807_amd/csrc/query.hip", "8a7a75a2ad759f50156271a15ebf7d6f529c805e", 2076635648),
-    "k_query_grouped_c5_bf16": ("paper_2109_14807_amd/csrc/query.hip", "8a7a75a2ad759f50156271a15ebf7d6f529c805e",
-                                966139392),
-    "k_query_grouped_c5_fp8": ("paper_2109_14807_amd/csrc/query.hip", "8a7a75a2ad759f50156271a15ebf7d6f529c805e",
-                               965117760),
+    "k_query_c3": ("paper_2109_14807_amd/csrc/query.hip", "a1e2724f94e86b56b0967e488a072eeaab4adb8a", 2056795136),
+    "k_query_grouped_c5_bf16": ("paper_2109_14807_amd/csrc/query.hip", "a1e2724f94e86b56b0967e488a072eeaab4adb8a",
+                                966130304),
+    "k_query_grouped_c5_fp8": ("paper_2109_14807_amd/csrc/query.hip", "a1e2724f94e86b56b0967e488a072eeaab4adb8a",
+                               965127168),
 }
 
 LEGS = ("c3", "c5", "r16", "c2", "clustered", "refine", "sweep", "cpu_baseline")
