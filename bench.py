@@ -65,9 +65,9 @@ MEASURED_TRAFFIC = {
     "k_mttkrp_z": ("paper_2109_14807_amd/csrc/cp_als.hip", "fc21e4c6223d0b00e6b413af67d951920b9cea9a", 34934241770),
     "k_query_c4": ("paper_2109_14807_amd/csrc/query.hip", "a1e2724f94e86b56b0967e488a072eeaab4adb8a", 554306304),
     "k_query_r16": ("paper_2109_14807_amd/csrc/query.hip", "a1e2724f94e86b56b0967e488a072eeaab4adb8a", 532277504),
-    "k_query_clustered": ("paper_2109_14807_amd/csrc/cluster.hip", "1c5724aef40734c52bbd83704fecd3945011d498", 9298941888),
-    "k_query_clustered_bf16": ("paper_2109_14807_amd/csrc/cluster.hip", "1c5724aef40734c52bbd83704fecd3945011d498",
-                               8388655040),
+    "k_query_clustered": ("paper_2109_14807_amd/csrc/cluster.hip", "08645f6f9e0410b9481c4a048e056380329dbfe0", 9302617408),
+    "k_query_clustered_bf16": ("paper_2109_14807_amd/csrc/cluster.hip", "08645f6f9e0410b9481c4a048e056380329dbfe0",
+                               8402666272),
     "k_query_c3": ("paper_2109_14807_amd/csrc/query.hip", "a1e2724f94e86b56b0967e488a072eeaab4adb8a", 2056795136),
     "k_query_grouped_c5_bf16": ("paper_2109_14807_amd/csrc/query.hip", "a1e2724f94e86b56b0967e488a072eeaab4adb8a",
                                 966130304),

@@ -1015,15 +1015,20 @@ __global__ __launch_bounds__(kClQueryThreads) void k_query_clustered(ClQueryArgs
       const int64_t qi = base + lane;
       const int64_t qc = qi < a.nq ? qi : a.nq - 1;
       const int32_t* rec = a.q + qc * 7;
-      const int u = glint_wrap(rec[0], a.nu), v = glint_wrap(rec[1], a.nv);
-      const int l = glint_clampi(rec[2], 0, a.nl - 1);
+      // records and results stream through once (non-temporal), the table
+      // rows stay in the caches for the footprint's other boxes
+      int f[7];
+#pragma unroll
+      for (int e = 0; e < 7; ++e) f[e] = __builtin_nontemporal_load(rec + e);
+      const int u = glint_wrap(f[0], a.nu), v = glint_wrap(f[1], a.nv);
+      const int l = glint_clampi(f[2], 0, a.nl - 1);
       ClRec cr;
       cr.tensor0 = ((u / a.cs) * a.ncv + v / a.cs) * a.nb * a.nb;
       cr.f = ((u % a.cs) * a.cs + v % a.cs) * a.nl + l;
-      cr.slo = glint_clampi(rec[3], 0, a.N);
-      cr.shi = glint_clampi(rec[4], 0, a.N);
-      cr.tlo = glint_clampi(rec[5], 0, a.N);
-      cr.thi = glint_clampi(rec[6], 0, a.N);
+      cr.slo = glint_clampi(f[3], 0, a.N);
+      cr.shi = glint_clampi(f[4], 0, a.N);
+      cr.tlo = glint_clampi(f[5], 0, a.N);
+      cr.thi = glint_clampi(f[6], 0, a.N);
       cr.pad = 0;
       cr.nblk = 0;
       const bool nonempty = cr.slo < cr.shi && cr.tlo < cr.thi;
@@ -1096,7 +1101,7 @@ __global__ __launch_bounds__(kClQueryThreads) void k_query_clustered(ClQueryArgs
     }
     __builtin_amdgcn_wave_barrier();
     const int64_t qo = base + g * LPQ + j;
-    if (qo < a.nq) a.out[qo] = res;
+    if (qo < a.nq) __builtin_nontemporal_store(res, a.out + qo);
   }
 }
 
