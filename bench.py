@@ -122,20 +122,19 @@ def log(msg):
 # ---------------------------------------------------------------------------
 
 def timed(fn, reps):
-    """Mean duration (ms) of fn's launches, each bracketed by HIP events on the
-    current stream (the stream the library calls enqueue on)."""
-    import numpy as np
+    """Mean duration (ms) of fn's launches: `reps` launches back to back
+    between two HIP events on the current stream (the stream the library
+    calls enqueue on), after one untimed launch."""
     import torch
     stream = torch.cuda.current_stream()
-    e0 = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
-    e1 = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     fn()
-    for i in range(reps):
-        e0[i].record(stream)
+    e0.record(stream)
+    for _ in range(reps):
         fn()
-        e1[i].record(stream)
+    e1.record(stream)
     torch.cuda.synchronize()
-    return float(np.mean([e0[i].elapsed_time(e1[i]) for i in range(reps)]))
+    return e0.elapsed_time(e1) / reps
 
 
 def stored_tables(tabs):
@@ -277,16 +276,18 @@ def headline(args, dev, keep):
     for _ in range(args.warmup):
         L.glint_query(fac, q, out)
     torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    # HIP events on the library's stream around the K back-to-back launches
+    # of the timed region: their mean launch duration is the roofline's
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     w0 = time.perf_counter()
-    for a, b in evs:
-        a.record(stream)
+    e0.record(stream)
+    for _ in range(args.steps):
         L.glint_query(fac, q, out)
-        b.record(stream)
+    e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
-    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    kernel_ms = e0.elapsed_time(e1) / args.steps
     ms_per_step = wall * 1e3 / args.steps
     log(f"c4: {args.steps} timed steps in {wall * 1e3:.2f} ms (kernel {kernel_ms:.4f} ms)")
 
