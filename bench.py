@@ -121,14 +121,30 @@ def log(msg):
 # helpers
 # ---------------------------------------------------------------------------
 
-def timed(fn, reps):
+def timed(fn, reps, spin_s=0.2):
     """Mean duration (ms) of fn's launches: `reps` launches back to back
     between two HIP events on the current stream (the stream the library
-    calls enqueue on), after one untimed launch."""
+    calls enqueue on), after untimed launches for about `spin_s` seconds (at
+    least one), so that the GPU has left the clocks it idles at while a leg
+    prepares its inputs on the host."""
     import torch
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    fn()
+    t0 = time.perf_counter()
+    n, calls = 1, 0
+    while True:
+        for _ in range(n):
+            fn()
+        calls += n
+        torch.cuda.synchronize()
+        if time.perf_counter() - t0 >= spin_s:
+            break
+        n = min(2 * n, 64)
+    if calls > 1:
+        # a short launch: one more is queued ahead of the first event, so that
+        # the timed launches run back to back from it (without it the host's
+        # latency to the first launch is timed too)
+        fn()
     e0.record(stream)
     for _ in range(reps):
         fn()
